@@ -1,0 +1,212 @@
+/*
+ * riga.h -- C ABI of the rIGA shift-and-invert eigensolver for one MI355X.
+ *
+ * Computes eigenpairs of the generalized symmetric eigenproblem
+ *     K u = lambda M u                                   (Eq. GHEP, Sec. 3.1)
+ * where K and M are the Galerkin stiffness and mass matrices of the Dirichlet
+ * problem -div(kappa grad u) = lambda rho u on the unit square or cube
+ * (Eqs. helmholtz, weakform--weakform3; kappa = rho = 1 is the paper's
+ * Laplace problem), discretised with tensor-product B-splines of degree p on
+ * a uniform mesh (Eqs. u, U, N), optionally refined into rIGA
+ * macro-elements by knots of multiplicity p every `sep_spacing` elements
+ * (Sec. 3.2).  The solver is shift-and-invert Lanczos (Eqs. ST_GHEP,
+ * Lanczos--LanczosAlphaBeta) on LDL^T factorisations of K - sigma M ordered
+ * by the tree of separators, with spectrum slicing driven by inertia
+ * (Remark on inertia) and Ritz extraction (Eqs. LanczosRitz, RitzValues).
+ *
+ * Conventions shared by every call:
+ *  - Every call returns riga_status (RIGA_OK = 0).  No C++ exception crosses
+ *    the ABI.  On error, riga_last_error() returns a thread-local message.
+ *  - Degrees of freedom are the interior tensor-product functions (the first
+ *    and last function in each direction are removed by the Dirichlet
+ *    condition), ordered lexicographically with x fastest (the vectorised
+ *    control tensor of the Remark on Tensor(u)).  Elements are ordered x
+ *    fastest as well.
+ *  - "_dev" pointers are device (HBM) pointers; "_host" pointers are host
+ *    memory.  The caller owns every buffer it passes; the library copies
+ *    what it keeps.  Work is ordered on the hipStream_t passed as `stream`
+ *    (NULL = the null stream); calls synchronise that stream before they
+ *    return host results.
+ *  - A riga_problem is owned by the caller until riga_destroy().  It must not
+ *    be used from two threads at once.
+ */
+#ifndef RIGA_H
+#define RIGA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RIGA_OK = 0,
+  RIGA_EINVAL = -1,        /* invalid argument or descriptor */
+  RIGA_ENOMEM = -2,        /* device or host allocation failed */
+  RIGA_EDEVICE = -3,       /* a HIP call failed (message names it) */
+  RIGA_ENOCONV = -4,       /* not all requested pairs converged; n_found holds the rest */
+  RIGA_ESINGULAR = -5,     /* K - sigma M numerically singular and shift perturbation disabled */
+  RIGA_EDEGENERATE = -6,   /* gradient requested for an eigenvalue that is not simple */
+  RIGA_EUNSUPPORTED = -7   /* valid request outside what this build implements */
+} riga_status;
+
+enum { RIGA_FP64 = 0, RIGA_MIXED = 1 };            /* riga_eigs_opts.precision */
+enum { RIGA_MAT_K = 0, RIGA_MAT_M = 1, RIGA_MAT_A = 2 }; /* riga_spmv: K, M, K - sigma M */
+
+typedef struct riga_problem riga_problem;
+
+/* Mesh and coefficients (Sec. 3.1--3.2). */
+typedef struct {
+  int32_t dim;            /* 2 or 3 */
+  int32_t ne[3];          /* elements per direction (unused entries ignored) */
+  int32_t p;              /* B-spline degree, 1..6 */
+  int32_t sep_spacing;    /* 0: maximum-continuity IGA; s > 0: knot multiplicity p at
+                             every element boundary k with k % s == 0 (rIGA, Sec. 3.2) */
+  int32_t nquad;          /* Gauss points per direction; 0 -> p + 1 */
+  const double* kappa;    /* [n_elem] per-element stiffness coefficient, > 0; NULL -> 1 */
+  const double* rho;      /* [n_elem] per-element mass coefficient, > 0; NULL -> 1 */
+  int32_t coeffs_on_device; /* kappa/rho are device pointers (1) or host pointers (0) */
+  int32_t leaf_dofs;      /* nested-dissection leaf size in DOFs; 0 -> default */
+  void* stream;           /* hipStream_t */
+} riga_mesh_desc;
+
+/* Eigen-solve request (Sec. 4.1: eigenvalues in [lambda_s, lambda_e]). */
+typedef struct {
+  double lo;              /* interval start (inclusive) */
+  double hi;              /* interval end (exclusive); +INFINITY -> the nev lowest >= lo */
+  int32_t nev;            /* number of pairs wanted, returned ascending */
+  int32_t precision;      /* RIGA_FP64, or RIGA_MIXED: FP32 fronts and solves refined in FP64 */
+  double tol;             /* accept a pair when ||K u - lambda M u||_2 / (||K||_1 ||u||_2) <= tol;
+                             0 -> 1e-9 */
+  int32_t max_basis;      /* Lanczos basis size per run; 0 -> default (<= 512) */
+  int32_t max_restarts;   /* Lanczos runs per shift; 0 -> default */
+  int32_t per_shift;      /* eigenpairs targeted per shift; 0 -> default */
+  uint64_t seed;          /* start vectors (counter-based hash of seed and index) */
+  void* stream;           /* hipStream_t */
+} riga_eigs_opts;
+
+/* Counters of the operation classes of Table matvecs, and timings (seconds). */
+typedef struct {
+  int32_t n_shift;        /* shifts used (N_sh) */
+  int32_t n_fact;         /* numeric factorisations (N_fa) */
+  int32_t n_fb;           /* forward/backward eliminations (N_fb) */
+  int32_t n_mv;           /* sparse matrix-vector products (N_mv), M, K and A */
+  int32_t n_it;           /* Lanczos runs (restarts included) */
+  int32_t n_ir;           /* iterative-refinement corrections (mixed precision) */
+  int32_t n_perturbed_pivots; /* pivots replaced by a perturbation (static pivoting) */
+  int32_t n_2x2_pivots;   /* Bunch-Kaufman 2x2 pivots taken */
+  double t_fact, t_fb, t_mv, t_orth, t_proj, t_ritz, t_total;
+  double flops_fact;      /* algorithmic flops of one factorisation */
+  double bytes_fb;        /* algorithmic bytes of one forward+backward elimination */
+} riga_stats;
+
+/* Static facts about an assembled problem (host-side analysis). */
+typedef struct {
+  int64_t n_dof;          /* interior DOFs N */
+  int64_t n_elem;         /* elements */
+  int64_t nnz;            /* structural non-zeros of K (= of M) */
+  int32_t n1[3];          /* interior functions per direction */
+  int32_t n_fronts;       /* nodes of the separator tree */
+  int32_t tree_height;    /* levels of the tree (leaves = 0) */
+  int32_t max_front;      /* largest front order */
+  int32_t max_fs;         /* largest fully-summed block */
+  int64_t nnz_l;          /* entries of L (lower, diagonal included) */
+  double flops_fact;      /* algorithmic flops of one factorisation */
+  int64_t front_pool;     /* entries of the dense front pool */
+} riga_problem_info_t;
+
+/* Allocation hooks (e.g. torch's caching allocator).  Optional. */
+typedef struct {
+  void* ctx;
+  void* (*alloc)(void* ctx, size_t bytes, void* stream);
+  void (*free)(void* ctx, void* ptr, void* stream);
+} riga_allocator;
+
+/* riga_set_allocator: route the library's device workspaces through `a`
+ * (NULL restores hipMalloc/hipFree).  Affects problems created afterwards. */
+riga_status riga_set_allocator(const riga_allocator* a);
+
+/* riga_analyze: host-only analysis of a mesh (no device needed): knot
+ * vectors and DOF maps (Sec. 3.1--3.2), the sparsity pattern, the tree of
+ * separators and the supernodal symbolic factorisation (Sec. 5, one symbolic
+ * factorisation per pattern).  *out receives a problem handle without device
+ * data; riga_problem_info and riga_tree_export work on it, the solver
+ * calls return RIGA_EINVAL.  Errors: RIGA_EINVAL for a bad descriptor. */
+riga_status riga_analyze(const riga_mesh_desc* desc, riga_problem** out);
+
+/* riga_assemble: riga_analyze, then assemble K and M on the device with
+ * Gauss quadrature (Eqs. 1Dmatrix/2Dmatrix generalised to per-element
+ * kappa, rho).  `desc->kappa/rho` are copied.  *out is owned by the caller.
+ * Errors: RIGA_EINVAL (descriptor, non-positive coefficient), RIGA_ENOMEM,
+ * RIGA_EDEVICE. */
+riga_status riga_assemble(const riga_mesh_desc* desc, riga_problem** out);
+
+riga_status riga_problem_info(const riga_problem* pr, riga_problem_info_t* info);
+
+/* riga_tree_export: copy the symbolic analysis to host arrays (any may be
+ * NULL).  perm[n_dof]: new (elimination) position of each DOF.
+ * front_k/front_f/front_parent/front_height[n_fronts]: fully-summed size,
+ * front order, parent (-1 = root) and height of each tree node, in
+ * elimination (post-)order.  front_rows: concatenated front index lists
+ * (original DOF indices, fully-summed first), sum(front_f) entries. */
+riga_status riga_tree_export(const riga_problem* pr, int32_t* perm, int32_t* front_k,
+                             int32_t* front_f, int32_t* front_parent, int32_t* front_height,
+                             int32_t* front_rows);
+
+/* riga_get_matrices: copy the assembled CSR matrices to the host (row_ptr
+ * [n_dof+1], col_idx [nnz], k_vals/m_vals [nnz]; any may be NULL).  Column
+ * indices ascending within a row. */
+riga_status riga_get_matrices(const riga_problem* pr, int64_t* row_ptr, int32_t* col_idx,
+                              double* k_vals, double* m_vals);
+
+/* riga_spmv: y = K x, M x or (K - sigma M) x for the last factorised sigma
+ * (Sec. 5.1 "mat-vec").  x_dev, y_dev: [n_dof] device FP64. */
+riga_status riga_spmv(riga_problem* pr, int32_t which, const double* x_dev, double* y_dev,
+                      void* stream);
+
+/* riga_factor: numeric LDL^T factorisation of K - sigma M with Bunch-Kaufman
+ * pivoting inside fronts (Sec. 5: one numeric factorisation per shift), in
+ * FP64 or (precision = RIGA_MIXED) FP32.  *neg_pivots (may be NULL) receives
+ * the inertia nu(K - sigma M), the number of eigenvalues below sigma (Remark
+ * on inertia).  The factorisation stays in the problem for riga_solve. */
+riga_status riga_factor(riga_problem* pr, double sigma, int32_t precision,
+                        int64_t* neg_pivots, riga_stats* stats);
+
+/* riga_solve: x = (K - sigma M)^{-1} b with the last factorisation (one
+ * forward/backward elimination; in RIGA_MIXED the FP32 solve is refined in
+ * FP64 until ||b - A x|| <= 1e-13 ||b|| or `max_ir` corrections).  b_dev,
+ * x_dev: [n_dof] device FP64, may not alias. */
+riga_status riga_solve(riga_problem* pr, const double* b_dev, double* x_dev, int32_t max_ir,
+                       void* stream);
+
+/* riga_eigs: the nev lowest eigenpairs with lambda in [lo, hi) (Sec. 4).
+ * evals_host[nev]: ascending eigenvalues (Rayleigh quotients).
+ * evecs_dev: [n_dof * nev] column-major device buffer for M-normalised
+ * eigenvectors, or NULL.  resid_host[nev] (or NULL): relative residuals
+ * ||K u - lambda M u||_2 / (||K||_1 ||u||_2).  *n_found: pairs returned.
+ * stats (or NULL): counters and timings.  Returns RIGA_ENOCONV (with
+ * n_found < nev pairs filled) when the budget ran out. */
+riga_status riga_eigs(riga_problem* pr, const riga_eigs_opts* opts, int32_t* n_found,
+                      double* evals_host, double* evecs_dev, double* resid_host,
+                      riga_stats* stats);
+
+/* riga_eig_grad: gradient of L = sum_i w_i lambda_i with respect to the
+ * per-element coefficients, for M-normalised simple eigenpairs (not in the
+ * paper; first-order perturbation: d lambda/d kappa_e = u^T K0_e u,
+ * d lambda/d rho_e = -lambda u^T M0_e u).  evals_host[k], w_host[k] host;
+ * evecs_dev [n_dof * k] column-major device; dkappa_dev, drho_dev [n_elem]
+ * device outputs.  RIGA_EDEGENERATE if two of the eigenvalues are within
+ * 1e-8 relative of each other. */
+riga_status riga_eig_grad(riga_problem* pr, int32_t k, const double* evals_host,
+                          const double* evecs_dev, const double* w_host, double* dkappa_dev,
+                          double* drho_dev, void* stream);
+
+void riga_destroy(riga_problem* pr);
+const char* riga_status_string(riga_status s);
+const char* riga_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RIGA_H */

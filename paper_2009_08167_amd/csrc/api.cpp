@@ -1,0 +1,279 @@
+// The C ABI (include/riga.h): argument checks, error mapping, handle
+// lifetime.  No exception crosses this boundary.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "problem.h"
+
+namespace riga {
+void set_allocator(const riga_allocator* a);
+void setup_device(riga_problem* pr, const riga_mesh_desc* desc);
+riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found, double* evals,
+                     double* evecs, double* resid, riga_stats* stats_out);
+}  // namespace riga
+
+namespace {
+
+thread_local std::string g_err;
+
+riga_status fail(riga_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+template <class F>
+riga_status guarded(F&& f) {
+  try {
+    g_err.clear();
+    return f();
+  } catch (const riga::Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(RIGA_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(RIGA_EINVAL, e.what());
+  } catch (...) {
+    return fail(RIGA_EINVAL, "unknown error");
+  }
+}
+
+riga_status do_analyze(const riga_mesh_desc* d, riga_problem** out) {
+  if (!d || !out) return fail(RIGA_EINVAL, "null descriptor or output");
+  *out = nullptr;
+  auto* pr = new riga_problem();
+  std::string err = riga::analyze(d->dim, d->ne, d->p, d->sep_spacing, d->nquad, d->leaf_dofs, pr->an);
+  if (!err.empty()) {
+    delete pr;
+    return fail(RIGA_EINVAL, err);
+  }
+  *out = pr;
+  return RIGA_OK;
+}
+
+bool need_device(const riga_problem* pr) { return pr && pr->has_device; }
+
+}  // namespace
+
+extern "C" {
+
+riga_status riga_set_allocator(const riga_allocator* a) {
+  return guarded([&] {
+    riga::set_allocator(a);
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_analyze(const riga_mesh_desc* desc, riga_problem** out) {
+  return guarded([&] { return do_analyze(desc, out); });
+}
+
+riga_status riga_assemble(const riga_mesh_desc* desc, riga_problem** out) {
+  return guarded([&]() -> riga_status {
+    riga_status s = do_analyze(desc, out);
+    if (s != RIGA_OK) return s;
+    try {
+      riga::setup_device(*out, desc);
+    } catch (...) {
+      delete *out;
+      *out = nullptr;
+      throw;
+    }
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_problem_info(const riga_problem* pr, riga_problem_info_t* info) {
+  if (!pr || !info) return fail(RIGA_EINVAL, "null argument");
+  const riga::Analysis& a = pr->an;
+  info->n_dof = a.N;
+  info->n_elem = a.n_elem;
+  info->nnz = a.row_ptr.empty() ? 0 : a.row_ptr[a.N];
+  for (int d = 0; d < 3; ++d) info->n1[d] = a.n1[d];
+  info->n_fronts = a.n_fronts;
+  info->tree_height = a.height;
+  info->max_front = a.max_front;
+  info->max_fs = a.max_fs;
+  info->nnz_l = a.nnz_l;
+  info->flops_fact = a.flops_fact;
+  info->front_pool = a.pool_size;
+  return RIGA_OK;
+}
+
+riga_status riga_tree_export(const riga_problem* pr, int32_t* perm, int32_t* front_k,
+                             int32_t* front_f, int32_t* front_parent, int32_t* front_height,
+                             int32_t* front_rows) {
+  if (!pr) return fail(RIGA_EINVAL, "null problem");
+  const riga::Analysis& a = pr->an;
+  if (perm) std::memcpy(perm, a.perm.data(), a.N * sizeof(int32_t));
+  if (front_k) std::memcpy(front_k, a.f_k.data(), a.n_fronts * sizeof(int32_t));
+  if (front_f) std::memcpy(front_f, a.f_f.data(), a.n_fronts * sizeof(int32_t));
+  if (front_parent) std::memcpy(front_parent, a.f_parent.data(), a.n_fronts * sizeof(int32_t));
+  if (front_height) std::memcpy(front_height, a.f_height.data(), a.n_fronts * sizeof(int32_t));
+  if (front_rows) std::memcpy(front_rows, a.rows.data(), a.rows.size() * sizeof(int32_t));
+  return RIGA_OK;
+}
+
+riga_status riga_get_matrices(const riga_problem* pr, int64_t* row_ptr, int32_t* col_idx,
+                              double* k_vals, double* m_vals) {
+  return guarded([&]() -> riga_status {
+    if (!pr) return fail(RIGA_EINVAL, "null problem");
+    const riga::Analysis& a = pr->an;
+    const int64_t nnz = a.row_ptr[a.N];
+    if (row_ptr) std::memcpy(row_ptr, a.row_ptr.data(), (a.N + 1) * sizeof(int64_t));
+    if (col_idx) std::memcpy(col_idx, a.col_idx.data(), nnz * sizeof(int32_t));
+    if (k_vals || m_vals) {
+      if (!need_device(pr)) return fail(RIGA_EINVAL, "problem has no device data (use riga_assemble)");
+      if (k_vals) HIPCHECK(hipMemcpy(k_vals, pr->kv.p, nnz * sizeof(double), hipMemcpyDeviceToHost));
+      if (m_vals) HIPCHECK(hipMemcpy(m_vals, pr->mv.p, nnz * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_spmv(riga_problem* pr, int32_t which, const double* x, double* y, void* stream) {
+  return guarded([&]() -> riga_status {
+    if (!need_device(pr) || !x || !y) return fail(RIGA_EINVAL, "bad problem or vectors");
+    hipStream_t s = (hipStream_t)stream;
+    const double* vals = nullptr;
+    if (which == RIGA_MAT_K) vals = pr->kv.p;
+    else if (which == RIGA_MAT_M) vals = pr->mv.p;
+    else if (which == RIGA_MAT_A) {
+      if (!pr->factored) return fail(RIGA_EINVAL, "no shift factorised yet");
+      if (!pr->av.p) pr->av.alloc(pr->kv.n, s);
+      riga::launch_axpby_vals(pr->kv.p, pr->mv.p, pr->sigma, pr->av.p, (int64_t)pr->kv.n, s);
+      vals = pr->av.p;
+    } else return fail(RIGA_EINVAL, "which must be RIGA_MAT_K, _M or _A");
+    riga::launch_spmv(pr, vals, x, y, nullptr, s);
+    HIPCHECK(hipStreamSynchronize(s));
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_factor(riga_problem* pr, double sigma, int32_t precision, int64_t* neg_pivots,
+                        riga_stats* stats) {
+  return guarded([&]() -> riga_status {
+    if (!need_device(pr)) return fail(RIGA_EINVAL, "problem has no device data");
+    if (!std::isfinite(sigma)) return fail(RIGA_EINVAL, "sigma must be finite");
+    if (precision != RIGA_FP64 && precision != RIGA_MIXED) return fail(RIGA_EINVAL, "bad precision");
+    riga::factor_numeric(pr, sigma, precision);
+    if (precision == RIGA_MIXED) {
+      if (!pr->av.p) pr->av.alloc(pr->kv.n, pr->stream);
+      riga::launch_axpby_vals(pr->kv.p, pr->mv.p, sigma, pr->av.p, (int64_t)pr->kv.n, pr->stream);
+      HIPCHECK(hipStreamSynchronize(pr->stream));
+    }
+    if (neg_pivots) *neg_pivots = pr->last_inertia;
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->n_fact = 1;
+      stats->n_perturbed_pivots = pr->last_perturbed;
+      stats->n_2x2_pivots = pr->last_2x2;
+      stats->flops_fact = pr->an.flops_fact;
+    }
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_solve(riga_problem* pr, const double* b, double* x, int32_t max_ir, void* stream) {
+  return guarded([&]() -> riga_status {
+    if (!need_device(pr) || !b || !x || b == x) return fail(RIGA_EINVAL, "bad problem or vectors");
+    if (!pr->factored) return fail(RIGA_EINVAL, "no factorisation");
+    hipStream_t s = (hipStream_t)stream;
+    riga::solve_fb(pr, b, x, s);
+    if (pr->fact_precision == RIGA_MIXED && max_ir > 0) {
+      // FP64 iterative refinement: r = b - A x, x += A32^{-1} r, until
+      // ||r|| <= 1e-13 ||b|| or max_ir corrections
+      const int64_t N = pr->an.N;
+      if (pr->ir_r.n < (size_t)N) {
+        pr->ir_r.alloc(N, s);
+        pr->ir_d.alloc(N, s);
+      }
+      riga::DBuf<double> part, nr;
+      part.alloc(256, s);
+      nr.alloc(2, s);
+      double h[2] = {0.0, 0.0};
+      riga::launch_dot(b, b, N, part.p, nr.p, s);
+      HIPCHECK(hipMemcpyAsync(&h[0], nr.p, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      const double bn2 = h[0];
+      for (int it = 0; it < max_ir; ++it) {
+        riga::launch_spmv(pr, pr->av.p, x, pr->ir_r.p, nullptr, s);
+        riga::launch_axpby(-1.0, pr->ir_r.p, b, pr->ir_r.p, N, s);
+        riga::launch_dot(pr->ir_r.p, pr->ir_r.p, N, part.p, nr.p + 1, s);
+        HIPCHECK(hipMemcpyAsync(&h[1], nr.p + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        if (h[1] <= 1e-26 * bn2) break;
+        riga::solve_fb(pr, pr->ir_r.p, pr->ir_d.p, s);
+        riga::launch_axpby(1.0, pr->ir_d.p, x, x, N, s);
+      }
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found, double* evals,
+                      double* evecs, double* resid, riga_stats* stats) {
+  return guarded([&]() -> riga_status {
+    if (!need_device(pr) || !o || !n_found) return fail(RIGA_EINVAL, "bad problem or options");
+    if (o->nev < 1) return fail(RIGA_EINVAL, "nev must be >= 1");
+    if (o->nev > pr->an.N) return fail(RIGA_EINVAL, "nev exceeds the number of DOFs");
+    if (!std::isfinite(o->lo) || !(o->hi > o->lo)) return fail(RIGA_EINVAL, "need finite lo < hi");
+    if (o->precision != RIGA_FP64 && o->precision != RIGA_MIXED) return fail(RIGA_EINVAL, "bad precision");
+    if (!evals) return fail(RIGA_EINVAL, "evals_host required");
+    riga_status st = riga::run_eigs(pr, o, n_found, evals, evecs, resid, stats);
+    if (st == RIGA_ENOCONV) g_err = "not all requested eigenpairs converged";
+    return st;
+  });
+}
+
+riga_status riga_eig_grad(riga_problem* pr, int32_t k, const double* evals, const double* evecs,
+                          const double* w, double* dkappa, double* drho, void* stream) {
+  return guarded([&]() -> riga_status {
+    if (!need_device(pr) || k < 1 || !evals || !evecs || !w || !dkappa || !drho)
+      return fail(RIGA_EINVAL, "bad arguments");
+    for (int i = 0; i < k; ++i)
+      for (int j = i + 1; j < k; ++j)
+        if (std::fabs(evals[i] - evals[j]) <= 1e-8 * std::max(std::fabs(evals[i]), std::fabs(evals[j])))
+          return fail(RIGA_EDEGENERATE, "eigenvalues " + std::to_string(i) + " and " +
+                                            std::to_string(j) + " are not simple");
+    hipStream_t s = (hipStream_t)stream;
+    riga::DBuf<double> lam, ww;
+    lam.alloc(k, s);
+    ww.alloc(k, s);
+    HIPCHECK(hipMemcpyAsync(lam.p, evals, k * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(ww.p, w, k * sizeof(double), hipMemcpyHostToDevice, s));
+    riga::launch_eig_grad(pr, k, evecs, lam.p, ww.p, dkappa, drho, s);
+    HIPCHECK(hipStreamSynchronize(s));
+    return RIGA_OK;
+  });
+}
+
+void riga_destroy(riga_problem* pr) {
+  if (!pr) return;
+  try {
+    if (pr->has_device) (void)hipStreamSynchronize(pr->stream);
+  } catch (...) {
+  }
+  delete pr;
+}
+
+const char* riga_status_string(riga_status s) {
+  switch (s) {
+    case RIGA_OK: return "ok";
+    case RIGA_EINVAL: return "invalid argument";
+    case RIGA_ENOMEM: return "out of memory";
+    case RIGA_EDEVICE: return "device error";
+    case RIGA_ENOCONV: return "not converged";
+    case RIGA_ESINGULAR: return "singular shifted matrix";
+    case RIGA_EDEGENERATE: return "degenerate eigenvalue";
+    case RIGA_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* riga_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

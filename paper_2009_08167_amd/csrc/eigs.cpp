@@ -1,0 +1,507 @@
+// Shift-and-invert Lanczos with full M-reorthogonalisation, explicit
+// restarts with locking, and spectrum slicing driven by inertia
+// (arXiv 2009.08167, Sec. 4: Eqs. ST_GHEP, Lanczos--RitzValues, Remark on
+// inertia, Eq. LanczosRestart and the deflation paragraph after it).
+//
+// The host only orchestrates: every vector operation, the factorisation,
+// the solves and the projected eigensolve run in the HIP kernels.  The host
+// reads back a few scalars per convergence check (Ritz values and the last
+// row of the projected eigenvectors) and the inertia of each factorisation.
+//
+// Storage: B = [U_locked | V] and W = M B, column-major N x (lock cap +
+// basis cap + 1), so one transposed product c = W^T x gives the M-inner
+// products against the locked vectors and the Lanczos basis together.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <numeric>
+
+#include "problem.h"
+
+namespace riga {
+
+void add_scalars_launch(const double* a, const double* b, double* out, hipStream_t s);
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+// RIGA_LOG=1 prints one line per Lanczos run and per shift to stderr.
+bool log_on() {
+  static const bool on = [] {
+    const char* v = std::getenv("RIGA_LOG");
+    return v && *v && *v != '0';
+  }();
+  return on;
+}
+double secs(clk::time_point a, clk::time_point b) {
+  return std::chrono::duration<double>(b - a).count();
+}
+
+struct Locked {
+  double lam;
+  double resid;
+  int col;       // column in B / W
+};
+
+struct Solver {
+  riga_problem* pr;
+  hipStream_t s;
+  int64_t N;
+  int lock_cap, mb, ncols;
+  double lo, hi, tol;
+  uint64_t seed;
+  int per_shift;
+  int max_restarts;
+  int precision;
+  int max_ir;
+  DBuf<double> B, W, x, y, c1, c2, partial, dotp, alpha, beta, scal;
+  DBuf<int32_t> flag;
+  DBuf<double> theta, S, tdwork, Sh, Ub, KU, MU, rqn, rqd, rn2, un2, lam, nrm;
+  DBuf<int32_t> sel;
+  DBuf<double> ir_r, ir_d;
+  std::vector<Locked> locked;
+  int nl = 0;            // locked columns
+  int n_evicted = 0;
+  uint64_t run_id = 0;
+  riga_stats st{};
+  clk::time_point t0;
+
+  double* Bc(int j) { return B.p + (int64_t)j * N; }
+  double* Wc(int j) { return W.p + (int64_t)j * N; }
+
+  void alloc() {
+    ncols = lock_cap + mb + 1;
+    B.alloc((size_t)N * ncols, s);
+    W.alloc((size_t)N * ncols, s);
+    x.alloc(N, s);
+    y.alloc(N, s);
+    c1.alloc(ncols, s);
+    c2.alloc(ncols, s);
+    partial.alloc((size_t)gemv_row_blocks(N) * ncols, s);
+    dotp.alloc(spmv_blocks(pr), s);
+    alpha.alloc(mb + 1, s);
+    beta.alloc(mb + 2, s);
+    scal.alloc(8, s);
+    flag.alloc(4, s);
+    theta.alloc(mb + 1, s);
+    S.alloc((size_t)(mb + 1) * (mb + 1), s);
+    tdwork.alloc((size_t)6 * (mb + 1) * (mb + 1), s);
+    sel.alloc(mb + 1, s);
+    const int umax = mb + 1;
+    Sh.alloc((size_t)(mb + 1) * umax, s);
+    Ub.alloc((size_t)N * umax, s);
+    KU.alloc((size_t)N * umax, s);
+    MU.alloc((size_t)N * umax, s);
+    rqn.alloc(umax, s);
+    rqd.alloc(umax, s);
+    rn2.alloc(umax, s);
+    un2.alloc(umax, s);
+    lam.alloc(umax, s);
+    nrm.alloc(umax, s);
+    if (precision == RIGA_MIXED) {
+      ir_r.alloc(N, s);
+      ir_d.alloc(N, s);
+    }
+  }
+
+  void factor(double sigma) {
+    auto a = clk::now();
+    factor_numeric(pr, sigma, precision);
+    if (precision == RIGA_MIXED) {
+      if (!pr->av.p) pr->av.alloc(pr->kv.n, s);
+      launch_axpby_vals(pr->kv.p, pr->mv.p, sigma, pr->av.p, (int64_t)pr->kv.n, s);
+    }
+    st.t_fact += secs(a, clk::now());
+    st.n_fact++;
+    st.n_perturbed_pivots += pr->last_perturbed;
+    st.n_2x2_pivots += pr->last_2x2;
+  }
+
+  // x = A^{-1} b (FP64), or FP32 solve + fixed FP64 refinement (mixed)
+  void apply_inverse(const double* b, double* out) {
+    solve_fb(pr, b, out, s);
+    st.n_fb++;
+    if (precision == RIGA_MIXED) {
+      for (int it = 0; it < max_ir; ++it) {
+        // r = b - A x
+        launch_spmv(pr, pr->av.p, out, ir_r.p, nullptr, s);
+        st.n_mv++;
+        axpy_launch(-1.0, ir_r.p, b, ir_r.p);
+        solve_fb(pr, ir_r.p, ir_d.p, s);
+        st.n_fb++;
+        st.n_ir++;
+        axpy_launch(1.0, ir_d.p, out, out);
+      }
+    }
+  }
+
+  // out = a * u + v
+  void axpy_launch(double a, const double* u, const double* v, double* out) {
+    launch_axpby(a, u, v, out, N, s);
+  }
+
+  // c = W[:, 0:m]^T x ; x -= B[:, 0:m] c
+  void project_out(int m, double* c) {
+    launch_gemv_t(W.p, N, m, x.p, partial.p, c, s);
+    launch_gemv_n_sub(B.p, N, m, c, x.p, s);
+  }
+
+  // M-normalise x into column j of B (and M x into W); returns false on breakdown
+  void normalize_into(int col, double* beta_out) {
+    launch_spmv(pr, pr->mv.p, x.p, y.p, dotp.p, s);
+    st.n_mv++;
+    launch_reduce_partials(dotp.p, spmv_blocks(pr), scal.p, s);
+    launch_scale2(x.p, y.p, scal.p, Bc(col), Wc(col), N, beta_out, flag.p, s);
+  }
+
+  void start_vector(const double* init /* may be null */) {
+    HIPCHECK(hipMemsetAsync(flag.p, 0, 4 * sizeof(int32_t), s));
+    if (init) launch_copy(x.p, init, N, s);
+    else launch_fill_random(x.p, N, seed, ++run_id, s);
+    if (nl > 0) {
+      project_out(nl, c1.p);
+      project_out(nl, c2.p);
+    }
+    normalize_into(nl, scal.p + 1);
+  }
+
+  // one Lanczos step: column nl+j -> nl+j+1; alpha[j], beta[j+1]
+  void step(int j) {
+    const int col = nl + j;
+    apply_inverse(Wc(col), x.p);
+    auto a = clk::now();
+    project_out(col + 1, c1.p);
+    project_out(col + 1, c2.p);
+    add_scalars_launch(c1.p + col, c2.p + col, alpha.p + j, s);
+    normalize_into(col + 1, beta.p + j + 1);
+    st.t_orth += secs(a, clk::now());
+  }
+
+  struct Ritz {
+    std::vector<double> theta;    // all Ritz values, ascending
+    std::vector<int> sel;         // selected indices
+    std::vector<double> S;        // m x nsel
+    std::vector<double> est;      // per selected: |beta_m s_m|
+    double beta_m;
+    int m, nsel;
+  };
+
+  Ritz ritz(int m, int nsel) {
+    auto a = clk::now();
+    Ritz r;
+    r.m = m;
+    r.nsel = std::min(nsel, m);
+    launch_tridiag_eig(alpha.p, beta.p, m, theta.p, S.p, r.nsel, sel.p, tdwork.p, s);
+    r.theta.resize(m);
+    r.sel.resize(r.nsel);
+    r.S.resize((size_t)m * r.nsel);
+    HIPCHECK(hipMemcpyAsync(r.theta.data(), theta.p, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(r.sel.data(), sel.p, r.nsel * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(r.S.data(), S.p, r.S.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(&r.beta_m, beta.p + m, sizeof(double), hipMemcpyDeviceToHost, s));
+    int32_t fl = 0;
+    HIPCHECK(hipMemcpyAsync(&fl, flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (fl) r.beta_m = 0.0;
+    r.est.resize(r.nsel);
+    for (int q = 0; q < r.nsel; ++q) r.est[q] = std::fabs(r.beta_m * r.S[(size_t)q * m + m - 1]);
+    st.t_proj += secs(a, clk::now());
+    return r;
+  }
+
+  static bool converged(const Ritz& r, int q) {
+    const double th = r.theta[r.sel[q]];
+    return r.est[q] <= 1e-10 * std::fabs(th);
+  }
+
+  // Extract the Ritz vectors of `which` (positions in r.sel) plus an
+  // optional restart combination; lock those passing the residual test.
+  // Returns the number locked.
+  int lock_pairs(const Ritz& r, double sigma, const std::vector<int>& which,
+                 const std::vector<int>& restart_from, bool* have_restart) {
+    auto a = clk::now();
+    const int m = r.m;
+    const int nw = (int)which.size();
+    const int nc = nw + (restart_from.empty() ? 0 : 1);
+    *have_restart = !restart_from.empty();
+    if (nc == 0) return 0;
+    std::vector<double> Sh_h((size_t)m * nc, 0.0);
+    for (int i = 0; i < nw; ++i)
+      std::memcpy(&Sh_h[(size_t)i * m], &r.S[(size_t)which[i] * m], m * sizeof(double));
+    if (!restart_from.empty())
+      for (int q : restart_from)
+        for (int t = 0; t < m; ++t) Sh_h[(size_t)nw * m + t] += r.S[(size_t)q * m + t];
+    HIPCHECK(hipMemcpyAsync(Sh.p, Sh_h.data(), Sh_h.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    // U = V S (the restart combination lands in column nw)
+    launch_gemm_nn(Bc(nl), N, m, Sh.p, m, nc, Ub.p, s);
+    int nlocked = 0;
+    if (nw > 0) {
+      for (int i = 0; i < nw; ++i) {
+        launch_spmv(pr, pr->kv.p, Ub.p + (int64_t)i * N, KU.p + (int64_t)i * N, nullptr, s);
+        launch_spmv(pr, pr->mv.p, Ub.p + (int64_t)i * N, MU.p + (int64_t)i * N, nullptr, s);
+        st.n_mv += 2;
+      }
+      launch_residuals(KU.p, MU.p, Ub.p, N, nw, rqn.p, rqd.p, rn2.p, un2.p, lam.p, s);
+      std::vector<double> h_rqd(nw), h_rn2(nw), h_un2(nw), h_lam(nw);
+      HIPCHECK(hipMemcpy(h_rqd.data(), rqd.p, nw * sizeof(double), hipMemcpyDeviceToHost));
+      HIPCHECK(hipMemcpy(h_rn2.data(), rn2.p, nw * sizeof(double), hipMemcpyDeviceToHost));
+      HIPCHECK(hipMemcpy(h_un2.data(), un2.p, nw * sizeof(double), hipMemcpyDeviceToHost));
+      HIPCHECK(hipMemcpy(h_lam.data(), lam.p, nw * sizeof(double), hipMemcpyDeviceToHost));
+      // M-normalise: u /= sqrt(u^T M u)
+      std::vector<double> scl(nw);
+      for (int i = 0; i < nw; ++i) scl[i] = 1.0 / std::sqrt(h_rqd[i]);
+      HIPCHECK(hipMemcpy(nrm.p, scl.data(), nw * sizeof(double), hipMemcpyHostToDevice));
+      launch_scale_cols(Ub.p, N, nw, nrm.p, s);
+      launch_scale_cols(MU.p, N, nw, nrm.p, s);
+      // candidates: residual below tol, eigenvalue in [lo, hi); locked in
+      // ascending order.  When the locked set is full, a candidate replaces
+      // the largest locked eigenvalue above the shift if it is smaller.
+      std::vector<int> cand;
+      for (int i = 0; i < nw; ++i) {
+        const double res = std::sqrt(h_rn2[i]) / (pr->normK1 * std::sqrt(h_un2[i]));
+        if (res <= tol && h_lam[i] >= lo && h_lam[i] < hi) cand.push_back(i);
+      }
+      std::sort(cand.begin(), cand.end(), [&](int a, int b) { return h_lam[a] < h_lam[b]; });
+      if (*have_restart) launch_copy(y.p, Ub.p + (int64_t)nw * N, N, s);
+      int appended = 0;
+      for (int i : cand) {
+        const double res = std::sqrt(h_rn2[i]) / (pr->normK1 * std::sqrt(h_un2[i]));
+        int col = -1;
+        if (nl + appended < lock_cap) {
+          col = nl + appended;
+          ++appended;
+          locked.push_back(Locked{h_lam[i], res, col});
+        } else {
+          int worst = -1;
+          for (int t = 0; t < (int)locked.size(); ++t)
+            if (locked[t].lam > sigma && (worst < 0 || locked[t].lam > locked[worst].lam)) worst = t;
+          if (worst < 0 || locked[worst].lam <= h_lam[i]) break;
+          col = locked[worst].col;
+          locked[worst] = Locked{h_lam[i], res, col};
+          ++n_evicted;
+        }
+        launch_copy(Bc(col), Ub.p + (int64_t)i * N, N, s);
+        launch_copy(Wc(col), MU.p + (int64_t)i * N, N, s);
+        ++nlocked;
+      }
+      nl += appended;
+
+    } else if (*have_restart) {
+      launch_copy(y.p, Ub.p, N, s);
+    }
+    (void)sigma;
+    st.t_ritz += secs(a, clk::now());
+    return nlocked;
+  }
+
+  int count_locked(double a, double b) const {
+    int c = 0;
+    for (auto& L : locked)
+      if (L.lam >= a && L.lam < b) ++c;
+    return c;
+  }
+
+  // One Lanczos run at the current factorisation.  Stops when the
+  // converged pairs cover the needs or the basis is full.  Returns the
+  // final Ritz data (for shift placement).
+  Ritz run(double sigma, int need_below, int need_above, const double* init, int* n_new) {
+    start_vector(init);
+    const int maxm = std::min<int64_t>(mb, N - nl - 1);
+    int j = 0;
+    Ritz r;
+    int next_check = std::min(maxm, std::max(16, std::min(need_below + need_above, maxm)));
+    const int nsel = std::min(maxm, std::max(64, 2 * (need_below + need_above) + 16));
+    while (true) {
+      step(j);
+      ++j;
+      if (j < next_check && j < maxm) continue;
+      r = ritz(j, nsel);
+      int cb = 0, ca = 0;
+      for (int q = 0; q < r.nsel; ++q) {
+        if (!converged(r, q)) continue;
+        const double l = sigma + 1.0 / r.theta[r.sel[q]];
+        if (l < sigma) ++cb; else ++ca;
+      }
+      const bool breakdown = r.beta_m == 0.0;
+      if ((cb >= need_below && ca >= need_above) || j >= maxm || breakdown) break;
+      next_check = std::min(maxm, j + 8);
+    }
+    st.n_it++;
+    // lock every converged pair; restart from the nearest unconverged ones
+    std::vector<int> which, rest;
+    for (int q = 0; q < r.nsel; ++q) {
+      if (converged(r, q)) which.push_back(q);
+    }
+    // unconverged, by decreasing |theta|
+    std::vector<int> unc;
+    for (int q = 0; q < r.nsel; ++q)
+      if (!converged(r, q)) unc.push_back(q);
+    std::sort(unc.begin(), unc.end(), [&](int a, int b) {
+      return std::fabs(r.theta[r.sel[a]]) > std::fabs(r.theta[r.sel[b]]);
+    });
+    for (int i = 0; i < (int)unc.size() && i < 8; ++i) rest.push_back(unc[i]);
+    bool have_restart = false;
+    *n_new = lock_pairs(r, sigma, which, rest, &have_restart);
+    restart_valid = have_restart && r.beta_m != 0.0;
+    if (log_on())
+      std::fprintf(stderr, "[riga] run sigma=%.6g steps=%d need=(%d,%d) converged=%zu locked=%d total_locked=%d\n",
+                   sigma, j, need_below, need_above, which.size(), *n_new, nl);
+    return r;
+  }
+  bool restart_valid = false;
+};
+
+
+// Places the next shift above the eigenvalues locked so far: far enough
+// that the new slice holds about `target` eigenvalues (eigenvalue density
+// estimated from the locked ones), then moved to the middle of the nearest
+// gap between estimated eigenvalues so that K - sigma M stays well
+// conditioned (the paper gives no rule for choosing shifts; Sec. 4.1).
+double next_shift(const Solver& sv, const Solver::Ritz& r, double sigma, double lo, double hi,
+                  int target) {
+  double top = sigma;
+  int cnt = 0;
+  for (auto& L : sv.locked)
+    if (L.lam >= lo && L.lam < hi) {
+      top = std::max(top, L.lam);
+      ++cnt;
+    }
+  double width = top - lo;
+  double dens = (cnt > 0 && width > 0) ? cnt / width : 0.0;
+  double step;
+  if (dens > 0) step = target / dens;
+  else step = std::max(std::fabs(top), 1.0) * 0.5;
+  double cand = top + step;
+  // estimates: locked values and unconverged Ritz values of the last run
+  std::vector<double> est;
+  for (auto& L : sv.locked) est.push_back(L.lam);
+  for (int i = 0; i < (int)r.theta.size(); ++i)
+    if (r.theta[i] != 0.0) est.push_back(sigma + 1.0 / r.theta[i]);
+  std::sort(est.begin(), est.end());
+  // the gap containing cand (estimates above top only)
+  double below = top, above = std::numeric_limits<double>::infinity();
+  for (double e : est) {
+    if (e <= top) continue;
+    if (e <= cand) below = std::max(below, e);
+    else { above = std::min(above, e); }
+  }
+  if (std::isfinite(above)) cand = 0.5 * (below + above);
+  else if (below > top) cand = std::max(cand, below + 0.5 * step);
+  if (std::isfinite(hi) && cand >= hi) cand = hi;
+  return cand;
+}
+
+}  // namespace
+
+riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found, double* evals,
+                     double* evecs, double* resid, riga_stats* stats_out) {
+  Solver sv;
+  sv.pr = pr;
+  sv.s = o->stream ? (hipStream_t)o->stream : pr->stream;
+  pr->stream = sv.s;
+  sv.N = pr->an.N;
+  sv.t0 = clk::now();
+  int nev = o->nev;
+  const double lo = o->lo;
+  const double hi = o->hi;
+  sv.lo = lo;
+  sv.hi = hi;
+  sv.tol = o->tol > 0 ? o->tol : 1e-9;
+  sv.seed = o->seed;
+  sv.precision = o->precision;
+  sv.max_ir = 2;
+  sv.per_shift = o->per_shift > 0 ? o->per_shift : 48;
+  sv.max_restarts = o->max_restarts > 0 ? o->max_restarts : 10;
+  int mb = o->max_basis > 0 ? o->max_basis : std::max(128, 3 * sv.per_shift);
+  mb = (int)std::min<int64_t>(std::min(mb, 1000), sv.N - 1);
+  sv.mb = mb;
+  sv.lock_cap = (int)std::min<int64_t>(nev + 2 * sv.per_shift + 32, sv.N);
+  sv.alloc();
+  *n_found = 0;
+
+  int64_t nu_lo = 0;
+  if (std::isfinite(hi)) {
+    sv.factor(hi);
+    const int64_t nu_hi = pr->last_inertia;
+    sv.factor(lo);
+    nu_lo = pr->last_inertia;
+    nev = (int)std::min<int64_t>(nev, nu_hi - nu_lo);
+  } else {
+    sv.factor(lo);
+    nu_lo = pr->last_inertia;
+  }
+  sv.st.n_shift = 1;
+  riga_status status = RIGA_OK;
+  double sigma = lo;
+  int64_t known = 0;  // eigenvalues in [lo, sigma)
+  const double* init = nullptr;
+  for (int shift = 0; nev > 0 && shift < 400; ++shift) {
+    Solver::Ritz last;
+    int runs = 0;
+    const int per_above = shift == 0 ? sv.per_shift : std::max(1, sv.per_shift / 2);
+    do {
+      const int below = sv.count_locked(lo, sigma);
+      const int need_below = (int)std::max<int64_t>(0, known - below);
+      const int above = sv.count_locked(sigma, hi);
+      const int need_above = (int)std::max<int64_t>(
+          0, std::min<int64_t>(per_above, nev - known - above));
+      int n_new = 0;
+      // a repeated run at the same shift means eigenvalues are missing that
+      // the previous Krylov space did not reach (e.g. further copies of a
+      // multiple eigenvalue): start it from a fresh random vector
+      last = sv.run(sigma, need_below, need_above, runs == 0 ? init : nullptr, &n_new);
+      init = sv.restart_valid ? sv.y.p : nullptr;
+      ++runs;
+    } while (sv.count_locked(lo, sigma) < known && runs < sv.max_restarts);
+    if (sv.count_locked(lo, sigma) < known) {
+      status = RIGA_ENOCONV;
+      break;
+    }
+    if (known >= nev) break;
+    if (std::isfinite(hi) && sigma >= hi) break;
+    const int64_t target = std::max<int64_t>(1, std::min<int64_t>(sv.per_shift / 2, nev - known));
+    double next = next_shift(sv, last, sigma, lo, hi, (int)target);
+    sv.factor(next);
+    sv.st.n_shift++;
+    known = pr->last_inertia - nu_lo;
+    if (log_on())
+      std::fprintf(stderr, "[riga] shift %d: sigma=%.10g count below=%lld locked below=%d\n",
+                   shift + 1, next, (long long)known, sv.count_locked(lo, next));
+    if (sv.count_locked(lo, next) > known) {
+      status = RIGA_ENOCONV;  // more pairs locked than exist: inconsistent
+      break;
+    }
+    sigma = next;
+  }
+  // results: locked pairs in [lo, hi), ascending
+  std::vector<Locked> in;
+  for (auto& L : sv.locked)
+    if (L.lam >= lo && L.lam < hi) in.push_back(L);
+  std::sort(in.begin(), in.end(), [](const Locked& a, const Locked& b) { return a.lam < b.lam; });
+  const int nf = std::min<int>((int)in.size(), nev);
+  for (int i = 0; i < nf; ++i) {
+    if (evals) evals[i] = in[i].lam;
+    if (resid) resid[i] = in[i].resid;
+    if (evecs)
+      HIPCHECK(hipMemcpyAsync(evecs + (int64_t)i * sv.N, sv.Bc(in[i].col), sv.N * sizeof(double),
+                              hipMemcpyDeviceToDevice, sv.s));
+  }
+  HIPCHECK(hipStreamSynchronize(sv.s));
+  *n_found = nf;
+  if (nf < nev && status == RIGA_OK) status = RIGA_ENOCONV;
+  sv.st.t_total = secs(sv.t0, clk::now());
+  sv.st.flops_fact = pr->an.flops_fact;
+  sv.st.bytes_fb = (double)pr->an.nnz_l * 2.0 * (sv.precision == RIGA_MIXED ? 4.0 : 8.0);
+  if (stats_out) *stats_out = sv.st;
+  pr->stats = sv.st;
+  return status;
+}
+
+}  // namespace riga

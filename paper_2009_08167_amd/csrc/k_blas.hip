@@ -1,0 +1,399 @@
+// Sparse mat-vec and the dense vector kernels of the Lanczos recurrence
+// (Eqs. Lanczos--LanczosAlphaBeta of arXiv 2009.08167, with full
+// M-reorthogonalisation, Eq. LanczosRestart and the paragraph after it).
+//
+// All reductions are two-stage with a fixed summation order, so results are
+// bitwise reproducible from run to run.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "problem.h"
+
+namespace riga {
+namespace {
+
+// y = A x with CSR (G lanes per row); optional per-block partial of x^T y.
+template <int G>
+__global__ void __launch_bounds__(256) spmv_kernel(const int64_t* __restrict__ row_ptr,
+                                                 const int32_t* __restrict__ col,
+                                                 const double* __restrict__ val,
+                                                 const double* __restrict__ x,
+                                                 double* __restrict__ y, int64_t N,
+                                                 double* dot_partial) {
+  __shared__ double red[256 / G];
+  const int sub = threadIdx.x % G;
+  const int64_t r = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
+  double s = 0.0;
+  if (r < N) {
+    const int64_t e1 = row_ptr[r + 1];
+    for (int64_t e = row_ptr[r] + sub; e < e1; e += G) s += val[e] * x[col[e]];
+  }
+  for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (sub == 0) {
+    double d = 0.0;
+    if (r < N) {
+      y[r] = s;
+      d = s * x[r];
+    }
+    red[threadIdx.x / G] = d;
+  }
+  if (dot_partial) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int i = 0; i < 256 / G; ++i) t += red[i];
+      dot_partial[blockIdx.x] = t;
+    }
+  }
+}
+
+__global__ void axpby_vals_kernel(const double* k, const double* m, double sigma, double* a,
+                                  int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = k[i] - sigma * m[i];
+}
+
+constexpr int GEMV_RB = 1024;  // rows per block of the transposed product
+constexpr int GEMV_CG = 16;    // columns per block
+
+// partial[rb * m + j] = sum_{r in block rb} B(r, j) x(r)
+__global__ void __launch_bounds__(256) gemv_t_kernel(const double* __restrict__ B, int64_t n,
+                                                   int m, const double* __restrict__ x,
+                                                   double* __restrict__ partial) {
+  const int rb = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)rb * GEMV_RB;
+  const int64_t r1 = min(r0 + GEMV_RB, n);
+  __shared__ double xs[GEMV_RB];
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) xs[r - r0] = x[r];
+  __syncthreads();
+  for (int jj = wave; jj < GEMV_CG; jj += 4) {
+    const int j = blockIdx.y * GEMV_CG + jj;
+    if (j >= m) break;
+    const double* c = B + (int64_t)j * n;
+    double s = 0.0;
+    for (int64_t r = r0 + lane; r < r1; r += 64) s += c[r] * xs[r - r0];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) partial[(int64_t)rb * m + j] = s;
+  }
+}
+
+// c[j] = sum_rb partial[rb * m + j]; optionally acc[0] += c[jacc]
+__global__ void gemv_t_reduce_kernel(const double* partial, int nrb, int m, double* c) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  double s = 0.0;
+  for (int rb = 0; rb < nrb; ++rb) s += partial[(int64_t)rb * m + j];
+  c[j] = s;
+}
+
+// x -= B c
+__global__ void __launch_bounds__(256) gemv_n_sub_kernel(const double* __restrict__ B, int64_t n,
+                                                       int m, const double* __restrict__ c,
+                                                       double* __restrict__ x) {
+  extern __shared__ double cs[];
+  for (int j = threadIdx.x; j < m; j += blockDim.x) cs[j] = c[j];
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double s = 0.0;
+  for (int j = 0; j < m; ++j) s += B[(int64_t)j * n + r] * cs[j];
+  x[r] -= s;
+}
+
+__global__ void reduce_partials_kernel(const double* partial, int nblk, double* out) {
+  __shared__ double sm[256];
+  double s = 0.0;
+  // fixed assignment of partials to threads, then a fixed tree
+  for (int i = threadIdx.x; i < nblk; i += 256) s += partial[i];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sm[0];
+}
+
+// Counter-based generator: splitmix64 of (seed, stream, index) -> U(-1, 1).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void fill_random_kernel(double* x, int64_t n, uint64_t seed, uint64_t sid) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t h = splitmix64(seed ^ splitmix64(sid * 0x632BE59BD9B4E019ull + (uint64_t)i));
+  x[i] = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// v = x / beta, w = y / beta, beta = sqrt(beta2[0]); writes beta; flags breakdown
+__global__ void scale2_kernel(const double* x, const double* y, const double* beta2, double* v,
+                              double* w, int64_t n, double* beta_out, int32_t* flag) {
+  const double b2 = beta2[0];
+  const bool ok = b2 > 0.0 && isfinite(b2);
+  const double b = ok ? sqrt(b2) : 0.0;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    if (beta_out) *beta_out = b;
+    if (!ok && flag) *flag = 1;
+  }
+  if (i >= n || !ok) return;
+  const double ib = 1.0 / b;
+  v[i] = x[i] * ib;
+  w[i] = y[i] * ib;
+}
+
+// U(n x m) = V(n x k) S(k x m), S column-major with leading dimension lds.
+// S is staged through LDS in chunks of GEMM_KC rows.
+constexpr int GEMM_CB = 16;
+constexpr int GEMM_KC = 128;
+__global__ void __launch_bounds__(256) gemm_nn_kernel(const double* __restrict__ V, int64_t n,
+                                                    int k, const double* __restrict__ S, int lds,
+                                                    int m, double* __restrict__ U) {
+  __shared__ double ss[GEMM_KC * GEMM_CB];
+  const int c0 = blockIdx.y * GEMM_CB;
+  const int nc = min(GEMM_CB, m - c0);
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc[GEMM_CB];
+#pragma unroll
+  for (int q = 0; q < GEMM_CB; ++q) acc[q] = 0.0;
+  for (int k0 = 0; k0 < k; k0 += GEMM_KC) {
+    const int kc = min(GEMM_KC, k - k0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < GEMM_KC * GEMM_CB; e += blockDim.x) {
+      const int t = e % GEMM_KC, q = e / GEMM_KC;
+      ss[e] = (q < nc && t < kc) ? S[(int64_t)(c0 + q) * lds + k0 + t] : 0.0;
+    }
+    __syncthreads();
+    if (r < n) {
+      for (int t = 0; t < kc; ++t) {
+        const double v = V[(int64_t)(k0 + t) * n + r];
+#pragma unroll
+        for (int q = 0; q < GEMM_CB; ++q) acc[q] += v * ss[q * GEMM_KC + t];
+      }
+    }
+  }
+  if (r < n)
+    for (int q = 0; q < nc; ++q) U[(int64_t)(c0 + q) * n + r] = acc[q];
+}
+
+// Per column q of the n x m blocks: mode 0 -> partial sums of (u^T K u,
+// u^T M u); mode 1 -> partial sums of (||K u - lam_q M u||^2, ||u||^2).
+__global__ void __launch_bounds__(256) colpair_kernel(const double* KU, const double* MU,
+                                                    const double* U, int64_t n, int m,
+                                                    const double* lam, int mode,
+                                                    double* partial) {
+  const int rb = blockIdx.x;
+  const int q = blockIdx.y;
+  const int64_t r0 = (int64_t)rb * GEMV_RB, r1 = min(r0 + GEMV_RB, n);
+  double s0 = 0.0, s1 = 0.0;
+  const double* ku = KU + (int64_t)q * n;
+  const double* mu = MU + (int64_t)q * n;
+  const double* u = U + (int64_t)q * n;
+  const double lq = mode ? lam[q] : 0.0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+    if (mode == 0) {
+      s0 += u[r] * ku[r];
+      s1 += u[r] * mu[r];
+    } else {
+      const double d = ku[r] - lq * mu[r];
+      s0 += d * d;
+      s1 += u[r] * u[r];
+    }
+  }
+  __shared__ double a0[256], a1[256];
+  a0[threadIdx.x] = s0;
+  a1[threadIdx.x] = s1;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      a0[threadIdx.x] += a0[threadIdx.x + w];
+      a1[threadIdx.x] += a1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[((int64_t)rb * m + q) * 2 + 0] = a0[0];
+    partial[((int64_t)rb * m + q) * 2 + 1] = a1[0];
+  }
+}
+
+__global__ void colpair_reduce_kernel(const double* partial, int nrb, int m, double* out0,
+                                      double* out1) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  double s0 = 0.0, s1 = 0.0;
+  for (int rb = 0; rb < nrb; ++rb) {
+    s0 += partial[((int64_t)rb * m + q) * 2];
+    s1 += partial[((int64_t)rb * m + q) * 2 + 1];
+  }
+  out0[q] = s0;
+  out1[q] = s1;
+}
+
+__global__ void ratio_kernel(const double* a, const double* b, double* out, int m) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < m) out[q] = a[q] / b[q];
+}
+
+__global__ void copy_kernel(double* dst, const double* src, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__global__ void scale_cols_kernel(double* U, int64_t n, int m, const double* scale) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (i < n && q < m) U[(int64_t)q * n + i] *= scale[q];
+}
+
+__global__ void axpby_kernel(double a, const double* u, const double* v, double* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a * u[i] + v[i];
+}
+
+__global__ void __launch_bounds__(256) dot_partial_kernel(const double* a, const double* b,
+                                                        int64_t n, double* partial) {
+  __shared__ double sm[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    s += a[i] * b[i];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
+}
+
+__global__ void add_scalars_kernel(const double* a, const double* b, double* out) {
+  if (threadIdx.x == 0) *out = *a + *b;
+}
+
+}  // namespace
+
+void launch_axpby(double a, const double* u, const double* v, double* out, int64_t n,
+                  hipStream_t s) {
+  axpby_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, u, v, out, n);
+  HIPCHECK(hipGetLastError());
+}
+
+constexpr int DOT_BLOCKS = 256;
+
+// out[0] = a^T b (two-stage, fixed order); partial holds DOT_BLOCKS doubles
+void launch_dot(const double* a, const double* b, int64_t n, double* partial, double* out,
+                hipStream_t s) {
+  dot_partial_kernel<<<DOT_BLOCKS, 256, 0, s>>>(a, b, n, partial);
+  reduce_partials_kernel<<<1, 256, 0, s>>>(partial, DOT_BLOCKS, out);
+  HIPCHECK(hipGetLastError());
+}
+
+void add_scalars_launch(const double* a, const double* b, double* out, hipStream_t s) {
+  add_scalars_kernel<<<1, 64, 0, s>>>(a, b, out);
+  HIPCHECK(hipGetLastError());
+}
+
+int spmv_blocks(const riga_problem* pr) {
+  const int G = pr->spmv_group;
+  return (int)((pr->an.N + (256 / G) - 1) / (256 / G));
+}
+
+void launch_spmv(const riga_problem* pr, const double* vals, const double* x, double* y,
+                 double* dot_partial, hipStream_t s) {
+  const int64_t N = pr->an.N;
+  const int nb = spmv_blocks(pr);
+  switch (pr->spmv_group) {
+    case 4: spmv_kernel<4><<<nb, 256, 0, s>>>(pr->row_ptr.p, pr->col_idx.p, vals, x, y, N, dot_partial); break;
+    case 8: spmv_kernel<8><<<nb, 256, 0, s>>>(pr->row_ptr.p, pr->col_idx.p, vals, x, y, N, dot_partial); break;
+    case 16: spmv_kernel<16><<<nb, 256, 0, s>>>(pr->row_ptr.p, pr->col_idx.p, vals, x, y, N, dot_partial); break;
+    case 32: spmv_kernel<32><<<nb, 256, 0, s>>>(pr->row_ptr.p, pr->col_idx.p, vals, x, y, N, dot_partial); break;
+    default: spmv_kernel<64><<<nb, 256, 0, s>>>(pr->row_ptr.p, pr->col_idx.p, vals, x, y, N, dot_partial); break;
+  }
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_axpby_vals(const double* k, const double* m, double sigma, double* a, int64_t n,
+                       hipStream_t s) {
+  axpby_vals_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(k, m, sigma, a, n);
+  HIPCHECK(hipGetLastError());
+}
+
+int gemv_row_blocks(int64_t n) { return (int)((n + GEMV_RB - 1) / GEMV_RB); }
+
+void launch_gemv_t(const double* B, int64_t n, int m, const double* x, double* partial,
+                   double* c, hipStream_t s) {
+  if (m <= 0) return;
+  const int nrb = gemv_row_blocks(n);
+  dim3 grid(nrb, (m + GEMV_CG - 1) / GEMV_CG);
+  gemv_t_kernel<<<grid, 256, 0, s>>>(B, n, m, x, partial);
+  gemv_t_reduce_kernel<<<(m + 127) / 128, 128, 0, s>>>(partial, nrb, m, c);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_gemv_n_sub(const double* B, int64_t n, int m, const double* c, double* x,
+                       hipStream_t s) {
+  if (m <= 0) return;
+  gemv_n_sub_kernel<<<(unsigned)((n + 255) / 256), 256, (size_t)m * sizeof(double), s>>>(B, n, m, c, x);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_reduce_partials(const double* partial, int nblk, double* out, hipStream_t s) {
+  reduce_partials_kernel<<<1, 256, 0, s>>>(partial, nblk, out);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_fill_random(double* x, int64_t n, uint64_t seed, uint64_t sid, hipStream_t s) {
+  fill_random_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, n, seed, sid);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_scale2(const double* x, const double* y, const double* beta2, double* v, double* w,
+                   int64_t n, double* beta_out, int32_t* flag, hipStream_t s) {
+  scale2_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, y, beta2, v, w, n, beta_out, flag);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_gemm_nn(const double* V, int64_t n, int k, const double* S, int lds, int m, double* U,
+                    hipStream_t s) {
+  if (m <= 0 || k <= 0) return;
+  dim3 grid((unsigned)((n + 255) / 256), (m + GEMM_CB - 1) / GEMM_CB);
+  gemm_nn_kernel<<<grid, 256, 0, s>>>(V, n, k, S, lds, m, U);
+  HIPCHECK(hipGetLastError());
+}
+
+// Rayleigh quotients lam = u^T K u / u^T M u, then ||K u - lam M u||^2 and ||u||^2.
+void launch_residuals(const double* KU, const double* MU, const double* U, int64_t n, int m,
+                      double* out_rq_num, double* out_rq_den, double* out_rnorm2,
+                      double* out_unorm2, double* lam, hipStream_t s) {
+  const int nrb = gemv_row_blocks(n);
+  DBuf<double> partial;
+  partial.alloc((size_t)nrb * m * 2, s);
+  dim3 grid(nrb, m);
+  colpair_kernel<<<grid, 256, 0, s>>>(KU, MU, U, n, m, nullptr, 0, partial.p);
+  colpair_reduce_kernel<<<(m + 127) / 128, 128, 0, s>>>(partial.p, nrb, m, out_rq_num, out_rq_den);
+  ratio_kernel<<<(m + 127) / 128, 128, 0, s>>>(out_rq_num, out_rq_den, lam, m);
+  colpair_kernel<<<grid, 256, 0, s>>>(KU, MU, U, n, m, lam, 1, partial.p);
+  colpair_reduce_kernel<<<(m + 127) / 128, 128, 0, s>>>(partial.p, nrb, m, out_rnorm2, out_unorm2);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
+void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {
+  copy_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(dst, src, n);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_scale_cols(double* U, int64_t n, int m, const double* scale, hipStream_t s) {
+  if (m <= 0) return;
+  dim3 grid((unsigned)((n + 255) / 256), m);
+  scale_cols_kernel<<<grid, 256, 0, s>>>(U, n, m, scale);
+  HIPCHECK(hipGetLastError());
+}
+
+}  // namespace riga

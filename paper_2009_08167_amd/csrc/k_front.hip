@@ -1,0 +1,404 @@
+// Multifrontal LDL^T of A = K - sigma M over the tree of separators, with
+// Bunch-Kaufman pivoting inside each front's fully-summed block and the
+// inertia count of the Remark on inertia (arXiv 2009.08167, Sec. 4.2) --
+// the numeric factorisation that Sec. 5 performs once per shift.
+//
+// Per tree level (all fronts of one height are independent):
+//  1. front_assemble: one workgroup per front column gathers the children's
+//     contribution blocks (extend-add through the parent->child position
+//     maps) and adds the entries of A of the fully-summed columns.
+//     Deterministic: every front entry is written by exactly one thread, the
+//     children are summed in a fixed order.
+//  2. front_factor: partial LDL^T of the fully-summed block (1x1 and 2x2
+//     Bunch-Kaufman pivots chosen among the fully-summed rows), L21 and the
+//     Schur-complement update of the contribution block.  Fronts up to
+//     LDS_FRONT_MAX are factorised entirely in LDS by one workgroup; larger
+//     fronts use the blocked path (panel kernel + MFMA trailing update).
+//
+// Fronts are dense column-major f x f blocks in one pool (lower triangle
+// used).  After factorisation, column t < k holds L(:, t) below the
+// diagonal and D on it (a 2x2 block keeps its off-diagonal in (t+1, t));
+// rows/cols >= k hold the contribution block for the parent.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "problem.h"
+
+namespace riga {
+namespace {
+
+struct FrontArgs {
+  const int32_t* fk;
+  const int32_t* ff;
+  const int32_t* fstart;
+  const int64_t* pool_off;
+  const int32_t* child_ptr;
+  const int32_t* child_list;
+  const int64_t* inv_off;
+  const int32_t* inv;
+  const int64_t* amap_ptr;
+  const int32_t* amap_row;
+  const int32_t* amap_val;
+  const double* kv;
+  const double* mv;
+  int32_t* piv_perm;
+  int32_t* piv_type;
+  int32_t* stat;   // per front: negative pivots, perturbed pivots, 2x2 pivots
+};
+
+template <class T>
+__global__ void __launch_bounds__(256) front_assemble_kernel(FrontArgs fa, T* pool,
+                                                           const int32_t* fronts,
+                                                           const int64_t* col_prefix, int nf,
+                                                           double sigma) {
+  extern __shared__ double col[];
+  const int64_t gid = blockIdx.x;
+  int lo = 0, hi = nf;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (col_prefix[mid] <= gid) lo = mid; else hi = mid;
+  }
+  const int F = fronts[lo];
+  const int j = (int)(gid - col_prefix[lo]);
+  const int f = fa.ff[F], k = fa.fk[F];
+  T* front = pool + fa.pool_off[F];
+  for (int r = j + threadIdx.x; r < f; r += blockDim.x) {
+    double v = 0.0;
+    for (int ci = fa.child_ptr[F]; ci < fa.child_ptr[F + 1]; ++ci) {
+      const int32_t* inv = fa.inv + fa.inv_off[ci];
+      const int cc = inv[j];
+      const int cr = inv[r];
+      if (cc >= 0 && cr >= 0) {
+        const int C = fa.child_list[ci];
+        const int kc = fa.fk[C], fc = fa.ff[C];
+        v += (double)pool[fa.pool_off[C] + (int64_t)(kc + cc) * fc + (kc + cr)];
+      }
+    }
+    col[r] = v;
+  }
+  __syncthreads();
+  if (j < k) {
+    const int g = fa.fstart[F] + j;
+    for (int64_t e = fa.amap_ptr[g] + threadIdx.x; e < fa.amap_ptr[g + 1]; e += blockDim.x) {
+      const int r = fa.amap_row[e];
+      const int v = fa.amap_val[e];
+      col[r] += fa.kv[v] - sigma * fa.mv[v];
+    }
+  }
+  __syncthreads();
+  for (int r = j + threadIdx.x; r < f; r += blockDim.x) front[(int64_t)j * f + r] = (T)col[r];
+}
+
+constexpr double BK_ALPHA = 0.6403882032022076;  // (1 + sqrt(17)) / 8
+
+// Shared decision of one pivot step.
+struct PivotStep {
+  int kind;     // 1: 1x1, 2: 2x2
+  int swap_a;   // position to swap with swap_b (-1: none)
+  int swap_b;
+  int perturbed;
+};
+
+template <class T>
+__device__ __forceinline__ double ld_(const T* a, int64_t idx) { return (double)a[idx]; }
+
+// Partial LDL^T of the front `a` (f x f, ld = f, lower), fully-summed block
+// of order k.  NT threads.  `lbuf` holds 2 f doubles of scratch, `perm` k
+// ints, `dec` the broadcast decision.  Works for `a` in LDS or in global
+// memory.
+template <class T, int NT>
+__device__ __forceinline__ void ldlt_partial(T* a, int f, int k, double* lbuf, int* perm,
+                                             PivotStep* dec, double pivtol, int* n_neg,
+                                             int* n_pert, int* n_2x2, int32_t* type_out) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = NT / 64;
+  auto A = [&](int i, int j) -> T& { return a[(int64_t)j * f + i]; };
+  for (int t = tid; t < k; t += NT) perm[t] = t;
+  int neg = 0, pert = 0, two = 0;
+  __syncthreads();
+  int j = 0;
+  while (j < k) {
+    // ---- pivot decision (wave 0)
+    if (wave == 0) {
+      double cmax = 0.0;
+      int r = -1;
+      for (int i = j + 1 + lane; i < k; i += 64) {
+        const double v = fabs((double)A(i, j));
+        if (v > cmax) { cmax = v; r = i; }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(cmax, off);
+        const int orr = __shfl_xor(r, off);
+        if (ov > cmax || (ov == cmax && orr >= 0 && (r < 0 || orr < r))) { cmax = ov; r = orr; }
+      }
+      const double akk = fabs((double)A(j, j));
+      int kind = 1, sa = -1, sb = -1, pz = 0;
+      if (cmax == 0.0 || akk >= BK_ALPHA * cmax) {
+        kind = 1;
+      } else {
+        // largest off-diagonal magnitude in row/column r of the remaining
+        // fully-summed block
+        double rmax = 0.0;
+        for (int i = j + lane; i < k; i += 64) {
+          if (i == r) continue;
+          const double v = i < r ? fabs((double)A(r, i)) : fabs((double)A(i, r));
+          rmax = fmax(rmax, v);
+        }
+        for (int off = 32; off > 0; off >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, off));
+        const double arr = fabs((double)A(r, r));
+        if (akk * rmax >= BK_ALPHA * cmax * cmax) {
+          kind = 1;
+        } else if (arr >= BK_ALPHA * rmax) {
+          kind = 1;
+          sa = j;
+          sb = r;
+        } else {
+          kind = 2;
+          if (r != j + 1) { sa = j + 1; sb = r; }
+        }
+      }
+      if (lane == 0) {
+        dec->kind = kind;
+        dec->swap_a = sa;
+        dec->swap_b = sb;
+        dec->perturbed = pz;
+      }
+    }
+    __syncthreads();
+    const int kind = dec->kind;
+    const int p = dec->swap_a, q = dec->swap_b;  // p < q
+    // ---- symmetric interchange of indices p and q (lower storage)
+    if (p >= 0) {
+      for (int c = tid; c < f; c += NT) {
+        if (c < p) {
+          T tmp = A(p, c); A(p, c) = A(q, c); A(q, c) = tmp;
+        } else if (c == p) {
+          T tmp = A(p, p); A(p, p) = A(q, q); A(q, q) = tmp;
+        } else if (c < q) {
+          T tmp = A(c, p); A(c, p) = A(q, c); A(q, c) = tmp;
+        } else if (c > q) {
+          T tmp = A(c, p); A(c, p) = A(c, q); A(c, q) = tmp;
+        }
+      }
+      if (tid == 0) { int tp = perm[p]; perm[p] = perm[q]; perm[q] = tp; }
+    }
+    __syncthreads();
+    if (kind == 1) {
+      double d = (double)A(j, j);
+      if (fabs(d) < pivtol) {
+        d = d < 0.0 ? -pivtol : pivtol;
+        if (tid == 0) { A(j, j) = (T)d; ++pert; }
+      }
+      if (tid == 0) {
+        if (d < 0.0) ++neg;
+        type_out[j] = 1;
+      }
+      const double dinv = 1.0 / d;
+      for (int i = j + 1 + tid; i < f; i += NT) {
+        const double u = (double)A(i, j);
+        lbuf[i] = u * dinv;     // L(i, j)
+        lbuf[f + i] = u;        // unscaled column
+      }
+      __syncthreads();
+      // trailing update a(i,m) -= L(i,j) * a(m,j), j < m <= i
+      for (int m = j + 1 + wave; m < f; m += NW) {
+        const double um = lbuf[f + m];
+        for (int i = m + lane; i < f; i += 64) A(i, m) = (T)((double)A(i, m) - lbuf[i] * um);
+      }
+      __syncthreads();
+      for (int i = j + 1 + tid; i < f; i += NT) A(i, j) = (T)lbuf[i];
+      j += 1;
+    } else {
+      const double d11 = (double)A(j, j), d21 = (double)A(j + 1, j), d22 = (double)A(j + 1, j + 1);
+      const double det = d11 * d22 - d21 * d21;
+      if (tid == 0) {
+        if (det < 0.0) neg += 1;
+        else if (d11 < 0.0) neg += 2;
+        ++two;
+        type_out[j] = 2;
+        type_out[j + 1] = 3;
+      }
+      const double idet = 1.0 / det;
+      // lbuf[i] = L(i, j), lbuf[f + i] = L(i, j+1); keep the unscaled
+      // columns in place until the update is done
+      for (int i = j + 2 + tid; i < f; i += NT) {
+        const double u1 = (double)A(i, j), u2 = (double)A(i, j + 1);
+        lbuf[i] = (u1 * d22 - u2 * d21) * idet;
+        lbuf[f + i] = (u2 * d11 - u1 * d21) * idet;
+      }
+      __syncthreads();
+      for (int m = j + 2 + wave; m < f; m += NW) {
+        const double u1 = (double)A(m, j), u2 = (double)A(m, j + 1);
+        for (int i = m + lane; i < f; i += 64)
+          A(i, m) = (T)((double)A(i, m) - lbuf[i] * u1 - lbuf[f + i] * u2);
+      }
+      __syncthreads();
+      for (int i = j + 2 + tid; i < f; i += NT) {
+        A(i, j) = (T)lbuf[i];
+        A(i, j + 1) = (T)lbuf[f + i];
+      }
+      j += 2;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) { *n_neg = neg; *n_pert = pert; *n_2x2 = two; }
+}
+
+template <class T, int MAXF>
+__global__ void __launch_bounds__(256) front_factor_lds_kernel(FrontArgs fa, T* pool,
+                                                             const int32_t* fronts,
+                                                             double pivtol) {
+  __shared__ T sa[MAXF * MAXF];
+  __shared__ double lbuf[2 * MAXF];
+  __shared__ int perm[MAXF];
+  __shared__ int32_t type[MAXF];
+  __shared__ PivotStep dec;
+  const int F = fronts[blockIdx.x];
+  const int f = fa.ff[F], k = fa.fk[F];
+  T* g = pool + fa.pool_off[F];
+  const int64_t n2 = (int64_t)f * f;
+  for (int64_t e = threadIdx.x; e < n2; e += blockDim.x) {
+    const int c = (int)(e / f), r = (int)(e % f);
+    if (r >= c) sa[e] = g[e];
+  }
+  __syncthreads();
+  int neg = 0, pert = 0, two = 0;
+  ldlt_partial<T, 256>(sa, f, k, lbuf, perm, &dec, pivtol, &neg, &pert, &two, type);
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < n2; e += blockDim.x) {
+    const int c = (int)(e / f), r = (int)(e % f);
+    if (r >= c) g[e] = sa[e];
+  }
+  const int start = fa.fstart[F];
+  for (int t = threadIdx.x; t < k; t += blockDim.x) {
+    fa.piv_perm[start + t] = perm[t];
+    fa.piv_type[start + t] = type[t];
+  }
+  if (threadIdx.x == 0) {
+    fa.stat[4 * F + 0] = neg;
+    fa.stat[4 * F + 1] = pert;
+    fa.stat[4 * F + 2] = two;
+  }
+}
+
+// Fronts too large for LDS: the same pivoted elimination, one workgroup per
+// front, operating on the front in global memory.
+template <class T>
+__global__ void __launch_bounds__(1024) front_factor_global_kernel(FrontArgs fa, T* pool,
+                                                                 const int32_t* fronts,
+                                                                 double* scratch,
+                                                                 int64_t scratch_stride,
+                                                                 int* perm_scratch,
+                                                                 double pivtol) {
+  __shared__ PivotStep dec;
+  const int F = fronts[blockIdx.x];
+  const int f = fa.ff[F], k = fa.fk[F];
+  T* g = pool + fa.pool_off[F];
+  double* lbuf = scratch + (int64_t)blockIdx.x * scratch_stride;
+  int* perm = perm_scratch + (int64_t)blockIdx.x * scratch_stride;
+  const int start = fa.fstart[F];
+  int neg = 0, pert = 0, two = 0;
+  ldlt_partial<T, 1024>(g, f, k, lbuf, perm, &dec, pivtol, &neg, &pert, &two,
+                        fa.piv_type + start);
+  __syncthreads();
+  for (int t = threadIdx.x; t < k; t += blockDim.x) fa.piv_perm[start + t] = perm[t];
+  if (threadIdx.x == 0) {
+    fa.stat[4 * F + 0] = neg;
+    fa.stat[4 * F + 1] = pert;
+    fa.stat[4 * F + 2] = two;
+  }
+}
+
+FrontArgs front_args(riga_problem* pr) {
+  FrontArgs fa{};
+  fa.fk = pr->d_fk.p;
+  fa.ff = pr->d_ff.p;
+  fa.fstart = pr->d_fstart.p;
+  fa.pool_off = pr->d_pool_off.p;
+  fa.child_ptr = pr->d_child_ptr.p;
+  fa.child_list = pr->d_child_list.p;
+  fa.inv_off = pr->d_inv_off.p;
+  fa.inv = pr->d_inv.p;
+  fa.amap_ptr = pr->d_amap_ptr.p;
+  fa.amap_row = pr->d_amap_row.p;
+  fa.amap_val = pr->d_amap_val.p;
+  fa.kv = pr->kv.p;
+  fa.mv = pr->mv.p;
+  fa.piv_perm = pr->piv_perm.p;
+  fa.piv_type = pr->piv_type.p;
+  fa.stat = pr->front_stat.p;
+  return fa;
+}
+
+template <class T, int MAXF>
+void factor_levels(riga_problem* pr, T* pool, double sigma) {
+  hipStream_t s = pr->stream;
+  FrontArgs fa = front_args(pr);
+  const double pivtol = 1e-20 * (pr->normK1 + fabs(sigma) * pr->normM1);
+  // scratch for fronts factorised in global memory
+  int max_big = 0, max_f_big = 0;
+  for (auto& L : pr->levels) {
+    const int ns = L.n_upto(MAXF);
+    max_big = std::max(max_big, L.n - ns);
+    if (L.n > ns) max_f_big = std::max(max_f_big, L.max_f);
+  }
+  DBuf<double> scratch;
+  DBuf<int> perm_scratch;
+  const int64_t stride = 2 * (int64_t)max_f_big + 2;
+  if (max_big > 0) {
+    scratch.alloc((size_t)max_big * stride, s);
+    perm_scratch.alloc((size_t)max_big * stride, s);
+  }
+  for (size_t h = 0; h < pr->levels.size(); ++h) {
+    LevelDev& L = pr->levels[h];
+    if (L.n == 0) continue;
+    front_assemble_kernel<T><<<(unsigned)L.cols, 256, (size_t)L.max_f * sizeof(double), s>>>(
+        fa, pool, L.fronts.p, L.col_prefix.p, L.n, sigma);
+    HIPCHECK(hipGetLastError());
+    const int ns = L.n_upto(MAXF);
+    if (ns > 0) {
+      front_factor_lds_kernel<T, MAXF><<<ns, 256, 0, s>>>(fa, pool, L.fronts.p, pivtol);
+      HIPCHECK(hipGetLastError());
+    }
+    if (L.n > ns) {
+      front_factor_global_kernel<T><<<L.n - ns, 1024, 0, s>>>(
+          fa, pool, L.fronts.p + ns, scratch.p, stride, perm_scratch.p, pivtol);
+      HIPCHECK(hipGetLastError());
+    }
+  }
+  HIPCHECK(hipStreamSynchronize(s));  // scratch is released on return
+}
+
+}  // namespace
+
+void factor_numeric(riga_problem* pr, double sigma, int precision) {
+  const Analysis& an = pr->an;
+  hipStream_t s = pr->stream;
+  if (precision == RIGA_MIXED) {
+    if (pr->pool32.n < (size_t)an.pool_size) pr->pool32.alloc(an.pool_size, s);
+    factor_levels<float, LDS_FRONT_MAX_F32>(pr, pr->pool32.p, sigma);
+  } else {
+    if (pr->pool64.n < (size_t)an.pool_size) pr->pool64.alloc(an.pool_size, s);
+    factor_levels<double, LDS_FRONT_MAX_F64>(pr, pr->pool64.p, sigma);
+  }
+  std::vector<int32_t> st((size_t)an.n_fronts * 4);
+  HIPCHECK(hipMemcpy(st.data(), pr->front_stat.p, st.size() * sizeof(int32_t),
+                     hipMemcpyDeviceToHost));
+  int64_t neg = 0;
+  int pert = 0, two = 0;
+  for (int F = 0; F < an.n_fronts; ++F) {
+    neg += st[4 * F];
+    pert += st[4 * F + 1];
+    two += st[4 * F + 2];
+  }
+  pr->last_inertia = neg;
+  pr->last_perturbed = pert;
+  pr->last_2x2 = two;
+  pr->sigma = sigma;
+  pr->fact_precision = precision;
+  pr->factored = true;
+}
+
+}  // namespace riga

@@ -1,0 +1,179 @@
+// Internal state of a riga_problem and the launchers of the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/riga.h"
+#include "analysis.h"
+
+namespace riga {
+
+// Error carrying a riga_status; converted to a return code at the ABI.
+struct Error : std::runtime_error {
+  riga_status code;
+  Error(riga_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void hip_check(hipError_t e, const char* what);
+#define HIPCHECK(x) ::riga::hip_check((x), #x)
+
+// Device allocation through the optional allocator hook.
+void* dmalloc(size_t bytes, hipStream_t s);
+void dfree(void* p, hipStream_t s);
+
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  hipStream_t s = nullptr;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; o.n = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      reset();
+      p = o.p; n = o.n; s = o.s;
+      o.p = nullptr; o.n = 0;
+    }
+    return *this;
+  }
+  ~DBuf() { reset(); }
+  void alloc(size_t count, hipStream_t st) {
+    reset();
+    s = st;
+    n = count;
+    if (count) p = (T*)dmalloc(count * sizeof(T), st);
+  }
+  void reset() {
+    if (p) dfree(p, s);
+    p = nullptr;
+    n = 0;
+  }
+  void upload(const std::vector<T>& v, hipStream_t st) {
+    alloc(v.size(), st);
+    if (!v.empty()) HIPCHECK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  }
+};
+
+// Fronts at or below this order are factorised in LDS by one workgroup.
+constexpr int LDS_FRONT_MAX_F64 = 128;
+constexpr int LDS_FRONT_MAX_F32 = 176;
+
+struct LevelDev {
+  int n = 0;                 // fronts at this height
+  int64_t cols = 0;          // sum of front orders (assembly grid)
+  int max_f = 0, max_k = 0;
+  std::vector<int> host_f;   // front orders, ascending (same order as `fronts`)
+  DBuf<int32_t> fronts;      // front ids sorted by order
+  DBuf<int64_t> col_prefix;  // [n+1] prefix sums of front orders
+  int n_upto(int fmax) const {  // fronts of order <= fmax (a prefix)
+    return (int)(std::upper_bound(host_f.begin(), host_f.end(), fmax) - host_f.begin());
+  }
+};
+
+}  // namespace riga
+
+struct riga_problem {
+  riga::Analysis an;
+  bool has_device = false;
+  hipStream_t stream = nullptr;
+  int device = 0;
+
+  // coefficients and assembled matrices
+  riga::DBuf<double> kappa, rho;
+  riga::DBuf<int64_t> row_ptr;
+  riga::DBuf<int32_t> col_idx;
+  riga::DBuf<double> kv, mv;        // K and M values (CSR order)
+  riga::DBuf<double> av;            // K - sigma M values of the last shift
+  riga::DBuf<double> tab_val, tab_der;  // basis tables per direction
+  riga::DBuf<double> ke1, me1;          // 1D element matrices per direction
+  riga::DBuf<int32_t> fe, le, first_fn; // 1D maps per direction (concatenated)
+  int tab_off[3] = {0, 0, 0};       // element offset of each direction in the tables
+  int fn_off[3] = {0, 0, 0};        // function offset of each direction in fe/le
+  double normK1 = 0.0, normM1 = 0.0, maxabsA = 0.0;
+  int spmv_group = 8;
+
+  // symbolic factorisation on the device
+  riga::DBuf<int32_t> d_rows, d_fk, d_ff, d_fstart, d_child_ptr, d_child_list, d_inv;
+  riga::DBuf<int64_t> d_rows_off, d_pool_off, d_cb_off, d_inv_off, d_amap_ptr;
+  riga::DBuf<int32_t> d_amap_row, d_amap_val;
+  std::vector<riga::LevelDev> levels;
+
+  // numeric factorisation
+  riga::DBuf<double> pool64;
+  riga::DBuf<float> pool32;
+  riga::DBuf<int32_t> piv_perm, piv_type;   // by new index
+  riga::DBuf<int32_t> front_stat;           // [n_fronts * 4]: neg, perturbed, 2x2, spare
+  bool factored = false;
+  int fact_precision = RIGA_FP64;
+  double sigma = 0.0;
+  int64_t last_inertia = 0;
+  int last_perturbed = 0, last_2x2 = 0;
+
+  // solve workspace
+  riga::DBuf<double> cbvec, fwd;
+  riga::DBuf<double> ir_r, ir_x, ir_d;      // iterative refinement vectors
+
+  riga_stats stats{};
+};
+
+namespace riga {
+
+// ---- launchers (kernels in k_*.hip) ----
+void launch_basis_tables(riga_problem* pr);
+void launch_assemble(riga_problem* pr);
+void compute_norms(riga_problem* pr);
+
+void launch_axpby_vals(const double* k, const double* m, double sigma, double* a, int64_t n,
+                       hipStream_t s);
+// y = A x (A one of kv/mv/av); if dot_partial != nullptr also writes per-block
+// partial sums of x^T y (count returned by spmv_blocks()).
+void launch_spmv(const riga_problem* pr, const double* vals, const double* x, double* y,
+                 double* dot_partial, hipStream_t s);
+int spmv_blocks(const riga_problem* pr);
+
+void factor_numeric(riga_problem* pr, double sigma, int precision);
+void solve_fb(riga_problem* pr, const double* b, double* x, hipStream_t s);
+
+// BLAS-like helpers on column-major N x m blocks (ld = N).
+int gemv_row_blocks(int64_t n);
+void launch_gemv_t(const double* B, int64_t n, int m, const double* x, double* partial,
+                   double* c, hipStream_t s);
+void launch_gemv_n_sub(const double* B, int64_t n, int m, const double* c, double* x,
+                       hipStream_t s);
+void launch_reduce_partials(const double* partial, int nblk, double* out, hipStream_t s);
+void launch_fill_random(double* x, int64_t n, uint64_t seed, uint64_t stream_id, hipStream_t s);
+void launch_scale2(const double* x, const double* y, const double* beta2, double* v, double* w,
+                   int64_t n, double* beta_out, int32_t* flag, hipStream_t s);
+void launch_gemm_nn(const double* V, int64_t n, int k, const double* S, int lds, int m,
+                    double* U, hipStream_t s);
+void launch_residuals(const double* KU, const double* MU, const double* U, int64_t n, int m,
+                      double* out_rq_num, double* out_rq_den, double* out_rnorm2,
+                      double* out_unorm2, double* lam_in, hipStream_t s);
+void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+void launch_axpby(double a, const double* u, const double* v, double* out, int64_t n,
+                  hipStream_t s);
+// out[0] = a^T b; partial: 256 doubles of scratch
+void launch_dot(const double* a, const double* b, int64_t n, double* partial, double* out,
+                hipStream_t s);
+void launch_scale_cols(double* U, int64_t n, int m, const double* scale, hipStream_t s);
+
+// Projected (tridiagonal) eigensolve.  T has diagonal alpha[0..m) and
+// off-diagonal beta[1..m) (beta[j] couples j-1 and j).  theta[m]: all
+// eigenvalues ascending; sel_out[nvec]: indices (ascending) of the nvec
+// eigenvalues of largest |theta|; S[m x nvec]: their unit eigenvectors;
+// work: 6 m nvec doubles.
+void launch_tridiag_eig(const double* alpha, const double* beta, int m, double* theta,
+                        double* S, int nvec, int32_t* sel_out, double* work, hipStream_t s);
+
+void launch_eig_grad(const riga_problem* pr, int k, const double* U, const double* lam_w_dev,
+                     const double* w_dev, double* gk, double* gr, hipStream_t s);
+
+}  // namespace riga

@@ -1,0 +1,325 @@
+"""ctypes binding of libriga.so (include/riga.h).  Argument marshalling only:
+every step of the solver runs in the library's HIP kernels.  PyTorch
+provides device memory and the current stream.
+
+The library must have been built (``python -m paper_2009_08167_amd.build``);
+loading fails loudly otherwise -- there is no fallback path.
+"""
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libriga.so")
+
+RIGA_OK, RIGA_EINVAL, RIGA_ENOMEM, RIGA_EDEVICE = 0, -1, -2, -3
+RIGA_ENOCONV, RIGA_ESINGULAR, RIGA_EDEGENERATE, RIGA_EUNSUPPORTED = -4, -5, -6, -7
+RIGA_FP64, RIGA_MIXED = 0, 1
+RIGA_MAT_K, RIGA_MAT_M, RIGA_MAT_A = 0, 1, 2
+
+EXPORTED = ["riga_set_allocator", "riga_analyze", "riga_assemble", "riga_problem_info",
+            "riga_tree_export", "riga_get_matrices", "riga_spmv", "riga_factor", "riga_solve",
+            "riga_eigs", "riga_eig_grad", "riga_destroy", "riga_status_string",
+            "riga_last_error"]
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("ne", C.c_int32 * 3), ("p", C.c_int32),
+                ("sep_spacing", C.c_int32), ("nquad", C.c_int32),
+                ("kappa", C.c_void_p), ("rho", C.c_void_p), ("coeffs_on_device", C.c_int32),
+                ("leaf_dofs", C.c_int32), ("stream", C.c_void_p)]
+
+
+class EigsOpts(C.Structure):
+    _fields_ = [("lo", C.c_double), ("hi", C.c_double), ("nev", C.c_int32),
+                ("precision", C.c_int32), ("tol", C.c_double), ("max_basis", C.c_int32),
+                ("max_restarts", C.c_int32), ("per_shift", C.c_int32), ("seed", C.c_uint64),
+                ("stream", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_shift", C.c_int32), ("n_fact", C.c_int32), ("n_fb", C.c_int32),
+                ("n_mv", C.c_int32), ("n_it", C.c_int32), ("n_ir", C.c_int32),
+                ("n_perturbed_pivots", C.c_int32), ("n_2x2_pivots", C.c_int32),
+                ("t_fact", C.c_double), ("t_fb", C.c_double), ("t_mv", C.c_double),
+                ("t_orth", C.c_double), ("t_proj", C.c_double), ("t_ritz", C.c_double),
+                ("t_total", C.c_double), ("flops_fact", C.c_double), ("bytes_fb", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ProblemInfo(C.Structure):
+    _fields_ = [("n_dof", C.c_int64), ("n_elem", C.c_int64), ("nnz", C.c_int64),
+                ("n1", C.c_int32 * 3), ("n_fronts", C.c_int32), ("tree_height", C.c_int32),
+                ("max_front", C.c_int32), ("max_fs", C.c_int32), ("nnz_l", C.c_int64),
+                ("flops_fact", C.c_double), ("front_pool", C.c_int64)]
+
+
+class RigaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("riga status %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libriga.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libriga.so not built: run `python -m paper_2009_08167_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.riga_analyze.argtypes = [C.POINTER(MeshDesc), C.POINTER(P)]
+        L.riga_assemble.argtypes = [C.POINTER(MeshDesc), C.POINTER(P)]
+        L.riga_problem_info.argtypes = [P, C.POINTER(ProblemInfo)]
+        L.riga_tree_export.argtypes = [P] + [P] * 6
+        L.riga_get_matrices.argtypes = [P, P, P, P, P]
+        L.riga_spmv.argtypes = [P, C.c_int32, P, P, P]
+        L.riga_factor.argtypes = [P, C.c_double, C.c_int32, C.POINTER(C.c_int64), C.POINTER(Stats)]
+        L.riga_solve.argtypes = [P, P, P, C.c_int32, P]
+        L.riga_eigs.argtypes = [P, C.POINTER(EigsOpts), C.POINTER(C.c_int32), P, P, P,
+                                C.POINTER(Stats)]
+        L.riga_eig_grad.argtypes = [P, C.c_int32, P, P, P, P, P, P]
+        L.riga_destroy.argtypes = [P]
+        L.riga_destroy.restype = None
+        L.riga_status_string.restype = C.c_char_p
+        L.riga_last_error.restype = C.c_char_p
+        for name in ["riga_analyze", "riga_assemble", "riga_problem_info", "riga_tree_export",
+                     "riga_get_matrices", "riga_spmv", "riga_factor", "riga_solve", "riga_eigs",
+                     "riga_eig_grad", "riga_set_allocator"]:
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code, allow=()):
+    if code != RIGA_OK and code not in allow:
+        raise RigaError(code, lib().riga_last_error().decode())
+    return code
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """An assembled (or only analysed) rIGA problem."""
+
+    def __init__(self, handle, dim, ne, p, s, device):
+        self._h = handle
+        self.dim, self.ne, self.p, self.s = dim, ne, p, s
+        self.device = device
+        inf = ProblemInfo()
+        _check(lib().riga_problem_info(self._h, C.byref(inf)))
+        self.info = {f: (list(getattr(inf, f)) if f == "n1" else getattr(inf, f))
+                     for f, _ in ProblemInfo._fields_}
+        self.n_dof = int(inf.n_dof)
+        self.n_elem = int(inf.n_elem)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().riga_destroy(h)
+            self._h = None
+
+    def close(self):
+        self.__del__()
+
+    def tree(self):
+        """Symbolic analysis as numpy arrays."""
+        nf = self.info["n_fronts"]
+        perm = np.zeros(self.n_dof, np.int32)
+        fk = np.zeros(nf, np.int32)
+        ff = np.zeros(nf, np.int32)
+        par = np.zeros(nf, np.int32)
+        hgt = np.zeros(nf, np.int32)
+        _check(lib().riga_tree_export(self._h, perm.ctypes.data, fk.ctypes.data, ff.ctypes.data,
+                                      par.ctypes.data, hgt.ctypes.data, None))
+        rows = np.zeros(int(ff.sum()), np.int32)
+        _check(lib().riga_tree_export(self._h, None, None, None, None, None, rows.ctypes.data))
+        return dict(perm=perm, k=fk, f=ff, parent=par, height=hgt, rows=rows)
+
+    def pattern(self):
+        nnz = self.info["nnz"]
+        rp = np.zeros(self.n_dof + 1, np.int64)
+        ci = np.zeros(nnz, np.int32)
+        _check(lib().riga_get_matrices(self._h, rp.ctypes.data, ci.ctypes.data, None, None))
+        return rp, ci
+
+    def matrices(self):
+        """(row_ptr, col_idx, K values, M values) copied from the device."""
+        import scipy.sparse as sp
+        nnz = self.info["nnz"]
+        rp = np.zeros(self.n_dof + 1, np.int64)
+        ci = np.zeros(nnz, np.int32)
+        kv = np.zeros(nnz)
+        mv = np.zeros(nnz)
+        _check(lib().riga_get_matrices(self._h, rp.ctypes.data, ci.ctypes.data, kv.ctypes.data,
+                                       mv.ctypes.data))
+        shape = (self.n_dof, self.n_dof)
+        return sp.csr_matrix((kv, ci, rp), shape=shape), sp.csr_matrix((mv, ci, rp), shape=shape)
+
+    def spmv(self, which, x, stream=None):
+        import torch
+        y = torch.empty_like(x)
+        _check(lib().riga_spmv(self._h, which, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def factor(self, sigma, precision=RIGA_FP64):
+        neg = C.c_int64(0)
+        st = Stats()
+        _check(lib().riga_factor(self._h, float(sigma), precision, C.byref(neg), C.byref(st)))
+        return int(neg.value), st.as_dict()
+
+    def solve(self, b, max_ir=0, stream=None):
+        import torch
+        x = torch.empty_like(b)
+        _check(lib().riga_solve(self._h, _ptr(b), _ptr(x), max_ir, _stream(stream)))
+        return x
+
+    def eigs(self, nev, lo=0.0, hi=math.inf, precision=RIGA_FP64, tol=1e-9, max_basis=0,
+             max_restarts=0, per_shift=0, seed=0, vectors=True, stream=None, allow_partial=False):
+        """nev lowest eigenpairs in [lo, hi).  Returns (lam numpy, U torch
+        [n_dof, nev] or None, resid numpy, stats dict)."""
+        import torch
+        o = EigsOpts(lo=lo, hi=hi, nev=nev, precision=precision, tol=tol, max_basis=max_basis,
+                     max_restarts=max_restarts, per_shift=per_shift, seed=seed,
+                     stream=_stream(stream))
+        lam = np.zeros(nev)
+        res = np.zeros(nev)
+        U = None
+        if vectors:
+            U = torch.zeros((nev, self.n_dof), dtype=torch.float64, device=self.device)
+        nf = C.c_int32(0)
+        st = Stats()
+        code = lib().riga_eigs(self._h, C.byref(o), C.byref(nf), lam.ctypes.data,
+                               _ptr(U) if U is not None else None, res.ctypes.data, C.byref(st))
+        _check(code, allow=(RIGA_ENOCONV,) if allow_partial else ())
+        n = int(nf.value)
+        if U is not None:
+            U = U[:n].T
+        return lam[:n], U, res[:n], st.as_dict()
+
+    def eig_grad(self, lam, U, w, stream=None):
+        """Gradient of sum_i w_i lam_i w.r.t. (kappa, rho); U: [n_dof, k]
+        M-normalised eigenvectors on the device."""
+        import torch
+        k = len(lam)
+        Uc = U.T.contiguous()  # column-major n_dof x k
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        gk = torch.empty(self.n_elem, dtype=torch.float64, device=self.device)
+        gr = torch.empty(self.n_elem, dtype=torch.float64, device=self.device)
+        _check(lib().riga_eig_grad(self._h, k, lam.ctypes.data, _ptr(Uc), w.ctypes.data,
+                                   _ptr(gk), _ptr(gr), _stream(stream)))
+        return gk, gr
+
+
+def _desc(dim, ne, p, s, kappa, rho, nquad, leaf_dofs, stream, keep):
+    d = MeshDesc()
+    d.dim = dim
+    nes = [ne] * dim if np.isscalar(ne) else list(ne)
+    for i in range(3):
+        d.ne[i] = nes[i] if i < dim else 1
+    d.p, d.sep_spacing, d.nquad, d.leaf_dofs = p, s, nquad, leaf_dofs
+    d.coeffs_on_device = 0
+    for name in ("kappa", "rho"):
+        v = kappa if name == "kappa" else rho
+        if v is None:
+            setattr(d, name, None)
+            continue
+        if hasattr(v, "is_cuda") and v.is_cuda:
+            v = v.contiguous().double()
+            d.coeffs_on_device = 1
+            keep.append(v)
+            setattr(d, name, v.data_ptr())
+        else:
+            a = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
+            keep.append(a)
+            setattr(d, name, a.ctypes.data)
+    if kappa is not None and rho is not None:
+        on_dev = [hasattr(v, "is_cuda") and v.is_cuda for v in (kappa, rho)]
+        if on_dev[0] != on_dev[1]:
+            raise ValueError("kappa and rho must both be host arrays or both device tensors")
+    d.stream = stream
+    return d
+
+
+def analyze(dim, ne, p, s, nquad=0, leaf_dofs=0):
+    """Host-only analysis (no device needed)."""
+    keep = []
+    d = _desc(dim, ne, p, s, None, None, nquad, leaf_dofs, None, keep)
+    h = C.c_void_p()
+    _check(lib().riga_analyze(C.byref(d), C.byref(h)))
+    return Problem(h, dim, ne, p, s, None)
+
+
+def assemble(dim, ne, p, s, kappa=None, rho=None, nquad=0, leaf_dofs=0, device="cuda:0",
+             stream=None):
+    """Analyse and assemble K, M on the device."""
+    import torch
+    dev = torch.device(device)
+    with torch.cuda.device(dev):
+        keep = []
+        d = _desc(dim, ne, p, s, kappa, rho, nquad, leaf_dofs, _stream(stream), keep)
+        h = C.c_void_p()
+        _check(lib().riga_assemble(C.byref(d), C.byref(h)))
+        return Problem(h, dim, ne, p, s, dev)
+
+
+def eigs(dim, ne, p, s, nev, kappa=None, rho=None, lo=0.0, hi=math.inf, precision=RIGA_FP64,
+         **kw):
+    pr = assemble(dim, ne, p, s, kappa, rho)
+    return pr.eigs(nev, lo=lo, hi=hi, precision=precision, **kw)
+
+
+def _autograd():
+    import torch
+
+    class EigSum(torch.autograd.Function):
+        """L = sum_i w_i lambda_i(kappa, rho) for the nev lowest eigenvalues;
+        backward through the adjoint kernel (riga_eig_grad)."""
+
+        @staticmethod
+        def forward(ctx, kappa, rho, w, dim, ne, p, s):
+            nev = w.numel()
+            pr = assemble(dim, ne, p, s, kappa.detach(), rho.detach(), device=kappa.device)
+            lam, U, _, _ = pr.eigs(nev)
+            ctx.pr, ctx.U = pr, U
+            ctx.lam = lam
+            ctx.save_for_backward(w)
+            lam_t = torch.as_tensor(lam, dtype=torch.float64, device=kappa.device)
+            return (w.to(torch.float64) * lam_t).sum()
+
+        @staticmethod
+        def backward(ctx, g):
+            (w,) = ctx.saved_tensors
+            wg = (w.detach().double() * g.detach().double()).cpu().numpy()
+            gk, gr = ctx.pr.eig_grad(ctx.lam, ctx.U, wg)
+            return gk, gr, None, None, None, None, None
+
+    return EigSum
+
+
+class _Lazy:
+    _cls = None
+
+    def apply(self, *a):
+        if _Lazy._cls is None:
+            _Lazy._cls = _autograd()
+        return _Lazy._cls.apply(*a)
+
+
+EigSum = _Lazy()

@@ -1,0 +1,158 @@
+"""CPU tests of the library's host-side analysis (no GPU): exported symbols,
+DOF maps and sparsity pattern against the oracle's assembly, and the
+symbolic factorisation against a brute-force symbolic elimination."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import assembly
+
+riga = pytest.importorskip("paper_2009_08167_amd.riga")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib_or_skip():
+    if not os.path.exists(riga.LIB_PATH):
+        pytest.skip("libriga.so not built")
+    return riga.lib()
+
+
+def test_exports_every_header_symbol():
+    L = _lib_or_skip()
+    text = open(os.path.join(ROOT, "include", "riga.h")).read()
+    names = set(re.findall(r"^(?:riga_status|void|const char\s*\*)\s*(riga_\w+)\s*\(", text,
+                           re.M))
+    assert {"riga_assemble", "riga_eigs", "riga_eig_grad"} <= names
+    for n in sorted(names):
+        assert hasattr(L, n), n
+    assert set(riga.EXPORTED) == names
+
+
+def test_invalid_descriptors_rejected():
+    _lib_or_skip()
+    for args in [(4, 8, 2, 0), (2, 8, 0, 0), (2, 8, 2, -1), (2, 0, 2, 0), (2, 8, 9, 0)]:
+        with pytest.raises(riga.RigaError) as e:
+            riga.analyze(*args)
+        assert e.value.code == riga.RIGA_EINVAL
+
+
+CASES = [(2, 16, 2, 0), (2, 16, 3, 4), (2, 20, 2, 6), (2, 13, 4, 5), (3, 6, 2, 0), (3, 8, 2, 4),
+         (2, 24, 1, 0), (2, 9, 3, 1)]
+
+
+@pytest.mark.parametrize("dim,ne,p,s", CASES)
+def test_pattern_matches_oracle(dim, ne, p, s):
+    _lib_or_skip()
+    pr = riga.analyze(dim, ne, p, s)
+    K, M = assembly.assemble(dim, ne, p, s)
+    assert pr.n_dof == K.shape[0]
+    rp, ci = pr.pattern()
+    P = sp.csr_matrix((np.ones(len(ci)), ci, rp), shape=K.shape)
+    # structural pattern: the oracle's non-zeros (mass entries are > 0 on
+    # the whole support overlap) equal the library's stored pattern
+    Mo = (abs(M) > 0).astype(float)
+    assert (P != Mo).nnz == 0
+    for r in range(0, pr.n_dof, max(1, pr.n_dof // 50)):
+        row = ci[rp[r]:rp[r + 1]]
+        assert (np.diff(row) > 0).all()
+
+
+def _fronts(t):
+    offs = np.concatenate([[0], np.cumsum(t["f"])])
+    return [t["rows"][offs[i]:offs[i + 1]] for i in range(len(t["f"]))]
+
+
+@pytest.mark.parametrize("dim,ne,p,s", CASES)
+def test_tree_is_a_valid_elimination_tree(dim, ne, p, s):
+    _lib_or_skip()
+    pr = riga.analyze(dim, ne, p, s, leaf_dofs=16)
+    t = pr.tree()
+    perm = t["perm"]
+    assert sorted(perm) == list(range(pr.n_dof))
+    fronts = _fronts(t)
+    nf = len(fronts)
+    # post-order, heights, each DOF fully summed in exactly one front
+    owner = -np.ones(pr.n_dof, np.int64)
+    start = 0
+    for F in range(nf):
+        par = t["parent"][F]
+        assert par == -1 or par > F
+        k = t["k"][F]
+        fs = fronts[F][:k]
+        assert (perm[fs] == np.arange(start, start + k)).all()
+        start += k
+        assert (owner[fs] == -1).all()
+        owner[fs] = F
+        # contribution-block rows are eliminated later, ascending
+        cb = perm[fronts[F][k:]]
+        assert (cb >= start).all() and (np.diff(cb) > 0).all()
+        if par >= 0:
+            assert set(fronts[F][k:]) <= set(fronts[par])
+            assert t["height"][par] >= t["height"][F] + 1
+    assert (owner >= 0).all()
+    # every matrix entry lies in the front of its earlier-eliminated index
+    rp, ci = pr.pattern()
+    fsets = [set(f) for f in fronts]
+    for r in range(pr.n_dof):
+        for c in ci[rp[r]:rp[r + 1]]:
+            a, b = (r, c) if perm[r] <= perm[c] else (c, r)
+            assert b in fsets[owner[a]]
+
+
+@pytest.mark.parametrize("dim,ne,p,s", [(2, 12, 2, 0), (2, 16, 3, 4), (3, 6, 2, 3), (2, 10, 4, 5)])
+def test_fronts_contain_exact_fill(dim, ne, p, s):
+    """Brute force: the symbolic Cholesky of P A P^T (SuperLU, natural order
+    on the permuted matrix, no pivoting) never fills outside the fronts, and
+    the supernodal count nnz(L) is at least the exact fill."""
+    _lib_or_skip()
+    pr = riga.analyze(dim, ne, p, s, leaf_dofs=24)
+    t = pr.tree()
+    perm = t["perm"]
+    K, M = assembly.assemble(dim, ne, p, s)
+    A = (K + M).tocsr()                    # SPD, same pattern
+    n = A.shape[0]
+    Pm = sp.csr_matrix((np.ones(n), (perm, np.arange(n))), shape=(n, n))
+    Ap = (Pm @ A @ Pm.T).tocsc()
+    lu = spla.splu(Ap, permc_spec="NATURAL", diag_pivot_thresh=0.0,
+                   options=dict(SymmetricMode=True))
+    assert (lu.perm_r == np.arange(n)).all()
+    L = sp.tril(lu.L, -1).tocoo()
+    fronts = _fronts(t)
+    iperm = np.argsort(perm)
+    owner = np.zeros(n, np.int64)
+    for F, fr in enumerate(fronts):
+        owner[perm[fr[:t["k"][F]]]] = F
+    fsets = [set(perm[f]) for f in fronts]
+    for i, j in zip(L.row, L.col):
+        assert i in fsets[owner[j]]
+    nnz_exact = L.nnz + n
+    assert pr.info["nnz_l"] >= nnz_exact
+    del iperm
+
+
+def test_riga_separators_are_single_layers():
+    """With rIGA the top separators cut at C^0 knots: one layer of DOFs
+    (Sec. 3.2), so the root fully-summed block is one line of the grid."""
+    _lib_or_skip()
+    pr = riga.analyze(2, 64, 3, 16)
+    t = pr.tree()
+    root = len(t["k"]) - 1
+    assert t["parent"][root] == -1
+    assert t["k"][root] == pr.info["n1"][1]
+    pr_iga = riga.analyze(2, 64, 3, 0)
+    t2 = pr_iga.tree()
+    assert t2["k"][-1] == 3 * pr_iga.info["n1"][1]   # p layers at a simple knot
+    assert pr.info["flops_fact"] < pr_iga.info["flops_fact"]
+
+
+def test_analysis_is_deterministic():
+    _lib_or_skip()
+    a = riga.analyze(2, 40, 3, 8).tree()
+    b = riga.analyze(2, 40, 3, 8).tree()
+    for k in a:
+        assert np.array_equal(a[k], b[k])
