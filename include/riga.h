@@ -142,6 +142,15 @@ riga_status riga_analyze(const riga_mesh_desc* desc, riga_problem** out);
  * RIGA_EDEVICE. */
 riga_status riga_assemble(const riga_mesh_desc* desc, riga_problem** out);
 
+/* riga_update_coefficients: replace kappa/rho (n_elem each; NULL -> 1) and
+ * re-assemble K and M on the device, reusing the analysis of the pattern.
+ * `on_device`: the arrays are device (1) or host (0) pointers; both are
+ * copied.  Invalidates the current factorisation.  Errors: RIGA_EINVAL
+ * (problem without device data, non-positive host coefficient),
+ * RIGA_EDEVICE. */
+riga_status riga_update_coefficients(riga_problem* pr, const double* kappa, const double* rho,
+                                     int32_t on_device, void* stream);
+
 riga_status riga_problem_info(const riga_problem* pr, riga_problem_info_t* info);
 
 /* riga_tree_export: copy the symbolic analysis to host arrays (any may be

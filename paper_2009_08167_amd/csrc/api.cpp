@@ -11,6 +11,8 @@
 namespace riga {
 void set_allocator(const riga_allocator* a);
 void setup_device(riga_problem* pr, const riga_mesh_desc* desc);
+void load_and_assemble(riga_problem* pr, const double* kappa, const double* rho, int on_device,
+                       hipStream_t s);
 riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found, double* evals,
                      double* evecs, double* resid, riga_stats* stats_out);
 }  // namespace riga
@@ -81,6 +83,16 @@ riga_status riga_assemble(const riga_mesh_desc* desc, riga_problem** out) {
       *out = nullptr;
       throw;
     }
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_update_coefficients(riga_problem* pr, const double* kappa, const double* rho,
+                                     int32_t on_device, void* stream) {
+  return guarded([&]() -> riga_status {
+    if (!need_device(pr)) return fail(RIGA_EINVAL, "problem has no device data");
+    pr->stream = (hipStream_t)stream;
+    riga::load_and_assemble(pr, kappa, rho, on_device, pr->stream);
     return RIGA_OK;
   });
 }

@@ -63,7 +63,7 @@ struct Solver {
   int max_ir;
   DBuf<double> B, W, x, y, c1, c2, partial, dotp, alpha, beta, scal;
   DBuf<int32_t> flag;
-  DBuf<double> theta, S, tdwork, Sh, Ub, KU, MU, rqn, rqd, rn2, un2, lam, nrm;
+  DBuf<double> theta, tdest, S, tdwork, Sh, Ub, KU, MU, rqn, rqd, rn2, un2, lam, nrm;
   DBuf<int32_t> sel;
   DBuf<double> ir_r, ir_d;
   std::vector<Locked> locked;
@@ -91,8 +91,9 @@ struct Solver {
     scal.alloc(8, s);
     flag.alloc(4, s);
     theta.alloc(mb + 1, s);
+    tdest.alloc(mb + 1, s);
     S.alloc((size_t)(mb + 1) * (mb + 1), s);
-    tdwork.alloc((size_t)6 * (mb + 1) * (mb + 1), s);
+    tdwork.alloc((size_t)6 * (mb + 1) * (mb + 64), s);
     sel.alloc(mb + 1, s);
     const int umax = mb + 1;
     Sh.alloc((size_t)(mb + 1) * umax, s);
@@ -185,59 +186,70 @@ struct Solver {
   }
 
   struct Ritz {
-    std::vector<double> theta;    // all Ritz values, ascending
-    std::vector<int> sel;         // selected indices
-    std::vector<double> S;        // m x nsel
-    std::vector<double> est;      // per selected: |beta_m s_m|
-    double beta_m;
-    int m, nsel;
+    std::vector<double> theta;    // all Ritz values of T_m, ascending
+    std::vector<double> est;      // Ritz estimates |beta_{m+1} s_m|
+    double beta_m = 0.0;
+    int m = 0;
   };
 
-  Ritz ritz(int m, int nsel) {
+  // Convergence check: eigenvalues of T_m and their Ritz estimates.
+  Ritz check(int m) {
     auto a = clk::now();
     Ritz r;
     r.m = m;
-    r.nsel = std::min(nsel, m);
-    launch_tridiag_eig(alpha.p, beta.p, m, theta.p, S.p, r.nsel, sel.p, tdwork.p, s);
+    launch_ritz_check(alpha.p, beta.p, m, theta.p, tdest.p, tdwork.p, s);
     r.theta.resize(m);
-    r.sel.resize(r.nsel);
-    r.S.resize((size_t)m * r.nsel);
+    r.est.resize(m);
     HIPCHECK(hipMemcpyAsync(r.theta.data(), theta.p, m * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipMemcpyAsync(r.sel.data(), sel.p, r.nsel * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipMemcpyAsync(r.S.data(), S.p, r.S.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(r.est.data(), tdest.p, m * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipMemcpyAsync(&r.beta_m, beta.p + m, sizeof(double), hipMemcpyDeviceToHost, s));
     int32_t fl = 0;
     HIPCHECK(hipMemcpyAsync(&fl, flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
-    if (fl) r.beta_m = 0.0;
-    r.est.resize(r.nsel);
-    for (int q = 0; q < r.nsel; ++q) r.est[q] = std::fabs(r.beta_m * r.S[(size_t)q * m + m - 1]);
+    if (fl) {
+      r.beta_m = 0.0;
+      std::fill(r.est.begin(), r.est.end(), 0.0);
+    }
     st.t_proj += secs(a, clk::now());
     return r;
   }
 
-  static bool converged(const Ritz& r, int q) {
-    const double th = r.theta[r.sel[q]];
-    return r.est[q] <= 1e-10 * std::fabs(th);
+  static bool converged(const Ritz& r, int i) { return r.est[i] <= 1e-10 * std::fabs(r.theta[i]); }
+
+  // Unit eigenvectors of T_m for the Ritz values theta[idx] (idx ascending),
+  // returned column by column (m x idx.size()).
+  std::vector<double> vectors(const Ritz& r, const std::vector<int>& idx) {
+    const int m = r.m, n = (int)idx.size();
+    std::vector<double> Sv((size_t)m * n);
+    if (n == 0) return Sv;
+    std::vector<int32_t> ix(idx.begin(), idx.end());
+    HIPCHECK(hipMemcpyAsync(sel.p, ix.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    launch_ritz_vectors(alpha.p, beta.p, m, theta.p, sel.p, n, S.p, tdwork.p, s);
+    HIPCHECK(hipMemcpyAsync(Sv.data(), S.p, Sv.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    return Sv;
   }
 
-  // Extract the Ritz vectors of `which` (positions in r.sel) plus an
-  // optional restart combination; lock those passing the residual test.
-  // Returns the number locked.
-  int lock_pairs(const Ritz& r, double sigma, const std::vector<int>& which,
-                 const std::vector<int>& restart_from, bool* have_restart) {
+  // Ritz vectors V s_q of the pairs `which` (columns of Sv) plus, if
+  // `restart_from` is not empty, the sum of those columns as a restart
+  // vector; lock the pairs that pass the residual test.  Returns the number
+  // locked.
+  int lock_pairs(const Ritz& r, double sigma, const std::vector<double>& Sv,
+                 const std::vector<int>& which, const std::vector<int>& restart_from,
+                 const std::vector<double>& lam_ritz, bool* have_restart) {
     auto a = clk::now();
     const int m = r.m;
     const int nw = (int)which.size();
     const int nc = nw + (restart_from.empty() ? 0 : 1);
     *have_restart = !restart_from.empty();
+    (void)lam_ritz;
     if (nc == 0) return 0;
     std::vector<double> Sh_h((size_t)m * nc, 0.0);
     for (int i = 0; i < nw; ++i)
-      std::memcpy(&Sh_h[(size_t)i * m], &r.S[(size_t)which[i] * m], m * sizeof(double));
+      std::memcpy(&Sh_h[(size_t)i * m], &Sv[(size_t)which[i] * m], m * sizeof(double));
     if (!restart_from.empty())
       for (int q : restart_from)
-        for (int t = 0; t < m; ++t) Sh_h[(size_t)nw * m + t] += r.S[(size_t)q * m + t];
+        for (int t = 0; t < m; ++t) Sh_h[(size_t)nw * m + t] += Sv[(size_t)q * m + t];
     HIPCHECK(hipMemcpyAsync(Sh.p, Sh_h.data(), Sh_h.size() * sizeof(double), hipMemcpyHostToDevice, s));
     // U = V S (the restart combination lands in column nw)
     launch_gemm_nn(Bc(nl), N, m, Sh.p, m, nc, Ub.p, s);
@@ -313,20 +325,19 @@ struct Solver {
   // final Ritz data (for shift placement).
   Ritz run(double sigma, int need_below, int need_above, const double* init, int* n_new) {
     start_vector(init);
-    const int maxm = std::min<int64_t>(mb, N - nl - 1);
+    const int maxm = (int)std::min<int64_t>(mb, N - nl - 1);
     int j = 0;
     Ritz r;
     int next_check = std::min(maxm, std::max(16, std::min(need_below + need_above, maxm)));
-    const int nsel = std::min(maxm, std::max(64, 2 * (need_below + need_above) + 16));
     while (true) {
       step(j);
       ++j;
       if (j < next_check && j < maxm) continue;
-      r = ritz(j, nsel);
+      r = check(j);
       int cb = 0, ca = 0;
-      for (int q = 0; q < r.nsel; ++q) {
-        if (!converged(r, q)) continue;
-        const double l = sigma + 1.0 / r.theta[r.sel[q]];
+      for (int i = 0; i < j; ++i) {
+        if (!converged(r, i)) continue;
+        const double l = sigma + 1.0 / r.theta[i];
         if (l < sigma) ++cb; else ++ca;
       }
       const bool breakdown = r.beta_m == 0.0;
@@ -335,20 +346,25 @@ struct Solver {
     }
     st.n_it++;
     // lock every converged pair; restart from the nearest unconverged ones
-    std::vector<int> which, rest;
-    for (int q = 0; q < r.nsel; ++q) {
-      if (converged(r, q)) which.push_back(q);
-    }
-    // unconverged, by decreasing |theta|
-    std::vector<int> unc;
-    for (int q = 0; q < r.nsel; ++q)
-      if (!converged(r, q)) unc.push_back(q);
+    std::vector<int> conv, unc;
+    for (int i = 0; i < j; ++i) (converged(r, i) ? conv : unc).push_back(i);
     std::sort(unc.begin(), unc.end(), [&](int a, int b) {
-      return std::fabs(r.theta[r.sel[a]]) > std::fabs(r.theta[r.sel[b]]);
+      return std::fabs(r.theta[a]) > std::fabs(r.theta[b]);
     });
-    for (int i = 0; i < (int)unc.size() && i < 8; ++i) rest.push_back(unc[i]);
+    if (unc.size() > 8) unc.resize(8);
+    std::vector<int> idx = conv;
+    idx.insert(idx.end(), unc.begin(), unc.end());
+    std::sort(idx.begin(), idx.end());
+    auto a = clk::now();
+    std::vector<double> Sv = vectors(r, idx);
+    st.t_proj += secs(a, clk::now());
+    std::vector<int> which, rest;
+    for (size_t q = 0; q < idx.size(); ++q) {
+      if (converged(r, idx[q])) which.push_back((int)q);
+      else rest.push_back((int)q);
+    }
     bool have_restart = false;
-    *n_new = lock_pairs(r, sigma, which, rest, &have_restart);
+    *n_new = lock_pairs(r, sigma, Sv, which, rest, r.theta, &have_restart);
     restart_valid = have_restart && r.beta_m != 0.0;
     if (log_on())
       std::fprintf(stderr, "[riga] run sigma=%.6g steps=%d need=(%d,%d) converged=%zu locked=%d total_locked=%d\n",

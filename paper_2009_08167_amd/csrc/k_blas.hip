@@ -79,13 +79,17 @@ __global__ void __launch_bounds__(256) gemv_t_kernel(const double* __restrict__ 
   }
 }
 
-// c[j] = sum_rb partial[rb * m + j]; optionally acc[0] += c[jacc]
-__global__ void gemv_t_reduce_kernel(const double* partial, int nrb, int m, double* c) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// c[j] = sum_rb partial[rb * m + j]: one wave per column, lanes over row
+// blocks in a fixed order, then a fixed butterfly
+__global__ void __launch_bounds__(256) gemv_t_reduce_kernel(const double* partial, int nrb, int m,
+                                                          double* c) {
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (j >= m) return;
   double s = 0.0;
-  for (int rb = 0; rb < nrb; ++rb) s += partial[(int64_t)rb * m + j];
-  c[j] = s;
+  for (int rb = lane; rb < nrb; rb += 64) s += partial[(int64_t)rb * m + j];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) c[j] = s;
 }
 
 // x -= B c
@@ -332,7 +336,7 @@ void launch_gemv_t(const double* B, int64_t n, int m, const double* x, double* p
   const int nrb = gemv_row_blocks(n);
   dim3 grid(nrb, (m + GEMV_CG - 1) / GEMV_CG);
   gemv_t_kernel<<<grid, 256, 0, s>>>(B, n, m, x, partial);
-  gemv_t_reduce_kernel<<<(m + 127) / 128, 128, 0, s>>>(partial, nrb, m, c);
+  gemv_t_reduce_kernel<<<(m + 3) / 4, 256, 0, s>>>(partial, nrb, m, c);
   HIPCHECK(hipGetLastError());
 }
 

@@ -36,15 +36,38 @@ struct SolveArgs {
   double* fwd;
 };
 
+constexpr int PB = 64;  // panel width of the blocked triangular solves
+
+// Loads the diagonal block L(p0:p0+pw, p0:p0+pw) (unit lower, strict part)
+// into LDS `blk` (row-major, ld PB+1), zeroing the D entry of 2x2 pivot
+// blocks, which is not part of L.
 template <class T>
-__global__ void __launch_bounds__(256) fwd_kernel(SolveArgs sa, const T* pool,
-                                                const int32_t* fronts, const double* b) {
-  extern __shared__ double y[];  // f + k doubles
-  const int F = fronts[blockIdx.x];
+__device__ __forceinline__ void load_diag_block(const T* L, int f, int p0, int pw,
+                                                const int32_t* type, double* blk) {
+  for (int e = threadIdx.x; e < PB * PB; e += blockDim.x) {
+    const int c = e / PB, r = e % PB;
+    double v = 0.0;
+    if (r < pw && c < pw && r > c) {
+      v = (double)L[(int64_t)(p0 + c) * f + p0 + r];
+      if (r == c + 1 && type[p0 + c] == 2) v = 0.0;
+    }
+    blk[r * (PB + 1) + c] = v;
+  }
+}
+
+template <class T>
+__device__ void fwd_front(const SolveArgs& sa, const T* pool, int F, const double* b,
+                          double* smem) {
+  double* blk = smem;                     // PB x (PB+1)
+  double* y = smem + PB * (PB + 1);       // f
   const int f = sa.ff[F], k = sa.fk[F], start = sa.fstart[F];
   const T* L = pool + sa.pool_off[F];
   const int32_t* rows = sa.rows + sa.rows_off[F];
-  double* z = y + f;
+  const int32_t* type = sa.piv_type + start;
+  const int32_t* perm = sa.piv_perm + start;
+  double* z = y + f;                      // k (permutation scratch)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // gather: own right-hand side entries plus the children's updates
   for (int i = threadIdx.x; i < f; i += blockDim.x) {
     double v = i < k ? b[rows[i]] : 0.0;
     for (int ci = sa.child_ptr[F]; ci < sa.child_ptr[F + 1]; ++ci) {
@@ -54,30 +77,46 @@ __global__ void __launch_bounds__(256) fwd_kernel(SolveArgs sa, const T* pool,
     y[i] = v;
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < k; t += blockDim.x) z[t] = y[sa.piv_perm[start + t]];
+  for (int t = threadIdx.x; t < k; t += blockDim.x) z[t] = y[perm[t]];
   __syncthreads();
   for (int t = threadIdx.x; t < k; t += blockDim.x) y[t] = z[t];
-  __syncthreads();
-  int t = 0;
-  while (t < k) {
-    const int ty = sa.piv_type[start + t];
-    if (ty == 2) {
-      const double z0 = y[t], z1 = y[t + 1];
-      const T* c0 = L + (int64_t)t * f;
-      const T* c1 = L + (int64_t)(t + 1) * f;
-      for (int i = t + 2 + threadIdx.x; i < f; i += blockDim.x)
-        y[i] -= (double)c0[i] * z0 + (double)c1[i] * z1;
-      t += 2;
-    } else {
-      const double z0 = y[t];
-      const T* c0 = L + (int64_t)t * f;
-      for (int i = t + 1 + threadIdx.x; i < f; i += blockDim.x) y[i] -= (double)c0[i] * z0;
-      t += 1;
+  // panels of the fully-summed block; a 2x2 pivot block never straddles two
+  int p0 = 0;
+  while (p0 < k) {
+    int pw = min(PB, k - p0);
+    if (pw > 1 && p0 + pw < k && type[p0 + pw - 1] == 2) --pw;
+    __syncthreads();
+    load_diag_block(L, f, p0, pw, type, blk);
+    __syncthreads();
+    if (wave == 0) {
+      double yl = lane < pw ? y[p0 + lane] : 0.0;
+      for (int t = 0; t < pw; ++t) {
+        const double zt = __shfl(yl, t);
+        if (lane > t) yl -= blk[lane * (PB + 1) + t] * zt;
+      }
+      if (lane < pw) y[p0 + lane] = yl;
     }
     __syncthreads();
+    // rows below the panel: y_r -= L(r, panel) z_panel (16 loads in flight)
+    for (int r = p0 + pw + threadIdx.x; r < f; r += blockDim.x) {
+      const T* lr = L + (int64_t)p0 * f + r;
+      double s = 0.0;
+      int t = 0;
+      for (; t + 16 <= pw; t += 16) {
+        double lv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) lv[u] = (double)lr[(int64_t)(t + u) * f];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += lv[u] * y[p0 + t + u];
+      }
+      for (; t < pw; ++t) s += (double)lr[(int64_t)t * f] * y[p0 + t];
+      y[r] -= s;
+    }
+    p0 += pw;
   }
+  __syncthreads();
   for (int t2 = threadIdx.x; t2 < k; t2 += blockDim.x) {
-    const int ty = sa.piv_type[start + t2];
+    const int ty = type[t2];
     const double d = (double)L[(int64_t)t2 * f + t2];
     if (ty == 1) {
       sa.fwd[start + t2] = y[t2] / d;
@@ -93,35 +132,72 @@ __global__ void __launch_bounds__(256) fwd_kernel(SolveArgs sa, const T* pool,
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) bwd_kernel(SolveArgs sa, const T* pool,
-                                                const int32_t* fronts, double* x) {
-  extern __shared__ double v[];  // k + (f - k) doubles
-  const int F = fronts[blockIdx.x];
+__global__ void __launch_bounds__(256) fwd_kernel(SolveArgs sa, const T* pool,
+                                                const int32_t* fronts, const double* b) {
+  extern __shared__ double smem[];
+  fwd_front<T>(sa, pool, fronts[blockIdx.x], b, smem);
+}
+
+template <class T>
+__device__ void bwd_front(const SolveArgs& sa, const T* pool, int F, double* x, double* smem) {
+  double* blk = smem;                     // PB x (PB+1)
+  double* xv = smem + PB * (PB + 1);      // f: v/x of the FS block, then x_CB
   const int f = sa.ff[F], k = sa.fk[F], start = sa.fstart[F];
   const T* L = pool + sa.pool_off[F];
   const int32_t* rows = sa.rows + sa.rows_off[F];
-  double* xcb = v + k;
-  for (int c = threadIdx.x; c < f - k; c += blockDim.x) xcb[c] = x[rows[k + c]];
-  __syncthreads();
-  // v_t = w_t - L21(:, t)^T x_CB : one wave per column
+  const int32_t* type = sa.piv_type + start;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int t = wave; t < k; t += nw) {
-    const T* col = L + (int64_t)t * f + k;
-    double s = 0.0;
-    for (int c = lane; c < f - k; c += 64) s += (double)col[c] * xcb[c];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) v[t] = sa.fwd[start + t] - s;
+  for (int c = threadIdx.x; c < f - k; c += blockDim.x) xv[k + c] = x[rows[k + c]];
+  for (int t = threadIdx.x; t < k; t += blockDim.x) xv[t] = sa.fwd[start + t];
+  // panels from the bottom: v_panel -= L(below, panel)^T x_below, then the
+  // transposed unit-triangular solve of the diagonal block
+  int p1 = k;
+  while (p1 > 0) {
+    int p0 = max(0, p1 - PB);
+    if (p0 > 0 && type[p0] == 3) ++p0;   // keep 2x2 pivot blocks whole
+    const int pw = p1 - p0;
+    __syncthreads();
+    // each wave takes 16 panel columns at once (independent loads), lanes
+    // over the rows below the panel
+    for (int t0 = wave * 16; t0 < pw; t0 += nw * 16) {
+      double acc[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+      for (int r = p1 + lane; r < f; r += 64) {
+        const double xr = xv[r];
+        const T* lr = L + (int64_t)(p0 + t0) * f + r;
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (t0 + u < pw) acc[u] += (double)lr[(int64_t)u * f] * xr;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        double s = acc[u];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0 && t0 + u < pw) xv[p0 + t0 + u] -= s;
+      }
+    }
+    load_diag_block(L, f, p0, pw, type, blk);
+    __syncthreads();
+    if (wave == 0) {
+      double vl = lane < pw ? xv[p0 + lane] : 0.0;
+      for (int j = pw - 1; j >= 0; --j) {
+        const double xj = __shfl(vl, j);
+        if (lane < j) vl -= blk[j * (PB + 1) + lane] * xj;
+      }
+      if (lane < pw) xv[p0 + lane] = vl;
+    }
+    p1 = p0;
   }
   __syncthreads();
-  // L11^T x' = v, last row first; a 2x2 pivot block has no L coupling
-  for (int i = k - 1; i >= 0; --i) {
-    const double xi = v[i];
-    const int skip = sa.piv_type[start + i] == 3 ? i - 1 : -1;
-    for (int s2 = threadIdx.x; s2 < i; s2 += blockDim.x)
-      if (s2 != skip) v[s2] -= (double)L[(int64_t)s2 * f + i] * xi;
-    __syncthreads();
-  }
-  for (int t = threadIdx.x; t < k; t += blockDim.x) x[rows[sa.piv_perm[start + t]]] = v[t];
+  for (int t = threadIdx.x; t < k; t += blockDim.x) x[rows[sa.piv_perm[start + t]]] = xv[t];
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) bwd_kernel(SolveArgs sa, const T* pool,
+                                                const int32_t* fronts, double* x) {
+  extern __shared__ double smem[];
+  bwd_front<T>(sa, pool, fronts[blockIdx.x], x, smem);
 }
 
 SolveArgs solve_args(riga_problem* pr) {
@@ -145,19 +221,32 @@ SolveArgs solve_args(riga_problem* pr) {
 }
 
 template <class T>
+void set_solve_attrs() {
+  static bool done = false;
+  if (done) return;
+  HIPCHECK(hipFuncSetAttribute((const void*)fwd_kernel<T>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 159 * 1024));
+  HIPCHECK(hipFuncSetAttribute((const void*)bwd_kernel<T>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 159 * 1024));
+  done = true;
+}
+
+// Level-by-level sweeps: one launch per tree level and direction.
+template <class T>
 void solve_levels(riga_problem* pr, const T* pool, const double* b, double* x, hipStream_t s) {
   SolveArgs sa = solve_args(pr);
   const int H = (int)pr->levels.size();
   for (int h = 0; h < H; ++h) {
     const LevelDev& L = pr->levels[h];
     if (L.n == 0) continue;
-    fwd_kernel<T><<<L.n, 256, (size_t)(L.max_f + L.max_k) * sizeof(double), s>>>(sa, pool,
-                                                                                 L.fronts.p, b);
+    fwd_kernel<T><<<L.n, 256, (size_t)(PB * (PB + 1) + L.max_f + L.max_k) * sizeof(double), s>>>(
+        sa, pool, L.fronts.p, b);
   }
   for (int h = H - 1; h >= 0; --h) {
     const LevelDev& L = pr->levels[h];
     if (L.n == 0) continue;
-    bwd_kernel<T><<<L.n, 256, (size_t)L.max_f * sizeof(double), s>>>(sa, pool, L.fronts.p, x);
+    bwd_kernel<T><<<L.n, 256, (size_t)(PB * (PB + 1) + L.max_f) * sizeof(double), s>>>(
+        sa, pool, L.fronts.p, x);
   }
   HIPCHECK(hipGetLastError());
 }
@@ -166,10 +255,13 @@ void solve_levels(riga_problem* pr, const T* pool, const double* b, double* x, h
 
 void solve_fb(riga_problem* pr, const double* b, double* x, hipStream_t s) {
   if (!pr->factored) throw Error(RIGA_EINVAL, "solve before factorisation");
-  if (pr->fact_precision == RIGA_MIXED)
+  if (pr->fact_precision == RIGA_MIXED) {
+    set_solve_attrs<float>();
     solve_levels<float>(pr, pr->pool32.p, b, x, s);
-  else
+  } else {
+    set_solve_attrs<double>();
     solve_levels<double>(pr, pr->pool64.p, b, x, s);
+  }
 }
 
 }  // namespace riga

@@ -165,13 +165,15 @@ void launch_dot(const double* a, const double* b, int64_t n, double* partial, do
                 hipStream_t s);
 void launch_scale_cols(double* U, int64_t n, int m, const double* scale, hipStream_t s);
 
-// Projected (tridiagonal) eigensolve.  T has diagonal alpha[0..m) and
-// off-diagonal beta[1..m) (beta[j] couples j-1 and j).  theta[m]: all
-// eigenvalues ascending; sel_out[nvec]: indices (ascending) of the nvec
-// eigenvalues of largest |theta|; S[m x nvec]: their unit eigenvectors;
-// work: 6 m nvec doubles.
-void launch_tridiag_eig(const double* alpha, const double* beta, int m, double* theta,
-                        double* S, int nvec, int32_t* sel_out, double* work, hipStream_t s);
+// Projected (tridiagonal) eigenproblem of T_m: diagonal alpha[0..m),
+// off-diagonal beta[1..m) (beta[j] couples j-1 and j), residual beta[m].
+// ritz_check: theta[m] all eigenvalues ascending, est[m] Ritz estimates
+// |beta[m] s_m| (work: 3 m (m+63) doubles).  ritz_vectors: unit eigenvectors S[m x nsel] of the
+// eigenvalues theta[sel[q]] (sel ascending); work: 6 m nsel doubles.
+void launch_ritz_check(const double* alpha, const double* beta, int m, double* theta, double* est,
+                       double* work, hipStream_t s);
+void launch_ritz_vectors(const double* alpha, const double* beta, int m, const double* theta,
+                         const int32_t* sel, int nsel, double* S, double* work, hipStream_t s);
 
 void launch_eig_grad(const riga_problem* pr, int k, const double* U, const double* lam_w_dev,
                      const double* w_dev, double* gk, double* gr, hipStream_t s);

@@ -52,19 +52,18 @@ void dfree(void* p, hipStream_t s) {
   (void)hipFree(p);
 }
 
-void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
-  Analysis& an = pr->an;
-  hipStream_t s = (hipStream_t)desc->stream;
-  pr->stream = s;
-  HIPCHECK(hipGetDevice(&pr->device));
-  const int64_t N = an.N, nnz = an.row_ptr[N];
-  pr->row_ptr.upload(an.row_ptr, s);
-  pr->col_idx.upload(an.col_idx, s);
-  // coefficients (copied); validated positive on the host when host-resident
+// Copies the per-element coefficients (host values are checked positive)
+// and assembles K and M on the device.
+void load_and_assemble(riga_problem* pr, const double* kappa, const double* rho, int on_device,
+                       hipStream_t s) {
+  const Analysis& an = pr->an;
   auto load_coef = [&](const double* src, DBuf<double>& dst, const char* name) {
-    if (!src) return;
-    dst.alloc(an.n_elem, s);
-    if (desc->coeffs_on_device) {
+    if (!src) {
+      dst.reset();
+      return;
+    }
+    if (dst.n != (size_t)an.n_elem) dst.alloc(an.n_elem, s);
+    if (on_device) {
       HIPCHECK(hipMemcpyAsync(dst.p, src, an.n_elem * sizeof(double), hipMemcpyDeviceToDevice, s));
     } else {
       for (int64_t e = 0; e < an.n_elem; ++e)
@@ -73,13 +72,25 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
       HIPCHECK(hipMemcpyAsync(dst.p, src, an.n_elem * sizeof(double), hipMemcpyHostToDevice, s));
     }
   };
-  load_coef(desc->kappa, pr->kappa, "kappa");
-  load_coef(desc->rho, pr->rho, "rho");
+  load_coef(kappa, pr->kappa, "kappa");
+  load_coef(rho, pr->rho, "rho");
+  launch_assemble(pr);
+  compute_norms(pr);
+  pr->factored = false;
+}
+
+void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
+  Analysis& an = pr->an;
+  hipStream_t s = (hipStream_t)desc->stream;
+  pr->stream = s;
+  HIPCHECK(hipGetDevice(&pr->device));
+  const int64_t N = an.N, nnz = an.row_ptr[N];
+  pr->row_ptr.upload(an.row_ptr, s);
+  pr->col_idx.upload(an.col_idx, s);
   pr->kv.alloc(nnz, s);
   pr->mv.alloc(nnz, s);
   launch_basis_tables(pr);
-  launch_assemble(pr);
-  compute_norms(pr);
+  load_and_assemble(pr, desc->kappa, desc->rho, desc->coeffs_on_device, s);
   const double avg = (double)nnz / (double)N;
   int g = 4;
   while (g < 64 && g * 3 < avg) g *= 2;

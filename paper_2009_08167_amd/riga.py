@@ -19,7 +19,8 @@ RIGA_ENOCONV, RIGA_ESINGULAR, RIGA_EDEGENERATE, RIGA_EUNSUPPORTED = -4, -5, -6, 
 RIGA_FP64, RIGA_MIXED = 0, 1
 RIGA_MAT_K, RIGA_MAT_M, RIGA_MAT_A = 0, 1, 2
 
-EXPORTED = ["riga_set_allocator", "riga_analyze", "riga_assemble", "riga_problem_info",
+EXPORTED = ["riga_set_allocator", "riga_analyze", "riga_assemble", "riga_update_coefficients",
+            "riga_problem_info",
             "riga_tree_export", "riga_get_matrices", "riga_spmv", "riga_factor", "riga_solve",
             "riga_eigs", "riga_eig_grad", "riga_destroy", "riga_status_string",
             "riga_last_error"]
@@ -78,6 +79,7 @@ def lib():
         L.riga_analyze.argtypes = [C.POINTER(MeshDesc), C.POINTER(P)]
         L.riga_assemble.argtypes = [C.POINTER(MeshDesc), C.POINTER(P)]
         L.riga_problem_info.argtypes = [P, C.POINTER(ProblemInfo)]
+        L.riga_update_coefficients.argtypes = [P, P, P, C.c_int32, P]
         L.riga_tree_export.argtypes = [P] + [P] * 6
         L.riga_get_matrices.argtypes = [P, P, P, P, P]
         L.riga_spmv.argtypes = [P, C.c_int32, P, P, P]
@@ -90,7 +92,8 @@ def lib():
         L.riga_destroy.restype = None
         L.riga_status_string.restype = C.c_char_p
         L.riga_last_error.restype = C.c_char_p
-        for name in ["riga_analyze", "riga_assemble", "riga_problem_info", "riga_tree_export",
+        for name in ["riga_analyze", "riga_assemble", "riga_update_coefficients",
+                     "riga_problem_info", "riga_tree_export",
                      "riga_get_matrices", "riga_spmv", "riga_factor", "riga_solve", "riga_eigs",
                      "riga_eig_grad", "riga_set_allocator"]:
             getattr(L, name).restype = C.c_int
@@ -136,6 +139,26 @@ class Problem:
 
     def close(self):
         self.__del__()
+
+    def update_coefficients(self, kappa, rho, stream=None):
+        """Re-assemble K, M on the device for new per-element coefficients
+        (torch device tensors or host arrays; None -> 1)."""
+        keep = []
+        on_dev = 0
+        ptrs = []
+        for v in (kappa, rho):
+            if v is None:
+                ptrs.append(None)
+            elif hasattr(v, "is_cuda") and v.is_cuda:
+                v = v.contiguous().double()
+                keep.append(v)
+                on_dev = 1
+                ptrs.append(C.c_void_p(v.data_ptr()))
+            else:
+                a = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
+                keep.append(a)
+                ptrs.append(C.c_void_p(a.ctypes.data))
+        _check(lib().riga_update_coefficients(self._h, ptrs[0], ptrs[1], on_dev, _stream(stream)))
 
     def tree(self):
         """Symbolic analysis as numpy arrays."""

@@ -66,7 +66,9 @@ def test_spmv_matches_oracle():
 
 
 FACT_CASES = [workloads.small(2, 16, 2, 0, 10, 0.3), workloads.small(2, 24, 3, 8, 10, 0.5),
-              workloads.small(3, 6, 2, 3, 10, 0.3), workloads.small(2, 40, 3, 8, 10, 0.3)]
+              workloads.small(3, 6, 2, 3, 10, 0.3), workloads.small(2, 40, 3, 8, 10, 0.3),
+              workloads.small(3, 10, 2, 0, 10, 0.3), workloads.small(2, 64, 3, 0, 10, 0.3),
+              workloads.small(2, 96, 2, 16, 10, 0.3)]
 
 
 @pytest.mark.parametrize("w", FACT_CASES, ids=lambda w: w.name)
