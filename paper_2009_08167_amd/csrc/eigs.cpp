@@ -433,6 +433,7 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
   sv.seed = o->seed;
   sv.precision = o->precision;
   sv.max_ir = 2;
+  if (const char* v = std::getenv("RIGA_MAX_IR")) sv.max_ir = std::max(0, std::atoi(v));
   sv.per_shift = o->per_shift > 0 ? o->per_shift : 48;
   sv.max_restarts = o->max_restarts > 0 ? o->max_restarts : 10;
   int mb = o->max_basis > 0 ? o->max_basis : std::max(128, 3 * sv.per_shift);

@@ -68,12 +68,24 @@ __global__ void __launch_bounds__(256) gemv_t_kernel(const double* __restrict__ 
   __shared__ double xs[GEMV_RB];
   for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) xs[r - r0] = x[r];
   __syncthreads();
+  // each wave: 4 columns, 16 rows per lane, all loads issued before use
+  constexpr int RPL = GEMV_RB / 64;
   for (int jj = wave; jj < GEMV_CG; jj += 4) {
     const int j = blockIdx.y * GEMV_CG + jj;
     if (j >= m) break;
     const double* c = B + (int64_t)j * n;
+    double v[RPL];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      const int64_t r = r0 + lane + 64 * u;
+      v[u] = r < r1 ? c[r] : 0.0;
+    }
     double s = 0.0;
-    for (int64_t r = r0 + lane; r < r1; r += 64) s += c[r] * xs[r - r0];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      const int64_t r = r0 + lane + 64 * u;
+      if (r < r1) s += v[u] * xs[r - r0];
+    }
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if (lane == 0) partial[(int64_t)rb * m + j] = s;
   }
@@ -101,8 +113,17 @@ __global__ void __launch_bounds__(256) gemv_n_sub_kernel(const double* __restric
   __syncthreads();
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
+  // 16 column loads in flight per thread
   double s = 0.0;
-  for (int j = 0; j < m; ++j) s += B[(int64_t)j * n + r] * cs[j];
+  int j = 0;
+  for (; j + 16 <= m; j += 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = B[(int64_t)(j + u) * n + r];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s += v[u] * cs[j + u];
+  }
+  for (; j < m; ++j) s += B[(int64_t)j * n + r] * cs[j];
   x[r] -= s;
 }
 

@@ -66,6 +66,12 @@ struct DBuf {
 constexpr int LDS_FRONT_MAX_F64 = 128;
 constexpr int LDS_FRONT_MAX_F32 = 176;
 
+// Packed per-front record read once by the solve kernels.
+struct FrontDesc {
+  int32_t f, k, start, pad;
+  int64_t pool_off, rows_off, cb_off, gmap_off;
+};
+
 struct LevelDev {
   int n = 0;                 // fronts at this height
   int64_t cols = 0;          // sum of front orders (assembly grid)
@@ -119,6 +125,9 @@ struct riga_problem {
 
   // solve workspace
   riga::DBuf<double> cbvec, fwd;
+  riga::DBuf<riga::FrontDesc> d_desc;
+  riga::DBuf<int32_t> d_gmap;               // [sum f * gstride] children's update indices
+  int gstride = 1;
   riga::DBuf<double> ir_r, ir_x, ir_d;      // iterative refinement vectors
 
   riga_stats stats{};

@@ -111,6 +111,36 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
   pr->d_amap_ptr.upload(an.amap_ptr, s);
   pr->d_amap_row.upload(an.amap_row, s);
   pr->d_amap_val.upload(an.amap_val, s);
+  // solve descriptors and the flattened gather map: for each front position,
+  // the absolute index in the update vectors of each child's contribution
+  {
+    int gs = 1;
+    for (int F = 0; F < an.n_fronts; ++F) gs = std::max(gs, an.child_ptr[F + 1] - an.child_ptr[F]);
+    if (gs > 4) throw Error(RIGA_EUNSUPPORTED, "a separator-tree node has more than 4 children");
+    pr->gstride = gs;
+    std::vector<FrontDesc> desc(an.n_fronts);
+    std::vector<int32_t> gmap((size_t)an.f_rows_off[an.n_fronts] * gs, -1);
+    for (int F = 0; F < an.n_fronts; ++F) {
+      FrontDesc& d = desc[F];
+      d.f = an.f_f[F];
+      d.k = an.f_k[F];
+      d.start = an.f_start[F];
+      d.pad = 0;
+      d.pool_off = an.f_pool_off[F];
+      d.rows_off = an.f_rows_off[F];
+      d.cb_off = an.f_cb_off[F];
+      d.gmap_off = an.f_rows_off[F] * gs;
+      for (int ci = an.child_ptr[F]; ci < an.child_ptr[F + 1]; ++ci) {
+        const int slot = ci - an.child_ptr[F], C = an.child_list[ci];
+        for (int i = 0; i < d.f; ++i) {
+          const int c = an.inv[an.inv_off[ci] + i];
+          if (c >= 0) gmap[d.gmap_off + (int64_t)i * gs + slot] = (int32_t)(an.f_cb_off[C] + c);
+        }
+      }
+    }
+    pr->d_desc.upload(desc, s);
+    pr->d_gmap.upload(gmap, s);
+  }
   pr->levels.clear();
   pr->levels.resize(an.height);
   for (int h = 0; h < an.height; ++h) {

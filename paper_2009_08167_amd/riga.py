@@ -133,9 +133,12 @@ class Problem:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().riga_destroy(h)
-            self._h = None
+        if h and _lib is not None:
+            try:
+                _lib.riga_destroy(h)
+            except Exception:
+                pass
+        self._h = None
 
     def close(self):
         self.__del__()

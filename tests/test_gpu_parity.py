@@ -193,3 +193,51 @@ def test_gradient_matches_oracle():
     # Euler identities (degree-1 homogeneity in kappa, -1 in rho)
     assert abs(kappa @ gk - wts @ lam) <= 1e-10 * (wts @ lam)
     assert abs(rho @ gr + wts @ lam) <= 1e-10 * (wts @ lam)
+
+
+MIXED_CASES = [workloads.small(2, 24, 3, 8, 10, 0.5), workloads.small(3, 10, 2, 5, 10, 0.0),
+               workloads.small(2, 64, 2, 16, 10, 0.3)]
+
+
+@pytest.mark.parametrize("w", MIXED_CASES, ids=lambda w: w.name)
+def test_mixed_factor_inertia_and_refined_solve(w):
+    """FP32 fronts: same inertia as FP64; FP64 iterative refinement brings
+    the solve to backward error <= 1e-13 relative residual."""
+    riga = _riga()
+    _say("mixed factor", w.name)
+    kappa, rho = w.coefficients()
+    pr = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho, leaf_dofs=32)
+    Ko, Mo = assembly.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal(pr.n_dof)
+    bd = torch.tensor(b, dtype=torch.float64, device="cuda")
+    for sigma in (0.0, 350.0, 1200.0):
+        n64, _ = pr.factor(sigma, riga.RIGA_FP64)
+        n32, _ = pr.factor(sigma, riga.RIGA_MIXED)
+        assert n32 == n64, (sigma, n32, n64)
+        x0 = pr.solve(bd, max_ir=0).cpu().numpy()
+        x = pr.solve(bd, max_ir=30).cpu().numpy()
+        A = (Ko - sigma * Mo).tocsr()
+        r0 = np.linalg.norm(b - A @ x0) / np.linalg.norm(b)
+        for it in (1, 2, 3, 4):
+            xi = pr.solve(bd, max_ir=it).cpu().numpy()
+            _say("  ir", it, np.linalg.norm(b - A @ xi) / np.linalg.norm(b))
+        r = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+        _say("sigma", sigma, "fp32 solve residual", r0, "refined", r)
+        assert r0 < 1e-2
+        assert r <= 1e-12, r
+
+
+@pytest.mark.parametrize("w", [workloads.small(2, 24, 3, 8, 30, 0.5),
+                               workloads.small(3, 8, 2, 4, 24, 0.0)], ids=lambda w: w.name)
+def test_mixed_eigs_match_fp64_bar(w):
+    riga = _riga()
+    _say("mixed eigs", w.name)
+    kappa, rho = w.coefficients()
+    pr = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho, leaf_dofs=32)
+    lam, U, res, st = pr.eigs(w.nev, precision=riga.RIGA_MIXED, per_shift=16)
+    _say("stats", st)
+    assert st["n_ir"] > 0
+    Ko, Mo = assembly.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
+    lr, Ur = eigen.dense_eigh(Ko, Mo)
+    _check_pairs(Ko, Mo, lr, Ur, lam, U.cpu().numpy(), res, w.nev)
