@@ -26,7 +26,10 @@
  *    memory.  The caller owns every buffer it passes; the library copies
  *    what it keeps.  Work is ordered on the hipStream_t passed as `stream`
  *    (NULL = the null stream); calls synchronise that stream before they
- *    return host results.
+ *    return host results.  The stream in riga_mesh_desc is the problem's
+ *    own: buffers the problem keeps are allocated on it, riga_destroy
+ *    synchronises it, and it must stay valid until then.  A stream passed to
+ *    any other call is used by that call only and is not remembered.
  *  - A riga_problem is owned by the caller until riga_destroy().  It must not
  *    be used from two threads at once.
  */
@@ -199,6 +202,20 @@ riga_status riga_solve(riga_problem* pr, const double* b_dev, double* x_dev, int
 riga_status riga_eigs(riga_problem* pr, const riga_eigs_opts* opts, int32_t* n_found,
                       double* evals_host, double* evecs_dev, double* resid_host,
                       riga_stats* stats);
+
+/* riga_eigs_batched: riga_eigs on `count` independent assembled problems at
+ * once (instances of uneven size run concurrently on the device: a pool of
+ * `workers` host threads, 0 -> 8, each with its own HIP stream; opts->stream
+ * is ignored and the call returns when all instances are done).  Per
+ * instance i: n_found[i], evals_host[i] ([nev] host), evecs_dev[i] ([n_dof_i
+ * * nev] device, or NULL; evecs_dev itself may be NULL), resid_host[i] (or
+ * NULL), stats[i] (stats may be NULL).  Each problem must appear once.
+ * Returns RIGA_OK, or the first error (RIGA_ENOCONV only if no other error)
+ * with riga_last_error() naming the instance. */
+riga_status riga_eigs_batched(riga_problem* const* probs, int32_t count, const riga_eigs_opts* opts,
+                              int32_t workers, int32_t* n_found, double* const* evals_host,
+                              double* const* evecs_dev, double* const* resid_host,
+                              riga_stats* stats);
 
 /* riga_eig_grad: gradient of L = sum_i w_i lambda_i with respect to the
  * per-element coefficients, for M-normalised simple eigenpairs (not in the

@@ -15,6 +15,10 @@ void load_and_assemble(riga_problem* pr, const double* kappa, const double* rho,
                        hipStream_t s);
 riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found, double* evals,
                      double* evecs, double* resid, riga_stats* stats_out);
+riga_status run_eigs_batched(riga_problem* const* probs, int count, const riga_eigs_opts* o,
+                             int32_t* n_found, double* const* evals, double* const* evecs,
+                             double* const* resid, riga_stats* stats, int workers,
+                             std::string* first_error);
 }  // namespace riga
 
 namespace {
@@ -91,7 +95,7 @@ riga_status riga_update_coefficients(riga_problem* pr, const double* kappa, cons
                                      int32_t on_device, void* stream) {
   return guarded([&]() -> riga_status {
     if (!need_device(pr)) return fail(RIGA_EINVAL, "problem has no device data");
-    pr->stream = (hipStream_t)stream;
+    riga::StreamBind bind(pr, (hipStream_t)stream);
     riga::load_and_assemble(pr, kappa, rho, on_device, pr->stream);
     return RIGA_OK;
   });
@@ -154,7 +158,7 @@ riga_status riga_spmv(riga_problem* pr, int32_t which, const double* x, double* 
     else if (which == RIGA_MAT_M) vals = pr->mv.p;
     else if (which == RIGA_MAT_A) {
       if (!pr->factored) return fail(RIGA_EINVAL, "no shift factorised yet");
-      if (!pr->av.p) pr->av.alloc(pr->kv.n, s);
+      if (!pr->av.p) pr->av.alloc(pr->kv.n, pr->home);
       riga::launch_axpby_vals(pr->kv.p, pr->mv.p, pr->sigma, pr->av.p, (int64_t)pr->kv.n, s);
       vals = pr->av.p;
     } else return fail(RIGA_EINVAL, "which must be RIGA_MAT_K, _M or _A");
@@ -172,7 +176,7 @@ riga_status riga_factor(riga_problem* pr, double sigma, int32_t precision, int64
     if (precision != RIGA_FP64 && precision != RIGA_MIXED) return fail(RIGA_EINVAL, "bad precision");
     riga::factor_numeric(pr, sigma, precision);
     if (precision == RIGA_MIXED) {
-      if (!pr->av.p) pr->av.alloc(pr->kv.n, pr->stream);
+      if (!pr->av.p) pr->av.alloc(pr->kv.n, pr->home);
       riga::launch_axpby_vals(pr->kv.p, pr->mv.p, sigma, pr->av.p, (int64_t)pr->kv.n, pr->stream);
       HIPCHECK(hipStreamSynchronize(pr->stream));
     }
@@ -199,8 +203,8 @@ riga_status riga_solve(riga_problem* pr, const double* b, double* x, int32_t max
       // ||r|| <= 1e-13 ||b|| or max_ir corrections
       const int64_t N = pr->an.N;
       if (pr->ir_r.n < (size_t)N) {
-        pr->ir_r.alloc(N, s);
-        pr->ir_d.alloc(N, s);
+        pr->ir_r.alloc(N, pr->home);
+        pr->ir_d.alloc(N, pr->home);
       }
       riga::DBuf<double> part, nr;
       part.alloc(256, s);
@@ -241,6 +245,27 @@ riga_status riga_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_foun
   });
 }
 
+riga_status riga_eigs_batched(riga_problem* const* probs, int32_t count, const riga_eigs_opts* o,
+                              int32_t workers, int32_t* n_found, double* const* evals,
+                              double* const* evecs, double* const* resid, riga_stats* stats) {
+  return guarded([&]() -> riga_status {
+    if (!probs || count < 1 || !o || !n_found || !evals) return fail(RIGA_EINVAL, "bad arguments");
+    for (int i = 0; i < count; ++i) {
+      if (!need_device(probs[i])) return fail(RIGA_EINVAL, "instance without device data");
+      if (!evals[i]) return fail(RIGA_EINVAL, "evals_host[i] required");
+      if (o->nev > probs[i]->an.N) return fail(RIGA_EINVAL, "nev exceeds an instance's DOFs");
+      for (int j = 0; j < i; ++j)
+        if (probs[j] == probs[i]) return fail(RIGA_EINVAL, "an instance appears twice");
+    }
+    if (o->nev < 1 || !std::isfinite(o->lo) || !(o->hi > o->lo)) return fail(RIGA_EINVAL, "bad options");
+    std::string err;
+    riga_status st = riga::run_eigs_batched(probs, count, o, n_found, evals, evecs, resid, stats,
+                                            workers, &err);
+    if (st != RIGA_OK) g_err = err;
+    return st;
+  });
+}
+
 riga_status riga_eig_grad(riga_problem* pr, int32_t k, const double* evals, const double* evecs,
                           const double* w, double* dkappa, double* drho, void* stream) {
   return guarded([&]() -> riga_status {
@@ -266,7 +291,7 @@ riga_status riga_eig_grad(riga_problem* pr, int32_t k, const double* evals, cons
 void riga_destroy(riga_problem* pr) {
   if (!pr) return;
   try {
-    if (pr->has_device) (void)hipStreamSynchronize(pr->stream);
+    if (pr->has_device) (void)hipStreamSynchronize(pr->home);
   } catch (...) {
   }
   delete pr;

@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -116,7 +118,7 @@ struct Solver {
     auto a = clk::now();
     factor_numeric(pr, sigma, precision);
     if (precision == RIGA_MIXED) {
-      if (!pr->av.p) pr->av.alloc(pr->kv.n, s);
+      if (!pr->av.p) pr->av.alloc(pr->kv.n, pr->home);
       launch_axpby_vals(pr->kv.p, pr->mv.p, sigma, pr->av.p, (int64_t)pr->kv.n, s);
     }
     st.t_fact += secs(a, clk::now());
@@ -420,8 +422,8 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
                      double* evecs, double* resid, riga_stats* stats_out) {
   Solver sv;
   sv.pr = pr;
-  sv.s = o->stream ? (hipStream_t)o->stream : pr->stream;
-  pr->stream = sv.s;
+  sv.s = o->stream ? (hipStream_t)o->stream : pr->home;
+  StreamBind bind(pr, sv.s);
   sv.N = pr->an.N;
   sv.t0 = clk::now();
   int nev = o->nev;
@@ -519,6 +521,71 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
   if (stats_out) *stats_out = sv.st;
   pr->stats = sv.st;
   return status;
+}
+
+// Many independent problems at once: a pool of host threads, each with its
+// own HIP stream, takes instances in order and runs the full solve on its
+// stream, so the kernels of different instances overlap on the device.
+riga_status run_eigs_batched(riga_problem* const* probs, int count, const riga_eigs_opts* o,
+                             int32_t* n_found, double* const* evals, double* const* evecs,
+                             double* const* resid, riga_stats* stats, int workers,
+                             std::string* first_error) {
+  if (workers <= 0) workers = 8;
+  workers = std::max(1, std::min(workers, count));
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  std::atomic<int> next(0);
+  std::vector<riga_status> status(count, RIGA_OK);
+  std::vector<std::string> errs(count);
+  std::vector<std::string> worker_err(workers);
+  for (int i = 0; i < count; ++i) n_found[i] = 0;
+  std::vector<std::thread> pool;
+  for (int w = 0; w < workers; ++w) {
+    pool.emplace_back([&, w] {
+      hipStream_t st = nullptr;
+      try {
+        HIPCHECK(hipSetDevice(dev));
+        (void)hipGetLastError();
+        HIPCHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        set_kernel_attributes();
+      } catch (const std::exception& e) {
+        worker_err[w] = e.what();
+        return;
+      }
+      for (int i = next++; i < count; i = next++) {
+        riga_eigs_opts oi = *o;
+        oi.stream = st;
+        try {
+          status[i] = run_eigs(probs[i], &oi, &n_found[i], evals[i], evecs ? evecs[i] : nullptr,
+                               resid ? resid[i] : nullptr, stats ? &stats[i] : nullptr);
+        } catch (const Error& e) {
+          status[i] = e.code;
+          errs[i] = e.what();
+        } catch (const std::exception& e) {
+          status[i] = RIGA_EINVAL;
+          errs[i] = e.what();
+        }
+      }
+      (void)hipStreamDestroy(st);
+    });
+  }
+  for (auto& t : pool) t.join();
+  riga_status worst = RIGA_OK;
+  int done = next.load() >= count ? count : next.load();
+  for (int w = 0; w < workers; ++w)
+    if (!worker_err[w].empty()) {
+      *first_error = "worker set-up: " + worker_err[w];
+      if (done < count) return RIGA_EDEVICE;
+    }
+  for (int i = 0; i < count; ++i) {
+    if (status[i] == RIGA_OK) continue;
+    if (worst == RIGA_OK || (worst == RIGA_ENOCONV && status[i] != RIGA_ENOCONV)) {
+      worst = status[i];
+      *first_error = "instance " + std::to_string(i) + ": " +
+                     (errs[i].empty() ? std::string("not converged") : errs[i]);
+    }
+  }
+  return worst;
 }
 
 }  // namespace riga

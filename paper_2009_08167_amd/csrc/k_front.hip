@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "problem.h"
 
@@ -555,16 +556,8 @@ void factor_levels(riga_problem* pr, T* pool, double sigma) {
   DBuf<int> perm_scratch;
   const int64_t stride = (int64_t)max_k_big + 1;
   if (max_big > 0) perm_scratch.alloc((size_t)max_big * stride, s);
-  static bool attr_set = false;
-  if (!attr_set) {
-    HIPCHECK(hipFuncSetAttribute((const void*)front_factor_blocked_kernel<double>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 PANEL_LDS * (int)sizeof(double)));
-    HIPCHECK(hipFuncSetAttribute((const void*)front_factor_blocked_kernel<float>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 PANEL_LDS * (int)sizeof(double)));
-    attr_set = true;
-  }
+  static std::once_flag attr_once;
+  std::call_once(attr_once, [] { set_kernel_attributes(); });
   for (size_t h = 0; h < pr->levels.size(); ++h) {
     LevelDev& L = pr->levels[h];
     if (L.n == 0) continue;
@@ -587,14 +580,23 @@ void factor_levels(riga_problem* pr, T* pool, double sigma) {
 
 }  // namespace
 
+void set_front_attributes() {
+  HIPCHECK(hipFuncSetAttribute((const void*)front_factor_blocked_kernel<double>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               PANEL_LDS * (int)sizeof(double)));
+  HIPCHECK(hipFuncSetAttribute((const void*)front_factor_blocked_kernel<float>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               PANEL_LDS * (int)sizeof(double)));
+}
+
 void factor_numeric(riga_problem* pr, double sigma, int precision) {
   const Analysis& an = pr->an;
   hipStream_t s = pr->stream;
   if (precision == RIGA_MIXED) {
-    if (pr->pool32.n < (size_t)an.pool_size) pr->pool32.alloc(an.pool_size, s);
+    if (pr->pool32.n < (size_t)an.pool_size) pr->pool32.alloc(an.pool_size, pr->home);
     factor_levels<float, LDS_FRONT_MAX_F32>(pr, pr->pool32.p, sigma);
   } else {
-    if (pr->pool64.n < (size_t)an.pool_size) pr->pool64.alloc(an.pool_size, s);
+    if (pr->pool64.n < (size_t)an.pool_size) pr->pool64.alloc(an.pool_size, pr->home);
     factor_levels<double, LDS_FRONT_MAX_F64>(pr, pr->pool64.p, sigma);
   }
   std::vector<int32_t> st((size_t)an.n_fronts * 4);

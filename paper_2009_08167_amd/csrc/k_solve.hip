@@ -13,6 +13,8 @@
 // of a front are summed in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "problem.h"
 
 namespace riga {
@@ -307,14 +309,17 @@ SolveArgs solve_args(riga_problem* pr) {
 constexpr int SOLVE_BIG_F = 256;
 
 template <class T>
-void set_solve_attrs() {
-  static bool done = false;
-  if (done) return;
+void apply_solve_attrs() {
   const void* ks[] = {(const void*)fwd_kernel<T, 256>, (const void*)fwd_kernel<T, 1024>,
                       (const void*)bwd_kernel<T, 256>, (const void*)bwd_kernel<T, 1024>};
   for (const void* k : ks)
     HIPCHECK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 159 * 1024));
-  done = true;
+}
+
+template <class T>
+void set_solve_attrs() {
+  static std::once_flag once;
+  std::call_once(once, [] { set_kernel_attributes(); });
 }
 
 // Level-by-level sweeps: per tree level and direction one launch for the
@@ -354,6 +359,11 @@ void solve_levels(riga_problem* pr, const T* pool, const double* b, double* x, h
 }
 
 }  // namespace
+
+void set_solve_attributes() {
+  apply_solve_attrs<double>();
+  apply_solve_attrs<float>();
+}
 
 void solve_fb(riga_problem* pr, const double* b, double* x, hipStream_t s) {
   if (!pr->factored) throw Error(RIGA_EINVAL, "solve before factorisation");

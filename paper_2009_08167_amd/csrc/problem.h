@@ -21,7 +21,9 @@ struct Error : std::runtime_error {
 };
 
 void hip_check(hipError_t e, const char* what);
-#define HIPCHECK(x) ::riga::hip_check((x), #x)
+#define RIGA_STR2(x) #x
+#define RIGA_STR(x) RIGA_STR2(x)
+#define HIPCHECK(x) ::riga::hip_check((x), __FILE__ ":" RIGA_STR(__LINE__) ": " #x)
 
 // Device allocation through the optional allocator hook.
 void* dmalloc(size_t bytes, hipStream_t s);
@@ -89,6 +91,10 @@ struct LevelDev {
 struct riga_problem {
   riga::Analysis an;
   bool has_device = false;
+  // `home` is the stream given at assembly and the one persistent buffers are
+  // allocated on; `stream` is the stream of the call in progress (equal to
+  // `home` between calls).
+  hipStream_t home = nullptr;
   hipStream_t stream = nullptr;
   int device = 0;
 
@@ -149,6 +155,20 @@ void launch_spmv(const riga_problem* pr, const double* vals, const double* x, do
 int spmv_blocks(const riga_problem* pr);
 
 void factor_numeric(riga_problem* pr, double sigma, int precision);
+// Raise the dynamic-LDS limit of the kernels that need more than 64 KB (for
+// the calling thread's device).
+// Binds a call's stream to the problem for the duration of the call only, so
+// no stream handle outlives the call that passed it.
+struct StreamBind {
+  riga_problem* pr;
+  hipStream_t prev;
+  StreamBind(riga_problem* p, hipStream_t s) : pr(p), prev(p->stream) { p->stream = s; }
+  ~StreamBind() { pr->stream = prev; }
+  StreamBind(const StreamBind&) = delete;
+  StreamBind& operator=(const StreamBind&) = delete;
+};
+
+void set_kernel_attributes();
 void solve_fb(riga_problem* pr, const double* b, double* x, hipStream_t s);
 
 // BLAS-like helpers on column-major N x m blocks (ld = N).

@@ -52,6 +52,14 @@ void dfree(void* p, hipStream_t s) {
   (void)hipFree(p);
 }
 
+void set_front_attributes();
+void set_solve_attributes();
+
+void set_kernel_attributes() {
+  set_front_attributes();
+  set_solve_attributes();
+}
+
 // Copies the per-element coefficients (host values are checked positive)
 // and assembles K and M on the device.
 void load_and_assemble(riga_problem* pr, const double* kappa, const double* rho, int on_device,
@@ -82,6 +90,7 @@ void load_and_assemble(riga_problem* pr, const double* kappa, const double* rho,
 void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
   Analysis& an = pr->an;
   hipStream_t s = (hipStream_t)desc->stream;
+  pr->home = s;
   pr->stream = s;
   HIPCHECK(hipGetDevice(&pr->device));
   const int64_t N = an.N, nnz = an.row_ptr[N];

@@ -22,7 +22,7 @@ RIGA_MAT_K, RIGA_MAT_M, RIGA_MAT_A = 0, 1, 2
 EXPORTED = ["riga_set_allocator", "riga_analyze", "riga_assemble", "riga_update_coefficients",
             "riga_problem_info",
             "riga_tree_export", "riga_get_matrices", "riga_spmv", "riga_factor", "riga_solve",
-            "riga_eigs", "riga_eig_grad", "riga_destroy", "riga_status_string",
+            "riga_eigs", "riga_eigs_batched", "riga_eig_grad", "riga_destroy", "riga_status_string",
             "riga_last_error"]
 
 
@@ -88,6 +88,8 @@ def lib():
         L.riga_eigs.argtypes = [P, C.POINTER(EigsOpts), C.POINTER(C.c_int32), P, P, P,
                                 C.POINTER(Stats)]
         L.riga_eig_grad.argtypes = [P, C.c_int32, P, P, P, P, P, P]
+        L.riga_eigs_batched.argtypes = [P, C.c_int32, C.POINTER(EigsOpts), C.c_int32,
+                                        C.POINTER(C.c_int32), P, P, P, P]
         L.riga_destroy.argtypes = [P]
         L.riga_destroy.restype = None
         L.riga_status_string.restype = C.c_char_p
@@ -95,7 +97,7 @@ def lib():
         for name in ["riga_analyze", "riga_assemble", "riga_update_coefficients",
                      "riga_problem_info", "riga_tree_export",
                      "riga_get_matrices", "riga_spmv", "riga_factor", "riga_solve", "riga_eigs",
-                     "riga_eig_grad", "riga_set_allocator"]:
+                     "riga_eig_grad", "riga_set_allocator", "riga_eigs_batched"]:
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -309,6 +311,34 @@ def eigs(dim, ne, p, s, nev, kappa=None, rho=None, lo=0.0, hi=math.inf, precisio
          **kw):
     pr = assemble(dim, ne, p, s, kappa, rho)
     return pr.eigs(nev, lo=lo, hi=hi, precision=precision, **kw)
+
+
+def eigs_batched(problems, nev, lo=0.0, hi=math.inf, precision=RIGA_FP64, tol=1e-9, workers=0,
+                 per_shift=0, seed=0, vectors=True, allow_partial=False):
+    """nev lowest pairs of every problem in `problems` (assembled on the same
+    device), solved concurrently.  Returns a list of (lam, U, resid, stats)."""
+    import torch
+    n = len(problems)
+    o = EigsOpts(lo=lo, hi=hi, nev=nev, precision=precision, tol=tol, max_basis=0,
+                 max_restarts=0, per_shift=per_shift, seed=seed, stream=None)
+    handles = (C.c_void_p * n)(*[p._h for p in problems])
+    nf = (C.c_int32 * n)()
+    lams = [np.zeros(nev) for _ in range(n)]
+    ress = [np.zeros(nev) for _ in range(n)]
+    Us = [torch.zeros((nev, p.n_dof), dtype=torch.float64, device=p.device) if vectors else None
+          for p in problems]
+    ev = (C.c_void_p * n)(*[a.ctypes.data for a in lams])
+    rs = (C.c_void_p * n)(*[a.ctypes.data for a in ress])
+    uv = (C.c_void_p * n)(*[u.data_ptr() for u in Us]) if vectors else None
+    sts = (Stats * n)()
+    torch.cuda.synchronize()  # output buffers were filled on torch's stream
+    code = lib().riga_eigs_batched(handles, n, C.byref(o), workers, nf, ev, uv, rs, sts)
+    _check(code, allow=(RIGA_ENOCONV,) if allow_partial else ())
+    out = []
+    for i in range(n):
+        k = int(nf[i])
+        out.append((lams[i][:k], Us[i][:k].T if vectors else None, ress[i][:k], sts[i].as_dict()))
+    return out
 
 
 def _autograd():
