@@ -322,7 +322,8 @@ std::string analyze(int dim, const int ne_in[3], int p, int s, int nquad, int le
   A.f_rows_off.resize(nf + 1);
   A.f_pool_off.resize(nf + 1);
   A.f_cb_off.resize(nf + 1);
-  A.f_rows_off[0] = A.f_pool_off[0] = A.f_cb_off[0] = 0;
+  A.f_h_off.resize(nf + 1);
+  A.f_rows_off[0] = A.f_pool_off[0] = A.f_cb_off[0] = A.f_h_off[0] = 0;
   A.nnz_l = 0;
   A.flops_fact = 0.0;
   A.max_front = A.max_fs = 0;
@@ -332,6 +333,7 @@ std::string analyze(int dim, const int ne_in[3], int p, int s, int nquad, int le
     A.f_rows_off[f + 1] = A.f_rows_off[f] + fo;
     A.f_pool_off[f + 1] = A.f_pool_off[f] + (int64_t)fo * fo;
     A.f_cb_off[f + 1] = A.f_cb_off[f] + (fo - k);
+    A.f_h_off[f + 1] = A.f_h_off[f] + (int64_t)fo * k;
     A.max_front = std::max(A.max_front, fo);
     A.max_fs = std::max(A.max_fs, k);
     A.nnz_l += (int64_t)k * (k + 1) / 2 + (int64_t)k * (fo - k);
@@ -342,6 +344,7 @@ std::string analyze(int dim, const int ne_in[3], int p, int s, int nquad, int le
   }
   A.pool_size = A.f_pool_off[nf];
   A.cb_size = A.f_cb_off[nf];
+  A.h_size = A.f_h_off[nf];
   A.rows.resize(A.f_rows_off[nf]);
   for (int f = 0; f < nf; ++f) {
     int64_t o = A.f_rows_off[f];

@@ -59,7 +59,9 @@ struct Analysis {
   std::vector<int32_t> rows;          // front index lists, ORIGINAL DOF indices
   std::vector<int64_t> f_pool_off;   // offset of the dense f x f front in the pool
   std::vector<int64_t> f_cb_off;     // offset of the contribution vector (sum of f-k)
+  std::vector<int64_t> f_h_off;      // offset of the f x k partitioned inverse
   int64_t pool_size = 0;             // sum f^2
+  int64_t h_size = 0;                // sum f k
   int64_t cb_size = 0;               // sum (f-k)
   // Children, and for each (parent, child) pair the map from parent front
   // position to child contribution-block position (-1 if none).

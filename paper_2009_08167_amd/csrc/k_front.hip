@@ -542,7 +542,7 @@ FrontArgs front_args(riga_problem* pr) {
 }
 
 template <class T, int MAXF>
-void factor_levels(riga_problem* pr, T* pool, double sigma) {
+void factor_levels(riga_problem* pr, T* pool, T* hpool, double sigma) {
   hipStream_t s = pr->stream;
   FrontArgs fa = front_args(pr);
   const double pivtol = 1e-20 * (pr->normK1 + fabs(sigma) * pr->normM1);
@@ -575,6 +575,7 @@ void factor_levels(riga_problem* pr, T* pool, double sigma) {
       HIPCHECK(hipGetLastError());
     }
   }
+  launch_front_inverse<T>(pr, pool, hpool, s);
   HIPCHECK(hipStreamSynchronize(s));  // scratch is released on return
 }
 
@@ -594,10 +595,12 @@ void factor_numeric(riga_problem* pr, double sigma, int precision) {
   hipStream_t s = pr->stream;
   if (precision == RIGA_MIXED) {
     if (pr->pool32.n < (size_t)an.pool_size) pr->pool32.alloc(an.pool_size, pr->home);
-    factor_levels<float, LDS_FRONT_MAX_F32>(pr, pr->pool32.p, sigma);
+    if (pr->h32.n < (size_t)an.h_size) pr->h32.alloc(an.h_size, pr->home);
+    factor_levels<float, LDS_FRONT_MAX_F32>(pr, pr->pool32.p, pr->h32.p, sigma);
   } else {
     if (pr->pool64.n < (size_t)an.pool_size) pr->pool64.alloc(an.pool_size, pr->home);
-    factor_levels<double, LDS_FRONT_MAX_F64>(pr, pr->pool64.p, sigma);
+    if (pr->h64.n < (size_t)an.h_size) pr->h64.alloc(an.h_size, pr->home);
+    factor_levels<double, LDS_FRONT_MAX_F64>(pr, pr->pool64.p, pr->h64.p, sigma);
   }
   std::vector<int32_t> st((size_t)an.n_fronts * 4);
   HIPCHECK(hipMemcpy(st.data(), pr->front_stat.p, st.size() * sizeof(int32_t),

@@ -68,10 +68,22 @@ struct DBuf {
 constexpr int LDS_FRONT_MAX_F64 = 128;
 constexpr int LDS_FRONT_MAX_F32 = 176;
 
-// Packed per-front record read once by the solve kernels.
+// Packed per-front record read once by the inverse and solve kernels.
 struct FrontDesc {
   int32_t f, k, start, pad;
-  int64_t pool_off, rows_off, cb_off, gmap_off;
+  int64_t pool_off;  // front in the factor pool (f x f, column-major)
+  int64_t h_off;     // partitioned inverse in the H pool (f x k, column-major)
+  int64_t rows_off, cb_off, gmap_off;
+};
+
+// Rows per forward-sweep work unit and columns per backward-sweep unit.
+constexpr int SWEEP_ROWS = 64;
+constexpr int SWEEP_COLS = 16;
+
+// One workgroup's share of a front: rows [lo, hi) (forward sweep, inverse)
+// or columns [lo, hi) (backward sweep).
+struct WorkUnit {
+  int32_t front, lo, hi, pad;
 };
 
 struct LevelDev {
@@ -81,6 +93,9 @@ struct LevelDev {
   std::vector<int> host_f;   // front orders, ascending (same order as `fronts`)
   DBuf<int32_t> fronts;      // front ids sorted by order
   DBuf<int64_t> col_prefix;  // [n+1] prefix sums of front orders
+  DBuf<WorkUnit> fwd_units;  // forward sweep: row blocks of this level's fronts
+  DBuf<WorkUnit> bwd_units;  // backward sweep: column blocks
+  int n_fwd = 0, n_bwd = 0;
   int n_upto(int fmax) const {  // fronts of order <= fmax (a prefix)
     return (int)(std::upper_bound(host_f.begin(), host_f.end(), fmax) - host_f.begin());
   }
@@ -121,6 +136,10 @@ struct riga_problem {
   // numeric factorisation
   riga::DBuf<double> pool64;
   riga::DBuf<float> pool32;
+  riga::DBuf<double> h64;                   // partitioned inverses, sum f * k
+  riga::DBuf<float> h32;
+  riga::DBuf<riga::WorkUnit> inv_units;     // row blocks of every front
+  int n_inv_units = 0;
   riga::DBuf<int32_t> piv_perm, piv_type;   // by new index
   riga::DBuf<int32_t> front_stat;           // [n_fronts * 4]: neg, perturbed, 2x2, spare
   bool factored = false;
@@ -155,6 +174,11 @@ void launch_spmv(const riga_problem* pr, const double* vals, const double* x, do
 int spmv_blocks(const riga_problem* pr);
 
 void factor_numeric(riga_problem* pr, double sigma, int precision);
+// H = [I; L21] L11^{-1} for every front (D kept on the diagonal), from the
+// factor pool into the H pool.
+template <class T>
+void launch_front_inverse(riga_problem* pr, const T* pool, T* h, hipStream_t s);
+size_t front_inverse_lds(int max_k);
 // Raise the dynamic-LDS limit of the kernels that need more than 64 KB (for
 // the calling thread's device).
 // Binds a call's stream to the problem for the duration of the call only, so

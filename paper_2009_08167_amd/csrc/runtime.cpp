@@ -54,10 +54,12 @@ void dfree(void* p, hipStream_t s) {
 
 void set_front_attributes();
 void set_solve_attributes();
+void set_inverse_attributes();
 
 void set_kernel_attributes() {
   set_front_attributes();
   set_solve_attributes();
+  set_inverse_attributes();
 }
 
 // Copies the per-element coefficients (host values are checked positive)
@@ -136,6 +138,7 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
       d.start = an.f_start[F];
       d.pad = 0;
       d.pool_off = an.f_pool_off[F];
+      d.h_off = an.f_h_off[F];
       d.rows_off = an.f_rows_off[F];
       d.cb_off = an.f_cb_off[F];
       d.gmap_off = an.f_rows_off[F] * gs;
@@ -168,7 +171,31 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
     L.cols = pref.back();
     L.fronts.upload(fr, s);
     L.col_prefix.upload(pref, s);
+    // sweep work units, largest fronts first
+    std::vector<WorkUnit> fu, bu;
+    for (auto it = fr.rbegin(); it != fr.rend(); ++it) {
+      const int F = *it, f = an.f_f[F], k = an.f_k[F];
+      for (int r = 0; r < f; r += SWEEP_ROWS) fu.push_back({F, r, std::min(f, r + SWEEP_ROWS), 0});
+      for (int c = 0; c < k; c += SWEEP_COLS) bu.push_back({F, c, std::min(k, c + SWEEP_COLS), 0});
+    }
+    L.n_fwd = (int)fu.size();
+    L.n_bwd = (int)bu.size();
+    L.fwd_units.upload(fu, s);
+    L.bwd_units.upload(bu, s);
   }
+  // inverse work units: row blocks of every front, most panels first
+  {
+    std::vector<int> order(an.n_fronts);
+    for (int F = 0; F < an.n_fronts; ++F) order[F] = F;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return an.f_k[a] > an.f_k[b]; });
+    std::vector<WorkUnit> iu;
+    for (int F : order)
+      for (int r = 0; r < an.f_f[F]; r += 64) iu.push_back({F, r, std::min(an.f_f[F], r + 64), 0});
+    pr->n_inv_units = (int)iu.size();
+    pr->inv_units.upload(iu, s);
+  }
+  if (front_inverse_lds(an.max_fs) > 159 * 1024)
+    throw Error(RIGA_EUNSUPPORTED, "fully-summed block too large for the inverse kernel's LDS");
   pr->piv_perm.alloc(N, s);
   pr->piv_type.alloc(N, s);
   pr->front_stat.alloc((size_t)an.n_fronts * 4, s);
