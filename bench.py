@@ -80,6 +80,126 @@ def time_solves(pr, sigma, precision, reps, torch):
     return t_fb, t_fact
 
 
+def timed_eigs(pr, nev, precision, torch, reps=1):
+    """Wall time of pr.eigs (after one untimed run) with the results on the
+    device and synchronised."""
+    pr.eigs(nev, precision=precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lam, U, res, st = pr.eigs(nev, precision=precision)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, lam, U, res, st
+
+
+def secondary_lines(riga, workloads, torch, np):
+    """The other workloads the metric is quoted for: 3D rIGA FP64 vs mixed
+    precision (and the IGA twin), 64 uneven instances batched, and the
+    adjoint gradient with its finite-difference check."""
+    out = {}
+    # 3D, 32^3, p = 2: rIGA (blocks of 8) FP64 vs FP32 fronts + FP64 refinement
+    w3 = workloads.c3(True)
+    log("assemble", w3.name)
+    pr3 = riga.assemble(w3.dim, w3.ne, w3.p, w3.s)
+    t64, l64, _, r64, s64 = timed_eigs(pr3, w3.nev, riga.RIGA_FP64, torch)
+    tmx, lmx, _, rmx, smx = timed_eigs(pr3, w3.nev, riga.RIGA_MIXED, torch)
+    rel = np.abs(lmx - l64) / l64
+    out["3d_riga_fp64_vs_mixed"] = {
+        "workload": w3.name, "n_dof": pr3.n_dof, "nev": w3.nev,
+        "fp64": {"value": w3.nev / t64, "seconds": t64, "n_fact": s64["n_fact"], "n_fb": s64["n_fb"],
+                 "max_residual": float(r64.max())},
+        "mixed": {"value": w3.nev / tmx, "seconds": tmx, "n_fact": smx["n_fact"], "n_fb": smx["n_fb"],
+                  "n_ir": smx["n_ir"], "max_residual": float(rmx.max())},
+        "mixed_speedup": t64 / tmx,
+        "max_rel_diff_per_pair": float(rel.max()), "median_rel_diff_per_pair": float(np.median(rel)),
+        "flops_fact": pr3.info["flops_fact"], "nnz_l": pr3.info["nnz_l"]}
+    log("3d riga: fp64 %.1f/s, mixed %.1f/s, max pair diff %.2e" % (w3.nev / t64, w3.nev / tmx, rel.max()))
+    del pr3
+    w3i = workloads.c3(False)
+    log("assemble", w3i.name)
+    pr3i = riga.assemble(w3i.dim, w3i.ne, w3i.p, w3i.s)
+    ti, li, _, ri, si = timed_eigs(pr3i, w3i.nev, riga.RIGA_FP64, torch)
+    out["3d_iga_fp64"] = {"workload": w3i.name, "n_dof": pr3i.n_dof, "value": w3i.nev / ti,
+                          "seconds": ti, "n_fact": si["n_fact"], "n_fb": si["n_fb"],
+                          "max_residual": float(ri.max()), "flops_fact": pr3i.info["flops_fact"],
+                          "nnz_l": pr3i.info["nnz_l"]}
+    out["3d_riga_over_iga_fp64"] = (w3.nev / t64) / (w3i.nev / ti)
+    log("3d iga: fp64 %.1f/s" % (w3i.nev / ti))
+    del pr3i
+    # 64 uneven 2D rIGA instances, 20 pairs each, one stream per worker
+    ws = workloads.c4()
+    log("assemble %d batch instances" % len(ws))
+    probs = []
+    for w in ws:
+        kap, rh = w.coefficients()
+        probs.append(riga.assemble(w.dim, w.ne, w.p, w.s, kap, rh))
+    total_dof = sum(p.n_dof for p in probs)
+    bat = {"instances": len(ws), "total_dof": total_dof, "nev_each": ws[0].nev}
+    for name, prec in (("mixed", riga.RIGA_MIXED), ("fp64", riga.RIGA_FP64)):
+        riga.eigs_batched(probs, ws[0].nev, precision=prec, vectors=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = riga.eigs_batched(probs, ws[0].nev, precision=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        npairs = sum(len(r[0]) for r in res)
+        bat[name] = {"value": npairs / dt, "seconds": dt, "pairs": npairs,
+                     "max_residual": float(max(r[2].max() for r in res))}
+        log("batch %s: %.1f eigenpairs/s" % (name, npairs / dt))
+    out["batched_64_riga"] = bat
+    del probs
+    # adjoint gradient of sum w_i lambda_i, 20 pairs, with central FD on 50
+    # elements x {kappa, rho}
+    w5 = workloads.c5()
+    kap, rh = w5.coefficients()
+    kd = torch.tensor(kap, dtype=torch.float64, device="cuda")
+    rd = torch.tensor(rh, dtype=torch.float64, device="cuda")
+    pr5 = riga.assemble(w5.dim, w5.ne, w5.p, w5.s, kd, rd)
+    wts = w5.extra["weights"]
+    te, lam5, U5, r5, _ = timed_eigs(pr5, w5.nev, riga.RIGA_FP64, torch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gk, gr = pr5.eig_grad(lam5, U5, wts)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    gk, gr = gk.cpu().numpy(), gr.cpu().numpy()
+    h = 1e-6
+    t0 = time.perf_counter()
+    worst = 0.0
+    for e in w5.extra["fd_elements"]:
+        for which in (0, 1):
+            vals = []
+            for sgn in (1, -1):
+                kp, rp = kd.clone(), rd.clone()
+                (kp if which == 0 else rp)[e] *= 1 + sgn * h
+                pr5.update_coefficients(kp, rp)
+                vals.append(wts @ pr5.eigs(w5.nev, vectors=False)[0])
+            base = kap[e] if which == 0 else rh[e]
+            fd = (vals[0] - vals[1]) / (2 * h * base)
+            adj = gk[e] if which == 0 else gr[e]
+            worst = max(worst, abs(adj - fd) / max(abs(fd), 1e-300))
+    tfd = time.perf_counter() - t0
+    pr5.update_coefficients(kd, rd)
+    out["gradient_2d_128_p3_riga16"] = {
+        "workload": w5.name, "n_dof": pr5.n_dof, "n_elem": w5.n_elem, "nev": w5.nev,
+        "eigs_seconds": te, "grad_seconds": tg, "value": w5.nev / te,
+        "fd_checks": 2 * len(w5.extra["fd_elements"]), "fd_seconds": tfd,
+        "fd_max_rel_dev": worst}
+    log("gradient: eigs %.3f s, adjoint %.2f ms, FD max rel dev %.2e" % (te, tg * 1e3, worst))
+    return out
+
+
+def calibrate_copy(torch, mib=256, reps=3):
+    """A plain device copy of known size, for scaling HBM counters."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def cpu_baseline():
     """The oracle as it stands, on a bounded sample: NumPy element assembly of
     the same problem plus ARPACK/SuperLU shift-and-invert for its 20 lowest
@@ -113,6 +233,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-iga", action="store_true", help="skip the IGA comparison")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 3D, batched and gradient workloads")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a 256 MiB device copy (for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -129,6 +253,8 @@ def main():
         sys.exit(1)
     riga.lib()
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        calibrate_copy(torch)
 
     w = workloads.c2(True)
     kappa, rho = w.coefficients()
@@ -143,7 +269,6 @@ def main():
     log("riga fp64: %.3f s/step, %.1f eigenpairs/s, stats %s" % (dt / args.steps, value, st))
 
     # dominant-kernel roofline, measured on the library's stream
-    sigma_mid = float(lam[len(lam) // 2])
     sigma_mid = 0.5 * (lam[len(lam) // 2] + lam[len(lam) // 2 + 1])
     t_fb, t_fact = time_solves(pr, sigma_mid, riga.RIGA_FP64, 30, torch)
     N = pr.n_dof
@@ -203,6 +328,8 @@ def main():
                       "fact_ms": t_fact * 1e3, "fact_TFLOPs": flops_fact / t_fact / 1e12},
     }
     out.update(extra)
+    if not args.no_secondary:
+        out["secondary_workloads"] = secondary_lines(riga, workloads, torch, np)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         cb, lam_cpu = cpu_baseline()

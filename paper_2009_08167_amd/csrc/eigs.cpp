@@ -150,10 +150,11 @@ struct Solver {
     launch_axpby(a, u, v, out, N, s);
   }
 
-  // c = W[:, 0:m]^T x ; x -= B[:, 0:m] c
-  void project_out(int m, double* c) {
-    launch_gemv_t(W.p, N, m, x.p, partial.p, c, s);
-    launch_gemv_n_sub(B.p, N, m, c, x.p, s);
+  // c[c0:m] = W[:, c0:m]^T x ; x -= B[:, c0:m] c[c0:m]
+  void project_out(int m, double* c, int c0 = 0) {
+    if (m <= c0) return;
+    launch_gemv_t(Wc(c0), N, m - c0, x.p, partial.p, c + c0, s);
+    launch_gemv_n_sub(Bc(c0), N, m - c0, c + c0, x.p, s);
   }
 
   // M-normalise x into column j of B (and M x into W); returns false on breakdown
@@ -180,8 +181,14 @@ struct Solver {
     const int col = nl + j;
     apply_inverse(Wc(col), x.p);
     auto a = clk::now();
+    // Classical Gram-Schmidt against [U_locked | V], then a second pass
+    // against V only: x = (K - sigma M)^{-1} M v_j starts M-orthogonal to the
+    // locked eigenvectors up to rounding and their residuals, so the first
+    // pass removes those components without cancellation; the cancellation
+    // the second pass repairs comes from the large components along v_j and
+    // v_{j-1}.
     project_out(col + 1, c1.p);
-    project_out(col + 1, c2.p);
+    project_out(col + 1, c2.p, nl);
     add_scalars_launch(c1.p + col, c2.p + col, alpha.p + j, s);
     normalize_into(col + 1, beta.p + j + 1);
     st.t_orth += secs(a, clk::now());

@@ -576,6 +576,7 @@ void factor_levels(riga_problem* pr, T* pool, T* hpool, double sigma) {
     }
   }
   launch_front_inverse<T>(pr, pool, hpool, s);
+  launch_pivot_maps(pr, s);
   HIPCHECK(hipStreamSynchronize(s));  // scratch is released on return
 }
 

@@ -12,7 +12,9 @@
 // except on the diagonal of the top k x k block, which keeps D(i, i), and on
 // the (t+1, t) slot of every 2x2 pivot block, which keeps D(t+1, t) (both
 // entries of L11^{-1} there are known: 1 and 0).  The strict upper triangle
-// of the top block is never written or read.
+// of the top block is never written or read.  D is also copied, by pivot
+// index, into two compact FP64 arrays (diagonal; (t+1, t) entry of 2x2
+// blocks) for the backward sweep.
 //
 // Rows of H are independent (row i solves h L11 = r_i with r_i = e_i or the
 // row of L21), so a workgroup takes a block of up to 64 rows and walks the
@@ -52,7 +54,8 @@ template <class T>
 __global__ void __launch_bounds__(256) front_inverse_kernel(const FrontDesc* __restrict__ desc,
                                                             const WorkUnit* __restrict__ units,
                                                             const T* __restrict__ pool, T* H,
-                                                            const int32_t* __restrict__ piv_type) {
+                                                            const int32_t* __restrict__ piv_type,
+                                                            double* dd, double* dsub) {
   extern __shared__ double smem[];
   double* Ac = smem;              // Ac[mm * LDP + ii] = H(r0 + ii, m0 + mm)
   double* Bc = Ac + IB * LDP;     // Bc[mm * LDP + c]  = L(m0 + mm, j0 + c)
@@ -167,9 +170,17 @@ __global__ void __launch_bounds__(256) front_inverse_kernel(const FrontDesc* __r
       if (ii < nr && c < pw) {
         const int i = r0 + ii, j = j0 + c;
         const int64_t o = (int64_t)j * f + i;
-        if (i >= k) Hf[o] = (T)Hp[ii * LDP + c];
-        else if (j == i || (j == i - 1 && type[j] == 2)) Hf[o] = L[o];
-        else if (j < i) Hf[o] = (T)Hp[ii * LDP + c];
+        if (i >= k) {
+          Hf[o] = (T)Hp[ii * LDP + c];
+        } else if (j == i) {
+          Hf[o] = L[o];
+          dd[d.start + i] = (double)L[o];
+        } else if (j == i - 1 && type[j] == 2) {
+          Hf[o] = L[o];
+          dsub[d.start + j] = (double)L[o];
+        } else if (j < i) {
+          Hf[o] = (T)Hp[ii * LDP + c];
+        }
       }
     }
     __syncthreads();
@@ -193,7 +204,7 @@ template <class T>
 void launch_front_inverse(riga_problem* pr, const T* pool, T* h, hipStream_t s) {
   if (pr->n_inv_units == 0) return;
   front_inverse_kernel<T><<<pr->n_inv_units, 256, front_inverse_lds(pr->an.max_fs), s>>>(
-      pr->d_desc.p, pr->inv_units.p, pool, h, pr->piv_type.p);
+      pr->d_desc.p, pr->inv_units.p, pool, h, pr->piv_type.p, pr->d_diag.p, pr->d_sub.p);
   HIPCHECK(hipGetLastError());
 }
 

@@ -29,114 +29,149 @@ namespace riga {
 namespace {
 
 struct SolveArgs {
-  const FrontDesc* desc;  // packed per-front record
-  const int32_t* gmap;    // per front position: children's update indices
-  int gstride;            // children slots per position (<= 4)
+  const int32_t* gmap;      // per front position: children's update indices
+  int gstride;              // children slots per position (<= 4)
   const int32_t* rows;
-  const int32_t* piv_perm;
-  const int32_t* piv_type;
-  double* cbvec;          // update vectors, one per front (f - k entries)
-  double* fwd;            // z of the forward sweep, by new (pivot-order) index
+  const int32_t* piv_type;  // 1: 1x1 pivot, 2/3: first/second of a 2x2 block
+  const int32_t* piv_dof;   // DOF of each pivot
+  const int32_t* piv_gmap;  // children's update indices of each pivot
+  const double* dd;         // D diagonal by pivot index
+  const double* dsub;       // D(t+1, t) of 2x2 blocks, at the block's first pivot
+  double* cbvec;            // update vectors, one per front (f - k entries)
+  double* fwd;              // z of the forward sweep, by new (pivot-order) index
 };
 
 // Forward sweep: 64 rows of one front per workgroup, lanes over rows (the
 // column-major H is read coalesced), the four waves over interleaved columns.
+// The first 16 loads of H are issued before the gather of y so that both
+// latencies overlap.
 template <class T>
 __global__ void __launch_bounds__(256) fwd_kernel(SolveArgs sa, const T* __restrict__ H,
                                                   const WorkUnit* __restrict__ units,
                                                   const double* __restrict__ b) {
   extern __shared__ double smem[];
   const WorkUnit u = units[blockIdx.x];
-  const FrontDesc d = sa.desc[u.front];
-  const int f = d.f, k = d.k, start = d.start;
+  const int f = u.f, k = u.k, start = u.start;
   const int lo = u.lo, hi = u.hi;
   double* y = smem;          // k: permuted fully-summed right-hand side
   double* psum = y + k;      // 4 x 64 partial sums
-  const int32_t* rows = sa.rows + d.rows_off;
-  const int32_t* gm = sa.gmap + d.gmap_off;
   const int gs = sa.gstride;
   const int tid = threadIdx.x, lane = tid & 63, g = tid >> 6;
+  const int i = lo + lane;
+  const bool row = i < hi;
+  const int jend = row ? (i < k ? i : k) : 0;
+  const T* hc = H + u.h_off + i;
+  double hv[16];
+  const bool first = g + 60 < jend;
+  if (first) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) hv[q] = (double)hc[(int64_t)(g + 4 * q) * f];
+  }
+  // the (i, i-1) slot of a 2x2 pivot block holds D, not L11^{-1} (= 0)
+  const int skip = (row && i < k && i > 0 && sa.piv_type[start + i] == 3) ? i - 1 : -1;
+  // update rows: the children's contributions at this position
+  double ycb = 0.0;
+  if (g == 0 && row && i >= k) {
+    const int32_t* gm = sa.gmap + u.gmap_off + (int64_t)i * gs;
+    int c[4];
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl) c[sl] = sl < gs ? gm[sl] : -1;
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl)
+      if (c[sl] >= 0) ycb += sa.cbvec[c[sl]];
+  }
   // the top rows need y_FS up to their own index, the update rows all of it
   const int kn = hi <= k ? hi : k;
   for (int t = tid; t < kn; t += 256) {
-    const int pos = sa.piv_perm[start + t];
+    const int n = start + t;
     int c[4];
 #pragma unroll
-    for (int sl = 0; sl < 4; ++sl) c[sl] = sl < gs ? gm[(int64_t)pos * gs + sl] : -1;
-    double v = b[rows[pos]];
+    for (int sl = 0; sl < 4; ++sl) c[sl] = sl < gs ? sa.piv_gmap[(int64_t)n * gs + sl] : -1;
+    double v = b[sa.piv_dof[n]];
 #pragma unroll
     for (int sl = 0; sl < 4; ++sl)
       if (c[sl] >= 0) v += sa.cbvec[c[sl]];
     y[t] = v;
   }
   __syncthreads();
-  const int i = lo + lane;
   double s = 0.0;
-  if (i < hi) {
-    const int jend = i < k ? i : k;
-    // the (i, i-1) slot of a 2x2 pivot block holds D, not L11^{-1} (= 0)
-    const int skip = (i < k && i > 0 && sa.piv_type[start + i] == 3) ? i - 1 : -1;
-    const T* hc = H + d.h_off + i;
-    int j = g;
-    for (; j + 60 < jend; j += 64) {
-      double hv[16];
+  int j = g;
+  if (first) {
 #pragma unroll
-      for (int q = 0; q < 16; ++q) hv[q] = (double)hc[(int64_t)(j + 4 * q) * f];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) s += (j + 4 * q == skip ? 0.0 : hv[q]) * y[j + 4 * q];
-    }
-    for (; j < jend; j += 4)
-      if (j != skip) s += (double)hc[(int64_t)j * f] * y[j];
+    for (int q = 0; q < 16; ++q) s += (g + 4 * q == skip ? 0.0 : hv[q]) * y[g + 4 * q];
+    j += 64;
   }
+  for (; j + 60 < jend; j += 64) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) hv[q] = (double)hc[(int64_t)(j + 4 * q) * f];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s += (j + 4 * q == skip ? 0.0 : hv[q]) * y[j + 4 * q];
+  }
+  for (; j < jend; j += 4)
+    if (j != skip) s += (double)hc[(int64_t)j * f] * y[j];
   psum[g * 64 + lane] = s;
   __syncthreads();
-  if (g == 0 && i < hi) {
+  if (g == 0 && row) {
     const double tot = (psum[lane] + psum[64 + lane]) + (psum[128 + lane] + psum[192 + lane]);
-    if (i < k) {
-      sa.fwd[start + i] = y[i] + tot;
-    } else {
-      int c[4];
-#pragma unroll
-      for (int sl = 0; sl < 4; ++sl) c[sl] = sl < gs ? gm[(int64_t)i * gs + sl] : -1;
-      double ycb = 0.0;
-#pragma unroll
-      for (int sl = 0; sl < 4; ++sl)
-        if (c[sl] >= 0) ycb += sa.cbvec[c[sl]];
-      sa.cbvec[d.cb_off + i - k] = ycb - tot;
-    }
+    if (i < k) sa.fwd[start + i] = y[i] + tot;
+    else sa.cbvec[u.cb_off + i - k] = ycb - tot;
   }
 }
 
 // Backward sweep: 16 columns of one front per workgroup; wave w takes
-// columns lo + w + 4c (c < 4), lanes over rows, 16 loads in flight per lane.
+// columns lo + w + 4c (c < 4), lanes over rows, 16 loads in flight per lane
+// (4 row chunks of 64 per iteration).  The first iteration's loads are
+// issued before the gather of v.
 template <class T>
 __global__ void __launch_bounds__(256) bwd_kernel(SolveArgs sa, const T* __restrict__ H,
                                                   const WorkUnit* __restrict__ units, double* x) {
+  constexpr int CPW = 4, RCH = 4;
   extern __shared__ double smem[];
   const WorkUnit u = units[blockIdx.x];
-  const FrontDesc d = sa.desc[u.front];
-  const int f = d.f, k = d.k, start = d.start;
+  const int f = u.f, k = u.k, start = u.start;
   const int lo = u.lo, hi = u.hi;
-  const T* Hf = H + d.h_off;
-  const int32_t* rows = sa.rows + d.rows_off;
+  const T* Hf = H + u.h_off;
+  const int32_t* rows = sa.rows + u.rows_off;
   double* v = smem;  // v[i - lo], i in [lo, f): D^{-1} z on the FS rows, -x below
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int jc[CPW];
+  bool two[CPW];
+  double acc[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    jc[c] = lo + wave + 4 * c;
+    two[c] = jc[c] < hi && sa.piv_type[start + jc[c]] == 2;
+    acc[c] = 0.0;
+  }
+  double hv[RCH][CPW];
+  auto load = [&](int i0) {
+#pragma unroll
+    for (int r = 0; r < RCH; ++r) {
+      const int i = i0 + 64 * r + lane;
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const int j = jc[c];
+        const bool use = j < hi && i < f && i > j && !(two[c] && i == j + 1);
+        hv[r][c] = use ? (double)Hf[(int64_t)j * f + i] : 0.0;
+      }
+    }
+  };
+  const int ibeg = lo + 1;
+  if (ibeg < f) load(ibeg);
   for (int i = lo + tid; i < f; i += 256) {
     double val;
     if (i < k) {
-      const int ty = sa.piv_type[start + i];
-      const double zi = sa.fwd[start + i];
-      const double dii = (double)Hf[(int64_t)i * f + i];
+      const int n = start + i;
+      const int ty = sa.piv_type[n];
+      const double zi = sa.fwd[n];
       if (ty == 1) {
-        val = zi / dii;
+        val = zi / sa.dd[n];
       } else if (ty == 2) {
-        const double d21 = (double)Hf[(int64_t)i * f + i + 1];
-        const double d22 = (double)Hf[(int64_t)(i + 1) * f + i + 1];
-        val = (d22 * zi - d21 * sa.fwd[start + i + 1]) / (dii * d22 - d21 * d21);
+        const double d11 = sa.dd[n], d21 = sa.dsub[n], d22 = sa.dd[n + 1];
+        val = (d22 * zi - d21 * sa.fwd[n + 1]) / (d11 * d22 - d21 * d21);
       } else {
-        const double d11 = (double)Hf[(int64_t)(i - 1) * f + i - 1];
-        const double d21 = (double)Hf[(int64_t)(i - 1) * f + i];
-        val = (d11 * zi - d21 * sa.fwd[start + i - 1]) / (d11 * dii - d21 * d21);
+        const double d11 = sa.dd[n - 1], d21 = sa.dsub[n - 1], d22 = sa.dd[n];
+        val = (d11 * zi - d21 * sa.fwd[n - 1]) / (d11 * d22 - d21 * d21);
       }
     } else {
       val = -x[rows[i]];
@@ -144,50 +179,50 @@ __global__ void __launch_bounds__(256) bwd_kernel(SolveArgs sa, const T* __restr
     v[i - lo] = val;
   }
   __syncthreads();
-  int jc[4];
-  bool two[4];
-  double acc[4];
+  for (int i0 = ibeg; i0 < f; i0 += 64 * RCH) {
+    if (i0 != ibeg) load(i0);
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    jc[c] = lo + wave + 4 * c;
-    two[c] = jc[c] < hi && sa.piv_type[start + jc[c]] == 2;
-    acc[c] = 0.0;
-  }
-  for (int i0 = lo + 1; i0 < f; i0 += 256) {
-    double hv[4][4], vv[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < RCH; ++r) {
       const int i = i0 + 64 * r + lane;
-      vv[r] = i < f ? v[i - lo] : 0.0;
+      const double vv = i < f ? v[i - lo] : 0.0;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int j = jc[c];
-        const bool use = j < hi && i < f && i > j && !(two[c] && i == j + 1);
-        hv[r][c] = use ? (double)Hf[(int64_t)j * f + i] : 0.0;
-      }
+      for (int c = 0; c < CPW; ++c) acc[c] += hv[r][c] * vv;
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] += hv[r][c] * vv[r];
   }
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < CPW; ++c) {
     double s = acc[c];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     const int j = jc[c];
-    if (lane == 0 && j < hi) x[rows[sa.piv_perm[start + j]]] = v[j - lo] + s;
+    if (lane == 0 && j < hi) x[sa.piv_dof[start + j]] = v[j - lo] + s;
   }
+}
+
+// Pivot-order copies of the forward gather maps: DOF and children's update
+// indices of every pivot (the pivot order changes with each factorisation).
+__global__ void pivot_maps_kernel(const FrontDesc* __restrict__ desc,
+                                  const int32_t* __restrict__ front_of,
+                                  const int32_t* __restrict__ piv_perm,
+                                  const int32_t* __restrict__ rows, const int32_t* __restrict__ gmap,
+                                  int gs, int64_t N, int32_t* piv_dof, int32_t* piv_gmap) {
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  const FrontDesc d = desc[front_of[n]];
+  const int pos = piv_perm[n];
+  piv_dof[n] = rows[d.rows_off + pos];
+  for (int sl = 0; sl < gs; ++sl) piv_gmap[n * gs + sl] = gmap[d.gmap_off + (int64_t)pos * gs + sl];
 }
 
 SolveArgs solve_args(riga_problem* pr) {
   SolveArgs sa{};
-  sa.desc = pr->d_desc.p;
   sa.gmap = pr->d_gmap.p;
   sa.gstride = pr->gstride;
   sa.rows = pr->d_rows.p;
-  sa.piv_perm = pr->piv_perm.p;
   sa.piv_type = pr->piv_type.p;
+  sa.piv_dof = pr->piv_dof.p;
+  sa.piv_gmap = pr->piv_gmap.p;
+  sa.dd = pr->d_diag.p;
+  sa.dsub = pr->d_sub.p;
   sa.cbvec = pr->cbvec.p;
   sa.fwd = pr->fwd.p;
   return sa;
@@ -228,6 +263,15 @@ void solve_levels(riga_problem* pr, const T* H, const double* b, double* x, hipS
 void set_solve_attributes() {
   apply_solve_attrs<double>();
   apply_solve_attrs<float>();
+}
+
+void launch_pivot_maps(riga_problem* pr, hipStream_t s) {
+  const int64_t N = pr->an.N;
+  if (N == 0) return;
+  pivot_maps_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(
+      pr->d_desc.p, pr->d_front_of.p, pr->piv_perm.p, pr->d_rows.p, pr->d_gmap.p, pr->gstride, N,
+      pr->piv_dof.p, pr->piv_gmap.p);
+  HIPCHECK(hipGetLastError());
 }
 
 void solve_fb(riga_problem* pr, const double* b, double* x, hipStream_t s) {

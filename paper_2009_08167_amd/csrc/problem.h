@@ -81,9 +81,12 @@ constexpr int SWEEP_ROWS = 64;
 constexpr int SWEEP_COLS = 16;
 
 // One workgroup's share of a front: rows [lo, hi) (forward sweep, inverse)
-// or columns [lo, hi) (backward sweep).
+// or columns [lo, hi) (backward sweep), with the front's record inlined so a
+// sweep workgroup starts from a single scalar load.
 struct WorkUnit {
-  int32_t front, lo, hi, pad;
+  int32_t front, lo, hi, f;
+  int32_t k, start, pad0, pad1;
+  int64_t h_off, rows_off, cb_off, gmap_off;
 };
 
 struct LevelDev {
@@ -151,6 +154,10 @@ struct riga_problem {
   // solve workspace
   riga::DBuf<double> cbvec, fwd;
   riga::DBuf<riga::FrontDesc> d_desc;
+  riga::DBuf<int32_t> d_front_of;           // front of each new (pivot-order) index
+  riga::DBuf<int32_t> piv_dof;              // DOF of each pivot (set per factorisation)
+  riga::DBuf<int32_t> piv_gmap;             // [N * gstride] children's update indices per pivot
+  riga::DBuf<double> d_diag, d_sub;         // D by pivot index: diagonal, (t+1, t) of 2x2 blocks
   riga::DBuf<int32_t> d_gmap;               // [sum f * gstride] children's update indices
   int gstride = 1;
   riga::DBuf<double> ir_r, ir_x, ir_d;      // iterative refinement vectors
@@ -179,6 +186,8 @@ void factor_numeric(riga_problem* pr, double sigma, int precision);
 template <class T>
 void launch_front_inverse(riga_problem* pr, const T* pool, T* h, hipStream_t s);
 size_t front_inverse_lds(int max_k);
+// Pivot-order gather maps of the sweeps (after each factorisation).
+void launch_pivot_maps(riga_problem* pr, hipStream_t s);
 // Raise the dynamic-LDS limit of the kernels that need more than 64 KB (for
 // the calling thread's device).
 // Binds a call's stream to the problem for the duration of the call only, so

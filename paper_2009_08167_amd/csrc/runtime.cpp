@@ -152,6 +152,14 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
     }
     pr->d_desc.upload(desc, s);
     pr->d_gmap.upload(gmap, s);
+    std::vector<int32_t> front_of(N);
+    for (int F = 0; F < an.n_fronts; ++F)
+      for (int t = 0; t < an.f_k[F]; ++t) front_of[an.f_start[F] + t] = F;
+    pr->d_front_of.upload(front_of, s);
+    pr->piv_dof.alloc(N, s);
+    pr->piv_gmap.alloc((size_t)N * gs, s);
+    pr->d_diag.alloc(N, s);
+    pr->d_sub.alloc(N, s);
   }
   pr->levels.clear();
   pr->levels.resize(an.height);
@@ -173,10 +181,25 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
     L.col_prefix.upload(pref, s);
     // sweep work units, largest fronts first
     std::vector<WorkUnit> fu, bu;
+    const int cw = SWEEP_COLS;
+    auto unit = [&](int F, int lo, int hi) {
+      WorkUnit w{};
+      w.front = F;
+      w.lo = lo;
+      w.hi = hi;
+      w.f = an.f_f[F];
+      w.k = an.f_k[F];
+      w.start = an.f_start[F];
+      w.h_off = an.f_h_off[F];
+      w.rows_off = an.f_rows_off[F];
+      w.cb_off = an.f_cb_off[F];
+      w.gmap_off = an.f_rows_off[F] * pr->gstride;
+      return w;
+    };
     for (auto it = fr.rbegin(); it != fr.rend(); ++it) {
       const int F = *it, f = an.f_f[F], k = an.f_k[F];
-      for (int r = 0; r < f; r += SWEEP_ROWS) fu.push_back({F, r, std::min(f, r + SWEEP_ROWS), 0});
-      for (int c = 0; c < k; c += SWEEP_COLS) bu.push_back({F, c, std::min(k, c + SWEEP_COLS), 0});
+      for (int r = 0; r < f; r += SWEEP_ROWS) fu.push_back(unit(F, r, std::min(f, r + SWEEP_ROWS)));
+      for (int c = 0; c < k; c += cw) bu.push_back(unit(F, c, std::min(k, c + cw)));
     }
     L.n_fwd = (int)fu.size();
     L.n_bwd = (int)bu.size();
@@ -190,7 +213,13 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return an.f_k[a] > an.f_k[b]; });
     std::vector<WorkUnit> iu;
     for (int F : order)
-      for (int r = 0; r < an.f_f[F]; r += 64) iu.push_back({F, r, std::min(an.f_f[F], r + 64), 0});
+      for (int r = 0; r < an.f_f[F]; r += 64) {
+        WorkUnit w{};
+        w.front = F;
+        w.lo = r;
+        w.hi = std::min(an.f_f[F], r + 64);
+        iu.push_back(w);
+      }
     pr->n_inv_units = (int)iu.size();
     pr->inv_units.upload(iu, s);
   }
