@@ -1,0 +1,583 @@
+// Fronts larger than the LDS-resident limit: right-looking blocked LDL^T
+// with Bunch-Kaufman pivoting inside the fully-summed block (the numeric
+// factorisation of Sec. 4.1/5.1 of arXiv 2009.08167, per shift), with the
+// work of one front spread over many workgroups.  All big fronts of one tree
+// level advance together, one panel per step:
+//
+//  1. big_panel_kernel (one 1024-thread workgroup per front): the panel's
+//     fully-summed rows [j0, k) x [j0, j0 + nb) are factorised in LDS.  The
+//     1x1 / 2x2 test uses the column maximum over all fully-summed rows; the
+//     2x2 partner is taken inside the panel, and when a column needs a
+//     partner beyond it the panel ends early (kb < nb factorised columns).
+//     Rows p, q of the earlier panels' L are interchanged in global memory.
+//  2. big_cbrows_kernel (many workgroups): the update-block rows [k, f) of
+//     the panel columns receive the same interchanges and eliminations:
+//     lanes hold the panel columns, pivots are broadcast with readlane.
+//  3. big_trailing_kernel (many workgroups): the trailing block
+//     [j0 + nb, f)^2 (lower triangle) receives A -= L_p W_p^T, W_p = L_p D_p,
+//     in 64 x 64 tiles on the FP64 MFMA units (operands staged in LDS, the
+//     tile read-modified-written coalesced).
+//
+// The panel start of each front lives in device memory, so the host issues
+// a fixed number of steps computed for panels that never end early, then
+// checks once per level whether any front needs more.  No workgroup waits
+// for another: each step is three ordinary launches on one stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "problem.h"
+
+namespace riga {
+namespace {
+
+constexpr int BF_NB = 64;        // widest panel
+constexpr int BF_LDS = 18432;    // doubles of the panel kernel's LDS panel
+constexpr int BF_TILE = 64;      // trailing-update tile
+constexpr double BF_ALPHA = 0.6403882032022076;  // (1 + sqrt(17)) / 8
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+struct BigState {
+  int32_t next;   // first column of the next panel
+  int32_t cur;    // first column of the panel of this step
+  int32_t kb;     // columns factorised in this step (0: nothing to do)
+  int32_t nb;     // panel width of this step
+  int32_t neg, pert, two, pad;
+};
+
+struct BigArgs {
+  const int32_t* fronts;  // this level's big fronts
+  const int32_t* ff;
+  const int32_t* fk;
+  const int32_t* fstart;
+  const int64_t* pool_off;
+  int32_t* piv_perm;      // by new index: front position of each pivot
+  int32_t* piv_type;      // by new index: 1, or 2 / 3 for a 2x2 block
+  int32_t* stat;          // per front: negative, perturbed, 2x2 pivots
+  int32_t* perm;          // [slot * perm_stride]: running pivot order
+  int64_t perm_stride;
+  int32_t* lperm;         // [slot * BF_NB]: this step's panel column order
+  BigState* st;
+  double pivtol;
+};
+
+struct Decision {
+  int kind;   // 1 or 2
+  int sa, sb; // interchange sa <-> sb (-1: none)
+  int end;    // the panel ends before this column
+};
+
+// Panel width for a fully-summed remainder of m rows (LDS holds m x nb).
+__host__ __device__ inline int panel_width(int m) {
+  int nb = BF_LDS / m;
+  nb = nb < BF_NB ? nb : BF_NB;
+  nb = nb < m ? nb : m;
+  return nb < 1 ? 1 : nb;
+}
+
+__device__ __forceinline__ double bcast(double v, int l) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <class T>
+__global__ void __launch_bounds__(1024) big_panel_kernel(BigArgs a, T* pool) {
+  extern __shared__ double Pn[];
+  __shared__ Decision dec;
+  __shared__ int lp[BF_NB];
+  constexpr int NT = 1024, NW = NT / 64;
+  const int b = blockIdx.x;
+  BigState* st = a.st + b;
+  const int F = a.fronts[b];
+  const int f = a.ff[F], k = a.fk[F], start = a.fstart[F];
+  const int j0 = st->next;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (j0 >= k) {
+    if (tid == 0) st->kb = 0;
+    return;
+  }
+  T* A = pool + a.pool_off[F];
+  int* perm = a.perm + (int64_t)b * a.perm_stride;
+  int32_t* type_out = a.piv_type + start;
+  const int m = k - j0;
+  const int nb = panel_width(m);
+  const int pend = j0 + nb;
+  auto P = [&](int r, int c) -> double& { return Pn[(c - j0) * m + (r - j0)]; };
+  for (int e = tid; e < nb * m; e += NT) {
+    const int c = e / m, r = e % m;
+    if (r >= c) Pn[e] = (double)A[(int64_t)(j0 + c) * f + j0 + r];
+  }
+  if (tid < nb) lp[tid] = tid;
+  int neg = 0, pert = 0, two = 0;
+  __syncthreads();
+  int jj = 0;
+  while (jj < nb) {
+    const int j = j0 + jj;
+    if (wave == 0) {
+      // column maximum over the fully-summed rows; candidate partner inside
+      // the panel
+      double cmax = 0.0, rin = 0.0;
+      int r = -1;
+      for (int i = j + 1 + lane; i < k; i += 64) {
+        const double v = fabs(P(i, j));
+        cmax = fmax(cmax, v);
+        if (i < pend && v > rin) { rin = v; r = i; }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        cmax = fmax(cmax, __shfl_xor(cmax, off));
+        const double ov = __shfl_xor(rin, off);
+        const int orr = __shfl_xor(r, off);
+        if (ov > rin || (ov == rin && orr >= 0 && (r < 0 || orr < r))) { rin = ov; r = orr; }
+      }
+      const double ajj = fabs(P(j, j));
+      int kind = 1, sa = -1, sb = -1, end = 0;
+      if (cmax == 0.0 || ajj >= BF_ALPHA * cmax) {
+        kind = 1;
+      } else if (r < 0) {
+        if (jj > 0) end = 1;   // the partner lies beyond the panel
+      } else {
+        double rmax = 0.0;
+        for (int i = j + lane; i < k; i += 64) {
+          if (i == r) continue;
+          rmax = fmax(rmax, i < r ? fabs(P(r, i)) : fabs(P(i, r)));
+        }
+        for (int off = 32; off > 0; off >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, off));
+        const double arr = fabs(P(r, r));
+        if (ajj * rmax >= BF_ALPHA * cmax * cmax) {
+          kind = 1;
+        } else if (arr >= BF_ALPHA * rmax) {
+          kind = 1;
+          sa = j;
+          sb = r;
+        } else if (jj + 1 < nb) {
+          kind = 2;
+          if (r != j + 1) { sa = j + 1; sb = r; }
+        } else {
+          end = jj > 0;        // no room for a 2x2 block in this panel
+        }
+      }
+      if (lane == 0) {
+        dec.kind = kind;
+        dec.sa = sa;
+        dec.sb = sb;
+        dec.end = end;
+      }
+    }
+    __syncthreads();
+    if (dec.end) break;
+    const int kind = dec.kind;
+    const int p = dec.sa, q = dec.sb;  // p < q < pend
+    if (p >= 0) {
+      // symmetric interchange of p and q: rows p, q of the earlier panels'
+      // L in global memory, the panel's fully-summed rows in LDS (the
+      // update-block rows follow from the panel column order lp)
+      for (int c = tid; c < j0; c += NT) {
+        T* col = A + (int64_t)c * f;
+        const T t0 = col[p];
+        col[p] = col[q];
+        col[q] = t0;
+      }
+      for (int c = j0 + tid; c < k; c += NT) {
+        if (c < p) {
+          const double t0 = P(p, c); P(p, c) = P(q, c); P(q, c) = t0;
+        } else if (c == p) {
+          const double t0 = P(p, p); P(p, p) = P(q, q); P(q, q) = t0;
+        } else if (c < q) {
+          const double t0 = P(c, p); P(c, p) = P(q, c); P(q, c) = t0;
+        } else if (c > q) {
+          const double t0 = P(c, p); P(c, p) = P(c, q); P(c, q) = t0;
+        }
+      }
+      if (tid == 0) {
+        const int tp = perm[p]; perm[p] = perm[q]; perm[q] = tp;
+        const int tl = lp[p - j0]; lp[p - j0] = lp[q - j0]; lp[q - j0] = tl;
+      }
+    }
+    __syncthreads();
+    if (kind == 1) {
+      double d = P(j, j);
+      if (fabs(d) < a.pivtol) d = d < 0.0 ? -a.pivtol : a.pivtol;
+      __syncthreads();
+      if (tid == 0) {
+        if (d != P(j, j)) ++pert;
+        P(j, j) = d;
+        if (d < 0.0) ++neg;
+        type_out[j] = 1;
+      }
+      const double dinv = 1.0 / d;
+      for (int r = j + 1 + tid; r < k; r += NT) P(r, j) *= dinv;
+      __syncthreads();
+      for (int c = j + 1 + wave; c < pend; c += NW) {
+        const double uc = P(c, j) * d;
+        for (int r = c + lane; r < k; r += 64) P(r, c) -= P(r, j) * uc;
+      }
+      jj += 1;
+    } else {
+      const double d11 = P(j, j), d21 = P(j + 1, j), d22 = P(j + 1, j + 1);
+      const double det = d11 * d22 - d21 * d21;
+      if (tid == 0) {
+        if (det < 0.0) neg += 1;
+        else if (d11 < 0.0) neg += 2;
+        ++two;
+        type_out[j] = 2;
+        type_out[j + 1] = 3;
+      }
+      const double idet = 1.0 / det;
+      for (int r = j + 2 + tid; r < k; r += NT) {
+        const double u1 = P(r, j), u2 = P(r, j + 1);
+        P(r, j) = (u1 * d22 - u2 * d21) * idet;
+        P(r, j + 1) = (u2 * d11 - u1 * d21) * idet;
+      }
+      __syncthreads();
+      for (int c = j + 2 + wave; c < pend; c += NW) {
+        const double l1 = P(c, j), l2 = P(c, j + 1);
+        const double u1 = l1 * d11 + l2 * d21, u2 = l1 * d21 + l2 * d22;
+        for (int r = c + lane; r < k; r += 64) P(r, c) -= P(r, j) * u1 + P(r, j + 1) * u2;
+      }
+      jj += 2;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  const int kb = jj;
+  for (int e = tid; e < nb * m; e += NT) {
+    const int c = e / m, r = e % m;
+    if (r >= c) A[(int64_t)(j0 + c) * f + j0 + r] = (T)Pn[e];
+  }
+  if (tid < nb) a.lperm[(int64_t)b * BF_NB + tid] = lp[tid];
+  if (tid == 0) {
+    st->cur = j0;
+    st->kb = kb;
+    st->nb = nb;
+    st->next = j0 + kb;
+    st->neg += neg;
+    st->pert += pert;
+    st->two += two;
+  }
+}
+
+// Update-block rows of the panel columns: gather them in the panel's column
+// order, eliminate with the panel's pivots (l = y (L_pp D)^{-T} on the kb
+// factorised columns, the rank-kb update on the other nb - kb), write back.
+// Lanes hold panel columns; each wave takes 16 rows.
+template <class T>
+__global__ void __launch_bounds__(256) big_cbrows_kernel(BigArgs a, T* pool) {
+  __shared__ double W[BF_NB * (BF_NB + 1)];   // W[t][c] = (L_pp D)(j0 + c, j0 + t)
+  __shared__ double dA[BF_NB], dB[BF_NB];
+  __shared__ int ty[BF_NB], lp[BF_NB];
+  const int b = blockIdx.y;
+  const BigState st = a.st[b];
+  if (st.kb == 0) return;
+  const int F = a.fronts[b];
+  const int f = a.ff[F], k = a.fk[F], start = a.fstart[F];
+  const int i0 = k + blockIdx.x * 64;
+  if (i0 >= f) return;
+  const int j0 = st.cur, kb = st.kb, nb = st.nb;
+  const T* A0 = pool + a.pool_off[F];
+  T* A = pool + a.pool_off[F];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid < nb) {
+    lp[tid] = a.lperm[(int64_t)b * BF_NB + tid];
+    if (tid < kb) {
+      const int t = tid;
+      const int tt = a.piv_type[start + j0 + t];
+      ty[t] = tt;
+      const double dd = (double)A0[(int64_t)(j0 + t) * f + j0 + t];
+      dA[t] = dd;
+      if (tt == 2) dB[t] = (double)A0[(int64_t)(j0 + t) * f + j0 + t + 1];
+      else if (tt == 3) dB[t] = (double)A0[(int64_t)(j0 + t - 1) * f + j0 + t];
+      else dB[t] = 0.0;
+    }
+  }
+  __syncthreads();
+  // W(c, t) for the panel's rows c > t
+  for (int e = tid; e < BF_NB * BF_NB; e += 256) {
+    const int c = e & 63, t = e >> 6;
+    double w = 0.0;
+    if (t < kb && c < nb && c > t) {
+      const T* Lc = A0 + (int64_t)(j0) * f + j0 + c;  // row j0 + c
+      const int tt = ty[t];
+      if (tt == 1) {
+        w = (double)Lc[(int64_t)t * f] * dA[t];
+      } else if (tt == 2) {
+        const double l1 = (double)Lc[(int64_t)t * f];
+        const double l2 = c > t + 1 ? (double)Lc[(int64_t)(t + 1) * f] : 0.0;
+        w = l1 * dA[t] + l2 * dB[t];
+      } else {
+        const double l1 = (double)Lc[(int64_t)(t - 1) * f];
+        const double l2 = (double)Lc[(int64_t)t * f];
+        w = l1 * dB[t] + l2 * dA[t];
+      }
+    }
+    W[t * (BF_NB + 1) + c] = w;
+  }
+  __syncthreads();
+  constexpr int R = 16;
+  double v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = i0 + wave * R + r;
+    v[r] = (i < f && lane < nb) ? (double)A[(int64_t)(j0 + lp[lane]) * f + i] : 0.0;
+  }
+  int t = 0;
+  while (t < kb) {
+    const int tt = ty[t];
+    if (tt == 1) {
+      const double wc = W[t * (BF_NB + 1) + lane];
+      const double dinv = 1.0 / dA[t];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double l = bcast(v[r], t) * dinv;
+        if (lane == t) v[r] = l;
+        else if (lane > t) v[r] -= l * wc;
+      }
+      t += 1;
+    } else {
+      const double d11 = dA[t], d21 = dB[t], d22 = dA[t + 1];
+      const double idet = 1.0 / (d11 * d22 - d21 * d21);
+      const double w1 = W[t * (BF_NB + 1) + lane], w2 = W[(t + 1) * (BF_NB + 1) + lane];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double y1 = bcast(v[r], t), y2 = bcast(v[r], t + 1);
+        const double l1 = (y1 * d22 - y2 * d21) * idet;
+        const double l2 = (y2 * d11 - y1 * d21) * idet;
+        if (lane == t) v[r] = l1;
+        else if (lane == t + 1) v[r] = l2;
+        else if (lane > t + 1) v[r] -= l1 * w1 + l2 * w2;
+      }
+      t += 2;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = i0 + wave * R + r;
+    if (i < f && lane < nb) A[(int64_t)(j0 + lane) * f + i] = (T)v[r];
+  }
+}
+
+// Trailing update of one 64 x 64 lower-triangle tile of [j0 + nb, f)^2:
+// A(i, c) -= sum_t L(i, t) W(c, t) over the kb factorised panel columns.
+template <class T>
+__global__ void __launch_bounds__(256) big_trailing_kernel(BigArgs a, T* pool) {
+  __shared__ double La[BF_NB * (BF_TILE + 1)];  // La[t][ii] = L(r0 + ii, j0 + t)
+  __shared__ double Wb[BF_NB * (BF_TILE + 1)];  // Wb[t][cc] = W(c0 + cc, j0 + t); tile result later
+  __shared__ double dA[BF_NB], dB[BF_NB];
+  __shared__ int ty[BF_NB];
+  const int b = blockIdx.y;
+  const BigState st = a.st[b];
+  if (st.kb == 0) return;
+  const int F = a.fronts[b];
+  const int f = a.ff[F], start = a.fstart[F];
+  const int j0 = st.cur, kb = st.kb, c0 = st.cur + st.nb;
+  if (c0 >= f) return;
+  const int nt = (f - c0 + BF_TILE - 1) / BF_TILE;
+  const int ntiles = nt * (nt + 1) / 2;
+  T* A = pool + a.pool_off[F];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid < kb) {
+    const int t = tid;
+    const int tt = a.piv_type[start + j0 + t];
+    ty[t] = tt;
+    dA[t] = (double)A[(int64_t)(j0 + t) * f + j0 + t];
+    if (tt == 2) dB[t] = (double)A[(int64_t)(j0 + t) * f + j0 + t + 1];
+    else if (tt == 3) dB[t] = (double)A[(int64_t)(j0 + t - 1) * f + j0 + t];
+    else dB[t] = 0.0;
+  }
+  __syncthreads();
+  const int kpad = (kb + 3) & ~3;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int bi = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+    while ((bi + 1) * (bi + 2) / 2 <= tile) ++bi;
+    while (bi * (bi + 1) / 2 > tile) --bi;
+    const int bj = tile - bi * (bi + 1) / 2;
+    const int r0 = c0 + bi * BF_TILE, cb0 = c0 + bj * BF_TILE;
+    // stage L rows of the tile and W of its columns (zero beyond kb / f)
+    for (int e = tid; e < BF_NB * BF_TILE; e += 256) {
+      const int ii = e & 63, t = e >> 6;
+      double lv = 0.0, wv = 0.0;
+      if (t < kb) {
+        const int i = r0 + ii, c = cb0 + ii;
+        if (i < f) lv = (double)A[(int64_t)(j0 + t) * f + i];
+        if (c < f) {
+          const int tt = ty[t];
+          if (tt == 1) {
+            wv = (double)A[(int64_t)(j0 + t) * f + c] * dA[t];
+          } else if (tt == 2) {
+            wv = (double)A[(int64_t)(j0 + t) * f + c] * dA[t] +
+                 (double)A[(int64_t)(j0 + t + 1) * f + c] * dB[t];
+          } else {
+            wv = (double)A[(int64_t)(j0 + t - 1) * f + c] * dB[t] +
+                 (double)A[(int64_t)(j0 + t) * f + c] * dA[t];
+          }
+        }
+      }
+      La[t * (BF_TILE + 1) + ii] = lv;
+      Wb[t * (BF_TILE + 1) + ii] = wv;
+    }
+    __syncthreads();
+    // wave w: column block w (16 columns), all four row blocks
+    v4d acc[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) acc[rt] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int t0 = 0; t0 < kpad; t0 += 4) {
+      const int kr = t0 + (lane >> 4);
+      const double bv = Wb[kr * (BF_TILE + 1) + wave * 16 + (lane & 15)];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) {
+        const double av = La[kr * (BF_TILE + 1) + rt * 16 + (lane & 15)];
+        acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[rt], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    // tile product to LDS (reusing Wb as Ct[ii][cc]), then a coalesced
+    // read-modify-write of the lower triangle
+    double* Ct = Wb;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ii = rt * 16 + (lane >> 4) + 4 * r;
+        Ct[ii * (BF_TILE + 1) + wave * 16 + (lane & 15)] = acc[rt][r];
+      }
+    __syncthreads();
+    for (int e = tid; e < BF_TILE * BF_TILE; e += 256) {
+      const int ii = e & 63, cc = e >> 6;
+      const int i = r0 + ii, c = cb0 + cc;
+      if (i < f && c < f && i >= c) {
+        T* ap = A + (int64_t)c * f + i;
+        *ap = (T)((double)*ap - Ct[ii * (BF_TILE + 1) + cc]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void big_init_kernel(BigArgs a, int nbig) {
+  const int b = blockIdx.x;
+  if (b >= nbig) return;
+  const int k = a.fk[a.fronts[b]];
+  int* perm = a.perm + (int64_t)b * a.perm_stride;
+  for (int t = threadIdx.x; t < k; t += blockDim.x) perm[t] = t;
+  if (threadIdx.x == 0) a.st[b] = BigState{0, 0, 0, 0, 0, 0, 0, 0};
+}
+
+__global__ void big_pending_kernel(BigArgs a, int nbig, int* pending) {
+  int c = 0;
+  for (int b = threadIdx.x; b < nbig; b += blockDim.x)
+    if (a.st[b].next < a.fk[a.fronts[b]]) ++c;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  __shared__ int part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) *pending = part[0] + part[1] + part[2] + part[3];
+}
+
+__global__ void big_finish_kernel(BigArgs a, int nbig) {
+  const int b = blockIdx.x;
+  if (b >= nbig) return;
+  const int F = a.fronts[b];
+  const int k = a.fk[F], start = a.fstart[F];
+  const int* perm = a.perm + (int64_t)b * a.perm_stride;
+  for (int t = threadIdx.x; t < k; t += blockDim.x) a.piv_perm[start + t] = perm[t];
+  if (threadIdx.x == 0) {
+    a.stat[4 * F + 0] = a.st[b].neg;
+    a.stat[4 * F + 1] = a.st[b].pert;
+    a.stat[4 * F + 2] = a.st[b].two;
+  }
+}
+
+}  // namespace
+
+void set_bigfront_attributes() {
+  HIPCHECK(hipFuncSetAttribute((const void*)big_panel_kernel<double>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, BF_LDS * (int)sizeof(double)));
+  HIPCHECK(hipFuncSetAttribute((const void*)big_panel_kernel<float>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, BF_LDS * (int)sizeof(double)));
+}
+
+int bigfront_max_k() { return BF_LDS; }
+
+template <class T>
+void factor_big_fronts(riga_problem* pr, T* pool, const int32_t* fronts,
+                       const std::vector<int>& big_f, const std::vector<int>& big_k,
+                       double pivtol, hipStream_t s) {
+  const int nbig = (int)big_f.size();
+  if (nbig == 0) return;
+  int maxk = 0, maxcb = 0, max_tiles = 0;
+  int steps = 0;
+  for (int i = 0; i < nbig; ++i) {
+    const int f = big_f[i], k = big_k[i];
+    maxk = std::max(maxk, k);
+    maxcb = std::max(maxcb, f - k);
+    int j0 = 0, n = 0;
+    while (j0 < k) {
+      j0 += panel_width(k - j0);
+      ++n;
+    }
+    steps = std::max(steps, n);
+    const int nb0 = panel_width(k);
+    const int nt = (f - nb0 + BF_TILE - 1) / BF_TILE;
+    max_tiles = std::max(max_tiles, nt * (nt + 1) / 2);
+  }
+  if (maxk > bigfront_max_k())
+    throw Error(RIGA_EUNSUPPORTED, "fully-summed block too large for the panel kernel");
+  // scratch sized for the largest level at set-up (kept with the problem)
+  const int64_t stride = maxk + 1;
+  const size_t need_perm = (size_t)nbig * stride, need_lp = (size_t)nbig * BF_NB;
+  const size_t need_st = (size_t)nbig * sizeof(BigState) / sizeof(int32_t) + 1;
+  if (pr->big_perm.n < need_perm) pr->big_perm.alloc(need_perm, pr->home);
+  if (pr->big_lperm.n < need_lp) pr->big_lperm.alloc(need_lp, pr->home);
+  if (pr->big_state.n < need_st) pr->big_state.alloc(need_st, pr->home);
+  int32_t* pending = pr->big_state.p + (need_st - 1);
+  BigArgs a{};
+  a.fronts = fronts;
+  a.ff = pr->d_ff.p;
+  a.fk = pr->d_fk.p;
+  a.fstart = pr->d_fstart.p;
+  a.pool_off = pr->d_pool_off.p;
+  a.piv_perm = pr->piv_perm.p;
+  a.piv_type = pr->piv_type.p;
+  a.stat = pr->front_stat.p;
+  a.perm = pr->big_perm.p;
+  a.perm_stride = stride;
+  a.lperm = pr->big_lperm.p;
+  a.st = reinterpret_cast<BigState*>(pr->big_state.p);
+  a.pivtol = pivtol;
+  big_init_kernel<<<nbig, 256, 0, s>>>(a, nbig);
+  HIPCHECK(hipGetLastError());
+  const unsigned cb_blocks = (unsigned)std::max(1, (maxcb + 63) / 64);
+  const unsigned tpf = (unsigned)std::max(1, std::min(max_tiles, std::max(1, 2048 / nbig)));
+  auto run = [&](int n) {
+    for (int it = 0; it < n; ++it) {
+      big_panel_kernel<T><<<nbig, 1024, BF_LDS * sizeof(double), s>>>(a, pool);
+      if (maxcb > 0) big_cbrows_kernel<T><<<dim3(cb_blocks, nbig), 256, 0, s>>>(a, pool);
+      big_trailing_kernel<T><<<dim3(tpf, nbig), 256, 0, s>>>(a, pool);
+    }
+    HIPCHECK(hipGetLastError());
+  };
+  run(steps);
+  // panels that ended early leave columns for further steps
+  for (int guard = 0;; ++guard) {
+    big_pending_kernel<<<1, 256, 0, s>>>(a, nbig, pending);
+    HIPCHECK(hipGetLastError());
+    int left = 0;
+    HIPCHECK(hipMemcpyAsync(&left, pending, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (left == 0) break;
+    if (guard > maxk) throw Error(RIGA_EDEVICE, "blocked factorisation made no progress");
+    run(4);
+  }
+  big_finish_kernel<<<nbig, 256, 0, s>>>(a, nbig);
+  HIPCHECK(hipGetLastError());
+}
+
+template void factor_big_fronts<double>(riga_problem*, double*, const int32_t*, const std::vector<int>&,
+                                        const std::vector<int>&, double, hipStream_t);
+template void factor_big_fronts<float>(riga_problem*, float*, const int32_t*, const std::vector<int>&,
+                                       const std::vector<int>&, double, hipStream_t);
+
+}  // namespace riga

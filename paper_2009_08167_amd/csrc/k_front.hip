@@ -13,7 +13,7 @@
 //     Bunch-Kaufman pivots chosen among the fully-summed rows), L21 and the
 //     Schur-complement update of the contribution block.  Fronts up to
 //     LDS_FRONT_MAX are factorised entirely in LDS by one workgroup; larger
-//     fronts use the blocked path (panel kernel + MFMA trailing update).
+//     fronts use the blocked multi-workgroup path of k_bigfront.hip.
 //
 // Fronts are dense column-major f x f blocks in one pool (lower triangle
 // used).  After factorisation, column t < k holds L(:, t) below the
@@ -281,245 +281,6 @@ __global__ void __launch_bounds__(256) front_factor_lds_kernel(FrontArgs fa, T* 
   }
 }
 
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-// LDS budget of the blocked kernel's panel (doubles).
-constexpr int PANEL_LDS = 18432;
-constexpr int PANEL_MAX = 32;
-
-// Fronts too large for LDS: blocked right-looking LDL^T, one workgroup per
-// front.  Each panel of up to PANEL_MAX fully-summed columns (all rows
-// below the panel's top) is factorised in LDS with Bunch-Kaufman pivots
-// whose partner column is restricted to the panel (the stability test still
-// uses the column maximum over all fully-summed rows); the trailing matrix
-// then receives the panel's update A -= L_p (L_p D_p)^T from f64 MFMA
-// (16x16x4) tiles.  When the 1x1 test fails on the panel's last column, the
-// panel ends early so that the column starts the next panel with partners.
-template <class T>
-__global__ void __launch_bounds__(512) front_factor_blocked_kernel(FrontArgs fa, T* pool,
-                                                                 const int32_t* fronts,
-                                                                 int* perm_scratch,
-                                                                 int64_t perm_stride,
-                                                                 double pivtol) {
-  extern __shared__ double Pn[];
-  __shared__ double dA[PANEL_MAX + 1], dB[PANEL_MAX + 1];
-  __shared__ int tinfo[PANEL_MAX + 1];
-  __shared__ PivotStep dec;
-  __shared__ int s_end;
-  const int F = fronts[blockIdx.x];
-  const int f = fa.ff[F], k = fa.fk[F];
-  const int start = fa.fstart[F];
-  T* A = pool + fa.pool_off[F];
-  int32_t* type_out = fa.piv_type + start;
-  int* perm = perm_scratch + (int64_t)blockIdx.x * perm_stride;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int NT = 512, NW = NT / 64;
-  for (int t = tid; t < k; t += NT) perm[t] = t;
-  int neg = 0, pert = 0, two = 0;
-  int j0 = 0;
-  while (j0 < k) {
-    const int m = f - j0;                 // panel rows
-    int nb = min(min(PANEL_MAX, k - j0), PANEL_LDS / m);
-    if (nb < 1) nb = 1;
-    auto P = [&](int r, int c) -> double& { return Pn[(c - j0) * m + (r - j0)]; };
-    __syncthreads();
-    for (int e = tid; e < nb * m; e += NT) {
-      const int c = e / m, r = e % m;
-      if (r >= c) Pn[e] = (double)A[(int64_t)(j0 + c) * f + j0 + r];
-    }
-    if (tid == 0) s_end = 0;
-    __syncthreads();
-    int jj = 0;
-    while (jj < nb) {
-      const int j = j0 + jj;
-      const int pend = j0 + nb;
-      if (wave == 0) {
-        double cmax = 0.0, rmax_in = 0.0;
-        int r = -1;
-        for (int i = j + 1 + lane; i < k; i += 64) {
-          const double v = fabs(P(i, j));
-          cmax = fmax(cmax, v);
-          if (i < pend && v > rmax_in) { rmax_in = v; r = i; }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-          cmax = fmax(cmax, __shfl_xor(cmax, off));
-          const double ov = __shfl_xor(rmax_in, off);
-          const int orr = __shfl_xor(r, off);
-          if (ov > rmax_in || (ov == rmax_in && orr >= 0 && (r < 0 || orr < r))) { rmax_in = ov; r = orr; }
-        }
-        const double akk = fabs(P(j, j));
-        int kind = 1, sa = -1, sb = -1, end_panel = 0;
-        if (cmax == 0.0 || akk >= BK_ALPHA * cmax) {
-          kind = 1;
-        } else if (r < 0) {
-          // no partner inside the panel: end the panel here if possible
-          if (jj > 0) end_panel = 1;
-        } else {
-          double rmax = 0.0;
-          for (int i = j + lane; i < k; i += 64) {
-            if (i == r) continue;
-            rmax = fmax(rmax, i < r ? fabs(P(r, i)) : fabs(P(i, r)));
-          }
-          for (int off = 32; off > 0; off >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, off));
-          const double arr = fabs(P(r, r));
-          if (akk * rmax >= BK_ALPHA * cmax * cmax) {
-            kind = 1;
-          } else if (arr >= BK_ALPHA * rmax) {
-            kind = 1;
-            sa = j;
-            sb = r;
-          } else {
-            kind = 2;
-            if (r != j + 1) { sa = j + 1; sb = r; }
-          }
-        }
-        if (lane == 0) {
-          dec.kind = kind;
-          dec.swap_a = sa;
-          dec.swap_b = sb;
-          dec.perturbed = end_panel;
-        }
-      }
-      __syncthreads();
-      if (dec.perturbed) break;  // panel ends before column j
-      const int kind = dec.kind;
-      const int p = dec.swap_a, q = dec.swap_b;
-      if (p >= 0) {
-        // symmetric interchange p <-> q: previous panels' rows in global
-        // memory, everything else in this panel
-        for (int c = tid; c < j0; c += NT) {
-          T tmp = A[(int64_t)c * f + p];
-          A[(int64_t)c * f + p] = A[(int64_t)c * f + q];
-          A[(int64_t)c * f + q] = tmp;
-        }
-        for (int c = j0 + tid; c < f; c += NT) {
-          if (c < p) {
-            double t0 = P(p, c); P(p, c) = P(q, c); P(q, c) = t0;
-          } else if (c == p) {
-            double t0 = P(p, p); P(p, p) = P(q, q); P(q, q) = t0;
-          } else if (c < q) {
-            double t0 = P(c, p); P(c, p) = P(q, c); P(q, c) = t0;
-          } else if (c > q) {
-            double t0 = P(c, p); P(c, p) = P(c, q); P(c, q) = t0;
-          }
-        }
-        if (tid == 0) { int tp = perm[p - 0]; perm[p] = perm[q]; perm[q] = tp; }
-      }
-      __syncthreads();
-      if (kind == 1) {
-        double d = P(j, j);
-        if (fabs(d) < pivtol) d = d < 0.0 ? -pivtol : pivtol;
-        __syncthreads();
-        if (tid == 0) {
-          if (d != P(j, j)) ++pert;
-          P(j, j) = d;
-          if (d < 0.0) ++neg;
-          type_out[j] = 1;
-          tinfo[jj] = 1;
-          dA[jj] = d;
-          dB[jj] = 0.0;
-        }
-        const double dinv = 1.0 / d;
-        for (int r = j + 1 + tid; r < f; r += NT) P(r, j) *= dinv;
-        __syncthreads();
-        for (int c = j + 1 + wave; c < pend; c += NW) {
-          const double uc = P(c, j) * d;
-          for (int r = c + lane; r < f; r += 64) P(r, c) -= P(r, j) * uc;
-        }
-      } else {
-        const double d11 = P(j, j), d21 = P(j + 1, j), d22 = P(j + 1, j + 1);
-        const double det = d11 * d22 - d21 * d21;
-        if (tid == 0) {
-          if (det < 0.0) neg += 1;
-          else if (d11 < 0.0) neg += 2;
-          ++two;
-          type_out[j] = 2;
-          type_out[j + 1] = 3;
-          tinfo[jj] = 2;
-          tinfo[jj + 1] = 3;
-          dA[jj] = d11;
-          dB[jj] = d21;
-          dA[jj + 1] = d22;
-          dB[jj + 1] = d21;
-        }
-        const double idet = 1.0 / det;
-        for (int r = j + 2 + tid; r < f; r += NT) {
-          const double a = P(r, j), b = P(r, j + 1);
-          P(r, j) = (a * d22 - b * d21) * idet;
-          P(r, j + 1) = (b * d11 - a * d21) * idet;
-        }
-        __syncthreads();
-        for (int c = j + 2 + wave; c < pend; c += NW) {
-          const double l1 = P(c, j), l2 = P(c, j + 1);
-          const double u1 = l1 * d11 + l2 * d21, u2 = l1 * d21 + l2 * d22;
-          for (int r = c + lane; r < f; r += 64) P(r, c) -= P(r, j) * u1 + P(r, j + 1) * u2;
-        }
-      }
-      jj += kind;
-      __syncthreads();
-    }
-    const int kb = jj;
-    __syncthreads();
-    // panel back to the front: factored columns hold L and D, the rest the
-    // values updated by this panel's columns
-    for (int e = tid; e < nb * m; e += NT) {
-      const int c = e / m, r = e % m;
-      if (r >= c) A[(int64_t)(j0 + c) * f + j0 + r] = (T)Pn[e];
-    }
-    // trailing update of columns >= j0 + nb: A(i, c) -= sum_t L(i, t) W(c, t),
-    // W = L D, over kb panel columns, lower triangle, 16x16 MFMA blocks
-    const int c0 = j0 + nb;
-    if (kb > 0 && c0 < f) {
-      const int nbk = (f - c0 + 15) / 16;
-      const int nblocks = nbk * (nbk + 1) / 2;
-      const int kpad = (kb + 3) & ~3;
-      for (int blk = wave; blk < nblocks; blk += NW) {
-        // block (bi, bj) with bi >= bj in the lower triangle
-        int bi = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
-        while ((bi + 1) * (bi + 2) / 2 <= blk) ++bi;
-        while (bi * (bi + 1) / 2 > blk) --bi;
-        const int bj = blk - bi * (bi + 1) / 2;
-        const int i0 = c0 + bi * 16, m0 = c0 + bj * 16;
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-        const int ia = i0 + (lane & 15);      // A-operand row
-        const int cb = m0 + (lane & 15);      // B-operand column
-        for (int t0 = 0; t0 < kpad; t0 += 4) {
-          const int tl = t0 + (lane >> 4);
-          double av = 0.0, bv = 0.0;
-          if (tl < kb) {
-            const int t = j0 + tl;
-            if (ia < f) av = P(ia, t);
-            if (cb < f) {
-              const int ty = tinfo[tl];
-              if (ty == 1) bv = P(cb, t) * dA[tl];
-              else if (ty == 2) bv = P(cb, t) * dA[tl] + P(cb, t + 1) * dB[tl];
-              else bv = P(cb, t - 1) * dB[tl] + P(cb, t) * dA[tl];
-            }
-          }
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-        }
-        // lane holds D(i, c) for c = lane & 15, i = (lane >> 4) + 4 r
-        const int cc = m0 + (lane & 15);
-        for (int r4 = 0; r4 < 4; ++r4) {
-          const int ii = i0 + (lane >> 4) + 4 * r4;
-          if (ii < f && cc < f && ii >= cc) {
-            T* ap = A + (int64_t)cc * f + ii;
-            *ap = (T)((double)*ap - acc[r4]);
-          }
-        }
-      }
-    }
-    j0 += kb;
-    __syncthreads();
-  }
-  for (int t = tid; t < k; t += NT) fa.piv_perm[start + t] = perm[t];
-  if (tid == 0) {
-    fa.stat[4 * F + 0] = neg;
-    fa.stat[4 * F + 1] = pert;
-    fa.stat[4 * F + 2] = two;
-  }
-}
-
 FrontArgs front_args(riga_problem* pr) {
   FrontArgs fa{};
   fa.fk = pr->d_fk.p;
@@ -546,16 +307,6 @@ void factor_levels(riga_problem* pr, T* pool, T* hpool, double sigma) {
   hipStream_t s = pr->stream;
   FrontArgs fa = front_args(pr);
   const double pivtol = 1e-20 * (pr->normK1 + fabs(sigma) * pr->normM1);
-  // scratch for fronts factorised by the blocked kernel (pivot permutations)
-  int max_big = 0, max_k_big = 0;
-  for (auto& L : pr->levels) {
-    const int ns = L.n_upto(MAXF);
-    max_big = std::max(max_big, L.n - ns);
-    if (L.n > ns) max_k_big = std::max(max_k_big, L.max_k);
-  }
-  DBuf<int> perm_scratch;
-  const int64_t stride = (int64_t)max_k_big + 1;
-  if (max_big > 0) perm_scratch.alloc((size_t)max_big * stride, s);
   static std::once_flag attr_once;
   std::call_once(attr_once, [] { set_kernel_attributes(); });
   for (size_t h = 0; h < pr->levels.size(); ++h) {
@@ -570,26 +321,19 @@ void factor_levels(riga_problem* pr, T* pool, T* hpool, double sigma) {
       HIPCHECK(hipGetLastError());
     }
     if (L.n > ns) {
-      front_factor_blocked_kernel<T><<<L.n - ns, 512, PANEL_LDS * sizeof(double), s>>>(
-          fa, pool, L.fronts.p + ns, perm_scratch.p, stride, pivtol);
-      HIPCHECK(hipGetLastError());
+      std::vector<int> bf(L.host_f.begin() + ns, L.host_f.end());
+      std::vector<int> bk(L.host_k.begin() + ns, L.host_k.end());
+      factor_big_fronts<T>(pr, pool, L.fronts.p + ns, bf, bk, pivtol, s);
     }
   }
   launch_front_inverse<T>(pr, pool, hpool, s);
   launch_pivot_maps(pr, s);
-  HIPCHECK(hipStreamSynchronize(s));  // scratch is released on return
+  HIPCHECK(hipStreamSynchronize(s));
 }
 
 }  // namespace
 
-void set_front_attributes() {
-  HIPCHECK(hipFuncSetAttribute((const void*)front_factor_blocked_kernel<double>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               PANEL_LDS * (int)sizeof(double)));
-  HIPCHECK(hipFuncSetAttribute((const void*)front_factor_blocked_kernel<float>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               PANEL_LDS * (int)sizeof(double)));
-}
+void set_front_attributes() {}
 
 void factor_numeric(riga_problem* pr, double sigma, int precision) {
   const Analysis& an = pr->an;

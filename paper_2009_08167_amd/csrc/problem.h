@@ -94,6 +94,7 @@ struct LevelDev {
   int64_t cols = 0;          // sum of front orders (assembly grid)
   int max_f = 0, max_k = 0;
   std::vector<int> host_f;   // front orders, ascending (same order as `fronts`)
+  std::vector<int> host_k;   // their fully-summed orders
   DBuf<int32_t> fronts;      // front ids sorted by order
   DBuf<int64_t> col_prefix;  // [n+1] prefix sums of front orders
   DBuf<WorkUnit> fwd_units;  // forward sweep: row blocks of this level's fronts
@@ -141,6 +142,7 @@ struct riga_problem {
   riga::DBuf<float> pool32;
   riga::DBuf<double> h64;                   // partitioned inverses, sum f * k
   riga::DBuf<float> h32;
+  riga::DBuf<int32_t> big_perm, big_lperm, big_state;  // blocked-factorisation scratch
   riga::DBuf<riga::WorkUnit> inv_units;     // row blocks of every front
   int n_inv_units = 0;
   riga::DBuf<int32_t> piv_perm, piv_type;   // by new index
@@ -186,6 +188,13 @@ void factor_numeric(riga_problem* pr, double sigma, int precision);
 template <class T>
 void launch_front_inverse(riga_problem* pr, const T* pool, T* h, hipStream_t s);
 size_t front_inverse_lds(int max_k);
+// Fronts above the LDS limit of one tree level (`fronts`, orders big_f,
+// fully-summed orders big_k): blocked LDL^T spread over many workgroups.
+template <class T>
+void factor_big_fronts(riga_problem* pr, T* pool, const int32_t* fronts,
+                       const std::vector<int>& big_f, const std::vector<int>& big_k,
+                       double pivtol, hipStream_t s);
+int bigfront_max_k();
 // Pivot-order gather maps of the sweeps (after each factorisation).
 void launch_pivot_maps(riga_problem* pr, hipStream_t s);
 // Raise the dynamic-LDS limit of the kernels that need more than 64 KB (for

@@ -55,11 +55,13 @@ void dfree(void* p, hipStream_t s) {
 void set_front_attributes();
 void set_solve_attributes();
 void set_inverse_attributes();
+void set_bigfront_attributes();
 
 void set_kernel_attributes() {
   set_front_attributes();
   set_solve_attributes();
   set_inverse_attributes();
+  set_bigfront_attributes();
 }
 
 // Copies the per-element coefficients (host values are checked positive)
@@ -170,11 +172,13 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
     L.n = (int)fr.size();
     std::vector<int64_t> pref(fr.size() + 1, 0);
     L.host_f.clear();
+    L.host_k.clear();
     for (size_t i = 0; i < fr.size(); ++i) {
       pref[i + 1] = pref[i] + an.f_f[fr[i]];
       L.max_f = std::max(L.max_f, an.f_f[fr[i]]);
       L.max_k = std::max(L.max_k, an.f_k[fr[i]]);
       L.host_f.push_back(an.f_f[fr[i]]);
+      L.host_k.push_back(an.f_k[fr[i]]);
     }
     L.cols = pref.back();
     L.fronts.upload(fr, s);
@@ -223,6 +227,8 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
     pr->n_inv_units = (int)iu.size();
     pr->inv_units.upload(iu, s);
   }
+  if (an.max_fs > bigfront_max_k())
+    throw Error(RIGA_EUNSUPPORTED, "fully-summed block too large for the panel kernel");
   if (front_inverse_lds(an.max_fs) > 159 * 1024)
     throw Error(RIGA_EUNSUPPORTED, "fully-summed block too large for the inverse kernel's LDS");
   pr->piv_perm.alloc(N, s);
