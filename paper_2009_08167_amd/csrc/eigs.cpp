@@ -65,7 +65,7 @@ struct Solver {
   int max_ir;
   DBuf<double> B, W, x, y, c1, c2, partial, dotp, alpha, beta, scal;
   DBuf<int32_t> flag;
-  DBuf<double> theta, tdest, S, tdwork, Sh, Ub, KU, MU, rqn, rqd, rn2, un2, lam, nrm;
+  DBuf<double> theta, tdest, S, Sh, Ub, KU, MU, rqn, rqd, rn2, un2, lam, nrm;
   DBuf<int32_t> sel;
   DBuf<double> ir_r, ir_d;
   std::vector<Locked> locked;
@@ -95,8 +95,7 @@ struct Solver {
     theta.alloc(mb + 1, s);
     tdest.alloc(mb + 1, s);
     S.alloc((size_t)(mb + 1) * (mb + 1), s);
-    tdwork.alloc((size_t)6 * (mb + 1) * (mb + 64), s);
-    sel.alloc(mb + 1, s);
+    sel.alloc(2 * (mb + 2), s);
     const int umax = mb + 1;
     Sh.alloc((size_t)(mb + 1) * umax, s);
     Ub.alloc((size_t)N * umax, s);
@@ -206,7 +205,7 @@ struct Solver {
     auto a = clk::now();
     Ritz r;
     r.m = m;
-    launch_ritz_check(alpha.p, beta.p, m, theta.p, tdest.p, tdwork.p, s);
+    launch_ritz_check(alpha.p, beta.p, m, theta.p, tdest.p, s);
     r.theta.resize(m);
     r.est.resize(m);
     HIPCHECK(hipMemcpyAsync(r.theta.data(), theta.p, m * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -232,8 +231,19 @@ struct Solver {
     std::vector<double> Sv((size_t)m * n);
     if (n == 0) return Sv;
     std::vector<int32_t> ix(idx.begin(), idx.end());
-    HIPCHECK(hipMemcpyAsync(sel.p, ix.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    launch_ritz_vectors(alpha.p, beta.p, m, theta.p, sel.p, n, S.p, tdwork.p, s);
+    // clusters: adjacent selected eigenvalues closer than 1e-3 relative
+    std::vector<int32_t> cl{0};
+    for (int i = 1; i < n; ++i) {
+      const double t0 = r.theta[idx[i - 1]], t1 = r.theta[idx[i]];
+      const bool close = idx[i] == idx[i - 1] + 1 &&
+                         std::fabs(t1 - t0) <= 1e-3 * std::max(std::fabs(t0), std::fabs(t1));
+      if (!close) cl.push_back(i);
+    }
+    cl.push_back(n);
+    const int ncl = (int)cl.size() - 1;
+    ix.insert(ix.end(), cl.begin(), cl.end());
+    HIPCHECK(hipMemcpyAsync(sel.p, ix.data(), ix.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    launch_ritz_vectors(alpha.p, beta.p, m, theta.p, sel.p, sel.p + n, ncl, S.p, s);
     HIPCHECK(hipMemcpyAsync(Sv.data(), S.p, Sv.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     return Sv;

@@ -41,31 +41,33 @@ struct SolveArgs {
   double* fwd;              // z of the forward sweep, by new (pivot-order) index
 };
 
-// Forward sweep: 64 rows of one front per workgroup, lanes over rows (the
-// column-major H is read coalesced), the four waves over interleaved columns.
-// The first 16 loads of H are issued before the gather of y so that both
-// latencies overlap.
-template <class T>
+// Forward sweep: RW rows of one front per workgroup, lanes over rows (the
+// column-major H is read coalesced), 256 / RW thread groups over interleaved
+// columns (RW = 16 on levels with few fronts, for more loads in flight per
+// row).  The first 16 loads of H are issued before the gather of y so that
+// both latencies overlap.
+template <class T, int RW>
 __global__ void __launch_bounds__(256) fwd_kernel(SolveArgs sa, const T* __restrict__ H,
                                                   const WorkUnit* __restrict__ units,
                                                   const double* __restrict__ b) {
+  constexpr int G = 256 / RW;
   extern __shared__ double smem[];
   const WorkUnit u = units[blockIdx.x];
   const int f = u.f, k = u.k, start = u.start;
   const int lo = u.lo, hi = u.hi;
   double* y = smem;          // k: permuted fully-summed right-hand side
-  double* psum = y + k;      // 4 x 64 partial sums
+  double* psum = y + k;      // G x RW partial sums
   const int gs = sa.gstride;
-  const int tid = threadIdx.x, lane = tid & 63, g = tid >> 6;
-  const int i = lo + lane;
+  const int tid = threadIdx.x, rl = tid % RW, g = tid / RW;
+  const int i = lo + rl;
   const bool row = i < hi;
   const int jend = row ? (i < k ? i : k) : 0;
   const T* hc = H + u.h_off + i;
   double hv[16];
-  const bool first = g + 60 < jend;
+  const bool first = g + 15 * G < jend;
   if (first) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) hv[q] = (double)hc[(int64_t)(g + 4 * q) * f];
+    for (int q = 0; q < 16; ++q) hv[q] = (double)hc[(int64_t)(g + G * q) * f];
   }
   // the (i, i-1) slot of a 2x2 pivot block holds D, not L11^{-1} (= 0)
   const int skip = (row && i < k && i > 0 && sa.piv_type[start + i] == 3) ? i - 1 : -1;
@@ -98,34 +100,36 @@ __global__ void __launch_bounds__(256) fwd_kernel(SolveArgs sa, const T* __restr
   int j = g;
   if (first) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) s += (g + 4 * q == skip ? 0.0 : hv[q]) * y[g + 4 * q];
-    j += 64;
+    for (int q = 0; q < 16; ++q) s += (g + G * q == skip ? 0.0 : hv[q]) * y[g + G * q];
+    j += 16 * G;
   }
-  for (; j + 60 < jend; j += 64) {
+  for (; j + 15 * G < jend; j += 16 * G) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) hv[q] = (double)hc[(int64_t)(j + 4 * q) * f];
+    for (int q = 0; q < 16; ++q) hv[q] = (double)hc[(int64_t)(j + G * q) * f];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) s += (j + 4 * q == skip ? 0.0 : hv[q]) * y[j + 4 * q];
+    for (int q = 0; q < 16; ++q) s += (j + G * q == skip ? 0.0 : hv[q]) * y[j + G * q];
   }
-  for (; j < jend; j += 4)
+  for (; j < jend; j += G)
     if (j != skip) s += (double)hc[(int64_t)j * f] * y[j];
-  psum[g * 64 + lane] = s;
+  psum[g * RW + rl] = s;
   __syncthreads();
   if (g == 0 && row) {
-    const double tot = (psum[lane] + psum[64 + lane]) + (psum[128 + lane] + psum[192 + lane]);
+    double tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < G; ++q) tot += psum[q * RW + rl];
     if (i < k) sa.fwd[start + i] = y[i] + tot;
     else sa.cbvec[u.cb_off + i - k] = ycb - tot;
   }
 }
 
-// Backward sweep: 16 columns of one front per workgroup; wave w takes
-// columns lo + w + 4c (c < 4), lanes over rows, 16 loads in flight per lane
-// (4 row chunks of 64 per iteration).  The first iteration's loads are
-// issued before the gather of v.
-template <class T>
+// Backward sweep: 4 CPW columns of one front per workgroup; wave w takes
+// columns lo + w + 4c (c < CPW), lanes over rows, 16 loads in flight per
+// lane (16 / CPW row chunks of 64 per iteration; CPW = 1 on levels with few
+// fronts).  The first iteration's loads are issued before the gather of v.
+template <class T, int CPW>
 __global__ void __launch_bounds__(256) bwd_kernel(SolveArgs sa, const T* __restrict__ H,
                                                   const WorkUnit* __restrict__ units, double* x) {
-  constexpr int CPW = 4, RCH = 4;
+  constexpr int RCH = 16 / CPW;
   extern __shared__ double smem[];
   const WorkUnit u = units[blockIdx.x];
   const int f = u.f, k = u.k, start = u.start;
@@ -230,7 +234,9 @@ SolveArgs solve_args(riga_problem* pr) {
 
 template <class T>
 void apply_solve_attrs() {
-  const void* ks[] = {(const void*)fwd_kernel<T>, (const void*)bwd_kernel<T>};
+  const void* ks[] = {(const void*)fwd_kernel<T, SWEEP_ROWS>, (const void*)fwd_kernel<T, SWEEP_ROWS_THIN>,
+                      (const void*)bwd_kernel<T, SWEEP_COLS / 4>,
+                      (const void*)bwd_kernel<T, SWEEP_COLS_THIN / 4>};
   for (const void* k : ks)
     HIPCHECK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 159 * 1024));
 }
@@ -248,12 +254,16 @@ void solve_levels(riga_problem* pr, const T* H, const double* b, double* x, hipS
   for (int h = 0; h < nl; ++h) {
     const LevelDev& L = pr->levels[h];
     if (L.n_fwd == 0) continue;
-    fwd_kernel<T><<<L.n_fwd, 256, (size_t)(L.max_k + 256) * sizeof(double), s>>>(sa, H, L.fwd_units.p, b);
+    const size_t lds = (size_t)(L.max_k + 256) * sizeof(double);
+    if (L.fwd_thin) fwd_kernel<T, SWEEP_ROWS_THIN><<<L.n_fwd, 256, lds, s>>>(sa, H, L.fwd_units.p, b);
+    else fwd_kernel<T, SWEEP_ROWS><<<L.n_fwd, 256, lds, s>>>(sa, H, L.fwd_units.p, b);
   }
   for (int h = nl - 1; h >= 0; --h) {
     const LevelDev& L = pr->levels[h];
     if (L.n_bwd == 0) continue;
-    bwd_kernel<T><<<L.n_bwd, 256, (size_t)L.max_f * sizeof(double), s>>>(sa, H, L.bwd_units.p, x);
+    const size_t lds = (size_t)L.max_f * sizeof(double);
+    if (L.bwd_thin) bwd_kernel<T, SWEEP_COLS_THIN / 4><<<L.n_bwd, 256, lds, s>>>(sa, H, L.bwd_units.p, x);
+    else bwd_kernel<T, SWEEP_COLS / 4><<<L.n_bwd, 256, lds, s>>>(sa, H, L.bwd_units.p, x);
   }
   HIPCHECK(hipGetLastError());
 }

@@ -76,9 +76,14 @@ struct FrontDesc {
   int64_t rows_off, cb_off, gmap_off;
 };
 
-// Rows per forward-sweep work unit and columns per backward-sweep unit.
+// Rows per forward-sweep work unit and columns per backward-sweep unit;
+// the thin shapes serve tree levels with few fronts (more workgroups and
+// more loads in flight per row or column).
 constexpr int SWEEP_ROWS = 64;
 constexpr int SWEEP_COLS = 16;
+constexpr int SWEEP_ROWS_THIN = 16;
+constexpr int SWEEP_COLS_THIN = 4;
+constexpr int SWEEP_THIN_BELOW = 512;  // units of the default shape
 
 // One workgroup's share of a front: rows [lo, hi) (forward sweep, inverse)
 // or columns [lo, hi) (backward sweep), with the front's record inlined so a
@@ -100,6 +105,7 @@ struct LevelDev {
   DBuf<WorkUnit> fwd_units;  // forward sweep: row blocks of this level's fronts
   DBuf<WorkUnit> bwd_units;  // backward sweep: column blocks
   int n_fwd = 0, n_bwd = 0;
+  bool fwd_thin = false, bwd_thin = false;
   int n_upto(int fmax) const {  // fronts of order <= fmax (a prefix)
     return (int)(std::upper_bound(host_f.begin(), host_f.end(), fmax) - host_f.begin());
   }
@@ -239,12 +245,14 @@ void launch_scale_cols(double* U, int64_t n, int m, const double* scale, hipStre
 // Projected (tridiagonal) eigenproblem of T_m: diagonal alpha[0..m),
 // off-diagonal beta[1..m) (beta[j] couples j-1 and j), residual beta[m].
 // ritz_check: theta[m] all eigenvalues ascending, est[m] Ritz estimates
-// |beta[m] s_m| (work: 3 m (m+63) doubles).  ritz_vectors: unit eigenvectors S[m x nsel] of the
-// eigenvalues theta[sel[q]] (sel ascending); work: 6 m nsel doubles.
+// |beta[m] s_m|.  ritz_vectors: unit eigenvectors S[m x nsel]
+// of the eigenvalues theta[sel[q]] (sel ascending), grouped in ncl clusters
+// [cl_start[c], cl_start[c+1]) of close eigenvalues.
 void launch_ritz_check(const double* alpha, const double* beta, int m, double* theta, double* est,
-                       double* work, hipStream_t s);
+                       hipStream_t s);
 void launch_ritz_vectors(const double* alpha, const double* beta, int m, const double* theta,
-                         const int32_t* sel, int nsel, double* S, double* work, hipStream_t s);
+                         const int32_t* sel, const int32_t* cl_start, int ncl, double* S,
+                         hipStream_t s);
 
 void launch_eig_grad(const riga_problem* pr, int k, const double* U, const double* lam_w_dev,
                      const double* w_dev, double* gk, double* gr, hipStream_t s);

@@ -56,12 +56,14 @@ void set_front_attributes();
 void set_solve_attributes();
 void set_inverse_attributes();
 void set_bigfront_attributes();
+void set_tridiag_attributes();
 
 void set_kernel_attributes() {
   set_front_attributes();
   set_solve_attributes();
   set_inverse_attributes();
   set_bigfront_attributes();
+  set_tridiag_attributes();
 }
 
 // Copies the per-element coefficients (host values are checked positive)
@@ -185,7 +187,15 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
     L.col_prefix.upload(pref, s);
     // sweep work units, largest fronts first
     std::vector<WorkUnit> fu, bu;
-    const int cw = SWEEP_COLS;
+    int64_t nu_f = 0, nu_b = 0;
+    for (int F : fr) {
+      nu_f += (an.f_f[F] + SWEEP_ROWS - 1) / SWEEP_ROWS;
+      nu_b += (an.f_k[F] + SWEEP_COLS - 1) / SWEEP_COLS;
+    }
+    L.fwd_thin = nu_f < SWEEP_THIN_BELOW;
+    L.bwd_thin = nu_b < SWEEP_THIN_BELOW;
+    const int rw = L.fwd_thin ? SWEEP_ROWS_THIN : SWEEP_ROWS;
+    const int cw = L.bwd_thin ? SWEEP_COLS_THIN : SWEEP_COLS;
     auto unit = [&](int F, int lo, int hi) {
       WorkUnit w{};
       w.front = F;
@@ -202,7 +212,7 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
     };
     for (auto it = fr.rbegin(); it != fr.rend(); ++it) {
       const int F = *it, f = an.f_f[F], k = an.f_k[F];
-      for (int r = 0; r < f; r += SWEEP_ROWS) fu.push_back(unit(F, r, std::min(f, r + SWEEP_ROWS)));
+      for (int r = 0; r < f; r += rw) fu.push_back(unit(F, r, std::min(f, r + rw)));
       for (int c = 0; c < k; c += cw) bu.push_back(unit(F, c, std::min(k, c + cw)));
     }
     L.n_fwd = (int)fu.size();
