@@ -200,6 +200,71 @@ def calibrate_copy(torch, mib=256, reps=3):
     del src, dst
 
 
+SWEEP_SOURCES = ("paper_2009_08167_amd/csrc/k_solve.hip", "paper_2009_08167_amd/csrc/k_inverse.hip",
+                 "paper_2009_08167_amd/csrc/problem.h", "paper_2009_08167_amd/csrc/runtime.cpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fb_traffic.json")
+
+
+def sweep_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pmc_summary(fetch_csv, write_csv):
+    """HBM bytes of one forward/backward sweep pair from two rocprofv3 --pmc
+    runs of `bench.py --calibrate-copy` (FETCH_SIZE, then WRITE_SIZE; KiB per
+    dispatch).  Each counter is scaled by known bytes / reading of the
+    256 MiB device copy at the start of the run; writes profiles/fb_traffic.json."""
+    import csv
+
+    def load(path):
+        rows = list(csv.DictReader(open(path)))
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        return rows
+
+    out = {"source_sha256": sweep_source_hash(), "unit": "bytes per sweep pair"}
+    for name, path in (("fetch", fetch_csv), ("write", write_csv)):
+        rows = load(path)
+        copies = [float(r["Counter_Value"]) for r in rows[:16] if "copyBuffer" in r["Kernel_Name"]]
+        big = max(copies)
+        calib = [c for c in copies if c > 0.25 * big]
+        scale = 256 * 1024 / (sum(calib) / len(calib))   # KiB known / KiB read
+        tot = 0.0
+        pairs = 0
+        prev_fwd = False
+        for r in rows:
+            kn = r["Kernel_Name"]
+            is_f, is_b = "fwd_kernel" in kn, "bwd_kernel" in kn
+            if is_f or is_b:
+                tot += float(r["Counter_Value"])
+            if is_b and prev_fwd:
+                pairs += 1
+            prev_fwd = is_f
+        out[name] = tot * 1024.0 * scale / pairs
+        out[name + "_scale"] = scale
+        out["sweep_pairs"] = pairs
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
+def sweep_traffic():
+    """Measured HBM bytes per sweep pair, if taken on the current sweep
+    kernels (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != sweep_source_hash():
+        return None
+    return t["fetch"] + t["write"]
+
+
 def cpu_baseline():
     """The oracle as it stands, on a bounded sample: NumPy element assembly of
     the same problem plus ARPACK/SuperLU shift-and-invert for its 20 lowest
@@ -237,7 +302,12 @@ def main():
                     help="skip the 3D, batched and gradient workloads")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a 256 MiB device copy (for scaling HBM counters)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 counter runs into profiles/fb_traffic.json and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the spectral slices would shard across GPUs; see DESIGN.md)", file=sys.stderr)
@@ -283,7 +353,7 @@ def main():
         ach = bytes_fb / t_fb / 1e9
         roof = {"kernel": "forward/backward elimination (fwd_kernel + bwd_kernel, all levels)",
                 "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "frac": ach / HBM_PEAK_GBS, "traffic": sweep_traffic(),
                 "per_launch": {"bytes": bytes_fb, "seconds": t_fb}}
     else:
         ach = flops_fact / t_fact / 1e12

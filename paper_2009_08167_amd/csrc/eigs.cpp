@@ -28,7 +28,6 @@
 
 namespace riga {
 
-void add_scalars_launch(const double* a, const double* b, double* out, hipStream_t s);
 
 namespace {
 
@@ -87,7 +86,7 @@ struct Solver {
     c1.alloc(ncols, s);
     c2.alloc(ncols, s);
     partial.alloc((size_t)gemv_row_blocks(N) * ncols, s);
-    dotp.alloc(spmv_blocks(pr), s);
+    dotp.alloc(spmv_dot_blocks(pr), s);
     alpha.alloc(mb + 1, s);
     beta.alloc(mb + 2, s);
     scal.alloc(8, s);
@@ -149,10 +148,12 @@ struct Solver {
     launch_axpby(a, u, v, out, N, s);
   }
 
-  // c[c0:m] = W[:, c0:m]^T x ; x -= B[:, c0:m] c[c0:m]
-  void project_out(int m, double* c, int c0 = 0) {
+  // c[c0:m] = W[:, c0:m]^T x ; x -= B[:, c0:m] c[c0:m]; with alpha_out,
+  // also *alpha_out = *addend + c[m - 1]
+  void project_out(int m, double* c, int c0 = 0, double* alpha_out = nullptr,
+                   const double* addend = nullptr) {
     if (m <= c0) return;
-    launch_gemv_t(Wc(c0), N, m - c0, x.p, partial.p, c + c0, s);
+    launch_gemv_t(Wc(c0), N, m - c0, x.p, partial.p, c + c0, alpha_out, addend, s);
     launch_gemv_n_sub(Bc(c0), N, m - c0, c + c0, x.p, s);
   }
 
@@ -160,8 +161,7 @@ struct Solver {
   void normalize_into(int col, double* beta_out) {
     launch_spmv(pr, pr->mv.p, x.p, y.p, dotp.p, s);
     st.n_mv++;
-    launch_reduce_partials(dotp.p, spmv_blocks(pr), scal.p, s);
-    launch_scale2(x.p, y.p, scal.p, Bc(col), Wc(col), N, beta_out, flag.p, s);
+    launch_scale2(x.p, y.p, dotp.p, spmv_dot_blocks(pr), Bc(col), Wc(col), N, beta_out, flag.p, s);
   }
 
   void start_vector(const double* init /* may be null */) {
@@ -187,8 +187,7 @@ struct Solver {
     // the second pass repairs comes from the large components along v_j and
     // v_{j-1}.
     project_out(col + 1, c1.p);
-    project_out(col + 1, c2.p, nl);
-    add_scalars_launch(c1.p + col, c2.p + col, alpha.p + j, s);
+    project_out(col + 1, c2.p, nl, alpha.p + j, c1.p + col);
     normalize_into(col + 1, beta.p + j + 1);
     st.t_orth += secs(a, clk::now());
   }
@@ -274,11 +273,8 @@ struct Solver {
     launch_gemm_nn(Bc(nl), N, m, Sh.p, m, nc, Ub.p, s);
     int nlocked = 0;
     if (nw > 0) {
-      for (int i = 0; i < nw; ++i) {
-        launch_spmv(pr, pr->kv.p, Ub.p + (int64_t)i * N, KU.p + (int64_t)i * N, nullptr, s);
-        launch_spmv(pr, pr->mv.p, Ub.p + (int64_t)i * N, MU.p + (int64_t)i * N, nullptr, s);
-        st.n_mv += 2;
-      }
+      launch_spmm_km(pr, Ub.p, nw, KU.p, MU.p, s);
+      st.n_mv += 2 * nw;
       launch_residuals(KU.p, MU.p, Ub.p, N, nw, rqn.p, rqd.p, rn2.p, un2.p, lam.p, s);
       std::vector<double> h_rqd(nw), h_rn2(nw), h_un2(nw), h_lam(nw);
       HIPCHECK(hipMemcpy(h_rqd.data(), rqd.p, nw * sizeof(double), hipMemcpyDeviceToHost));
@@ -556,15 +552,16 @@ riga_status run_eigs_batched(riga_problem* const* probs, int count, const riga_e
   std::vector<std::string> errs(count);
   std::vector<std::string> worker_err(workers);
   for (int i = 0; i < count; ++i) n_found[i] = 0;
+  // kernel attributes are per device and process: set them once here, not
+  // from the workers while others launch
+  set_kernel_attributes();
   std::vector<std::thread> pool;
   for (int w = 0; w < workers; ++w) {
     pool.emplace_back([&, w] {
       hipStream_t st = nullptr;
       try {
         HIPCHECK(hipSetDevice(dev));
-        (void)hipGetLastError();
         HIPCHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-        set_kernel_attributes();
       } catch (const std::exception& e) {
         worker_err[w] = e.what();
         return;

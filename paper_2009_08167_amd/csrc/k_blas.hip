@@ -6,6 +6,7 @@
 // bitwise reproducible from run to run.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "problem.h"
@@ -13,7 +14,8 @@
 namespace riga {
 namespace {
 
-// y = A x with CSR (G lanes per row); optional per-block partial of x^T y.
+// y = A x with CSR (G lanes per row, grid-stride over row groups); with
+// dot_partial, also one partial of x^T y per workgroup (fixed order).
 template <int G>
 __global__ void __launch_bounds__(256) spmv_kernel(const int64_t* __restrict__ row_ptr,
                                                  const int32_t* __restrict__ col,
@@ -23,28 +25,73 @@ __global__ void __launch_bounds__(256) spmv_kernel(const int64_t* __restrict__ r
                                                  double* dot_partial) {
   __shared__ double red[256 / G];
   const int sub = threadIdx.x % G;
-  const int64_t r = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
-  double s = 0.0;
-  if (r < N) {
-    const int64_t e1 = row_ptr[r + 1];
-    for (int64_t e = row_ptr[r] + sub; e < e1; e += G) s += val[e] * x[col[e]];
-  }
-  for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if (sub == 0) {
-    double d = 0.0;
+  double d = 0.0;
+  for (int64_t r0 = (int64_t)blockIdx.x * (256 / G); r0 < N; r0 += (int64_t)gridDim.x * (256 / G)) {
+    const int64_t r = r0 + threadIdx.x / G;
+    double s = 0.0;
     if (r < N) {
-      y[r] = s;
-      d = s * x[r];
+      const int64_t e1 = row_ptr[r + 1];
+      for (int64_t e = row_ptr[r] + sub; e < e1; e += G) s += val[e] * x[col[e]];
     }
-    red[threadIdx.x / G] = d;
+    for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (sub == 0 && r < N) {
+      y[r] = s;
+      d += s * x[r];
+    }
   }
   if (dot_partial) {
+    if (sub == 0) red[threadIdx.x / G] = d;
     __syncthreads();
     if (threadIdx.x == 0) {
       double t = 0.0;
       for (int i = 0; i < 256 / G; ++i) t += red[i];
       dot_partial[blockIdx.x] = t;
     }
+  }
+}
+
+// KU = K U and MU = M U for NV columns of U per workgroup row (CSR pattern
+// and both value arrays read once per NV columns), G lanes per row.
+template <int G, int NV>
+__global__ void __launch_bounds__(256) spmm_km_kernel(const int64_t* __restrict__ row_ptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const double* __restrict__ kv,
+                                                    const double* __restrict__ mv,
+                                                    const double* __restrict__ U, int nw,
+                                                    double* __restrict__ KU,
+                                                    double* __restrict__ MU, int64_t N) {
+  const int sub = threadIdx.x % G;
+  const int64_t r = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
+  const int v0 = blockIdx.y * NV;
+  double sk[NV], sm[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) sk[q] = sm[q] = 0.0;
+  if (r < N) {
+    const int64_t e1 = row_ptr[r + 1];
+    for (int64_t e = row_ptr[r] + sub; e < e1; e += G) {
+      const int64_t c = col[e];
+      const double a = kv[e], b = mv[e];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const double xv = v0 + q < nw ? U[(int64_t)(v0 + q) * N + c] : 0.0;
+        sk[q] += a * xv;
+        sm[q] += b * xv;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+    for (int off = G / 2; off > 0; off >>= 1) {
+      sk[q] += __shfl_xor(sk[q], off);
+      sm[q] += __shfl_xor(sm[q], off);
+    }
+  if (sub == 0 && r < N) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+      if (v0 + q < nw) {
+        KU[(int64_t)(v0 + q) * N + r] = sk[q];
+        MU[(int64_t)(v0 + q) * N + r] = sm[q];
+      }
   }
 }
 
@@ -73,12 +120,12 @@ __global__ void __launch_bounds__(256) gemv_t_kernel(const double* __restrict__ 
   for (int jj = wave; jj < GEMV_CG; jj += 4) {
     const int j = blockIdx.y * GEMV_CG + jj;
     if (j >= m) break;
-    const double* c = B + (int64_t)j * n;
+    const double* cj = B + (int64_t)j * n;
     double v[RPL];
 #pragma unroll
     for (int u = 0; u < RPL; ++u) {
       const int64_t r = r0 + lane + 64 * u;
-      v[u] = r < r1 ? c[r] : 0.0;
+      v[u] = r < r1 ? cj[r] : 0.0;
     }
     double s = 0.0;
 #pragma unroll
@@ -92,16 +139,21 @@ __global__ void __launch_bounds__(256) gemv_t_kernel(const double* __restrict__ 
 }
 
 // c[j] = sum_rb partial[rb * m + j]: one wave per column, lanes over row
-// blocks in a fixed order, then a fixed butterfly
+// blocks in a fixed order, then a fixed butterfly.  With alpha_out, the wave
+// of column m - 1 also writes *alpha_out = *addend + c[m - 1].
 __global__ void __launch_bounds__(256) gemv_t_reduce_kernel(const double* partial, int nrb, int m,
-                                                          double* c) {
+                                                          double* c, double* alpha_out,
+                                                          const double* addend) {
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (j >= m) return;
   double s = 0.0;
   for (int rb = lane; rb < nrb; rb += 64) s += partial[(int64_t)rb * m + j];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if (lane == 0) c[j] = s;
+  if (lane == 0) {
+    c[j] = s;
+    if (alpha_out && j == m - 1) *alpha_out = *addend + s;
+  }
 }
 
 // x -= B c
@@ -156,10 +208,22 @@ __global__ void fill_random_kernel(double* x, int64_t n, uint64_t seed, uint64_t
   x[i] = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
-// v = x / beta, w = y / beta, beta = sqrt(beta2[0]); writes beta; flags breakdown
-__global__ void scale2_kernel(const double* x, const double* y, const double* beta2, double* v,
-                              double* w, int64_t n, double* beta_out, int32_t* flag) {
-  const double b2 = beta2[0];
+// v = x / beta, w = y / beta, beta^2 = sum of the np partials (each
+// workgroup adds them in the same fixed order); writes beta; flags breakdown
+__global__ void __launch_bounds__(256) scale2_kernel(const double* x, const double* y,
+                                                   const double* partial, int np, double* v,
+                                                   double* w, int64_t n, double* beta_out,
+                                                   int32_t* flag) {
+  __shared__ double sm[256];
+  double t = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) t += partial[i];
+  sm[threadIdx.x] = t;
+  __syncthreads();
+  for (int q = 128; q > 0; q >>= 1) {
+    if ((int)threadIdx.x < q) sm[threadIdx.x] += sm[threadIdx.x + q];
+    __syncthreads();
+  }
+  const double b2 = sm[0];
   const bool ok = b2 > 0.0 && isfinite(b2);
   const double b = ok ? sqrt(b2) : 0.0;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -297,10 +361,6 @@ __global__ void __launch_bounds__(256) dot_partial_kernel(const double* a, const
   if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
 }
 
-__global__ void add_scalars_kernel(const double* a, const double* b, double* out) {
-  if (threadIdx.x == 0) *out = *a + *b;
-}
-
 }  // namespace
 
 void launch_axpby(double a, const double* u, const double* v, double* out, int64_t n,
@@ -319,26 +379,46 @@ void launch_dot(const double* a, const double* b, int64_t n, double* partial, do
   HIPCHECK(hipGetLastError());
 }
 
-void add_scalars_launch(const double* a, const double* b, double* out, hipStream_t s) {
-  add_scalars_kernel<<<1, 64, 0, s>>>(a, b, out);
-  HIPCHECK(hipGetLastError());
-}
-
 int spmv_blocks(const riga_problem* pr) {
   const int G = pr->spmv_group;
   return (int)((pr->an.N + (256 / G) - 1) / (256 / G));
 }
 
+int spmv_dot_blocks(const riga_problem* pr) { return std::min(spmv_blocks(pr), 1024); }
+
 void launch_spmv(const riga_problem* pr, const double* vals, const double* x, double* y,
                  double* dot_partial, hipStream_t s) {
   const int64_t N = pr->an.N;
-  const int nb = spmv_blocks(pr);
+  // with a dot product the grid is capped, so that the partials stay few
+  const int nb = dot_partial ? spmv_dot_blocks(pr) : spmv_blocks(pr);
+  auto* rp = pr->row_ptr.p;
+  auto* ci = pr->col_idx.p;
   switch (pr->spmv_group) {
-    case 4: spmv_kernel<4><<<nb, 256, 0, s>>>(pr->row_ptr.p, pr->col_idx.p, vals, x, y, N, dot_partial); break;
-    case 8: spmv_kernel<8><<<nb, 256, 0, s>>>(pr->row_ptr.p, pr->col_idx.p, vals, x, y, N, dot_partial); break;
-    case 16: spmv_kernel<16><<<nb, 256, 0, s>>>(pr->row_ptr.p, pr->col_idx.p, vals, x, y, N, dot_partial); break;
-    case 32: spmv_kernel<32><<<nb, 256, 0, s>>>(pr->row_ptr.p, pr->col_idx.p, vals, x, y, N, dot_partial); break;
-    default: spmv_kernel<64><<<nb, 256, 0, s>>>(pr->row_ptr.p, pr->col_idx.p, vals, x, y, N, dot_partial); break;
+    case 4: spmv_kernel<4><<<nb, 256, 0, s>>>(rp, ci, vals, x, y, N, dot_partial); break;
+    case 8: spmv_kernel<8><<<nb, 256, 0, s>>>(rp, ci, vals, x, y, N, dot_partial); break;
+    case 16: spmv_kernel<16><<<nb, 256, 0, s>>>(rp, ci, vals, x, y, N, dot_partial); break;
+    case 32: spmv_kernel<32><<<nb, 256, 0, s>>>(rp, ci, vals, x, y, N, dot_partial); break;
+    default: spmv_kernel<64><<<nb, 256, 0, s>>>(rp, ci, vals, x, y, N, dot_partial); break;
+  }
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_spmm_km(const riga_problem* pr, const double* U, int nw, double* KU, double* MU,
+                    hipStream_t s) {
+  if (nw <= 0) return;
+  constexpr int NV = 8;
+  const int64_t N = pr->an.N;
+  const dim3 grid((unsigned)spmv_blocks(pr), (nw + NV - 1) / NV);
+  auto* rp = pr->row_ptr.p;
+  auto* ci = pr->col_idx.p;
+  auto* k = pr->kv.p;
+  auto* m = pr->mv.p;
+  switch (pr->spmv_group) {
+    case 4: spmm_km_kernel<4, NV><<<grid, 256, 0, s>>>(rp, ci, k, m, U, nw, KU, MU, N); break;
+    case 8: spmm_km_kernel<8, NV><<<grid, 256, 0, s>>>(rp, ci, k, m, U, nw, KU, MU, N); break;
+    case 16: spmm_km_kernel<16, NV><<<grid, 256, 0, s>>>(rp, ci, k, m, U, nw, KU, MU, N); break;
+    case 32: spmm_km_kernel<32, NV><<<grid, 256, 0, s>>>(rp, ci, k, m, U, nw, KU, MU, N); break;
+    default: spmm_km_kernel<64, NV><<<grid, 256, 0, s>>>(rp, ci, k, m, U, nw, KU, MU, N); break;
   }
   HIPCHECK(hipGetLastError());
 }
@@ -351,13 +431,15 @@ void launch_axpby_vals(const double* k, const double* m, double sigma, double* a
 
 int gemv_row_blocks(int64_t n) { return (int)((n + GEMV_RB - 1) / GEMV_RB); }
 
+int gemv_col_groups(int m) { return (m + GEMV_CG - 1) / GEMV_CG; }
+
 void launch_gemv_t(const double* B, int64_t n, int m, const double* x, double* partial,
-                   double* c, hipStream_t s) {
+                   double* c, double* alpha_out, const double* addend, hipStream_t s) {
   if (m <= 0) return;
   const int nrb = gemv_row_blocks(n);
-  dim3 grid(nrb, (m + GEMV_CG - 1) / GEMV_CG);
+  dim3 grid(nrb, gemv_col_groups(m));
   gemv_t_kernel<<<grid, 256, 0, s>>>(B, n, m, x, partial);
-  gemv_t_reduce_kernel<<<(m + 3) / 4, 256, 0, s>>>(partial, nrb, m, c);
+  gemv_t_reduce_kernel<<<(m + 3) / 4, 256, 0, s>>>(partial, nrb, m, c, alpha_out, addend);
   HIPCHECK(hipGetLastError());
 }
 
@@ -378,9 +460,9 @@ void launch_fill_random(double* x, int64_t n, uint64_t seed, uint64_t sid, hipSt
   HIPCHECK(hipGetLastError());
 }
 
-void launch_scale2(const double* x, const double* y, const double* beta2, double* v, double* w,
-                   int64_t n, double* beta_out, int32_t* flag, hipStream_t s) {
-  scale2_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, y, beta2, v, w, n, beta_out, flag);
+void launch_scale2(const double* x, const double* y, const double* partial, int np, double* v,
+                   double* w, int64_t n, double* beta_out, int32_t* flag, hipStream_t s) {
+  scale2_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, y, partial, np, v, w, n, beta_out, flag);
   HIPCHECK(hipGetLastError());
 }
 

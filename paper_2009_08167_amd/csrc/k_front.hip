@@ -307,8 +307,7 @@ void factor_levels(riga_problem* pr, T* pool, T* hpool, double sigma) {
   hipStream_t s = pr->stream;
   FrontArgs fa = front_args(pr);
   const double pivtol = 1e-20 * (pr->normK1 + fabs(sigma) * pr->normM1);
-  static std::once_flag attr_once;
-  std::call_once(attr_once, [] { set_kernel_attributes(); });
+  set_kernel_attributes();
   for (size_t h = 0; h < pr->levels.size(); ++h) {
     LevelDev& L = pr->levels[h];
     if (L.n == 0) continue;

@@ -241,11 +241,6 @@ void apply_solve_attrs() {
     HIPCHECK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 159 * 1024));
 }
 
-void attrs_once() {
-  static std::once_flag once;
-  std::call_once(once, [] { set_kernel_attributes(); });
-}
-
 // One launch per tree level and direction.
 template <class T>
 void solve_levels(riga_problem* pr, const T* H, const double* b, double* x, hipStream_t s) {
@@ -286,7 +281,7 @@ void launch_pivot_maps(riga_problem* pr, hipStream_t s) {
 
 void solve_fb(riga_problem* pr, const double* b, double* x, hipStream_t s) {
   if (!pr->factored) throw Error(RIGA_EINVAL, "solve before factorisation");
-  attrs_once();
+  set_kernel_attributes();
   if (pr->fact_precision == RIGA_MIXED) solve_levels<float>(pr, pr->h32.p, b, x, s);
   else solve_levels<double>(pr, pr->h64.p, b, x, s);
 }

@@ -182,11 +182,15 @@ void compute_norms(riga_problem* pr);
 
 void launch_axpby_vals(const double* k, const double* m, double sigma, double* a, int64_t n,
                        hipStream_t s);
-// y = A x (A one of kv/mv/av); if dot_partial != nullptr also writes per-block
-// partial sums of x^T y (count returned by spmv_blocks()).
+// y = A x (A one of kv/mv/av); with dot_partial, also spmv_dot_blocks()
+// partial sums of x^T y.
 void launch_spmv(const riga_problem* pr, const double* vals, const double* x, double* y,
                  double* dot_partial, hipStream_t s);
 int spmv_blocks(const riga_problem* pr);
+int spmv_dot_blocks(const riga_problem* pr);
+// KU = K U, MU = M U for the nw columns of U (N x nw, column-major).
+void launch_spmm_km(const riga_problem* pr, const double* U, int nw, double* KU, double* MU,
+                    hipStream_t s);
 
 void factor_numeric(riga_problem* pr, double sigma, int precision);
 // H = [I; L21] L11^{-1} for every front (D kept on the diagonal), from the
@@ -203,8 +207,6 @@ void factor_big_fronts(riga_problem* pr, T* pool, const int32_t* fronts,
 int bigfront_max_k();
 // Pivot-order gather maps of the sweeps (after each factorisation).
 void launch_pivot_maps(riga_problem* pr, hipStream_t s);
-// Raise the dynamic-LDS limit of the kernels that need more than 64 KB (for
-// the calling thread's device).
 // Binds a call's stream to the problem for the duration of the call only, so
 // no stream handle outlives the call that passed it.
 struct StreamBind {
@@ -216,19 +218,25 @@ struct StreamBind {
   StreamBind& operator=(const StreamBind&) = delete;
 };
 
+// Raises the dynamic-LDS limit of the kernels that need more than 64 KB;
+// runs once per process (later calls return at once).
 void set_kernel_attributes();
 void solve_fb(riga_problem* pr, const double* b, double* x, hipStream_t s);
 
 // BLAS-like helpers on column-major N x m blocks (ld = N).
 int gemv_row_blocks(int64_t n);
+int gemv_col_groups(int m);
+// c = B^T x; partial holds gemv_row_blocks(n) * m doubles.  With alpha_out,
+// also *alpha_out = *addend + c[m - 1].
 void launch_gemv_t(const double* B, int64_t n, int m, const double* x, double* partial,
-                   double* c, hipStream_t s);
+                   double* c, double* alpha_out, const double* addend, hipStream_t s);
 void launch_gemv_n_sub(const double* B, int64_t n, int m, const double* c, double* x,
                        hipStream_t s);
 void launch_reduce_partials(const double* partial, int nblk, double* out, hipStream_t s);
 void launch_fill_random(double* x, int64_t n, uint64_t seed, uint64_t stream_id, hipStream_t s);
-void launch_scale2(const double* x, const double* y, const double* beta2, double* v, double* w,
-                   int64_t n, double* beta_out, int32_t* flag, hipStream_t s);
+// v = x / beta, w = y / beta with beta^2 the sum of partial[0..np).
+void launch_scale2(const double* x, const double* y, const double* partial, int np, double* v,
+                   double* w, int64_t n, double* beta_out, int32_t* flag, hipStream_t s);
 void launch_gemm_nn(const double* V, int64_t n, int k, const double* S, int lds, int m,
                     double* U, hipStream_t s);
 void launch_residuals(const double* KU, const double* MU, const double* U, int64_t n, int m,

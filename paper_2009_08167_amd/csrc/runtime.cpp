@@ -59,11 +59,14 @@ void set_bigfront_attributes();
 void set_tridiag_attributes();
 
 void set_kernel_attributes() {
-  set_front_attributes();
-  set_solve_attributes();
-  set_inverse_attributes();
-  set_bigfront_attributes();
-  set_tridiag_attributes();
+  static std::once_flag once;
+  std::call_once(once, [] {
+    set_front_attributes();
+    set_solve_attributes();
+    set_inverse_attributes();
+    set_bigfront_attributes();
+    set_tridiag_attributes();
+  });
 }
 
 // Copies the per-element coefficients (host values are checked positive)
