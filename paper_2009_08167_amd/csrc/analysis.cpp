@@ -333,7 +333,7 @@ std::string analyze(int dim, const int ne_in[3], int p, int s, int nquad, int le
     A.f_rows_off[f + 1] = A.f_rows_off[f] + fo;
     A.f_pool_off[f + 1] = A.f_pool_off[f] + (int64_t)fo * fo;
     A.f_cb_off[f + 1] = A.f_cb_off[f] + (fo - k);
-    A.f_h_off[f + 1] = A.f_h_off[f] + (int64_t)fo * k;
+    A.f_h_off[f + 1] = A.f_h_off[f] + (int64_t)h_ld(fo) * k;
     A.max_front = std::max(A.max_front, fo);
     A.max_fs = std::max(A.max_fs, k);
     A.nnz_l += (int64_t)k * (k + 1) / 2 + (int64_t)k * (fo - k);

@@ -11,6 +11,11 @@
 
 namespace riga {
 
+// Leading dimension of a front's partitioned-inverse block: the order rounded
+// up to 32 elements, so that every column starts on a 128-byte boundary.
+inline int h_ld(int f) { return (f + 31) & ~31; }
+
+
 // One direction of the tensor-product space.  Knot positions are kept as
 // integer element-boundary indices (knot value = index / ne), so that the
 // support of every function is an exact element range.
@@ -59,7 +64,7 @@ struct Analysis {
   std::vector<int32_t> rows;          // front index lists, ORIGINAL DOF indices
   std::vector<int64_t> f_pool_off;   // offset of the dense f x f front in the pool
   std::vector<int64_t> f_cb_off;     // offset of the contribution vector (sum of f-k)
-  std::vector<int64_t> f_h_off;      // offset of the f x k partitioned inverse
+  std::vector<int64_t> f_h_off;      // offset of the h_ld(f) x k partitioned inverse
   int64_t pool_size = 0;             // sum f^2
   int64_t h_size = 0;                // sum f k
   int64_t cb_size = 0;               // sum (f-k)

@@ -6,8 +6,9 @@
 //
 // For a front of order f with k fully-summed variables, the factorisation
 // leaves L = [L11; L21] (f x k, unit lower L11, pivot order) and the block
-// diagonal D.  This kernel writes, in a separate pool with the same
-// column-major layout (leading dimension f),
+// diagonal D.  This kernel writes, in a separate pool, column-major with the
+// leading dimension ldh (f rounded up to 32 elements, every column starting
+// on a 128-byte boundary),
 //     H = [I; L21] * L11^{-1}   =  [ L11^{-1} ; L21 L11^{-1} ]
 // except on the diagonal of the top k x k block, which keeps D(i, i), and on
 // the (t+1, t) slot of every 2x2 pivot block, which keeps D(t+1, t) (both
@@ -63,7 +64,7 @@ __global__ void __launch_bounds__(256) front_inverse_kernel(const FrontDesc* __r
   int32_t* type = (int32_t*)(Hp + IB * LDP);
   const WorkUnit u = units[blockIdx.x];
   const FrontDesc d = desc[u.front];
-  const int f = d.f, k = d.k;
+  const int f = d.f, k = d.k, ldh = d.ldh;
   const int r0 = u.lo, nr = u.hi - u.lo;
   const T* L = pool + d.pool_off;
   T* Hf = H + d.h_off;
@@ -98,9 +99,9 @@ __global__ void __launch_bounds__(256) front_inverse_kernel(const FrontDesc* __r
           double a = 0.0;
           if (ii < nr && mm < mw) {
             const int i = r0 + ii, m = m0 + mm;
-            if (i >= k) a = (double)Hf[(int64_t)m * f + i];
+            if (i >= k) a = (double)Hf[(int64_t)m * ldh + i];
             else if (m == i) a = 1.0;
-            else if (m < i && !(m == i - 1 && type[m] == 2)) a = (double)Hf[(int64_t)m * f + i];
+            else if (m < i && !(m == i - 1 && type[m] == 2)) a = (double)Hf[(int64_t)m * ldh + i];
           }
           Ac[mm * LDP + ii] = a;
           const int mb = e & 63, cb = e >> 6;
@@ -169,15 +170,15 @@ __global__ void __launch_bounds__(256) front_inverse_kernel(const FrontDesc* __r
       const int ii = e & 63, c = e >> 6;
       if (ii < nr && c < pw) {
         const int i = r0 + ii, j = j0 + c;
-        const int64_t o = (int64_t)j * f + i;
+        const int64_t o = (int64_t)j * ldh + i, ol = (int64_t)j * f + i;
         if (i >= k) {
           Hf[o] = (T)Hp[ii * LDP + c];
         } else if (j == i) {
-          Hf[o] = L[o];
-          dd[d.start + i] = (double)L[o];
+          Hf[o] = L[ol];
+          dd[d.start + i] = (double)L[ol];
         } else if (j == i - 1 && type[j] == 2) {
-          Hf[o] = L[o];
-          dsub[d.start + j] = (double)L[o];
+          Hf[o] = L[ol];
+          dsub[d.start + j] = (double)L[ol];
         } else if (j < i) {
           Hf[o] = (T)Hp[ii * LDP + c];
         }

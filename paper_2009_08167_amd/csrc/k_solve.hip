@@ -53,7 +53,8 @@ __global__ void __launch_bounds__(256) fwd_kernel(SolveArgs sa, const T* __restr
   constexpr int G = 256 / RW;
   extern __shared__ double smem[];
   const WorkUnit u = units[blockIdx.x];
-  const int f = u.f, k = u.k, start = u.start;
+  if (u.front < 0) return;  // padding slot of the XCD interleave
+  const int k = u.k, start = u.start, ldh = u.ldh;
   const int lo = u.lo, hi = u.hi;
   double* y = smem;          // k: permuted fully-summed right-hand side
   double* psum = y + k;      // G x RW partial sums
@@ -67,7 +68,7 @@ __global__ void __launch_bounds__(256) fwd_kernel(SolveArgs sa, const T* __restr
   const bool first = g + 15 * G < jend;
   if (first) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) hv[q] = (double)hc[(int64_t)(g + G * q) * f];
+    for (int q = 0; q < 16; ++q) hv[q] = (double)hc[(int64_t)(g + G * q) * ldh];
   }
   // the (i, i-1) slot of a 2x2 pivot block holds D, not L11^{-1} (= 0)
   const int skip = (row && i < k && i > 0 && sa.piv_type[start + i] == 3) ? i - 1 : -1;
@@ -105,12 +106,12 @@ __global__ void __launch_bounds__(256) fwd_kernel(SolveArgs sa, const T* __restr
   }
   for (; j + 15 * G < jend; j += 16 * G) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) hv[q] = (double)hc[(int64_t)(j + G * q) * f];
+    for (int q = 0; q < 16; ++q) hv[q] = (double)hc[(int64_t)(j + G * q) * ldh];
 #pragma unroll
     for (int q = 0; q < 16; ++q) s += (j + G * q == skip ? 0.0 : hv[q]) * y[j + G * q];
   }
   for (; j < jend; j += G)
-    if (j != skip) s += (double)hc[(int64_t)j * f] * y[j];
+    if (j != skip) s += (double)hc[(int64_t)j * ldh] * y[j];
   psum[g * RW + rl] = s;
   __syncthreads();
   if (g == 0 && row) {
@@ -132,7 +133,8 @@ __global__ void __launch_bounds__(256) bwd_kernel(SolveArgs sa, const T* __restr
   constexpr int RCH = 16 / CPW;
   extern __shared__ double smem[];
   const WorkUnit u = units[blockIdx.x];
-  const int f = u.f, k = u.k, start = u.start;
+  if (u.front < 0) return;  // padding slot of the XCD interleave
+  const int f = u.f, k = u.k, start = u.start, ldh = u.ldh;
   const int lo = u.lo, hi = u.hi;
   const T* Hf = H + u.h_off;
   const int32_t* rows = sa.rows + u.rows_off;
@@ -156,11 +158,13 @@ __global__ void __launch_bounds__(256) bwd_kernel(SolveArgs sa, const T* __restr
       for (int c = 0; c < CPW; ++c) {
         const int j = jc[c];
         const bool use = j < hi && i < f && i > j && !(two[c] && i == j + 1);
-        hv[r][c] = use ? (double)Hf[(int64_t)j * f + i] : 0.0;
+        hv[r][c] = use ? (double)Hf[(int64_t)j * ldh + i] : 0.0;
       }
     }
   };
-  const int ibeg = lo + 1;
+  // row chunks start on a 16-row boundary (whole cache lines); rows at or
+  // above a column's diagonal are masked
+  const int ibeg = (lo + 1) & ~15;
   if (ibeg < f) load(ibeg);
   for (int i = lo + tid; i < f; i += 256) {
     double val;
@@ -188,7 +192,7 @@ __global__ void __launch_bounds__(256) bwd_kernel(SolveArgs sa, const T* __restr
 #pragma unroll
     for (int r = 0; r < RCH; ++r) {
       const int i = i0 + 64 * r + lane;
-      const double vv = i < f ? v[i - lo] : 0.0;
+      const double vv = (i > lo && i < f) ? v[i - lo] : 0.0;
 #pragma unroll
       for (int c = 0; c < CPW; ++c) acc[c] += hv[r][c] * vv;
     }

@@ -70,7 +70,7 @@ constexpr int LDS_FRONT_MAX_F32 = 176;
 
 // Packed per-front record read once by the inverse and solve kernels.
 struct FrontDesc {
-  int32_t f, k, start, pad;
+  int32_t f, k, start, ldh;  // ldh: leading dimension of the front's H block
   int64_t pool_off;  // front in the factor pool (f x f, column-major)
   int64_t h_off;     // partitioned inverse in the H pool (f x k, column-major)
   int64_t rows_off, cb_off, gmap_off;
@@ -84,13 +84,14 @@ constexpr int SWEEP_COLS = 16;
 constexpr int SWEEP_ROWS_THIN = 16;
 constexpr int SWEEP_COLS_THIN = 4;
 constexpr int SWEEP_THIN_BELOW = 512;  // units of the default shape
+constexpr int XCDS = 8;                // accelerator complex dies of an MI355X
 
 // One workgroup's share of a front: rows [lo, hi) (forward sweep, inverse)
 // or columns [lo, hi) (backward sweep), with the front's record inlined so a
 // sweep workgroup starts from a single scalar load.
 struct WorkUnit {
   int32_t front, lo, hi, f;
-  int32_t k, start, pad0, pad1;
+  int32_t k, start, ldh, pad;
   int64_t h_off, rows_off, cb_off, gmap_off;
 };
 

@@ -143,7 +143,7 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
       d.f = an.f_f[F];
       d.k = an.f_k[F];
       d.start = an.f_start[F];
-      d.pad = 0;
+      d.ldh = h_ld(d.f);
       d.pool_off = an.f_pool_off[F];
       d.h_off = an.f_h_off[F];
       d.rows_off = an.f_rows_off[F];
@@ -207,17 +207,39 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
       w.f = an.f_f[F];
       w.k = an.f_k[F];
       w.start = an.f_start[F];
+      w.ldh = h_ld(an.f_f[F]);
       w.h_off = an.f_h_off[F];
       w.rows_off = an.f_rows_off[F];
       w.cb_off = an.f_cb_off[F];
       w.gmap_off = an.f_rows_off[F] * pr->gstride;
       return w;
     };
-    for (auto it = fr.rbegin(); it != fr.rend(); ++it) {
-      const int F = *it, f = an.f_f[F], k = an.f_k[F];
-      for (int r = 0; r < f; r += rw) fu.push_back(unit(F, r, std::min(f, r + rw)));
-      for (int c = 0; c < k; c += cw) bu.push_back(unit(F, c, std::min(k, c + cw)));
-    }
+    // All units of one front go to one XCD (workgroups are dispatched to the
+    // 8 XCDs round-robin by index), so the gathers that every unit of a
+    // front repeats hit that XCD's L2; fronts are spread over the XCDs
+    // largest first, and empty slots (front -1) pad the interleave.
+    auto xcd_order = [&](bool rows_split, int width) {
+      std::vector<std::vector<WorkUnit>> q(XCDS);
+      std::vector<int64_t> load(XCDS, 0);
+      for (auto it = fr.rbegin(); it != fr.rend(); ++it) {
+        const int F = *it, f = an.f_f[F], k = an.f_k[F];
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        const int n = rows_split ? f : k;
+        for (int a = 0; a < n; a += width) q[x].push_back(unit(F, a, std::min(n, a + width)));
+        load[x] += (n + width - 1) / width;
+      }
+      size_t len = 0;
+      for (auto& v : q) len = std::max(len, v.size());
+      std::vector<WorkUnit> out;
+      WorkUnit none{};
+      none.front = -1;
+      for (size_t i = 0; i < len; ++i)
+        for (int x = 0; x < XCDS; ++x) out.push_back(i < q[x].size() ? q[x][i] : none);
+      while (!out.empty() && out.back().front < 0) out.pop_back();
+      return out;
+    };
+    fu = xcd_order(true, rw);
+    bu = xcd_order(false, cw);
     L.n_fwd = (int)fu.size();
     L.n_bwd = (int)bu.size();
     L.fwd_units.upload(fu, s);
