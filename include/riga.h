@@ -82,9 +82,9 @@ typedef struct {
   int32_t precision;      /* RIGA_FP64, or RIGA_MIXED: FP32 fronts and solves refined in FP64 */
   double tol;             /* accept a pair when ||K u - lambda M u||_2 / (||K||_1 ||u||_2) <= tol;
                              0 -> 1e-9 */
-  int32_t max_basis;      /* Lanczos basis size per run; 0 -> default (<= 512) */
-  int32_t max_restarts;   /* Lanczos runs per shift; 0 -> default */
-  int32_t per_shift;      /* eigenpairs targeted per shift; 0 -> default */
+  int32_t max_basis;      /* Lanczos basis size per run; 0 -> max(160, 4 per_shift + 32) */
+  int32_t max_restarts;   /* Lanczos runs per shift; 0 -> 10 */
+  int32_t per_shift;      /* eigenpairs targeted per shift; 0 -> 32 */
   uint64_t seed;          /* start vectors (counter-based hash of seed and index) */
   void* stream;           /* hipStream_t */
 } riga_eigs_opts;
@@ -197,8 +197,10 @@ riga_status riga_solve(riga_problem* pr, const double* b_dev, double* x_dev, int
  * evecs_dev: [n_dof * nev] column-major device buffer for M-normalised
  * eigenvectors, or NULL.  resid_host[nev] (or NULL): relative residuals
  * ||K u - lambda M u||_2 / (||K||_1 ||u||_2).  *n_found: pairs returned.
- * stats (or NULL): counters and timings.  Returns RIGA_ENOCONV (with
- * n_found < nev pairs filled) when the budget ran out. */
+ * stats (or NULL): counters and timings.  Returns RIGA_ENOCONV when the
+ * restart budget ran out; then n_found < nev and the pairs returned are the
+ * complete set of eigenvalues in [lo, sigma) for the last shift sigma whose
+ * inertia count they matched. */
 riga_status riga_eigs(riga_problem* pr, const riga_eigs_opts* opts, int32_t* n_found,
                       double* evals_host, double* evecs_dev, double* resid_host,
                       riga_stats* stats);

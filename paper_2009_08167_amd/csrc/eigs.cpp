@@ -449,9 +449,9 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
   sv.precision = o->precision;
   sv.max_ir = 2;
   if (const char* v = std::getenv("RIGA_MAX_IR")) sv.max_ir = std::max(0, std::atoi(v));
-  sv.per_shift = o->per_shift > 0 ? o->per_shift : 48;
+  sv.per_shift = o->per_shift > 0 ? o->per_shift : 32;
   sv.max_restarts = o->max_restarts > 0 ? o->max_restarts : 10;
-  int mb = o->max_basis > 0 ? o->max_basis : std::max(128, 3 * sv.per_shift);
+  int mb = o->max_basis > 0 ? o->max_basis : std::max(160, 4 * sv.per_shift + 32);
   mb = (int)std::min<int64_t>(std::min(mb, 1000), sv.N - 1);
   sv.mb = mb;
   sv.lock_cap = (int)std::min<int64_t>(nev + 2 * sv.per_shift + 32, sv.N);
@@ -473,6 +473,7 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
   riga_status status = RIGA_OK;
   double sigma = lo;
   int64_t known = 0;  // eigenvalues in [lo, sigma)
+  double verified = lo;  // every eigenvalue in [lo, verified) is locked
   const double* init = nullptr;
   for (int shift = 0; nev > 0 && shift < 400; ++shift) {
     Solver::Ritz last;
@@ -496,6 +497,7 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
       status = RIGA_ENOCONV;
       break;
     }
+    verified = sigma;
     if (known >= nev) break;
     if (std::isfinite(hi) && sigma >= hi) break;
     const int64_t target = std::max<int64_t>(1, std::min<int64_t>(sv.per_shift / 2, nev - known));
@@ -512,10 +514,13 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
     }
     sigma = next;
   }
-  // results: locked pairs in [lo, hi), ascending
+  // results: locked pairs in [lo, hi), ascending; when the budget ran out,
+  // only those below the last shift whose inertia count they complete (the
+  // others are eigenpairs, but some eigenvalue below them may be missing)
+  const double top = status == RIGA_OK ? hi : std::min(hi, verified);
   std::vector<Locked> in;
   for (auto& L : sv.locked)
-    if (L.lam >= lo && L.lam < hi) in.push_back(L);
+    if (L.lam >= lo && L.lam < top) in.push_back(L);
   std::sort(in.begin(), in.end(), [](const Locked& a, const Locked& b) { return a.lam < b.lam; });
   const int nf = std::min<int>((int)in.size(), nev);
   for (int i = 0; i < nf; ++i) {

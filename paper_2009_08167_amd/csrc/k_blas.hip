@@ -384,12 +384,11 @@ int spmv_blocks(const riga_problem* pr) {
   return (int)((pr->an.N + (256 / G) - 1) / (256 / G));
 }
 
-int spmv_dot_blocks(const riga_problem* pr) { return std::min(spmv_blocks(pr), 1024); }
+int spmv_dot_blocks(const riga_problem* pr) { return spmv_blocks(pr); }
 
 void launch_spmv(const riga_problem* pr, const double* vals, const double* x, double* y,
                  double* dot_partial, hipStream_t s) {
   const int64_t N = pr->an.N;
-  // with a dot product the grid is capped, so that the partials stay few
   const int nb = dot_partial ? spmv_dot_blocks(pr) : spmv_blocks(pr);
   auto* rp = pr->row_ptr.p;
   auto* ci = pr->col_idx.p;

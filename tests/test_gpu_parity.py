@@ -241,3 +241,22 @@ def test_mixed_eigs_match_fp64_bar(w):
     Ko, Mo = assembly.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
     lr, Ur = eigen.dense_eigh(Ko, Mo)
     _check_pairs(Ko, Mo, lr, Ur, lam, U.cpu().numpy(), res, w.nev)
+
+
+def test_budget_exhausted_returns_only_verified_pairs():
+    """With a tiny restart budget on a spectrum with 3- and 6-fold
+    multiplicities (3D, kappa = rho = 1), the solver may stop early; every
+    pair it returns must then be exactly the lowest eigenvalues (no gap), as
+    the inertia count at its last completed shift guarantees."""
+    riga = _riga()
+    w = workloads.small(3, 6, 2, 3, 60, 0.0)
+    _say("budget", w.name)
+    pr = riga.assemble(w.dim, w.ne, w.p, w.s, leaf_dofs=32)
+    lam, U, res, st = pr.eigs(w.nev, per_shift=8, max_basis=20, max_restarts=1, allow_partial=True)
+    _say("found", len(lam), "stats", st)
+    Ko, Mo = assembly.assemble(w.dim, w.ne, w.p, w.s)
+    lr = eigen.dense_eigh(Ko, Mo)[0]
+    n = len(lam)
+    if n:
+        assert np.max(np.abs(lam - lr[:n]) / lr[:n]) <= 1e-10
+        assert res.max() <= 1e-9
