@@ -263,43 +263,50 @@ __global__ void __launch_bounds__(1024) big_panel_kernel(BigArgs a, T* pool) {
 // Update-block rows of the panel columns: gather them in the panel's column
 // order, eliminate with the panel's pivots (l = y (L_pp D)^{-T} on the kb
 // factorised columns, the rank-kb update on the other nb - kb), write back.
-// Lanes hold panel columns; each wave takes 16 rows.
+// One thread per row with the row's nb panel entries in registers (loads and
+// stores coalesced across the rows), W(c, t) = (L_pp D)(c, t) read from LDS
+// as a broadcast.
 template <class T>
 __global__ void __launch_bounds__(256) big_cbrows_kernel(BigArgs a, T* pool) {
-  __shared__ double W[BF_NB * (BF_NB + 1)];   // W[t][c] = (L_pp D)(j0 + c, j0 + t)
-  __shared__ double dA[BF_NB], dB[BF_NB];
+  __shared__ double W[BF_NB * BF_NB];   // W[t * BF_NB + c] = (L_pp D)(j0 + c, j0 + t)
+  __shared__ double dA[BF_NB], dB[BF_NB], dinv[BF_NB];
   __shared__ int ty[BF_NB], lp[BF_NB];
   const int b = blockIdx.y;
   const BigState st = a.st[b];
   if (st.kb == 0) return;
   const int F = a.fronts[b];
   const int f = a.ff[F], k = a.fk[F], start = a.fstart[F];
-  const int i0 = k + blockIdx.x * 64;
+  const int i0 = k + blockIdx.x * 256;
   if (i0 >= f) return;
   const int j0 = st.cur, kb = st.kb, nb = st.nb;
-  const T* A0 = pool + a.pool_off[F];
   T* A = pool + a.pool_off[F];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid < nb) {
-    lp[tid] = a.lperm[(int64_t)b * BF_NB + tid];
+  const int tid = threadIdx.x;
+  if (tid < BF_NB) {
+    lp[tid] = tid < nb ? a.lperm[(int64_t)b * BF_NB + tid] : 0;
+    int tt = 0;
+    double da = 1.0, db = 0.0;
     if (tid < kb) {
-      const int t = tid;
-      const int tt = a.piv_type[start + j0 + t];
-      ty[t] = tt;
-      const double dd = (double)A0[(int64_t)(j0 + t) * f + j0 + t];
-      dA[t] = dd;
-      if (tt == 2) dB[t] = (double)A0[(int64_t)(j0 + t) * f + j0 + t + 1];
-      else if (tt == 3) dB[t] = (double)A0[(int64_t)(j0 + t - 1) * f + j0 + t];
-      else dB[t] = 0.0;
+      tt = a.piv_type[start + j0 + tid];
+      da = (double)A[(int64_t)(j0 + tid) * f + j0 + tid];
+      if (tt == 2) db = (double)A[(int64_t)(j0 + tid) * f + j0 + tid + 1];
+      else if (tt == 3) db = (double)A[(int64_t)(j0 + tid - 1) * f + j0 + tid];
     }
+    ty[tid] = tt;
+    dA[tid] = da;
+    dB[tid] = db;
   }
   __syncthreads();
-  // W(c, t) for the panel's rows c > t
+  if (tid < BF_NB) {
+    // 1 / d for 1x1 pivots, 1 / det for the first pivot of a 2x2 block
+    const int tt = ty[tid];
+    dinv[tid] = tt == 1 ? 1.0 / dA[tid]
+                        : (tt == 2 ? 1.0 / (dA[tid] * dA[tid + 1] - dB[tid] * dB[tid]) : 0.0);
+  }
   for (int e = tid; e < BF_NB * BF_NB; e += 256) {
     const int c = e & 63, t = e >> 6;
     double w = 0.0;
     if (t < kb && c < nb && c > t) {
-      const T* Lc = A0 + (int64_t)(j0) * f + j0 + c;  // row j0 + c
+      const T* Lc = A + (int64_t)j0 * f + j0 + c;  // row j0 + c
       const int tt = ty[t];
       if (tt == 1) {
         w = (double)Lc[(int64_t)t * f] * dA[t];
@@ -313,50 +320,38 @@ __global__ void __launch_bounds__(256) big_cbrows_kernel(BigArgs a, T* pool) {
         w = l1 * dB[t] + l2 * dA[t];
       }
     }
-    W[t * (BF_NB + 1) + c] = w;
+    W[t * BF_NB + c] = w;
   }
   __syncthreads();
-  constexpr int R = 16;
-  double v[R];
+  const int i = i0 + tid;
+  if (i >= f) return;
+  double v[BF_NB];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int i = i0 + wave * R + r;
-    v[r] = (i < f && lane < nb) ? (double)A[(int64_t)(j0 + lp[lane]) * f + i] : 0.0;
-  }
-  int t = 0;
-  while (t < kb) {
-    const int tt = ty[t];
+  for (int c = 0; c < BF_NB; ++c) v[c] = c < nb ? (double)A[(int64_t)(j0 + lp[c]) * f + i] : 0.0;
+#pragma unroll
+  for (int t = 0; t < BF_NB; ++t) {
+    const int tt = t < kb ? ty[t] : 0;
     if (tt == 1) {
-      const double wc = W[t * (BF_NB + 1) + lane];
-      const double dinv = 1.0 / dA[t];
+      const double l = v[t] * dinv[t];
+      v[t] = l;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const double l = bcast(v[r], t) * dinv;
-        if (lane == t) v[r] = l;
-        else if (lane > t) v[r] -= l * wc;
-      }
-      t += 1;
-    } else {
-      const double d11 = dA[t], d21 = dB[t], d22 = dA[t + 1];
-      const double idet = 1.0 / (d11 * d22 - d21 * d21);
-      const double w1 = W[t * (BF_NB + 1) + lane], w2 = W[(t + 1) * (BF_NB + 1) + lane];
+      for (int c = t + 1; c < BF_NB; ++c) v[c] -= l * W[t * BF_NB + c];
+    } else if (tt == 2) {
+      const double d11 = dA[t], d21 = dB[t], d22 = dA[t + 1], idet = dinv[t];
+      const double y1 = v[t], y2 = v[t + 1];
+      const double l1 = (y1 * d22 - y2 * d21) * idet;
+      const double l2 = (y2 * d11 - y1 * d21) * idet;
+      v[t] = l1;
+      v[t + 1] = l2;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const double y1 = bcast(v[r], t), y2 = bcast(v[r], t + 1);
-        const double l1 = (y1 * d22 - y2 * d21) * idet;
-        const double l2 = (y2 * d11 - y1 * d21) * idet;
-        if (lane == t) v[r] = l1;
-        else if (lane == t + 1) v[r] = l2;
-        else if (lane > t + 1) v[r] -= l1 * w1 + l2 * w2;
-      }
-      t += 2;
+      for (int c = t + 2; c < BF_NB; ++c)
+        v[c] -= l1 * W[t * BF_NB + c] + l2 * W[(t + 1) * BF_NB + c];
     }
+    // tt == 3: second pivot of a 2x2 block, done with the first
   }
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int i = i0 + wave * R + r;
-    if (i < f && lane < nb) A[(int64_t)(j0 + lane) * f + i] = (T)v[r];
-  }
+  for (int c = 0; c < BF_NB; ++c)
+    if (c < nb) A[(int64_t)(j0 + c) * f + i] = (T)v[c];
 }
 
 // Trailing update of one 64 x 64 lower-triangle tile of [j0 + nb, f)^2:
@@ -549,7 +544,7 @@ void factor_big_fronts(riga_problem* pr, T* pool, const int32_t* fronts,
   a.pivtol = pivtol;
   big_init_kernel<<<nbig, 256, 0, s>>>(a, nbig);
   HIPCHECK(hipGetLastError());
-  const unsigned cb_blocks = (unsigned)std::max(1, (maxcb + 63) / 64);
+  const unsigned cb_blocks = (unsigned)std::max(1, (maxcb + 255) / 256);
   const unsigned tpf = (unsigned)std::max(1, std::min(max_tiles, std::max(1, 2048 / nbig)));
   auto run = [&](int n) {
     for (int it = 0; it < n; ++it) {

@@ -105,14 +105,13 @@ struct PivotStep {
 // of order k.  NT threads.  `lbuf` holds 2 f doubles of scratch, `perm` k
 // ints, `dec` the broadcast decision.  Works for `a` in LDS or in global
 // memory.
-template <class T, int NT>
-__device__ __forceinline__ void ldlt_partial(T* a, int f, int k, double* lbuf, int* perm,
+template <class T, int NT, class Acc>
+__device__ __forceinline__ void ldlt_partial(Acc A, int f, int k, double* lbuf, int* perm,
                                              PivotStep* dec, double pivtol, int* n_neg,
                                              int* n_pert, int* n_2x2, int32_t* type_out) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   constexpr int NW = NT / 64;
-  auto A = [&](int i, int j) -> T& { return a[(int64_t)j * f + i]; };
   for (int t = tid; t < k; t += NT) perm[t] = t;
   int neg = 0, pert = 0, two = 0;
   __syncthreads();
@@ -244,11 +243,13 @@ __device__ __forceinline__ void ldlt_partial(T* a, int f, int k, double* lbuf, i
   if (tid == 0) { *n_neg = neg; *n_pert = pert; *n_2x2 = two; }
 }
 
+// The front in LDS as a packed lower triangle (column j holds rows j..f-1),
+// f (f + 1) / 2 entries, so that two workgroups fit on a CU.
 template <class T, int MAXF>
 __global__ void __launch_bounds__(256) front_factor_lds_kernel(FrontArgs fa, T* pool,
                                                              const int32_t* fronts,
                                                              double pivtol) {
-  __shared__ T sa[MAXF * MAXF];
+  __shared__ T sa[MAXF * (MAXF + 1) / 2];
   __shared__ double lbuf[2 * MAXF];
   __shared__ int perm[MAXF];
   __shared__ int32_t type[MAXF];
@@ -256,18 +257,20 @@ __global__ void __launch_bounds__(256) front_factor_lds_kernel(FrontArgs fa, T* 
   const int F = fronts[blockIdx.x];
   const int f = fa.ff[F], k = fa.fk[F];
   T* g = pool + fa.pool_off[F];
+  auto pk = [f](int i, int j) { return j * f - ((j * (j - 1)) >> 1) + (i - j); };
   const int64_t n2 = (int64_t)f * f;
   for (int64_t e = threadIdx.x; e < n2; e += blockDim.x) {
     const int c = (int)(e / f), r = (int)(e % f);
-    if (r >= c) sa[e] = g[e];
+    if (r >= c) sa[pk(r, c)] = g[e];
   }
   __syncthreads();
   int neg = 0, pert = 0, two = 0;
-  ldlt_partial<T, 256>(sa, f, k, lbuf, perm, &dec, pivtol, &neg, &pert, &two, type);
+  auto A = [&](int i, int j) -> T& { return sa[pk(i, j)]; };
+  ldlt_partial<T, 256>(A, f, k, lbuf, perm, &dec, pivtol, &neg, &pert, &two, type);
   __syncthreads();
   for (int64_t e = threadIdx.x; e < n2; e += blockDim.x) {
     const int c = (int)(e / f), r = (int)(e % f);
-    if (r >= c) g[e] = sa[e];
+    if (r >= c) g[e] = sa[pk(r, c)];
   }
   const int start = fa.fstart[F];
   for (int t = threadIdx.x; t < k; t += blockDim.x) {
