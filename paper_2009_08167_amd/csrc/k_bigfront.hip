@@ -84,6 +84,10 @@ __device__ __forceinline__ double bcast(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Pivot steps with two workgroup barriers each: the column(s) of a pivot are
+// scaled into L lazily, by waves 1.. while wave 0 takes the next decision
+// (which reads only later columns); the rank-1/2 update uses the unscaled
+// columns.
 template <class T>
 __global__ void __launch_bounds__(1024) big_panel_kernel(BigArgs a, T* pool) {
   extern __shared__ double Pn[];
@@ -113,6 +117,22 @@ __global__ void __launch_bounds__(1024) big_panel_kernel(BigArgs a, T* pool) {
   }
   if (tid < nb) lp[tid] = tid;
   int neg = 0, pert = 0, two = 0;
+  // pending scaling of the previous pivot's column(s)
+  int pj = -1, pkind = 0;
+  double p11 = 0.0, p21 = 0.0, p22 = 0.0;
+  auto scale_pending = [&](int t0, int nt) {
+    if (pkind == 1) {
+      const double dinv = 1.0 / p11;
+      for (int r = pj + 1 + t0; r < k; r += nt) P(r, pj) *= dinv;
+    } else if (pkind == 2) {
+      const double idet = 1.0 / (p11 * p22 - p21 * p21);
+      for (int r = pj + 2 + t0; r < k; r += nt) {
+        const double u1 = P(r, pj), u2 = P(r, pj + 1);
+        P(r, pj) = (u1 * p22 - u2 * p21) * idet;
+        P(r, pj + 1) = (u2 * p11 - u1 * p21) * idet;
+      }
+    }
+  };
   __syncthreads();
   int jj = 0;
   while (jj < nb) {
@@ -166,8 +186,11 @@ __global__ void __launch_bounds__(1024) big_panel_kernel(BigArgs a, T* pool) {
         dec.sb = sb;
         dec.end = end;
       }
+    } else {
+      scale_pending(tid - 64, NT - 64);
     }
     __syncthreads();
+    pkind = 0;
     if (dec.end) break;
     const int kind = dec.kind;
     const int p = dec.sa, q = dec.sb;  // p < q < pend
@@ -196,29 +219,32 @@ __global__ void __launch_bounds__(1024) big_panel_kernel(BigArgs a, T* pool) {
         const int tp = perm[p]; perm[p] = perm[q]; perm[q] = tp;
         const int tl = lp[p - j0]; lp[p - j0] = lp[q - j0]; lp[q - j0] = tl;
       }
-    }
-    __syncthreads();
-    if (kind == 1) {
-      double d = P(j, j);
-      if (fabs(d) < a.pivtol) d = d < 0.0 ? -a.pivtol : a.pivtol;
       __syncthreads();
+    }
+    if (kind == 1) {
+      // every thread computes the same (possibly perturbed) pivot
+      const double a0 = P(j, j);
+      const double d = fabs(a0) < a.pivtol ? (a0 < 0.0 ? -a.pivtol : a.pivtol) : a0;
       if (tid == 0) {
-        if (d != P(j, j)) ++pert;
-        P(j, j) = d;
+        if (d != a0) ++pert;
         if (d < 0.0) ++neg;
         type_out[j] = 1;
       }
       const double dinv = 1.0 / d;
-      for (int r = j + 1 + tid; r < k; r += NT) P(r, j) *= dinv;
-      __syncthreads();
       for (int c = j + 1 + wave; c < pend; c += NW) {
-        const double uc = P(c, j) * d;
+        const double uc = P(c, j) * dinv;
         for (int r = c + lane; r < k; r += 64) P(r, c) -= P(r, j) * uc;
       }
+      __syncthreads();
+      if (tid == 0) P(j, j) = d;
+      pj = j;
+      pkind = 1;
+      p11 = d;
       jj += 1;
     } else {
       const double d11 = P(j, j), d21 = P(j + 1, j), d22 = P(j + 1, j + 1);
       const double det = d11 * d22 - d21 * d21;
+      const double idet = 1.0 / det;
       if (tid == 0) {
         if (det < 0.0) neg += 1;
         else if (d11 < 0.0) neg += 2;
@@ -226,22 +252,23 @@ __global__ void __launch_bounds__(1024) big_panel_kernel(BigArgs a, T* pool) {
         type_out[j] = 2;
         type_out[j + 1] = 3;
       }
-      const double idet = 1.0 / det;
-      for (int r = j + 2 + tid; r < k; r += NT) {
-        const double u1 = P(r, j), u2 = P(r, j + 1);
-        P(r, j) = (u1 * d22 - u2 * d21) * idet;
-        P(r, j + 1) = (u2 * d11 - u1 * d21) * idet;
+      // A(r, c) -= [a_rj a_rj+1] D^{-1} [a_cj; a_cj+1] with the unscaled columns
+      for (int c = j + 2 + wave; c < pend; c += NW) {
+        const double u1 = P(c, j), u2 = P(c, j + 1);
+        const double w1 = (u1 * d22 - u2 * d21) * idet, w2 = (u2 * d11 - u1 * d21) * idet;
+        for (int r = c + lane; r < k; r += 64) P(r, c) -= P(r, j) * w1 + P(r, j + 1) * w2;
       }
       __syncthreads();
-      for (int c = j + 2 + wave; c < pend; c += NW) {
-        const double l1 = P(c, j), l2 = P(c, j + 1);
-        const double u1 = l1 * d11 + l2 * d21, u2 = l1 * d21 + l2 * d22;
-        for (int r = c + lane; r < k; r += 64) P(r, c) -= P(r, j) * u1 + P(r, j + 1) * u2;
-      }
+      pj = j;
+      pkind = 2;
+      p11 = d11;
+      p21 = d21;
+      p22 = d22;
       jj += 2;
     }
-    __syncthreads();
   }
+  // the last pivot's column(s)
+  scale_pending(tid, NT);
   __syncthreads();
   const int kb = jj;
   for (int e = tid; e < nb * m; e += NT) {
