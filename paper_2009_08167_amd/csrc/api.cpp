@@ -157,10 +157,11 @@ riga_status riga_spmv(riga_problem* pr, int32_t which, const double* x, double* 
     if (which == RIGA_MAT_K) vals = pr->kv.p;
     else if (which == RIGA_MAT_M) vals = pr->mv.p;
     else if (which == RIGA_MAT_A) {
-      if (!pr->factored) return fail(RIGA_EINVAL, "no shift factorised yet");
-      if (!pr->av.p) pr->av.alloc(pr->kv.n, pr->home);
-      riga::launch_axpby_vals(pr->kv.p, pr->mv.p, pr->sigma, pr->av.p, (int64_t)pr->kv.n, s);
-      vals = pr->av.p;
+      riga::Factor& F = pr->fac[pr->cur];
+      if (!F.factored) return fail(RIGA_EINVAL, "no shift factorised yet");
+      if (F.av.n < pr->kv.n) F.av.alloc(pr->kv.n, pr->home);
+      riga::launch_axpby_vals(pr->kv.p, pr->mv.p, F.sigma, F.av.p, (int64_t)pr->kv.n, s);
+      vals = F.av.p;
     } else return fail(RIGA_EINVAL, "which must be RIGA_MAT_K, _M or _A");
     riga::launch_spmv(pr, vals, x, y, nullptr, s);
     HIPCHECK(hipStreamSynchronize(s));
@@ -174,18 +175,15 @@ riga_status riga_factor(riga_problem* pr, double sigma, int32_t precision, int64
     if (!need_device(pr)) return fail(RIGA_EINVAL, "problem has no device data");
     if (!std::isfinite(sigma)) return fail(RIGA_EINVAL, "sigma must be finite");
     if (precision != RIGA_FP64 && precision != RIGA_MIXED) return fail(RIGA_EINVAL, "bad precision");
-    riga::factor_numeric(pr, sigma, precision);
-    if (precision == RIGA_MIXED) {
-      if (!pr->av.p) pr->av.alloc(pr->kv.n, pr->home);
-      riga::launch_axpby_vals(pr->kv.p, pr->mv.p, sigma, pr->av.p, (int64_t)pr->kv.n, pr->stream);
-      HIPCHECK(hipStreamSynchronize(pr->stream));
-    }
-    if (neg_pivots) *neg_pivots = pr->last_inertia;
+    riga::Factor& F = pr->fac[pr->cur];
+    riga::factor_reserve(pr, F, precision, pr->home);
+    riga::factor_numeric(pr, F, sigma, precision, pr->home);
+    if (neg_pivots) *neg_pivots = F.inertia;
     if (stats) {
       std::memset(stats, 0, sizeof(*stats));
       stats->n_fact = 1;
-      stats->n_perturbed_pivots = pr->last_perturbed;
-      stats->n_2x2_pivots = pr->last_2x2;
+      stats->n_perturbed_pivots = F.perturbed;
+      stats->n_2x2_pivots = F.two;
       stats->flops_fact = pr->an.flops_fact;
     }
     return RIGA_OK;
@@ -195,10 +193,11 @@ riga_status riga_factor(riga_problem* pr, double sigma, int32_t precision, int64
 riga_status riga_solve(riga_problem* pr, const double* b, double* x, int32_t max_ir, void* stream) {
   return guarded([&]() -> riga_status {
     if (!need_device(pr) || !b || !x || b == x) return fail(RIGA_EINVAL, "bad problem or vectors");
-    if (!pr->factored) return fail(RIGA_EINVAL, "no factorisation");
+    const riga::Factor& F = pr->fac[pr->cur];
+    if (!F.factored) return fail(RIGA_EINVAL, "no factorisation");
     hipStream_t s = (hipStream_t)stream;
-    riga::solve_fb(pr, b, x, s);
-    if (pr->fact_precision == RIGA_MIXED && max_ir > 0) {
+    riga::solve_fb(pr, F, b, x, s);
+    if (F.precision == RIGA_MIXED && max_ir > 0) {
       // FP64 iterative refinement: r = b - A x, x += A32^{-1} r, until
       // ||r|| <= 1e-13 ||b|| or max_ir corrections
       const int64_t N = pr->an.N;
@@ -215,13 +214,13 @@ riga_status riga_solve(riga_problem* pr, const double* b, double* x, int32_t max
       HIPCHECK(hipStreamSynchronize(s));
       const double bn2 = h[0];
       for (int it = 0; it < max_ir; ++it) {
-        riga::launch_spmv(pr, pr->av.p, x, pr->ir_r.p, nullptr, s);
+        riga::launch_spmv(pr, F.av.p, x, pr->ir_r.p, nullptr, s);
         riga::launch_axpby(-1.0, pr->ir_r.p, b, pr->ir_r.p, N, s);
         riga::launch_dot(pr->ir_r.p, pr->ir_r.p, N, part.p, nr.p + 1, s);
         HIPCHECK(hipMemcpyAsync(&h[1], nr.p + 1, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
         if (h[1] <= 1e-26 * bn2) break;
-        riga::solve_fb(pr, pr->ir_r.p, pr->ir_d.p, s);
+        riga::solve_fb(pr, F, pr->ir_r.p, pr->ir_d.p, s);
         riga::launch_axpby(1.0, pr->ir_d.p, x, x, N, s);
       }
     }

@@ -23,6 +23,7 @@
 #include <cstring>
 #include <limits>
 #include <numeric>
+#include <string>
 
 #include "problem.h"
 
@@ -112,30 +113,36 @@ struct Solver {
     }
   }
 
+  Factor& cur() { return pr->fac[pr->cur]; }
+
+  // counts one factorisation (in place or look-ahead) in the statistics
+  void count_factor(const Factor& F) {
+    st.n_fact++;
+    st.n_perturbed_pivots += F.perturbed;
+    st.n_2x2_pivots += F.two;
+  }
+
+  // factorises K - sigma M in place of the current factorisation
   void factor(double sigma) {
     auto a = clk::now();
-    factor_numeric(pr, sigma, precision);
-    if (precision == RIGA_MIXED) {
-      if (!pr->av.p) pr->av.alloc(pr->kv.n, pr->home);
-      launch_axpby_vals(pr->kv.p, pr->mv.p, sigma, pr->av.p, (int64_t)pr->kv.n, s);
-    }
+    factor_reserve(pr, cur(), precision, pr->home);
+    factor_numeric(pr, cur(), sigma, precision, s);
     st.t_fact += secs(a, clk::now());
-    st.n_fact++;
-    st.n_perturbed_pivots += pr->last_perturbed;
-    st.n_2x2_pivots += pr->last_2x2;
+    count_factor(cur());
   }
 
   // x = A^{-1} b (FP64), or FP32 solve + fixed FP64 refinement (mixed)
   void apply_inverse(const double* b, double* out) {
-    solve_fb(pr, b, out, s);
+    const Factor& F = cur();
+    solve_fb(pr, F, b, out, s);
     st.n_fb++;
     if (precision == RIGA_MIXED) {
       for (int it = 0; it < max_ir; ++it) {
         // r = b - A x
-        launch_spmv(pr, pr->av.p, out, ir_r.p, nullptr, s);
+        launch_spmv(pr, F.av.p, out, ir_r.p, nullptr, s);
         st.n_mv++;
         axpy_launch(-1.0, ir_r.p, b, ir_r.p);
-        solve_fb(pr, ir_r.p, ir_d.p, s);
+        solve_fb(pr, F, ir_r.p, ir_d.p, s);
         st.n_fb++;
         st.n_ir++;
         axpy_launch(1.0, ir_d.p, out, out);
@@ -277,14 +284,18 @@ struct Solver {
       st.n_mv += 2 * nw;
       launch_residuals(KU.p, MU.p, Ub.p, N, nw, rqn.p, rqd.p, rn2.p, un2.p, lam.p, s);
       std::vector<double> h_rqd(nw), h_rn2(nw), h_un2(nw), h_lam(nw);
-      HIPCHECK(hipMemcpy(h_rqd.data(), rqd.p, nw * sizeof(double), hipMemcpyDeviceToHost));
-      HIPCHECK(hipMemcpy(h_rn2.data(), rn2.p, nw * sizeof(double), hipMemcpyDeviceToHost));
-      HIPCHECK(hipMemcpy(h_un2.data(), un2.p, nw * sizeof(double), hipMemcpyDeviceToHost));
-      HIPCHECK(hipMemcpy(h_lam.data(), lam.p, nw * sizeof(double), hipMemcpyDeviceToHost));
+      // copies on the solve's own stream: the null stream would not order
+      // them after its kernels, and could wait on unrelated streams
+      HIPCHECK(hipMemcpyAsync(h_rqd.data(), rqd.p, nw * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipMemcpyAsync(h_rn2.data(), rn2.p, nw * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipMemcpyAsync(h_un2.data(), un2.p, nw * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipMemcpyAsync(h_lam.data(), lam.p, nw * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
       // M-normalise: u /= sqrt(u^T M u)
       std::vector<double> scl(nw);
       for (int i = 0; i < nw; ++i) scl[i] = 1.0 / std::sqrt(h_rqd[i]);
-      HIPCHECK(hipMemcpy(nrm.p, scl.data(), nw * sizeof(double), hipMemcpyHostToDevice));
+      HIPCHECK(hipMemcpyAsync(nrm.p, scl.data(), nw * sizeof(double), hipMemcpyHostToDevice, s));
+      HIPCHECK(hipStreamSynchronize(s));  // scl is pageable host memory
       launch_scale_cols(Ub.p, N, nw, nrm.p, s);
       launch_scale_cols(MU.p, N, nw, nrm.p, s);
       // candidates: residual below tol, eigenvalue in [lo, hi); locked in
@@ -322,6 +333,7 @@ struct Solver {
 
     } else if (*have_restart) {
       launch_copy(y.p, Ub.p, N, s);
+      HIPCHECK(hipStreamSynchronize(s));  // Sh_h (pageable) must outlive its upload
     }
     (void)sigma;
     st.t_ritz += secs(a, clk::now());
@@ -390,6 +402,30 @@ struct Solver {
 };
 
 
+// Moves cand to the middle of the gap between estimated eigenvalues above
+// top that contains it (estimates: the locked values and the Ritz values of
+// run r, made at shift sigma); clamps to hi.
+double place_in_gap(const Solver& sv, const Solver::Ritz& r, double sigma, double top, double cand,
+                    double step, double hi) {
+  std::vector<double> est;
+  for (auto& L : sv.locked) est.push_back(L.lam);
+  for (int i = 0; i < (int)r.theta.size(); ++i)
+    if (r.theta[i] != 0.0) est.push_back(sigma + 1.0 / r.theta[i]);
+  std::sort(est.begin(), est.end());
+  // the gap containing cand (estimates above top only)
+  double below = top, above = std::numeric_limits<double>::infinity();
+  for (double e : est) {
+    if (e <= top) continue;
+    if (e <= cand) below = std::max(below, e);
+    else { above = std::min(above, e); }
+  }
+  if (std::isfinite(above)) cand = 0.5 * (below + above);
+  else if (below > top) cand = std::max(cand, below + 0.5 * step);
+  if (std::isfinite(hi) && cand >= hi) cand = hi;
+  return cand;
+}
+
+
 // Places the next shift above the eigenvalues locked so far: far enough
 // that the new slice holds about `target` eigenvalues (eigenvalue density
 // estimated from the locked ones), then moved to the middle of the nearest
@@ -409,24 +445,93 @@ double next_shift(const Solver& sv, const Solver::Ritz& r, double sigma, double 
   double step;
   if (dens > 0) step = target / dens;
   else step = std::max(std::fabs(top), 1.0) * 0.5;
-  double cand = top + step;
-  // estimates: locked values and unconverged Ritz values of the last run
-  std::vector<double> est;
-  for (auto& L : sv.locked) est.push_back(L.lam);
-  for (int i = 0; i < (int)r.theta.size(); ++i)
-    if (r.theta[i] != 0.0) est.push_back(sigma + 1.0 / r.theta[i]);
-  std::sort(est.begin(), est.end());
-  // the gap containing cand (estimates above top only)
-  double below = top, above = std::numeric_limits<double>::infinity();
-  for (double e : est) {
-    if (e <= top) continue;
-    if (e <= cand) below = std::max(below, e);
-    else { above = std::min(above, e); }
+  return place_in_gap(sv, r, sigma, top, top + step, step, hi);
+}
+
+// Look-ahead guess of the shift that next_shift will choose once the runs at
+// sigma have finished, made before they start: those runs lock about
+// `per_above` eigenvalues above sigma, so the top of the locked set moves to
+// about sigma + per_above / density; the guess lies `target` eigenvalues
+// beyond, in a gap of the estimates known now (locked values and the Ritz
+// values of the last run, made at shift r_sigma).  Returns NaN when the
+// locked set gives no density yet.
+double predict_shift(const Solver& sv, const Solver::Ritz& r, double r_sigma, double sigma,
+                     double lo, double hi, int per_above, int target) {
+  double top = sigma;
+  int cnt = 0;
+  for (auto& L : sv.locked)
+    if (L.lam >= lo && L.lam < hi) {
+      top = std::max(top, L.lam);
+      ++cnt;
+    }
+  const double width = top - lo;
+  if (cnt == 0 || !(width > 0)) return std::numeric_limits<double>::quiet_NaN();
+  const double dens = cnt / width;
+  top = std::max(top, sigma + per_above / dens);
+  const double step = target / dens;
+  return place_in_gap(sv, r, r_sigma, top, top + step, step, hi);
+}
+
+// A factorisation at a predicted shift made on a second host thread and
+// stream into the spare Factor, while the Lanczos runs at the current shift
+// use the other one.  The destructor waits for it, so no exit path leaves
+// the thread writing into the problem.
+struct LookAhead {
+  riga_problem* pr = nullptr;
+  hipStream_t s2 = nullptr;
+  std::thread th;
+  bool active = false;
+  double sigma = 0.0;
+  std::string err;
+  riga_status code = RIGA_OK;
+
+  ~LookAhead() {
+    if (th.joinable()) th.join();
+    if (s2) (void)hipStreamDestroy(s2);
   }
-  if (std::isfinite(above)) cand = 0.5 * (below + above);
-  else if (below > top) cand = std::max(cand, below + 0.5 * step);
-  if (std::isfinite(hi) && cand >= hi) cand = hi;
-  return cand;
+
+  Factor& spare() { return pr->fac[1 - pr->cur]; }
+
+  // s: the stream of the Lanczos runs, whose work on the spare Factor (if
+  // it was the current one before) must be finished before it is reused
+  void start(double sig, int precision, hipStream_t s) {
+    factor_reserve(pr, spare(), precision, pr->home);
+    HIPCHECK(hipStreamSynchronize(s));
+    if (!s2) HIPCHECK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+    sigma = sig;
+    err.clear();
+    code = RIGA_OK;
+    active = true;
+    const int dev = pr->device;
+    th = std::thread([this, dev, precision] {
+      try {
+        HIPCHECK(hipSetDevice(dev));
+        factor_numeric(pr, spare(), sigma, precision, s2);
+      } catch (const Error& e) {
+        code = e.code;
+        err = e.what();
+      } catch (const std::exception& e) {
+        code = RIGA_EDEVICE;
+        err = e.what();
+      }
+    });
+  }
+
+  // waits for the factorisation; rethrows its error
+  void join() {
+    if (th.joinable()) th.join();
+    active = false;
+    if (code != RIGA_OK) throw Error(code, "look-ahead factorisation: " + err);
+  }
+};
+
+// RIGA_LOOKAHEAD=0 factorises every shift in place, after its runs.
+bool lookahead_on() {
+  static const bool on = [] {
+    const char* v = std::getenv("RIGA_LOOKAHEAD");
+    return !(v && *v == '0');
+  }();
+  return on;
 }
 
 }  // namespace
@@ -461,13 +566,13 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
   int64_t nu_lo = 0;
   if (std::isfinite(hi)) {
     sv.factor(hi);
-    const int64_t nu_hi = pr->last_inertia;
+    const int64_t nu_hi = sv.cur().inertia;
     sv.factor(lo);
-    nu_lo = pr->last_inertia;
+    nu_lo = sv.cur().inertia;
     nev = (int)std::min<int64_t>(nev, nu_hi - nu_lo);
   } else {
     sv.factor(lo);
-    nu_lo = pr->last_inertia;
+    nu_lo = sv.cur().inertia;
   }
   sv.st.n_shift = 1;
   riga_status status = RIGA_OK;
@@ -475,10 +580,19 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
   int64_t known = 0;  // eigenvalues in [lo, sigma)
   double verified = lo;  // every eigenvalue in [lo, verified) is locked
   const double* init = nullptr;
+  LookAhead la;
+  la.pr = pr;
+  Solver::Ritz last;        // final Ritz data of the last run
+  double last_sigma = lo;   // its shift
   for (int shift = 0; nev > 0 && shift < 400; ++shift) {
-    Solver::Ritz last;
     int runs = 0;
     const int per_above = shift == 0 ? sv.per_shift : std::max(1, sv.per_shift / 2);
+    const int64_t target = std::max<int64_t>(1, std::min<int64_t>(sv.per_shift / 2, nev - known));
+    // factorise at the guessed next shift while the runs at this one proceed
+    if (lookahead_on() && shift > 0 && known < nev && !(std::isfinite(hi) && sigma >= hi)) {
+      const double guess = predict_shift(sv, last, last_sigma, sigma, lo, hi, per_above, (int)target);
+      if (std::isfinite(guess) && guess > sigma) la.start(guess, sv.precision, sv.s);
+    }
     do {
       const int below = sv.count_locked(lo, sigma);
       const int need_below = (int)std::max<int64_t>(0, known - below);
@@ -490,6 +604,7 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
       // the previous Krylov space did not reach (e.g. further copies of a
       // multiple eigenvalue): start it from a fresh random vector
       last = sv.run(sigma, need_below, need_above, runs == 0 ? init : nullptr, &n_new);
+      last_sigma = sigma;
       init = sv.restart_valid ? sv.y.p : nullptr;
       ++runs;
     } while (sv.count_locked(lo, sigma) < known && runs < sv.max_restarts);
@@ -500,11 +615,31 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
     verified = sigma;
     if (known >= nev) break;
     if (std::isfinite(hi) && sigma >= hi) break;
-    const int64_t target = std::max<int64_t>(1, std::min<int64_t>(sv.per_shift / 2, nev - known));
     double next = next_shift(sv, last, sigma, lo, hi, (int)target);
-    sv.factor(next);
+    bool taken = false;
+    if (la.active) {
+      // the look-ahead factorisation replaces the one at `next` when it
+      // moves past this shift and leaves no more eigenvalues below it to
+      // find than one run is sized for
+      auto a = clk::now();
+      la.join();
+      sv.st.t_fact += secs(a, clk::now());
+      const Factor& F = la.spare();
+      sv.count_factor(F);
+      const int64_t known_g = F.inertia - nu_lo;
+      const int64_t missing = known_g - sv.count_locked(lo, la.sigma);
+      taken = la.sigma > sigma && known_g > known && missing <= sv.per_shift;
+      if (log_on())
+        std::fprintf(stderr, "[riga] look-ahead sigma=%.10g (placed after the runs: %.10g): %s\n",
+                     la.sigma, next, taken ? "taken" : "discarded");
+      if (taken) {
+        pr->cur = 1 - pr->cur;
+        next = la.sigma;
+      }
+    }
+    if (!taken) sv.factor(next);
     sv.st.n_shift++;
-    known = pr->last_inertia - nu_lo;
+    known = sv.cur().inertia - nu_lo;
     if (log_on())
       std::fprintf(stderr, "[riga] shift %d: sigma=%.10g count below=%lld locked below=%d\n",
                    shift + 1, next, (long long)known, sv.count_locked(lo, next));

@@ -524,7 +524,7 @@ void set_bigfront_attributes() {
 int bigfront_max_k() { return BF_LDS; }
 
 template <class T>
-void factor_big_fronts(riga_problem* pr, T* pool, const int32_t* fronts,
+void factor_big_fronts(riga_problem* pr, Factor& F, T* pool, const int32_t* fronts,
                        const std::vector<int>& big_f, const std::vector<int>& big_k,
                        double pivtol, hipStream_t s) {
   const int nbig = (int)big_f.size();
@@ -547,27 +547,27 @@ void factor_big_fronts(riga_problem* pr, T* pool, const int32_t* fronts,
   }
   if (maxk > bigfront_max_k())
     throw Error(RIGA_EUNSUPPORTED, "fully-summed block too large for the panel kernel");
-  // scratch sized for the largest level at set-up (kept with the problem)
+  // scratch reserved before the factorisation for the largest level: it is
+  // never reallocated while kernels of an earlier level may still use it
   const int64_t stride = maxk + 1;
   const size_t need_perm = (size_t)nbig * stride, need_lp = (size_t)nbig * BF_NB;
   const size_t need_st = (size_t)nbig * sizeof(BigState) / sizeof(int32_t) + 1;
-  if (pr->big_perm.n < need_perm) pr->big_perm.alloc(need_perm, pr->home);
-  if (pr->big_lperm.n < need_lp) pr->big_lperm.alloc(need_lp, pr->home);
-  if (pr->big_state.n < need_st) pr->big_state.alloc(need_st, pr->home);
-  int32_t* pending = pr->big_state.p + (need_st - 1);
+  if (F.big_perm.n < need_perm || F.big_lperm.n < need_lp || F.big_state.n < need_st)
+    throw Error(RIGA_EINVAL, "blocked-factorisation scratch not reserved");
+  int32_t* pending = F.big_state.p + (F.big_state.n - 1);
   BigArgs a{};
   a.fronts = fronts;
   a.ff = pr->d_ff.p;
   a.fk = pr->d_fk.p;
   a.fstart = pr->d_fstart.p;
   a.pool_off = pr->d_pool_off.p;
-  a.piv_perm = pr->piv_perm.p;
-  a.piv_type = pr->piv_type.p;
-  a.stat = pr->front_stat.p;
-  a.perm = pr->big_perm.p;
+  a.piv_perm = F.piv_perm.p;
+  a.piv_type = F.piv_type.p;
+  a.stat = F.front_stat.p;
+  a.perm = F.big_perm.p;
   a.perm_stride = stride;
-  a.lperm = pr->big_lperm.p;
-  a.st = reinterpret_cast<BigState*>(pr->big_state.p);
+  a.lperm = F.big_lperm.p;
+  a.st = reinterpret_cast<BigState*>(F.big_state.p);
   a.pivtol = pivtol;
   big_init_kernel<<<nbig, 256, 0, s>>>(a, nbig);
   HIPCHECK(hipGetLastError());
@@ -597,9 +597,30 @@ void factor_big_fronts(riga_problem* pr, T* pool, const int32_t* fronts,
   HIPCHECK(hipGetLastError());
 }
 
-template void factor_big_fronts<double>(riga_problem*, double*, const int32_t*, const std::vector<int>&,
-                                        const std::vector<int>&, double, hipStream_t);
-template void factor_big_fronts<float>(riga_problem*, float*, const int32_t*, const std::vector<int>&,
-                                       const std::vector<int>&, double, hipStream_t);
+void bigfront_reserve(riga_problem* pr, Factor& F, int lds_max_f, hipStream_t s) {
+  size_t need_perm = 0, need_lp = 0, need_st = 0;
+  for (const LevelDev& L : pr->levels) {
+    const int ns = L.n_upto(lds_max_f);
+    const int nbig = L.n - ns;
+    if (nbig <= 0) continue;
+    int maxk = 0;
+    for (int i = ns; i < L.n; ++i) maxk = std::max(maxk, L.host_k[i]);
+    need_perm = std::max(need_perm, (size_t)nbig * (size_t)(maxk + 1));
+    need_lp = std::max(need_lp, (size_t)nbig * BF_NB);
+    need_st = std::max(need_st, (size_t)nbig * sizeof(BigState) / sizeof(int32_t) + 1);
+  }
+  if (need_perm == 0) return;
+  // the pending counter takes the last slot of big_state, past every level's states
+  if (F.big_perm.n < need_perm) F.big_perm.alloc(need_perm, s);
+  if (F.big_lperm.n < need_lp) F.big_lperm.alloc(need_lp, s);
+  if (F.big_state.n < need_st) F.big_state.alloc(need_st, s);
+}
+
+template void factor_big_fronts<double>(riga_problem*, Factor&, double*, const int32_t*,
+                                        const std::vector<int>&, const std::vector<int>&, double,
+                                        hipStream_t);
+template void factor_big_fronts<float>(riga_problem*, Factor&, float*, const int32_t*,
+                                       const std::vector<int>&, const std::vector<int>&, double,
+                                       hipStream_t);
 
 }  // namespace riga

@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(256) front_factor_lds_kernel(FrontArgs fa, T* 
   }
 }
 
-FrontArgs front_args(riga_problem* pr) {
+FrontArgs front_args(riga_problem* pr, Factor& F) {
   FrontArgs fa{};
   fa.fk = pr->d_fk.p;
   fa.ff = pr->d_ff.p;
@@ -299,16 +299,15 @@ FrontArgs front_args(riga_problem* pr) {
   fa.amap_val = pr->d_amap_val.p;
   fa.kv = pr->kv.p;
   fa.mv = pr->mv.p;
-  fa.piv_perm = pr->piv_perm.p;
-  fa.piv_type = pr->piv_type.p;
-  fa.stat = pr->front_stat.p;
+  fa.piv_perm = F.piv_perm.p;
+  fa.piv_type = F.piv_type.p;
+  fa.stat = F.front_stat.p;
   return fa;
 }
 
 template <class T, int MAXF>
-void factor_levels(riga_problem* pr, T* pool, T* hpool, double sigma) {
-  hipStream_t s = pr->stream;
-  FrontArgs fa = front_args(pr);
+void factor_levels(riga_problem* pr, Factor& F, T* pool, T* hpool, double sigma, hipStream_t s) {
+  FrontArgs fa = front_args(pr, F);
   const double pivtol = 1e-20 * (pr->normK1 + fabs(sigma) * pr->normM1);
   set_kernel_attributes();
   for (size_t h = 0; h < pr->levels.size(); ++h) {
@@ -325,11 +324,11 @@ void factor_levels(riga_problem* pr, T* pool, T* hpool, double sigma) {
     if (L.n > ns) {
       std::vector<int> bf(L.host_f.begin() + ns, L.host_f.end());
       std::vector<int> bk(L.host_k.begin() + ns, L.host_k.end());
-      factor_big_fronts<T>(pr, pool, L.fronts.p + ns, bf, bk, pivtol, s);
+      factor_big_fronts<T>(pr, F, pool, L.fronts.p + ns, bf, bk, pivtol, s);
     }
   }
-  launch_front_inverse<T>(pr, pool, hpool, s);
-  launch_pivot_maps(pr, s);
+  launch_front_inverse<T>(pr, F, pool, hpool, s);
+  launch_pivot_maps(pr, F, s);
   HIPCHECK(hipStreamSynchronize(s));
 }
 
@@ -337,34 +336,51 @@ void factor_levels(riga_problem* pr, T* pool, T* hpool, double sigma) {
 
 void set_front_attributes() {}
 
-void factor_numeric(riga_problem* pr, double sigma, int precision) {
+void factor_reserve(riga_problem* pr, Factor& F, int precision, hipStream_t s) {
   const Analysis& an = pr->an;
-  hipStream_t s = pr->stream;
   if (precision == RIGA_MIXED) {
-    if (pr->pool32.n < (size_t)an.pool_size) pr->pool32.alloc(an.pool_size, pr->home);
-    if (pr->h32.n < (size_t)an.h_size) pr->h32.alloc(an.h_size, pr->home);
-    factor_levels<float, LDS_FRONT_MAX_F32>(pr, pr->pool32.p, pr->h32.p, sigma);
+    if (F.pool32.n < (size_t)an.pool_size) F.pool32.alloc(an.pool_size, s);
+    if (F.h32.n < (size_t)an.h_size) F.h32.alloc(an.h_size, s);
+    if (F.av.n < pr->kv.n) F.av.alloc(pr->kv.n, s);
+    bigfront_reserve(pr, F, LDS_FRONT_MAX_F32, s);
   } else {
-    if (pr->pool64.n < (size_t)an.pool_size) pr->pool64.alloc(an.pool_size, pr->home);
-    if (pr->h64.n < (size_t)an.h_size) pr->h64.alloc(an.h_size, pr->home);
-    factor_levels<double, LDS_FRONT_MAX_F64>(pr, pr->pool64.p, pr->h64.p, sigma);
+    if (F.pool64.n < (size_t)an.pool_size) F.pool64.alloc(an.pool_size, s);
+    if (F.h64.n < (size_t)an.h_size) F.h64.alloc(an.h_size, s);
+    bigfront_reserve(pr, F, LDS_FRONT_MAX_F64, s);
+  }
+}
+
+void factor_numeric(riga_problem* pr, Factor& F, double sigma, int precision, hipStream_t s) {
+  const Analysis& an = pr->an;
+  F.factored = false;
+  if (precision == RIGA_MIXED) {
+    if (F.pool32.n < (size_t)an.pool_size || F.h32.n < (size_t)an.h_size || F.av.n < pr->kv.n)
+      throw Error(RIGA_EINVAL, "factorisation buffers not reserved");
+    factor_levels<float, LDS_FRONT_MAX_F32>(pr, F, F.pool32.p, F.h32.p, sigma, s);
+    // K - sigma M for the refinement residuals
+    launch_axpby_vals(pr->kv.p, pr->mv.p, sigma, F.av.p, (int64_t)pr->kv.n, s);
+  } else {
+    if (F.pool64.n < (size_t)an.pool_size || F.h64.n < (size_t)an.h_size)
+      throw Error(RIGA_EINVAL, "factorisation buffers not reserved");
+    factor_levels<double, LDS_FRONT_MAX_F64>(pr, F, F.pool64.p, F.h64.p, sigma, s);
   }
   std::vector<int32_t> st((size_t)an.n_fronts * 4);
-  HIPCHECK(hipMemcpy(st.data(), pr->front_stat.p, st.size() * sizeof(int32_t),
-                     hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpyAsync(st.data(), F.front_stat.p, st.size() * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
   int64_t neg = 0;
   int pert = 0, two = 0;
-  for (int F = 0; F < an.n_fronts; ++F) {
-    neg += st[4 * F];
-    pert += st[4 * F + 1];
-    two += st[4 * F + 2];
+  for (int f = 0; f < an.n_fronts; ++f) {
+    neg += st[4 * f];
+    pert += st[4 * f + 1];
+    two += st[4 * f + 2];
   }
-  pr->last_inertia = neg;
-  pr->last_perturbed = pert;
-  pr->last_2x2 = two;
-  pr->sigma = sigma;
-  pr->fact_precision = precision;
-  pr->factored = true;
+  F.inertia = neg;
+  F.perturbed = pert;
+  F.two = two;
+  F.sigma = sigma;
+  F.precision = precision;
+  F.factored = true;
 }
 
 }  // namespace riga

@@ -202,14 +202,14 @@ void set_inverse_attributes() {
 }
 
 template <class T>
-void launch_front_inverse(riga_problem* pr, const T* pool, T* h, hipStream_t s) {
+void launch_front_inverse(riga_problem* pr, Factor& F, const T* pool, T* h, hipStream_t s) {
   if (pr->n_inv_units == 0) return;
   front_inverse_kernel<T><<<pr->n_inv_units, 256, front_inverse_lds(pr->an.max_fs), s>>>(
-      pr->d_desc.p, pr->inv_units.p, pool, h, pr->piv_type.p, pr->d_diag.p, pr->d_sub.p);
+      pr->d_desc.p, pr->inv_units.p, pool, h, F.piv_type.p, F.d_diag.p, F.d_sub.p);
   HIPCHECK(hipGetLastError());
 }
 
-template void launch_front_inverse<double>(riga_problem*, const double*, double*, hipStream_t);
-template void launch_front_inverse<float>(riga_problem*, const float*, float*, hipStream_t);
+template void launch_front_inverse<double>(riga_problem*, Factor&, const double*, double*, hipStream_t);
+template void launch_front_inverse<float>(riga_problem*, Factor&, const float*, float*, hipStream_t);
 
 }  // namespace riga

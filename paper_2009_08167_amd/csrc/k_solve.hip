@@ -221,16 +221,16 @@ __global__ void pivot_maps_kernel(const FrontDesc* __restrict__ desc,
   for (int sl = 0; sl < gs; ++sl) piv_gmap[n * gs + sl] = gmap[d.gmap_off + (int64_t)pos * gs + sl];
 }
 
-SolveArgs solve_args(riga_problem* pr) {
+SolveArgs solve_args(riga_problem* pr, const Factor& F) {
   SolveArgs sa{};
   sa.gmap = pr->d_gmap.p;
   sa.gstride = pr->gstride;
   sa.rows = pr->d_rows.p;
-  sa.piv_type = pr->piv_type.p;
-  sa.piv_dof = pr->piv_dof.p;
-  sa.piv_gmap = pr->piv_gmap.p;
-  sa.dd = pr->d_diag.p;
-  sa.dsub = pr->d_sub.p;
+  sa.piv_type = F.piv_type.p;
+  sa.piv_dof = F.piv_dof.p;
+  sa.piv_gmap = F.piv_gmap.p;
+  sa.dd = F.d_diag.p;
+  sa.dsub = F.d_sub.p;
   sa.cbvec = pr->cbvec.p;
   sa.fwd = pr->fwd.p;
   return sa;
@@ -247,8 +247,9 @@ void apply_solve_attrs() {
 
 // One launch per tree level and direction.
 template <class T>
-void solve_levels(riga_problem* pr, const T* H, const double* b, double* x, hipStream_t s) {
-  SolveArgs sa = solve_args(pr);
+void solve_levels(riga_problem* pr, const Factor& F, const T* H, const double* b, double* x,
+                  hipStream_t s) {
+  SolveArgs sa = solve_args(pr, F);
   const int nl = (int)pr->levels.size();
   for (int h = 0; h < nl; ++h) {
     const LevelDev& L = pr->levels[h];
@@ -274,20 +275,20 @@ void set_solve_attributes() {
   apply_solve_attrs<float>();
 }
 
-void launch_pivot_maps(riga_problem* pr, hipStream_t s) {
+void launch_pivot_maps(riga_problem* pr, Factor& F, hipStream_t s) {
   const int64_t N = pr->an.N;
   if (N == 0) return;
   pivot_maps_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(
-      pr->d_desc.p, pr->d_front_of.p, pr->piv_perm.p, pr->d_rows.p, pr->d_gmap.p, pr->gstride, N,
-      pr->piv_dof.p, pr->piv_gmap.p);
+      pr->d_desc.p, pr->d_front_of.p, F.piv_perm.p, pr->d_rows.p, pr->d_gmap.p, pr->gstride, N,
+      F.piv_dof.p, F.piv_gmap.p);
   HIPCHECK(hipGetLastError());
 }
 
-void solve_fb(riga_problem* pr, const double* b, double* x, hipStream_t s) {
-  if (!pr->factored) throw Error(RIGA_EINVAL, "solve before factorisation");
+void solve_fb(riga_problem* pr, const Factor& F, const double* b, double* x, hipStream_t s) {
+  if (!F.factored) throw Error(RIGA_EINVAL, "solve before factorisation");
   set_kernel_attributes();
-  if (pr->fact_precision == RIGA_MIXED) solve_levels<float>(pr, pr->h32.p, b, x, s);
-  else solve_levels<double>(pr, pr->h64.p, b, x, s);
+  if (F.precision == RIGA_MIXED) solve_levels<float>(pr, F, F.h32.p, b, x, s);
+  else solve_levels<double>(pr, F, F.h64.p, b, x, s);
 }
 
 }  // namespace riga

@@ -112,6 +112,25 @@ struct LevelDev {
   }
 };
 
+// One numeric factorisation of K - sigma M and everything the sweeps read
+// from it.  A problem holds two, so that the factorisation at the next shift
+// can proceed on another stream while the sweeps use the current one.
+struct Factor {
+  DBuf<double> pool64, h64;            // fronts (f x f) and partitioned inverses
+  DBuf<float> pool32, h32;             // the same in FP32 (mixed precision)
+  DBuf<int32_t> piv_perm, piv_type;    // by new index
+  DBuf<int32_t> front_stat;            // [n_fronts * 4]: neg, perturbed, 2x2, spare
+  DBuf<int32_t> piv_dof, piv_gmap;     // pivot-order gather maps of the sweeps
+  DBuf<double> d_diag, d_sub;          // D by pivot index: diagonal, (t+1, t) of 2x2 blocks
+  DBuf<double> av;                     // K - sigma M values (refinement residuals)
+  DBuf<int32_t> big_perm, big_lperm, big_state;  // blocked-factorisation scratch
+  bool factored = false;
+  int precision = 0;
+  double sigma = 0.0;
+  int64_t inertia = 0;
+  int perturbed = 0, two = 0;
+};
+
 }  // namespace riga
 
 struct riga_problem {
@@ -129,7 +148,6 @@ struct riga_problem {
   riga::DBuf<int64_t> row_ptr;
   riga::DBuf<int32_t> col_idx;
   riga::DBuf<double> kv, mv;        // K and M values (CSR order)
-  riga::DBuf<double> av;            // K - sigma M values of the last shift
   riga::DBuf<double> tab_val, tab_der;  // basis tables per direction
   riga::DBuf<double> ke1, me1;          // 1D element matrices per direction
   riga::DBuf<int32_t> fe, le, first_fn; // 1D maps per direction (concatenated)
@@ -144,29 +162,16 @@ struct riga_problem {
   riga::DBuf<int32_t> d_amap_row, d_amap_val;
   std::vector<riga::LevelDev> levels;
 
-  // numeric factorisation
-  riga::DBuf<double> pool64;
-  riga::DBuf<float> pool32;
-  riga::DBuf<double> h64;                   // partitioned inverses, sum f * k
-  riga::DBuf<float> h32;
-  riga::DBuf<int32_t> big_perm, big_lperm, big_state;  // blocked-factorisation scratch
+  // numeric factorisations: fac[cur] is the one riga_factor / riga_solve use
+  riga::Factor fac[2];
+  int cur = 0;
   riga::DBuf<riga::WorkUnit> inv_units;     // row blocks of every front
   int n_inv_units = 0;
-  riga::DBuf<int32_t> piv_perm, piv_type;   // by new index
-  riga::DBuf<int32_t> front_stat;           // [n_fronts * 4]: neg, perturbed, 2x2, spare
-  bool factored = false;
-  int fact_precision = RIGA_FP64;
-  double sigma = 0.0;
-  int64_t last_inertia = 0;
-  int last_perturbed = 0, last_2x2 = 0;
 
   // solve workspace
   riga::DBuf<double> cbvec, fwd;
   riga::DBuf<riga::FrontDesc> d_desc;
   riga::DBuf<int32_t> d_front_of;           // front of each new (pivot-order) index
-  riga::DBuf<int32_t> piv_dof;              // DOF of each pivot (set per factorisation)
-  riga::DBuf<int32_t> piv_gmap;             // [N * gstride] children's update indices per pivot
-  riga::DBuf<double> d_diag, d_sub;         // D by pivot index: diagonal, (t+1, t) of 2x2 blocks
   riga::DBuf<int32_t> d_gmap;               // [sum f * gstride] children's update indices
   int gstride = 1;
   riga::DBuf<double> ir_r, ir_x, ir_d;      // iterative refinement vectors
@@ -193,21 +198,32 @@ int spmv_dot_blocks(const riga_problem* pr);
 void launch_spmm_km(const riga_problem* pr, const double* U, int nw, double* KU, double* MU,
                     hipStream_t s);
 
-void factor_numeric(riga_problem* pr, double sigma, int precision);
+// Factorises K - sigma M into F on stream s (host-synchronous: returns with
+// F complete, its inertia read back).  Reads only the problem's symbolic
+// data and matrices, so it may run on another thread and stream while the
+// sweeps use the other Factor.
+void factor_numeric(riga_problem* pr, Factor& F, double sigma, int precision, hipStream_t s);
+// Allocates every buffer factor_numeric(F, precision) writes (a no-op once
+// done): call it on the thread and stream that own the problem before a
+// factorisation runs on another stream.
+void factor_reserve(riga_problem* pr, Factor& F, int precision, hipStream_t s);
 // H = [I; L21] L11^{-1} for every front (D kept on the diagonal), from the
 // factor pool into the H pool.
 template <class T>
-void launch_front_inverse(riga_problem* pr, const T* pool, T* h, hipStream_t s);
+void launch_front_inverse(riga_problem* pr, Factor& F, const T* pool, T* h, hipStream_t s);
 size_t front_inverse_lds(int max_k);
 // Fronts above the LDS limit of one tree level (`fronts`, orders big_f,
 // fully-summed orders big_k): blocked LDL^T spread over many workgroups.
 template <class T>
-void factor_big_fronts(riga_problem* pr, T* pool, const int32_t* fronts,
+void factor_big_fronts(riga_problem* pr, Factor& F, T* pool, const int32_t* fronts,
                        const std::vector<int>& big_f, const std::vector<int>& big_k,
                        double pivtol, hipStream_t s);
 int bigfront_max_k();
+// Allocates the blocked-factorisation scratch of F for every level (fronts
+// above lds_max_f), so that no level reallocates it mid-factorisation.
+void bigfront_reserve(riga_problem* pr, Factor& F, int lds_max_f, hipStream_t s);
 // Pivot-order gather maps of the sweeps (after each factorisation).
-void launch_pivot_maps(riga_problem* pr, hipStream_t s);
+void launch_pivot_maps(riga_problem* pr, Factor& F, hipStream_t s);
 // Binds a call's stream to the problem for the duration of the call only, so
 // no stream handle outlives the call that passed it.
 struct StreamBind {
@@ -222,7 +238,7 @@ struct StreamBind {
 // Raises the dynamic-LDS limit of the kernels that need more than 64 KB;
 // runs once per process (later calls return at once).
 void set_kernel_attributes();
-void solve_fb(riga_problem* pr, const double* b, double* x, hipStream_t s);
+void solve_fb(riga_problem* pr, const Factor& F, const double* b, double* x, hipStream_t s);
 
 // BLAS-like helpers on column-major N x m blocks (ld = N).
 int gemv_row_blocks(int64_t n);

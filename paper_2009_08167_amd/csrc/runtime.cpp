@@ -93,7 +93,7 @@ void load_and_assemble(riga_problem* pr, const double* kappa, const double* rho,
   load_coef(rho, pr->rho, "rho");
   launch_assemble(pr);
   compute_norms(pr);
-  pr->factored = false;
+  pr->fac[0].factored = pr->fac[1].factored = false;
 }
 
 void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
@@ -163,10 +163,12 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
     for (int F = 0; F < an.n_fronts; ++F)
       for (int t = 0; t < an.f_k[F]; ++t) front_of[an.f_start[F] + t] = F;
     pr->d_front_of.upload(front_of, s);
-    pr->piv_dof.alloc(N, s);
-    pr->piv_gmap.alloc((size_t)N * gs, s);
-    pr->d_diag.alloc(N, s);
-    pr->d_sub.alloc(N, s);
+    for (Factor& F : pr->fac) {
+      F.piv_dof.alloc(N, s);
+      F.piv_gmap.alloc((size_t)N * gs, s);
+      F.d_diag.alloc(N, s);
+      F.d_sub.alloc(N, s);
+    }
   }
   pr->levels.clear();
   pr->levels.resize(an.height);
@@ -266,9 +268,11 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
     throw Error(RIGA_EUNSUPPORTED, "fully-summed block too large for the panel kernel");
   if (front_inverse_lds(an.max_fs) > 159 * 1024)
     throw Error(RIGA_EUNSUPPORTED, "fully-summed block too large for the inverse kernel's LDS");
-  pr->piv_perm.alloc(N, s);
-  pr->piv_type.alloc(N, s);
-  pr->front_stat.alloc((size_t)an.n_fronts * 4, s);
+  for (Factor& F : pr->fac) {
+    F.piv_perm.alloc(N, s);
+    F.piv_type.alloc(N, s);
+    F.front_stat.alloc((size_t)an.n_fronts * 4, s);
+  }
   pr->cbvec.alloc(std::max<int64_t>(an.cb_size, 1), s);
   pr->fwd.alloc(N, s);
   HIPCHECK(hipStreamSynchronize(s));
