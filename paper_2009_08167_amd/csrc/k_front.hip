@@ -329,7 +329,6 @@ void factor_levels(riga_problem* pr, Factor& F, T* pool, T* hpool, double sigma,
   }
   launch_front_inverse<T>(pr, F, pool, hpool, s);
   launch_pivot_maps(pr, F, s);
-  HIPCHECK(hipStreamSynchronize(s));
 }
 
 }  // namespace
@@ -348,6 +347,7 @@ void factor_reserve(riga_problem* pr, Factor& F, int precision, hipStream_t s) {
     if (F.h64.n < (size_t)an.h_size) F.h64.alloc(an.h_size, s);
     bigfront_reserve(pr, F, LDS_FRONT_MAX_F64, s);
   }
+  top_reserve(pr, F, precision, s);
 }
 
 void factor_numeric(riga_problem* pr, Factor& F, double sigma, int precision, hipStream_t s) {
@@ -357,12 +357,14 @@ void factor_numeric(riga_problem* pr, Factor& F, double sigma, int precision, hi
     if (F.pool32.n < (size_t)an.pool_size || F.h32.n < (size_t)an.h_size || F.av.n < pr->kv.n)
       throw Error(RIGA_EINVAL, "factorisation buffers not reserved");
     factor_levels<float, LDS_FRONT_MAX_F32>(pr, F, F.pool32.p, F.h32.p, sigma, s);
+    build_top<float>(pr, F, F.h32.p, F.trow32.p, F.tcol32.p, s);
     // K - sigma M for the refinement residuals
     launch_axpby_vals(pr->kv.p, pr->mv.p, sigma, F.av.p, (int64_t)pr->kv.n, s);
   } else {
     if (F.pool64.n < (size_t)an.pool_size || F.h64.n < (size_t)an.h_size)
       throw Error(RIGA_EINVAL, "factorisation buffers not reserved");
     factor_levels<double, LDS_FRONT_MAX_F64>(pr, F, F.pool64.p, F.h64.p, sigma, s);
+    build_top<double>(pr, F, F.h64.p, F.trow64.p, F.tcol64.p, s);
   }
   std::vector<int32_t> st((size_t)an.n_fronts * 4);
   HIPCHECK(hipMemcpyAsync(st.data(), F.front_stat.p, st.size() * sizeof(int32_t),

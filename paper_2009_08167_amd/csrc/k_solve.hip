@@ -246,11 +246,13 @@ void apply_solve_attrs() {
 }
 
 // One launch per tree level and direction.
+// One launch per tree level and direction below the top block (all levels
+// when there is none), three for the top block.
 template <class T>
-void solve_levels(riga_problem* pr, const Factor& F, const T* H, const double* b, double* x,
-                  hipStream_t s) {
+void solve_levels(riga_problem* pr, const Factor& F, const T* H, const T* trow, const T* tcol,
+                  const double* b, double* x, hipStream_t s) {
   SolveArgs sa = solve_args(pr, F);
-  const int nl = (int)pr->levels.size();
+  const int nl = pr->top.cut >= 0 ? pr->top.cut : (int)pr->levels.size();
   for (int h = 0; h < nl; ++h) {
     const LevelDev& L = pr->levels[h];
     if (L.n_fwd == 0) continue;
@@ -258,6 +260,7 @@ void solve_levels(riga_problem* pr, const Factor& F, const T* H, const double* b
     if (L.fwd_thin) fwd_kernel<T, SWEEP_ROWS_THIN><<<L.n_fwd, 256, lds, s>>>(sa, H, L.fwd_units.p, b);
     else fwd_kernel<T, SWEEP_ROWS><<<L.n_fwd, 256, lds, s>>>(sa, H, L.fwd_units.p, b);
   }
+  if (pr->top.cut >= 0) sweep_top<T>(pr, F, trow, tcol, b, x, s);
   for (int h = nl - 1; h >= 0; --h) {
     const LevelDev& L = pr->levels[h];
     if (L.n_bwd == 0) continue;
@@ -287,8 +290,8 @@ void launch_pivot_maps(riga_problem* pr, Factor& F, hipStream_t s) {
 void solve_fb(riga_problem* pr, const Factor& F, const double* b, double* x, hipStream_t s) {
   if (!F.factored) throw Error(RIGA_EINVAL, "solve before factorisation");
   set_kernel_attributes();
-  if (F.precision == RIGA_MIXED) solve_levels<float>(pr, F, F.h32.p, b, x, s);
-  else solve_levels<double>(pr, F, F.h64.p, b, x, s);
+  if (F.precision == RIGA_MIXED) solve_levels<float>(pr, F, F.h32.p, F.trow32.p, F.tcol32.p, b, x, s);
+  else solve_levels<double>(pr, F, F.h64.p, F.trow64.p, F.tcol64.p, b, x, s);
 }
 
 }  // namespace riga

@@ -112,6 +112,65 @@ struct LevelDev {
   }
 };
 
+// ---- explicit inverse of the top of the separator tree ----
+// The fronts at heights >= cut (closed under taking parents) form the top
+// block T; its variables are numbered 0..nT-1 in pivot order (a postorder,
+// so the top fronts of any subtree hold a contiguous range ending with the
+// subtree's root).  Each factorisation also stores L_TT^{-1} (unit lower)
+// twice: by rows (row j holds columns [rlo_j, j], the top variables of the
+// subtree of j's front) for the forward sweep, and by columns (one block per
+// top front F: rows = the variables of F and of its ancestors, stacked) for
+// the backward sweep.
+struct TopRowUnit {  // forward: rows [r0, r1), tpr threads per row
+  int32_t r0, r1, tpr, pad;
+};
+struct TopColUnit {  // backward: columns [c0, c1) of top front tf
+  int32_t tf, c0, c1, pad;
+};
+struct TopFront {
+  int64_t coff;                // column block (ld x k, column-major)
+  int32_t ld, h, k, start;     // h: stacked rows (own and ancestors'), ld >= h
+  int32_t tstart, anc_off, n_anc, pad;
+};
+struct TopAnc {  // one front of a top front's stacked rows
+  int32_t tstart, start, k, rowpos;
+};
+// Construction: the block of L_TT^{-1} with the rows of top front P and the
+// columns of top front F (F in the subtree of P), from P's partitioned
+// inverse and the block that the child of P on the way to F passed up.
+struct TopPair {
+  int32_t kP, fP, startP, tstartP;
+  int32_t kF, ldF, colbase, ldh;  // colbase: F's first column in P's row segments
+  int64_t h_off;                  // P's partitioned inverse
+  int64_t inv_off;                // position map of that child (-1 if F == P)
+  int64_t cb_in;                  // its (f_C - k_C) x kF block, row-major (-1 if F == P)
+  int64_t cb_out;                 // (fP - kP) x kF block for P's parent (-1 at a root)
+  int64_t xcol;                   // column block of F at P's stacked rows
+};
+struct TopTile {  // 64 x 64 output tile of a pair
+  int32_t pair, r0, c0, pad;
+};
+struct TopDev {
+  int cut = -1;  // -1: no top block, every level is swept by level
+  int nT = 0, tgs = 0;
+  int64_t e_row = 0, e_col = 0, e_cb = 0;
+  int max_h = 0;
+  DBuf<int32_t> n_of_j;   // [nT] pivot index of each top variable
+  DBuf<int32_t> slist;    // [nT * tgs] update-vector entries of each (front, position)
+  DBuf<int64_t> roff;     // [nT] row offsets
+  DBuf<int32_t> rlo, rlen;
+  DBuf<TopRowUnit> fwd_units;
+  DBuf<TopColUnit> bwd_units;
+  int n_fwd = 0, n_bwd = 0;
+  DBuf<TopFront> fronts;
+  DBuf<TopAnc> anc;
+  DBuf<TopPair> pairs;
+  std::vector<DBuf<TopTile>> tiles;  // per height, cut upwards
+  std::vector<int> n_tiles;
+  DBuf<double> r, y;                 // sweep vectors [nT]
+  DBuf<double> cb;                   // construction blocks [e_cb]
+};
+
 // One numeric factorisation of K - sigma M and everything the sweeps read
 // from it.  A problem holds two, so that the factorisation at the next shift
 // can proceed on another stream while the sweeps use the current one.
@@ -124,6 +183,9 @@ struct Factor {
   DBuf<double> d_diag, d_sub;          // D by pivot index: diagonal, (t+1, t) of 2x2 blocks
   DBuf<double> av;                     // K - sigma M values (refinement residuals)
   DBuf<int32_t> big_perm, big_lperm, big_state;  // blocked-factorisation scratch
+  DBuf<double> trow64, tcol64;         // L_TT^{-1} by rows and by columns
+  DBuf<float> trow32, tcol32;
+  DBuf<int32_t> tmap, tdof;            // top gather maps in pivot order
   bool factored = false;
   int precision = 0;
   double sigma = 0.0;
@@ -174,6 +236,7 @@ struct riga_problem {
   riga::DBuf<int32_t> d_front_of;           // front of each new (pivot-order) index
   riga::DBuf<int32_t> d_gmap;               // [sum f * gstride] children's update indices
   int gstride = 1;
+  riga::TopDev top;                         // explicit inverse of the top levels
   riga::DBuf<double> ir_r, ir_x, ir_d;      // iterative refinement vectors
 
   riga_stats stats{};
@@ -224,6 +287,16 @@ int bigfront_max_k();
 void bigfront_reserve(riga_problem* pr, Factor& F, int lds_max_f, hipStream_t s);
 // Pivot-order gather maps of the sweeps (after each factorisation).
 void launch_pivot_maps(riga_problem* pr, Factor& F, hipStream_t s);
+// Top block: chooses the cut and builds its static maps (at set-up); builds
+// L_TT^{-1} of factorisation F from its partitioned inverses h; runs the
+// top part of a forward/backward sweep.
+void setup_top(riga_problem* pr);
+void top_reserve(riga_problem* pr, Factor& F, int precision, hipStream_t s);
+template <class T>
+void build_top(riga_problem* pr, Factor& F, const T* h, T* trow, T* tcol, hipStream_t s);
+template <class T>
+void sweep_top(riga_problem* pr, const Factor& F, const T* trow, const T* tcol, const double* b,
+               double* x, hipStream_t s);
 // Binds a call's stream to the problem for the duration of the call only, so
 // no stream handle outlives the call that passed it.
 struct StreamBind {

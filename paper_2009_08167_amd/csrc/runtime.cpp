@@ -57,6 +57,7 @@ void set_solve_attributes();
 void set_inverse_attributes();
 void set_bigfront_attributes();
 void set_tridiag_attributes();
+void set_top_attributes();
 
 void set_kernel_attributes() {
   static std::once_flag once;
@@ -66,6 +67,7 @@ void set_kernel_attributes() {
     set_inverse_attributes();
     set_bigfront_attributes();
     set_tridiag_attributes();
+    set_top_attributes();
   });
 }
 
@@ -275,6 +277,7 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
   }
   pr->cbvec.alloc(std::max<int64_t>(an.cb_size, 1), s);
   pr->fwd.alloc(N, s);
+  setup_top(pr);
   HIPCHECK(hipStreamSynchronize(s));
   pr->has_device = true;
 }
