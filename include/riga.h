@@ -192,6 +192,16 @@ riga_status riga_factor(riga_problem* pr, double sigma, int32_t precision,
 riga_status riga_solve(riga_problem* pr, const double* b_dev, double* x_dev, int32_t max_ir,
                        void* stream);
 
+/* riga_solve_multi: X(:, i) = (K - sigma M)^{-1} B(:, i), i < nrhs, with the
+ * last factorisation: one forward/backward elimination per column, queued on
+ * `stream` one after another with no host synchronisation between them (the
+ * call returns when the last is done).  In RIGA_MIXED with max_ir > 0 each
+ * column is refined as in riga_solve.  B_dev, X_dev: device FP64,
+ * column-major with leading dimension ld >= n_dof, not overlapping.
+ * nrhs = 0 is a no-op; nrhs < 0 or ld < n_dof is RIGA_EINVAL. */
+riga_status riga_solve_multi(riga_problem* pr, const double* B_dev, double* X_dev, int32_t nrhs,
+                             int64_t ld, int32_t max_ir, void* stream);
+
 /* riga_eigs: the nev lowest eigenpairs with lambda in [lo, hi) (Sec. 4).
  * evals_host[nev]: ascending eigenvalues (Rayleigh quotients).
  * evecs_dev: [n_dof * nev] column-major device buffer for M-normalised

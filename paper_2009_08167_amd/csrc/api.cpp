@@ -190,40 +190,66 @@ riga_status riga_factor(riga_problem* pr, double sigma, int32_t precision, int64
   });
 }
 
+namespace {
+
+// x = A^{-1} b with the current factorisation; in mixed precision refined in
+// FP64 (r = b - A x, x += A32^{-1} r) until ||r|| <= 1e-13 ||b|| or max_ir
+// corrections.  Returns without synchronising when no refinement runs.
+void solve_one(riga_problem* pr, const riga::Factor& F, const double* b, double* x, int32_t max_ir,
+               hipStream_t s) {
+  riga::solve_fb(pr, F, b, x, s);
+  if (F.precision != RIGA_MIXED || max_ir <= 0) return;
+  const int64_t N = pr->an.N;
+  if (pr->ir_r.n < (size_t)N) {
+    pr->ir_r.alloc(N, pr->home);
+    pr->ir_d.alloc(N, pr->home);
+  }
+  riga::DBuf<double> part, nr;
+  part.alloc(256, s);
+  nr.alloc(2, s);
+  double h[2] = {0.0, 0.0};
+  riga::launch_dot(b, b, N, part.p, nr.p, s);
+  HIPCHECK(hipMemcpyAsync(&h[0], nr.p, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  const double bn2 = h[0];
+  for (int it = 0; it < max_ir; ++it) {
+    riga::launch_spmv(pr, F.av.p, x, pr->ir_r.p, nullptr, s);
+    riga::launch_axpby(-1.0, pr->ir_r.p, b, pr->ir_r.p, N, s);
+    riga::launch_dot(pr->ir_r.p, pr->ir_r.p, N, part.p, nr.p + 1, s);
+    HIPCHECK(hipMemcpyAsync(&h[1], nr.p + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (h[1] <= 1e-26 * bn2) break;
+    riga::solve_fb(pr, F, pr->ir_r.p, pr->ir_d.p, s);
+    riga::launch_axpby(1.0, pr->ir_d.p, x, x, N, s);
+  }
+}
+
+}  // namespace
+
 riga_status riga_solve(riga_problem* pr, const double* b, double* x, int32_t max_ir, void* stream) {
   return guarded([&]() -> riga_status {
     if (!need_device(pr) || !b || !x || b == x) return fail(RIGA_EINVAL, "bad problem or vectors");
     const riga::Factor& F = pr->fac[pr->cur];
     if (!F.factored) return fail(RIGA_EINVAL, "no factorisation");
     hipStream_t s = (hipStream_t)stream;
-    riga::solve_fb(pr, F, b, x, s);
-    if (F.precision == RIGA_MIXED && max_ir > 0) {
-      // FP64 iterative refinement: r = b - A x, x += A32^{-1} r, until
-      // ||r|| <= 1e-13 ||b|| or max_ir corrections
-      const int64_t N = pr->an.N;
-      if (pr->ir_r.n < (size_t)N) {
-        pr->ir_r.alloc(N, pr->home);
-        pr->ir_d.alloc(N, pr->home);
-      }
-      riga::DBuf<double> part, nr;
-      part.alloc(256, s);
-      nr.alloc(2, s);
-      double h[2] = {0.0, 0.0};
-      riga::launch_dot(b, b, N, part.p, nr.p, s);
-      HIPCHECK(hipMemcpyAsync(&h[0], nr.p, sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHECK(hipStreamSynchronize(s));
-      const double bn2 = h[0];
-      for (int it = 0; it < max_ir; ++it) {
-        riga::launch_spmv(pr, F.av.p, x, pr->ir_r.p, nullptr, s);
-        riga::launch_axpby(-1.0, pr->ir_r.p, b, pr->ir_r.p, N, s);
-        riga::launch_dot(pr->ir_r.p, pr->ir_r.p, N, part.p, nr.p + 1, s);
-        HIPCHECK(hipMemcpyAsync(&h[1], nr.p + 1, sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHECK(hipStreamSynchronize(s));
-        if (h[1] <= 1e-26 * bn2) break;
-        riga::solve_fb(pr, F, pr->ir_r.p, pr->ir_d.p, s);
-        riga::launch_axpby(1.0, pr->ir_d.p, x, x, N, s);
-      }
-    }
+    solve_one(pr, F, b, x, max_ir, s);
+    HIPCHECK(hipStreamSynchronize(s));
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_solve_multi(riga_problem* pr, const double* B, double* X, int32_t nrhs, int64_t ld,
+                             int32_t max_ir, void* stream) {
+  return guarded([&]() -> riga_status {
+    if (!need_device(pr) || nrhs < 0) return fail(RIGA_EINVAL, "bad problem or nrhs");
+    if (nrhs == 0) return RIGA_OK;
+    if (!B || !X || ld < pr->an.N) return fail(RIGA_EINVAL, "bad blocks or leading dimension");
+    const int64_t span = ld * (int64_t)(nrhs - 1) + pr->an.N;
+    if (B < X + span && X < B + span) return fail(RIGA_EINVAL, "B and X overlap");
+    const riga::Factor& F = pr->fac[pr->cur];
+    if (!F.factored) return fail(RIGA_EINVAL, "no factorisation");
+    hipStream_t s = (hipStream_t)stream;
+    for (int32_t i = 0; i < nrhs; ++i) solve_one(pr, F, B + ld * i, X + ld * i, max_ir, s);
     HIPCHECK(hipStreamSynchronize(s));
     return RIGA_OK;
   });

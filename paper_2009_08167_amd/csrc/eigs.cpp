@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <limits>
 #include <numeric>
 #include <string>
@@ -65,7 +66,10 @@ struct Solver {
   int max_ir;
   DBuf<double> B, W, x, y, c1, c2, partial, dotp, alpha, beta, scal;
   DBuf<int32_t> flag;
-  DBuf<double> theta, tdest, S, Sh, Ub, KU, MU, rqn, rqd, rn2, un2, lam, nrm;
+  DBuf<double> chk, S, Sh, Ub, KU, MU, res3, rqn, lam, rpart;
+  double* theta = nullptr;  // in chk: theta[mb + 1], est[mb + 1], beta_m, flag
+  double* tdest = nullptr;
+  double* chk_extra = nullptr;
   DBuf<int32_t> sel;
   DBuf<double> ir_r, ir_d;
   std::vector<Locked> locked;
@@ -86,14 +90,16 @@ struct Solver {
     y.alloc(N, s);
     c1.alloc(ncols, s);
     c2.alloc(ncols, s);
-    partial.alloc((size_t)gemv_row_blocks(N) * ncols, s);
+    partial.alloc((size_t)proj_row_blocks(N) * ncols, s);
     dotp.alloc(spmv_dot_blocks(pr), s);
     alpha.alloc(mb + 1, s);
     beta.alloc(mb + 2, s);
     scal.alloc(8, s);
     flag.alloc(4, s);
-    theta.alloc(mb + 1, s);
-    tdest.alloc(mb + 1, s);
+    chk.alloc(2 * (mb + 1) + 2, s);
+    theta = chk.p;
+    tdest = chk.p + (mb + 1);
+    chk_extra = chk.p + 2 * (mb + 1);
     S.alloc((size_t)(mb + 1) * (mb + 1), s);
     sel.alloc(2 * (mb + 2), s);
     const int umax = mb + 1;
@@ -102,11 +108,9 @@ struct Solver {
     KU.alloc((size_t)N * umax, s);
     MU.alloc((size_t)N * umax, s);
     rqn.alloc(umax, s);
-    rqd.alloc(umax, s);
-    rn2.alloc(umax, s);
-    un2.alloc(umax, s);
+    res3.alloc(3 * (size_t)umax, s);  // u^T M u, ||K u - lam M u||^2, ||u||^2
     lam.alloc(umax, s);
-    nrm.alloc(umax, s);
+    rpart.alloc(residual_partials(N, umax), s);
     if (precision == RIGA_MIXED) {
       ir_r.alloc(N, s);
       ir_d.alloc(N, s);
@@ -160,8 +164,7 @@ struct Solver {
   void project_out(int m, double* c, int c0 = 0, double* alpha_out = nullptr,
                    const double* addend = nullptr) {
     if (m <= c0) return;
-    launch_gemv_t(Wc(c0), N, m - c0, x.p, partial.p, c + c0, alpha_out, addend, s);
-    launch_gemv_n_sub(Bc(c0), N, m - c0, c + c0, x.p, s);
+    launch_project(Wc(c0), Bc(c0), N, m - c0, x.p, partial.p, c + c0, alpha_out, addend, s);
   }
 
   // M-normalise x into column j of B (and M x into W); returns false on breakdown
@@ -211,15 +214,15 @@ struct Solver {
     auto a = clk::now();
     Ritz r;
     r.m = m;
-    launch_ritz_check(alpha.p, beta.p, m, theta.p, tdest.p, s);
-    r.theta.resize(m);
-    r.est.resize(m);
-    HIPCHECK(hipMemcpyAsync(r.theta.data(), theta.p, m * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipMemcpyAsync(r.est.data(), tdest.p, m * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipMemcpyAsync(&r.beta_m, beta.p + m, sizeof(double), hipMemcpyDeviceToHost, s));
-    int32_t fl = 0;
-    HIPCHECK(hipMemcpyAsync(&fl, flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    launch_ritz_check(alpha.p, beta.p, m, theta, tdest, flag.p, chk_extra, s);
+    // one read-back: theta, estimates, beta_m and the breakdown flag
+    std::vector<double> h(chk.n);
+    HIPCHECK(hipMemcpyAsync(h.data(), chk.p, chk.n * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
+    r.theta.assign(h.begin(), h.begin() + m);
+    r.est.assign(h.begin() + (mb + 1), h.begin() + (mb + 1) + m);
+    r.beta_m = h[2 * (mb + 1)];
+    const bool fl = h[2 * (mb + 1) + 1] != 0.0;
     if (fl) {
       r.beta_m = 0.0;
       std::fill(r.est.begin(), r.est.end(), 0.0);
@@ -249,7 +252,7 @@ struct Solver {
     const int ncl = (int)cl.size() - 1;
     ix.insert(ix.end(), cl.begin(), cl.end());
     HIPCHECK(hipMemcpyAsync(sel.p, ix.data(), ix.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    launch_ritz_vectors(alpha.p, beta.p, m, theta.p, sel.p, sel.p + n, ncl, S.p, s);
+    launch_ritz_vectors(alpha.p, beta.p, m, theta, sel.p, sel.p + n, ncl, S.p, s);
     HIPCHECK(hipMemcpyAsync(Sv.data(), S.p, Sv.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     return Sv;
@@ -282,22 +285,21 @@ struct Solver {
     if (nw > 0) {
       launch_spmm_km(pr, Ub.p, nw, KU.p, MU.p, s);
       st.n_mv += 2 * nw;
-      launch_residuals(KU.p, MU.p, Ub.p, N, nw, rqn.p, rqd.p, rn2.p, un2.p, lam.p, s);
-      std::vector<double> h_rqd(nw), h_rn2(nw), h_un2(nw), h_lam(nw);
-      // copies on the solve's own stream: the null stream would not order
-      // them after its kernels, and could wait on unrelated streams
-      HIPCHECK(hipMemcpyAsync(h_rqd.data(), rqd.p, nw * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHECK(hipMemcpyAsync(h_rn2.data(), rn2.p, nw * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHECK(hipMemcpyAsync(h_un2.data(), un2.p, nw * sizeof(double), hipMemcpyDeviceToHost, s));
+      const int umax = (int)lam.n;
+      double* rqd = res3.p;
+      double* rn2 = res3.p + umax;
+      double* un2 = res3.p + 2 * (size_t)umax;
+      launch_residuals(KU.p, MU.p, Ub.p, N, nw, rqn.p, rqd, rn2, un2, lam.p, rpart.p, s);
+      // M-normalise on the device: u /= sqrt(u^T M u), and M u with it
+      launch_scale_cols_rsqrt(Ub.p, MU.p, N, nw, rqd, s);
+      // one read-back (on the solve's own stream: the null stream would not
+      // order it after the kernels, and could wait on unrelated streams)
+      std::vector<double> h3(3 * (size_t)umax), h_lam(nw);
+      HIPCHECK(hipMemcpyAsync(h3.data(), res3.p, h3.size() * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHECK(hipMemcpyAsync(h_lam.data(), lam.p, nw * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHECK(hipStreamSynchronize(s));
-      // M-normalise: u /= sqrt(u^T M u)
-      std::vector<double> scl(nw);
-      for (int i = 0; i < nw; ++i) scl[i] = 1.0 / std::sqrt(h_rqd[i]);
-      HIPCHECK(hipMemcpyAsync(nrm.p, scl.data(), nw * sizeof(double), hipMemcpyHostToDevice, s));
-      HIPCHECK(hipStreamSynchronize(s));  // scl is pageable host memory
-      launch_scale_cols(Ub.p, N, nw, nrm.p, s);
-      launch_scale_cols(MU.p, N, nw, nrm.p, s);
+      const double* h_rn2 = h3.data() + umax;
+      const double* h_un2 = h3.data() + 2 * (size_t)umax;
       // candidates: residual below tol, eigenvalue in [lo, hi); locked in
       // ascending order.  When the locked set is full, a candidate replaces
       // the largest locked eigenvalue above the shift if it is smaller.
@@ -309,6 +311,7 @@ struct Solver {
       std::sort(cand.begin(), cand.end(), [&](int a, int b) { return h_lam[a] < h_lam[b]; });
       if (*have_restart) launch_copy(y.p, Ub.p + (int64_t)nw * N, N, s);
       int appended = 0;
+      std::vector<int> dst_col, src_col;  // a column evicted twice keeps the last copy
       for (int i : cand) {
         const double res = std::sqrt(h_rn2[i]) / (pr->normK1 * std::sqrt(h_un2[i]));
         int col = -1;
@@ -325,10 +328,15 @@ struct Solver {
           locked[worst] = Locked{h_lam[i], res, col};
           ++n_evicted;
         }
-        launch_copy(Bc(col), Ub.p + (int64_t)i * N, N, s);
-        launch_copy(Wc(col), MU.p + (int64_t)i * N, N, s);
+        const auto it = std::find(dst_col.begin(), dst_col.end(), col);
+        if (it != dst_col.end()) src_col[it - dst_col.begin()] = i;
+        else {
+          dst_col.push_back(col);
+          src_col.push_back(i);
+        }
         ++nlocked;
       }
+      launch_copy_cols(dst_col, src_col, N, B.p, Ub.p, W.p, MU.p, s);
       nl += appended;
 
     } else if (*have_restart) {
@@ -350,7 +358,9 @@ struct Solver {
   // One Lanczos run at the current factorisation.  Stops when the
   // converged pairs cover the needs or the basis is full.  Returns the
   // final Ritz data (for shift placement).
-  Ritz run(double sigma, int need_below, int need_above, const double* init, int* n_new) {
+  // on_check (optional) sees the Ritz data of every convergence check.
+  Ritz run(double sigma, int need_below, int need_above, const double* init, int* n_new,
+           const std::function<void(const Ritz&)>& on_check = nullptr) {
     start_vector(init);
     const int maxm = (int)std::min<int64_t>(mb, N - nl - 1);
     int j = 0;
@@ -361,6 +371,7 @@ struct Solver {
       ++j;
       if (j < next_check && j < maxm) continue;
       r = check(j);
+      if (on_check) on_check(r);
       int cb = 0, ca = 0;
       for (int i = 0; i < j; ++i) {
         if (!converged(r, i)) continue;
@@ -467,9 +478,36 @@ double predict_shift(const Solver& sv, const Solver::Ritz& r, double r_sigma, do
   const double width = top - lo;
   if (cnt == 0 || !(width > 0)) return std::numeric_limits<double>::quiet_NaN();
   const double dens = cnt / width;
-  top = std::max(top, sigma + per_above / dens);
+  // pairs locked above sigma already count towards the runs' target
+  if (sv.count_locked(sigma, hi) < per_above) top = std::max(top, sigma + per_above / dens);
   const double step = target / dens;
   return place_in_gap(sv, r, r_sigma, top, top + step, step, hi);
+}
+
+// The same guess made during the first run at the lowest shift, before
+// anything is locked: the converged Ritz values of a convergence check
+// stand in for the locked eigenvalues.  Over this wider range the count
+// of eigenvalues below lambda is extrapolated with its asymptotic growth,
+// proportional to (lambda - lo)^{dim/2} (Weyl), not linearly.  NaN while
+// fewer than 8 have converged.
+double predict_from_ritz(const Solver& sv, const Solver::Ritz& r, double sigma, double lo, double hi,
+                         int per_above, int target, int dim) {
+  int cnt = 0, above = 0;
+  double top = sigma;
+  for (int i = 0; i < (int)r.theta.size(); ++i) {
+    if (r.theta[i] == 0.0 || !Solver::converged(r, i)) continue;
+    const double l = sigma + 1.0 / r.theta[i];
+    if (l < lo || l >= hi) continue;
+    ++cnt;
+    if (l >= sigma) ++above;
+    top = std::max(top, l);
+  }
+  const double width = top - lo;
+  if (cnt < 8 || !(width > 0)) return std::numeric_limits<double>::quiet_NaN();
+  const double want = cnt + std::max(0, per_above - above) + target;
+  const double cand = lo + width * std::pow(want / cnt, 2.0 / dim);
+  const double step = cand - top;
+  return place_in_gap(sv, r, sigma, top, cand, step, hi);
 }
 
 // A factorisation at a predicted shift made on a second host thread and
@@ -603,7 +641,17 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
       // a repeated run at the same shift means eigenvalues are missing that
       // the previous Krylov space did not reach (e.g. further copies of a
       // multiple eigenvalue): start it from a fresh random vector
-      last = sv.run(sigma, need_below, need_above, runs == 0 ? init : nullptr, &n_new);
+      // at the lowest shift the look-ahead starts from the first run's
+      // convergence checks
+      std::function<void(const Solver::Ritz&)> hook;
+      if (shift == 0 && lookahead_on() && !la.active && !(std::isfinite(hi) && sigma >= hi))
+        hook = [&](const Solver::Ritz& r) {
+          if (la.active) return;
+          const double guess =
+              predict_from_ritz(sv, r, sigma, lo, hi, per_above, (int)target, pr->an.dim);
+          if (std::isfinite(guess) && guess > sigma) la.start(guess, sv.precision, sv.s);
+        };
+      last = sv.run(sigma, need_below, need_above, runs == 0 ? init : nullptr, &n_new, hook);
       last_sigma = sigma;
       init = sv.restart_valid ? sv.y.p : nullptr;
       ++runs;
@@ -658,13 +706,14 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
     if (L.lam >= lo && L.lam < top) in.push_back(L);
   std::sort(in.begin(), in.end(), [](const Locked& a, const Locked& b) { return a.lam < b.lam; });
   const int nf = std::min<int>((int)in.size(), nev);
+  std::vector<int> out_col, in_col;
   for (int i = 0; i < nf; ++i) {
     if (evals) evals[i] = in[i].lam;
     if (resid) resid[i] = in[i].resid;
-    if (evecs)
-      HIPCHECK(hipMemcpyAsync(evecs + (int64_t)i * sv.N, sv.Bc(in[i].col), sv.N * sizeof(double),
-                              hipMemcpyDeviceToDevice, sv.s));
+    out_col.push_back(i);
+    in_col.push_back(in[i].col);
   }
+  if (evecs) launch_copy_cols(out_col, in_col, sv.N, evecs, sv.B.p, nullptr, nullptr, sv.s);
   HIPCHECK(hipStreamSynchronize(sv.s));
   *n_found = nf;
   if (nf < nev && status == RIGA_OK) status = RIGA_ENOCONV;

@@ -9,6 +9,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <vector>
+
 #include "problem.h"
 
 namespace riga {
@@ -101,67 +103,79 @@ __global__ void axpby_vals_kernel(const double* k, const double* m, double sigma
   if (i < n) a[i] = k[i] - sigma * m[i];
 }
 
-constexpr int GEMV_RB = 1024;  // rows per block of the transposed product
-constexpr int GEMV_CG = 16;    // columns per block
+constexpr int GEMV_RB = 1024;  // rows per block of the column-pair reductions
 
-// partial[rb * m + j] = sum_{r in block rb} B(r, j) x(r)
-__global__ void __launch_bounds__(256) gemv_t_kernel(const double* __restrict__ B, int64_t n,
-                                                   int m, const double* __restrict__ x,
+// Projection x -= B (W^T x) of one Gram-Schmidt pass, in two launches:
+// proj_t_kernel forms partial sums of c = W^T x over row blocks of PROJ_RB
+// rows (8 columns per workgroup, 2 per wave, x read once per wave); every
+// workgroup of proj_n_kernel sums the partials of all columns in the same
+// fixed order, so c needs no launch of its own, and subtracts B c.
+constexpr int PROJ_RB = 4096;  // rows per partial sum
+constexpr int PROJ_CG = 8;     // columns per workgroup of the transposed product
+
+__global__ void __launch_bounds__(256) proj_t_kernel(const double* __restrict__ W, int64_t n, int m,
+                                                   const double* __restrict__ x,
                                                    double* __restrict__ partial) {
   const int rb = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t r0 = (int64_t)rb * GEMV_RB;
-  const int64_t r1 = min(r0 + GEMV_RB, n);
-  __shared__ double xs[GEMV_RB];
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) xs[r - r0] = x[r];
-  __syncthreads();
-  // each wave: 4 columns, 16 rows per lane, all loads issued before use
-  constexpr int RPL = GEMV_RB / 64;
-  for (int jj = wave; jj < GEMV_CG; jj += 4) {
-    const int j = blockIdx.y * GEMV_CG + jj;
-    if (j >= m) break;
-    const double* cj = B + (int64_t)j * n;
-    double v[RPL];
+  const int j0 = blockIdx.y * PROJ_CG + 2 * wave;
+  if (j0 >= m) return;
+  const bool two = j0 + 1 < m;
+  const int64_t r0 = (int64_t)rb * PROJ_RB, r1 = min(r0 + PROJ_RB, n);
+  const double* c0 = W + (int64_t)j0 * n;
+  const double* c1 = W + (int64_t)(two ? j0 + 1 : j0) * n;
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t rc = r0; rc < r1; rc += 64 * 16) {
+    double xv[16], a0[16], a1[16];
 #pragma unroll
-    for (int u = 0; u < RPL; ++u) {
-      const int64_t r = r0 + lane + 64 * u;
-      v[u] = r < r1 ? cj[r] : 0.0;
+    for (int u = 0; u < 16; ++u) {
+      const int64_t r = rc + lane + 64 * u;
+      const bool ok = r < r1;
+      xv[u] = ok ? x[r] : 0.0;
+      a0[u] = ok ? c0[r] : 0.0;
+      a1[u] = ok ? c1[r] : 0.0;
     }
-    double s = 0.0;
 #pragma unroll
-    for (int u = 0; u < RPL; ++u) {
-      const int64_t r = r0 + lane + 64 * u;
-      if (r < r1) s += v[u] * xs[r - r0];
+    for (int u = 0; u < 16; ++u) {
+      s0 += a0[u] * xv[u];
+      s1 += a1[u] * xv[u];
     }
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) partial[(int64_t)rb * m + j] = s;
   }
-}
-
-// c[j] = sum_rb partial[rb * m + j]: one wave per column, lanes over row
-// blocks in a fixed order, then a fixed butterfly.  With alpha_out, the wave
-// of column m - 1 also writes *alpha_out = *addend + c[m - 1].
-__global__ void __launch_bounds__(256) gemv_t_reduce_kernel(const double* partial, int nrb, int m,
-                                                          double* c, double* alpha_out,
-                                                          const double* addend) {
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (j >= m) return;
-  double s = 0.0;
-  for (int rb = lane; rb < nrb; rb += 64) s += partial[(int64_t)rb * m + j];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  for (int off = 32; off > 0; off >>= 1) {
+    s0 += __shfl_xor(s0, off);
+    s1 += __shfl_xor(s1, off);
+  }
   if (lane == 0) {
-    c[j] = s;
-    if (alpha_out && j == m - 1) *alpha_out = *addend + s;
+    partial[(int64_t)rb * m + j0] = s0;
+    if (two) partial[(int64_t)rb * m + j0 + 1] = s1;
   }
 }
 
-// x -= B c
-__global__ void __launch_bounds__(256) gemv_n_sub_kernel(const double* __restrict__ B, int64_t n,
-                                                       int m, const double* __restrict__ c,
-                                                       double* __restrict__ x) {
+// c = sum of the nrb partials (rb ascending, eight loads in flight);
+// x -= B c.  Workgroup 0 also stores c and, with alpha_out,
+// *alpha_out = *addend + c[m - 1].
+__global__ void __launch_bounds__(256) proj_n_kernel(const double* __restrict__ B, int64_t n, int m,
+                                                   const double* __restrict__ partial, int nrb,
+                                                   double* c_out, double* alpha_out,
+                                                   const double* addend, double* __restrict__ x) {
   extern __shared__ double cs[];
-  for (int j = threadIdx.x; j < m; j += blockDim.x) cs[j] = c[j];
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    double sj = 0.0;
+    int rb = 0;
+    for (; rb + 8 <= nrb; rb += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = partial[(int64_t)(rb + q) * m + j];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sj += v[q];
+    }
+    for (; rb < nrb; ++rb) sj += partial[(int64_t)rb * m + j];
+    cs[j] = sj;
+    if (blockIdx.x == 0) {
+      c_out[j] = sj;
+      if (alpha_out && j == m - 1) *alpha_out = *addend + sj;
+    }
+  }
   __syncthreads();
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
@@ -214,16 +228,23 @@ __global__ void __launch_bounds__(256) scale2_kernel(const double* x, const doub
                                                    const double* partial, int np, double* v,
                                                    double* w, int64_t n, double* beta_out,
                                                    int32_t* flag) {
-  __shared__ double sm[256];
+  __shared__ double sm[4];
+  // every workgroup sums all partials: eight loads in flight per thread,
+  // then the wave and workgroup reductions (fixed order)
   double t = 0.0;
-  for (int i = threadIdx.x; i < np; i += 256) t += partial[i];
-  sm[threadIdx.x] = t;
-  __syncthreads();
-  for (int q = 128; q > 0; q >>= 1) {
-    if ((int)threadIdx.x < q) sm[threadIdx.x] += sm[threadIdx.x + q];
-    __syncthreads();
+  int i0 = threadIdx.x;
+  for (; i0 + 7 * 256 < np; i0 += 8 * 256) {
+    double pv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) pv[q] = partial[i0 + q * 256];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) t += pv[q];
   }
-  const double b2 = sm[0];
+  for (; i0 < np; i0 += 256) t += partial[i0];
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = t;
+  __syncthreads();
+  const double b2 = (sm[0] + sm[1]) + (sm[2] + sm[3]);
   const bool ok = b2 > 0.0 && isfinite(b2);
   const double b = ok ? sqrt(b2) : 0.0;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -341,6 +362,27 @@ __global__ void scale_cols_kernel(double* U, int64_t n, int m, const double* sca
   if (i < n && q < m) U[(int64_t)q * n + i] *= scale[q];
 }
 
+// U(:, q) and V(:, q) scaled by 1 / sqrt(d[q])
+__global__ void scale_cols_rsqrt_kernel(double* U, double* V, int64_t n, int m, const double* d) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (i >= n || q >= m) return;
+  const double sc = 1.0 / sqrt(d[q]);
+  U[(int64_t)q * n + i] *= sc;
+  V[(int64_t)q * n + i] *= sc;
+}
+
+// Column copies dst(:, dcol[q]) = src(:, scol[q]) for up to COLS_PER_COPY
+// pairs, for two matrices at once (the second pair may be null).
+__global__ void copy_cols_kernel(ColCopy cc, int64_t n, double* d0, const double* s0, double* d1,
+                                 const double* s1) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (i >= n || q >= cc.count) return;
+  d0[(int64_t)cc.dst[q] * n + i] = s0[(int64_t)cc.src[q] * n + i];
+  if (d1) d1[(int64_t)cc.dst[q] * n + i] = s1[(int64_t)cc.src[q] * n + i];
+}
+
 __global__ void axpby_kernel(double a, const double* u, const double* v, double* out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = a * u[i] + v[i];
@@ -430,22 +472,16 @@ void launch_axpby_vals(const double* k, const double* m, double sigma, double* a
 
 int gemv_row_blocks(int64_t n) { return (int)((n + GEMV_RB - 1) / GEMV_RB); }
 
-int gemv_col_groups(int m) { return (m + GEMV_CG - 1) / GEMV_CG; }
+int proj_row_blocks(int64_t n) { return (int)((n + PROJ_RB - 1) / PROJ_RB); }
 
-void launch_gemv_t(const double* B, int64_t n, int m, const double* x, double* partial,
-                   double* c, double* alpha_out, const double* addend, hipStream_t s) {
+void launch_project(const double* W, const double* B, int64_t n, int m, double* x, double* partial,
+                    double* c, double* alpha_out, const double* addend, hipStream_t s) {
   if (m <= 0) return;
-  const int nrb = gemv_row_blocks(n);
-  dim3 grid(nrb, gemv_col_groups(m));
-  gemv_t_kernel<<<grid, 256, 0, s>>>(B, n, m, x, partial);
-  gemv_t_reduce_kernel<<<(m + 3) / 4, 256, 0, s>>>(partial, nrb, m, c, alpha_out, addend);
-  HIPCHECK(hipGetLastError());
-}
-
-void launch_gemv_n_sub(const double* B, int64_t n, int m, const double* c, double* x,
-                       hipStream_t s) {
-  if (m <= 0) return;
-  gemv_n_sub_kernel<<<(unsigned)((n + 255) / 256), 256, (size_t)m * sizeof(double), s>>>(B, n, m, c, x);
+  const int nrb = proj_row_blocks(n);
+  dim3 grid(nrb, (m + PROJ_CG - 1) / PROJ_CG);
+  proj_t_kernel<<<grid, 256, 0, s>>>(W, n, m, x, partial);
+  proj_n_kernel<<<(unsigned)((n + 255) / 256), 256, (size_t)m * sizeof(double), s>>>(
+      B, n, m, partial, nrb, c, alpha_out, addend, x);
   HIPCHECK(hipGetLastError());
 }
 
@@ -474,20 +510,41 @@ void launch_gemm_nn(const double* V, int64_t n, int k, const double* S, int lds,
 }
 
 // Rayleigh quotients lam = u^T K u / u^T M u, then ||K u - lam M u||^2 and ||u||^2.
+int residual_partials(int64_t n, int m) { return gemv_row_blocks(n) * m * 2; }
+
 void launch_residuals(const double* KU, const double* MU, const double* U, int64_t n, int m,
                       double* out_rq_num, double* out_rq_den, double* out_rnorm2,
-                      double* out_unorm2, double* lam, hipStream_t s) {
+                      double* out_unorm2, double* lam, double* partial, hipStream_t s) {
   const int nrb = gemv_row_blocks(n);
-  DBuf<double> partial;
-  partial.alloc((size_t)nrb * m * 2, s);
   dim3 grid(nrb, m);
-  colpair_kernel<<<grid, 256, 0, s>>>(KU, MU, U, n, m, nullptr, 0, partial.p);
-  colpair_reduce_kernel<<<(m + 127) / 128, 128, 0, s>>>(partial.p, nrb, m, out_rq_num, out_rq_den);
+  colpair_kernel<<<grid, 256, 0, s>>>(KU, MU, U, n, m, nullptr, 0, partial);
+  colpair_reduce_kernel<<<(m + 127) / 128, 128, 0, s>>>(partial, nrb, m, out_rq_num, out_rq_den);
   ratio_kernel<<<(m + 127) / 128, 128, 0, s>>>(out_rq_num, out_rq_den, lam, m);
-  colpair_kernel<<<grid, 256, 0, s>>>(KU, MU, U, n, m, lam, 1, partial.p);
-  colpair_reduce_kernel<<<(m + 127) / 128, 128, 0, s>>>(partial.p, nrb, m, out_rnorm2, out_unorm2);
+  colpair_kernel<<<grid, 256, 0, s>>>(KU, MU, U, n, m, lam, 1, partial);
+  colpair_reduce_kernel<<<(m + 127) / 128, 128, 0, s>>>(partial, nrb, m, out_rnorm2, out_unorm2);
   HIPCHECK(hipGetLastError());
-  HIPCHECK(hipStreamSynchronize(s));
+}
+
+void launch_scale_cols_rsqrt(double* U, double* V, int64_t n, int m, const double* d, hipStream_t s) {
+  if (m <= 0) return;
+  dim3 grid((unsigned)((n + 255) / 256), m);
+  scale_cols_rsqrt_kernel<<<grid, 256, 0, s>>>(U, V, n, m, d);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_copy_cols(const std::vector<int>& dst, const std::vector<int>& src, int64_t n, double* d0,
+                      const double* s0, double* d1, const double* s1, hipStream_t s) {
+  for (size_t q0 = 0; q0 < dst.size(); q0 += COLS_PER_COPY) {
+    ColCopy cc{};
+    cc.count = (int)std::min<size_t>(COLS_PER_COPY, dst.size() - q0);
+    for (int q = 0; q < cc.count; ++q) {
+      cc.dst[q] = dst[q0 + q];
+      cc.src[q] = src[q0 + q];
+    }
+    dim3 grid((unsigned)((n + 255) / 256), cc.count);
+    copy_cols_kernel<<<grid, 256, 0, s>>>(cc, n, d0, s0, d1, s1);
+    HIPCHECK(hipGetLastError());
+  }
 }
 
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {

@@ -107,8 +107,13 @@ __device__ double multisect(const double* a, const double* b, int m, int t, cons
 // x_r = 1: x_i = -l_i x_{i+1} above r, x_{i+1} = -u_i x_i below r, so
 // ||x||^2 = Q+_r + P-_r - 1 and x_m = R-_r.  est = |beta_{m+1} s_m|.
 __global__ void __launch_bounds__(128) ritz_check_kernel(const double* alpha, const double* beta,
-                                                       int m, double* theta_out, double* est) {
+                                                       int m, double* theta_out, double* est,
+                                                       const int32_t* flag, double* extra) {
   extern __shared__ double sm[];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    extra[0] = beta[m];
+    extra[1] = (double)flag[0];
+  }
   double* a = sm;
   double* b = sm + m;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -288,10 +293,10 @@ __global__ void __launch_bounds__(64) ritz_vectors_kernel(const double* alpha, c
 }  // namespace
 
 void launch_ritz_check(const double* alpha, const double* beta, int m, double* theta, double* est,
-                       hipStream_t s) {
+                       const int32_t* flag, double* extra, hipStream_t s) {
   if (m > TD_MAX) throw Error(RIGA_EUNSUPPORTED, "Lanczos basis larger than 1024");
   const size_t lds = (size_t)12 * m * sizeof(double);
-  ritz_check_kernel<<<(m + 1) / 2, 128, lds, s>>>(alpha, beta, m, theta, est);
+  ritz_check_kernel<<<(m + 1) / 2, 128, lds, s>>>(alpha, beta, m, theta, est, flag, extra);
   HIPCHECK(hipGetLastError());
 }
 

@@ -315,13 +315,12 @@ void solve_fb(riga_problem* pr, const Factor& F, const double* b, double* x, hip
 
 // BLAS-like helpers on column-major N x m blocks (ld = N).
 int gemv_row_blocks(int64_t n);
-int gemv_col_groups(int m);
-// c = B^T x; partial holds gemv_row_blocks(n) * m doubles.  With alpha_out,
+// One Gram-Schmidt pass: c = W^T x, then x -= B c (W, B: n x m column-major,
+// ld = n); partial holds proj_row_blocks(n) * m doubles.  With alpha_out,
 // also *alpha_out = *addend + c[m - 1].
-void launch_gemv_t(const double* B, int64_t n, int m, const double* x, double* partial,
-                   double* c, double* alpha_out, const double* addend, hipStream_t s);
-void launch_gemv_n_sub(const double* B, int64_t n, int m, const double* c, double* x,
-                       hipStream_t s);
+int proj_row_blocks(int64_t n);
+void launch_project(const double* W, const double* B, int64_t n, int m, double* x, double* partial,
+                    double* c, double* alpha_out, const double* addend, hipStream_t s);
 void launch_reduce_partials(const double* partial, int nblk, double* out, hipStream_t s);
 void launch_fill_random(double* x, int64_t n, uint64_t seed, uint64_t stream_id, hipStream_t s);
 // v = x / beta, w = y / beta with beta^2 the sum of partial[0..np).
@@ -329,9 +328,21 @@ void launch_scale2(const double* x, const double* y, const double* partial, int 
                    double* w, int64_t n, double* beta_out, int32_t* flag, hipStream_t s);
 void launch_gemm_nn(const double* V, int64_t n, int k, const double* S, int lds, int m,
                     double* U, hipStream_t s);
+// partial: residual_partials(n, m) doubles of scratch
+int residual_partials(int64_t n, int m);
 void launch_residuals(const double* KU, const double* MU, const double* U, int64_t n, int m,
                       double* out_rq_num, double* out_rq_den, double* out_rnorm2,
-                      double* out_unorm2, double* lam_in, hipStream_t s);
+                      double* out_unorm2, double* lam_in, double* partial, hipStream_t s);
+// U(:, q), V(:, q) *= 1 / sqrt(d[q]) for q < m
+void launch_scale_cols_rsqrt(double* U, double* V, int64_t n, int m, const double* d, hipStream_t s);
+// d0(:, dst[q]) = s0(:, src[q]) and, if d1, d1(:, dst[q]) = s1(:, src[q])
+constexpr int COLS_PER_COPY = 32;
+struct ColCopy {
+  int32_t count;
+  int32_t dst[COLS_PER_COPY], src[COLS_PER_COPY];
+};
+void launch_copy_cols(const std::vector<int>& dst, const std::vector<int>& src, int64_t n, double* d0,
+                      const double* s0, double* d1, const double* s1, hipStream_t s);
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 void launch_axpby(double a, const double* u, const double* v, double* out, int64_t n,
                   hipStream_t s);
@@ -346,8 +357,9 @@ void launch_scale_cols(double* U, int64_t n, int m, const double* scale, hipStre
 // |beta[m] s_m|.  ritz_vectors: unit eigenvectors S[m x nsel]
 // of the eigenvalues theta[sel[q]] (sel ascending), grouped in ncl clusters
 // [cl_start[c], cl_start[c+1]) of close eigenvalues.
+// ritz_check also stores beta[m] and the breakdown flag at extra[0], extra[1]
 void launch_ritz_check(const double* alpha, const double* beta, int m, double* theta, double* est,
-                       hipStream_t s);
+                       const int32_t* flag, double* extra, hipStream_t s);
 void launch_ritz_vectors(const double* alpha, const double* beta, int m, const double* theta,
                          const int32_t* sel, const int32_t* cl_start, int ncl, double* S,
                          hipStream_t s);

@@ -22,7 +22,7 @@ RIGA_MAT_K, RIGA_MAT_M, RIGA_MAT_A = 0, 1, 2
 EXPORTED = ["riga_set_allocator", "riga_analyze", "riga_assemble", "riga_update_coefficients",
             "riga_problem_info",
             "riga_tree_export", "riga_get_matrices", "riga_spmv", "riga_factor", "riga_solve",
-            "riga_eigs", "riga_eigs_batched", "riga_eig_grad", "riga_destroy", "riga_status_string",
+            "riga_solve_multi", "riga_eigs", "riga_eigs_batched", "riga_eig_grad", "riga_destroy", "riga_status_string",
             "riga_last_error"]
 
 
@@ -85,6 +85,7 @@ def lib():
         L.riga_spmv.argtypes = [P, C.c_int32, P, P, P]
         L.riga_factor.argtypes = [P, C.c_double, C.c_int32, C.POINTER(C.c_int64), C.POINTER(Stats)]
         L.riga_solve.argtypes = [P, P, P, C.c_int32, P]
+        L.riga_solve_multi.argtypes = [P, P, P, C.c_int32, C.c_int64, C.c_int32, P]
         L.riga_eigs.argtypes = [P, C.POINTER(EigsOpts), C.POINTER(C.c_int32), P, P, P,
                                 C.POINTER(Stats)]
         L.riga_eig_grad.argtypes = [P, C.c_int32, P, P, P, P, P, P]
@@ -96,8 +97,8 @@ def lib():
         L.riga_last_error.restype = C.c_char_p
         for name in ["riga_analyze", "riga_assemble", "riga_update_coefficients",
                      "riga_problem_info", "riga_tree_export",
-                     "riga_get_matrices", "riga_spmv", "riga_factor", "riga_solve", "riga_eigs",
-                     "riga_eig_grad", "riga_set_allocator", "riga_eigs_batched"]:
+                     "riga_get_matrices", "riga_spmv", "riga_factor", "riga_solve", "riga_solve_multi",
+                     "riga_eigs", "riga_eig_grad", "riga_set_allocator", "riga_eigs_batched"]:
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -216,6 +217,17 @@ class Problem:
         x = torch.empty_like(b)
         _check(lib().riga_solve(self._h, _ptr(b), _ptr(x), max_ir, _stream(stream)))
         return x
+
+    def solve_multi(self, B, max_ir=0, stream=None):
+        """Columns of X = A^{-1} B for B a contiguous [nrhs, n_dof] device
+        tensor (one right-hand side per row), solved back to back."""
+        import torch
+        if B.dim() != 2 or B.shape[1] != self.n_dof or not B.is_contiguous():
+            raise ValueError("B must be a contiguous [nrhs, n_dof] tensor")
+        X = torch.empty_like(B)
+        _check(lib().riga_solve_multi(self._h, _ptr(B), _ptr(X), B.shape[0], self.n_dof, max_ir,
+                                      _stream(stream)))
+        return X
 
     def eigs(self, nev, lo=0.0, hi=math.inf, precision=RIGA_FP64, tol=1e-9, max_basis=0,
              max_restarts=0, per_shift=0, seed=0, vectors=True, stream=None, allow_partial=False):

@@ -260,3 +260,21 @@ def test_budget_exhausted_returns_only_verified_pairs():
     if n:
         assert np.max(np.abs(lam - lr[:n]) / lr[:n]) <= 1e-10
         assert res.max() <= 1e-9
+
+
+def test_solve_multi_matches_solve():
+    """riga_solve_multi queues the sweeps back to back: every column equals
+    riga_solve's result bit for bit, FP64 and refined mixed precision."""
+    riga = _riga()
+    w = workloads.small(2, 40, 3, 8, 10, 0.3)
+    _say("solve_multi", w.name)
+    kappa, rho = w.coefficients()
+    pr = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho, leaf_dofs=32)
+    B = torch.randn(5, pr.n_dof, dtype=torch.float64, device="cuda")
+    for prec, ir in ((riga.RIGA_FP64, 0), (riga.RIGA_MIXED, 3)):
+        pr.factor(650.0, prec)
+        X = pr.solve_multi(B, max_ir=ir)
+        for i in range(B.shape[0]):
+            x = pr.solve(B[i].contiguous(), max_ir=ir)
+            assert torch.equal(X[i], x), (prec, i)
+    assert pr.solve_multi(B[:0]).shape[0] == 0
