@@ -526,7 +526,7 @@ int bigfront_max_k() { return BF_LDS; }
 template <class T>
 void factor_big_fronts(riga_problem* pr, Factor& F, T* pool, const int32_t* fronts,
                        const std::vector<int>& big_f, const std::vector<int>& big_k,
-                       double pivtol, hipStream_t s) {
+                       double pivtol, int level, bool checked, hipStream_t s) {
   const int nbig = (int)big_f.size();
   if (nbig == 0) return;
   int maxk = 0, maxcb = 0, max_tiles = 0;
@@ -581,6 +581,16 @@ void factor_big_fronts(riga_problem* pr, Factor& F, T* pool, const int32_t* fron
     }
     HIPCHECK(hipGetLastError());
   };
+  if (!checked) {
+    // one step more than predicted covers a panel that ended early (a 2x2
+    // pivot at its edge); the steps of finished fronts return at once
+    if (F.big_pend.n < pr->levels.size()) throw Error(RIGA_EINVAL, "pending counts not reserved");
+    run(steps + 1);
+    big_pending_kernel<<<1, 256, 0, s>>>(a, nbig, F.big_pend.p + level);
+    big_finish_kernel<<<nbig, 256, 0, s>>>(a, nbig);
+    HIPCHECK(hipGetLastError());
+    return;
+  }
   run(steps);
   // panels that ended early leave columns for further steps
   for (int guard = 0;; ++guard) {
@@ -609,6 +619,7 @@ void bigfront_reserve(riga_problem* pr, Factor& F, int lds_max_f, hipStream_t s)
     need_lp = std::max(need_lp, (size_t)nbig * BF_NB);
     need_st = std::max(need_st, (size_t)nbig * sizeof(BigState) / sizeof(int32_t) + 1);
   }
+  if (F.big_pend.n < pr->levels.size()) F.big_pend.alloc(pr->levels.size(), s);
   if (need_perm == 0) return;
   // the pending counter takes the last slot of big_state, past every level's states
   if (F.big_perm.n < need_perm) F.big_perm.alloc(need_perm, s);
@@ -618,9 +629,9 @@ void bigfront_reserve(riga_problem* pr, Factor& F, int lds_max_f, hipStream_t s)
 
 template void factor_big_fronts<double>(riga_problem*, Factor&, double*, const int32_t*,
                                         const std::vector<int>&, const std::vector<int>&, double,
-                                        hipStream_t);
+                                        int, bool, hipStream_t);
 template void factor_big_fronts<float>(riga_problem*, Factor&, float*, const int32_t*,
                                        const std::vector<int>&, const std::vector<int>&, double,
-                                       hipStream_t);
+                                       int, bool, hipStream_t);
 
 }  // namespace riga

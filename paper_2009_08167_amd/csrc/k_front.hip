@@ -21,7 +21,9 @@
 // rows/cols >= k hold the contribution block for the parent.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <mutex>
 
 #include "problem.h"
@@ -199,8 +201,10 @@ __device__ __forceinline__ void ldlt_partial(Acc A, int f, int k, double* lbuf, 
         lbuf[f + i] = u;        // unscaled column
       }
       __syncthreads();
-      // trailing update a(i,m) -= L(i,j) * a(m,j), j < m <= i
-      for (int m = j + 1 + wave; m < f; m += NW) {
+      // trailing update a(i,m) -= L(i,j) * a(m,j), j < m <= i, on the
+      // fully-summed columns only (the contribution block is updated once,
+      // after the last pivot)
+      for (int m = j + 1 + wave; m < k; m += NW) {
         const double um = lbuf[f + m];
         for (int i = m + lane; i < f; i += 64) A(i, m) = (T)((double)A(i, m) - lbuf[i] * um);
       }
@@ -226,7 +230,7 @@ __device__ __forceinline__ void ldlt_partial(Acc A, int f, int k, double* lbuf, 
         lbuf[f + i] = (u2 * d11 - u1 * d21) * idet;
       }
       __syncthreads();
-      for (int m = j + 2 + wave; m < f; m += NW) {
+      for (int m = j + 2 + wave; m < k; m += NW) {
         const double u1 = (double)A(m, j), u2 = (double)A(m, j + 1);
         for (int i = m + lane; i < f; i += 64)
           A(i, m) = (T)((double)A(i, m) - lbuf[i] * u1 - lbuf[f + i] * u2);
@@ -240,6 +244,65 @@ __device__ __forceinline__ void ldlt_partial(Acc A, int f, int k, double* lbuf, 
     }
     __syncthreads();
   }
+  // contribution block: C(i, m) -= sum_t L(i, t) W(m, t), k <= m <= i < f,
+  // with W = L21 D (D block diagonal: 1x1 and 2x2 pivots).  Each thread
+  // owns 4 x 4 tiles of the lower triangle of C, entries in registers.
+  const int fk = f - k;
+  const int nt = (fk + 3) >> 2, ntiles = nt * (nt + 1) / 2;
+  for (int tl = tid; tl < ntiles; tl += NT) {
+    int ti = (int)((sqrt(8.0 * tl + 1.0) - 1.0) * 0.5);
+    while (ti * (ti + 1) / 2 > tl) --ti;
+    while ((ti + 1) * (ti + 2) / 2 <= tl) ++ti;
+    const int mi = tl - ti * (ti + 1) / 2;
+    const int i0 = k + 4 * ti, m0 = k + 4 * mi;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    int t = 0;
+    while (t < k) {
+      if (type_out[t] == 2) {
+        const double d11 = (double)A(t, t), d21 = (double)A(t + 1, t), d22 = (double)A(t + 1, t + 1);
+        double li0[4], li1[4], w0[4], w1[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int i = min(i0 + a, f - 1), m = min(m0 + a, f - 1);
+          li0[a] = (double)A(i, t);
+          li1[a] = (double)A(i, t + 1);
+          const double lm0 = (double)A(m, t), lm1 = (double)A(m, t + 1);
+          w0[a] = lm0 * d11 + lm1 * d21;
+          w1[a] = lm0 * d21 + lm1 * d22;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] += li0[a] * w0[b] + li1[a] * w1[b];
+        t += 2;
+      } else {
+        const double d = (double)A(t, t);
+        double li[4], w[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          li[a] = (double)A(min(i0 + a, f - 1), t);
+          w[a] = (double)A(min(m0 + a, f - 1), t) * d;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] += li[a] * w[b];
+        t += 1;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int i = i0 + a, m = m0 + b;
+        if (i < f && m <= i) A(i, m) = (T)((double)A(i, m) - acc[a][b]);
+      }
+  }
+  __syncthreads();
   if (tid == 0) { *n_neg = neg; *n_pert = pert; *n_2x2 = two; }
 }
 
@@ -258,18 +321,29 @@ __global__ void __launch_bounds__(256) front_factor_lds_kernel(FrontArgs fa, T* 
   const int f = fa.ff[F], k = fa.fk[F];
   T* g = pool + fa.pool_off[F];
   auto pk = [f](int i, int j) { return j * f - ((j * (j - 1)) >> 1) + (i - j); };
-  const int64_t n2 = (int64_t)f * f;
-  for (int64_t e = threadIdx.x; e < n2; e += blockDim.x) {
-    const int c = (int)(e / f), r = (int)(e % f);
-    if (r >= c) sa[pk(r, c)] = g[e];
+  const int n2 = f * f;
+  // eight loads in flight per thread before their LDS stores
+  for (int e0 = threadIdx.x; e0 < n2; e0 += 8 * 256) {
+    T v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + 256 * q;
+      v[q] = e < n2 && (e % f) >= (e / f) ? g[e] : (T)0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + 256 * q;
+      const int c = e / f, r = e % f;
+      if (e < n2 && r >= c) sa[pk(r, c)] = v[q];
+    }
   }
   __syncthreads();
   int neg = 0, pert = 0, two = 0;
   auto A = [&](int i, int j) -> T& { return sa[pk(i, j)]; };
   ldlt_partial<T, 256>(A, f, k, lbuf, perm, &dec, pivtol, &neg, &pert, &two, type);
   __syncthreads();
-  for (int64_t e = threadIdx.x; e < n2; e += blockDim.x) {
-    const int c = (int)(e / f), r = (int)(e % f);
+  for (int e = threadIdx.x; e < n2; e += blockDim.x) {
+    const int c = e / f, r = e % f;
     if (r >= c) g[e] = sa[pk(r, c)];
   }
   const int start = fa.fstart[F];
@@ -306,7 +380,8 @@ FrontArgs front_args(riga_problem* pr, Factor& F) {
 }
 
 template <class T, int MAXF>
-void factor_levels(riga_problem* pr, Factor& F, T* pool, T* hpool, double sigma, hipStream_t s) {
+void factor_levels(riga_problem* pr, Factor& F, T* pool, T* hpool, double sigma, bool checked,
+                   hipStream_t s) {
   FrontArgs fa = front_args(pr, F);
   const double pivtol = 1e-20 * (pr->normK1 + fabs(sigma) * pr->normM1);
   set_kernel_attributes();
@@ -324,7 +399,7 @@ void factor_levels(riga_problem* pr, Factor& F, T* pool, T* hpool, double sigma,
     if (L.n > ns) {
       std::vector<int> bf(L.host_f.begin() + ns, L.host_f.end());
       std::vector<int> bk(L.host_k.begin() + ns, L.host_k.end());
-      factor_big_fronts<T>(pr, F, pool, L.fronts.p + ns, bf, bk, pivtol, s);
+      factor_big_fronts<T>(pr, F, pool, L.fronts.p + ns, bf, bk, pivtol, (int)h, checked, s);
     }
   }
   launch_front_inverse<T>(pr, F, pool, hpool, s);
@@ -356,20 +431,36 @@ void factor_numeric(riga_problem* pr, Factor& F, double sigma, int precision, hi
   if (precision == RIGA_MIXED) {
     if (F.pool32.n < (size_t)an.pool_size || F.h32.n < (size_t)an.h_size || F.av.n < pr->kv.n)
       throw Error(RIGA_EINVAL, "factorisation buffers not reserved");
-    factor_levels<float, LDS_FRONT_MAX_F32>(pr, F, F.pool32.p, F.h32.p, sigma, s);
-    build_top<float>(pr, F, F.h32.p, F.trow32.p, F.tcol32.p, s);
-    // K - sigma M for the refinement residuals
-    launch_axpby_vals(pr->kv.p, pr->mv.p, sigma, F.av.p, (int64_t)pr->kv.n, s);
-  } else {
-    if (F.pool64.n < (size_t)an.pool_size || F.h64.n < (size_t)an.h_size)
-      throw Error(RIGA_EINVAL, "factorisation buffers not reserved");
-    factor_levels<double, LDS_FRONT_MAX_F64>(pr, F, F.pool64.p, F.h64.p, sigma, s);
-    build_top<double>(pr, F, F.h64.p, F.trow64.p, F.tcol64.p, s);
+  } else if (F.pool64.n < (size_t)an.pool_size || F.h64.n < (size_t)an.h_size) {
+    throw Error(RIGA_EINVAL, "factorisation buffers not reserved");
   }
-  std::vector<int32_t> st((size_t)an.n_fronts * 4);
-  HIPCHECK(hipMemcpyAsync(st.data(), F.front_stat.p, st.size() * sizeof(int32_t),
-                          hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipStreamSynchronize(s));
+  const size_t nlev = pr->levels.size();
+  std::vector<int32_t> st((size_t)an.n_fronts * 4), pend(nlev, 0);
+  // the blocked fronts run their predicted panel steps without waiting for
+  // the host; in the rare case that a front needed more, the whole
+  // factorisation is repeated with the host checking every level
+  // (RIGA_FACTOR_CHECKED=1 checks every level from the start)
+  const char* ev = std::getenv("RIGA_FACTOR_CHECKED");
+  const int first = (ev && *ev == '1') ? 1 : 0;
+  for (int pass = first; pass < 2; ++pass) {
+    const bool checked = pass == 1;
+    if (nlev) HIPCHECK(hipMemsetAsync(F.big_pend.p, 0, nlev * sizeof(int32_t), s));
+    if (precision == RIGA_MIXED) {
+      factor_levels<float, LDS_FRONT_MAX_F32>(pr, F, F.pool32.p, F.h32.p, sigma, checked, s);
+      build_top<float>(pr, F, F.h32.p, F.trow32.p, F.tcol32.p, s);
+      // K - sigma M for the refinement residuals
+      launch_axpby_vals(pr->kv.p, pr->mv.p, sigma, F.av.p, (int64_t)pr->kv.n, s);
+    } else {
+      factor_levels<double, LDS_FRONT_MAX_F64>(pr, F, F.pool64.p, F.h64.p, sigma, checked, s);
+      build_top<double>(pr, F, F.h64.p, F.trow64.p, F.tcol64.p, s);
+    }
+    HIPCHECK(hipMemcpyAsync(st.data(), F.front_stat.p, st.size() * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, s));
+    if (nlev)
+      HIPCHECK(hipMemcpyAsync(pend.data(), F.big_pend.p, nlev * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (std::all_of(pend.begin(), pend.end(), [](int32_t v) { return v == 0; })) break;
+  }
   int64_t neg = 0;
   int pert = 0, two = 0;
   for (int f = 0; f < an.n_fronts; ++f) {

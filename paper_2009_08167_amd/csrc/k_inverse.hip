@@ -77,15 +77,26 @@ __global__ void __launch_bounds__(256) front_inverse_kernel(const FrontDesc* __r
   const int nrt = (nr + 15) / 16;
   for (int q = qlast; q >= 0; --q) {
     const int j0 = q * IB, pw = min(IB, k - j0), j1 = j0 + pw;
-    // right-hand side rows: e_i in the top block, L21 rows below
-    for (int e = tid; e < IB * IB; e += 256) {
-      const int ii = e & 63, c = e >> 6;
-      double v = 0.0;
-      if (ii < nr && c < pw) {
-        const int i = r0 + ii, j = j0 + c;
-        v = i < k ? (i == j ? 1.0 : 0.0) : (double)L[(int64_t)j * f + i];
+    // right-hand side rows: e_i in the top block, L21 rows below (every
+    // load of the thread's share issued before the LDS stores)
+    {
+      double rv[IB * IB / 256];
+#pragma unroll
+      for (int q = 0; q < IB * IB / 256; ++q) {
+        const int e = tid + 256 * q;
+        const int ii = e & 63, c = e >> 6;
+        double v = 0.0;
+        if (ii < nr && c < pw) {
+          const int i = r0 + ii, j = j0 + c;
+          v = i < k ? (i == j ? 1.0 : 0.0) : (double)L[(int64_t)j * f + i];
+        }
+        rv[q] = v;
       }
-      Hp[ii * LDP + c] = v;
+#pragma unroll
+      for (int q = 0; q < IB * IB / 256; ++q) {
+        const int e = tid + 256 * q;
+        Hp[(e & 63) * LDP + (e >> 6)] = rv[q];
+      }
     }
     // Hp -= H(:, j1:k) * L11(j1:k, panel), 64-deep chunks on the MFMA units
     if (j1 < k) {
@@ -94,7 +105,10 @@ __global__ void __launch_bounds__(256) front_inverse_kernel(const FrontDesc* __r
       for (int rt = 0; rt < 4; ++rt) acc[rt] = v4d{0.0, 0.0, 0.0, 0.0};
       for (int m0 = j1; m0 < k; m0 += IB) {
         const int mw = min(IB, k - m0);
-        for (int e = tid; e < IB * IB; e += 256) {
+        double ar[IB * IB / 256], br[IB * IB / 256];
+#pragma unroll
+        for (int q = 0; q < IB * IB / 256; ++q) {
+          const int e = tid + 256 * q;
           const int ii = e & 63, mm = e >> 6;
           double a = 0.0;
           if (ii < nr && mm < mw) {
@@ -103,9 +117,15 @@ __global__ void __launch_bounds__(256) front_inverse_kernel(const FrontDesc* __r
             else if (m == i) a = 1.0;
             else if (m < i && !(m == i - 1 && type[m] == 2)) a = (double)Hf[(int64_t)m * ldh + i];
           }
-          Ac[mm * LDP + ii] = a;
+          ar[q] = a;
           const int mb = e & 63, cb = e >> 6;
-          Bc[mb * LDP + cb] = (mb < mw && cb < pw) ? l_entry(L, f, m0 + mb, j0 + cb, type) : 0.0;
+          br[q] = (mb < mw && cb < pw) ? l_entry(L, f, m0 + mb, j0 + cb, type) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < IB * IB / 256; ++q) {
+          const int e = tid + 256 * q;
+          Ac[(e >> 6) * LDP + (e & 63)] = ar[q];
+          Bc[(e & 63) * LDP + (e >> 6)] = br[q];
         }
         __syncthreads();
         const int cl = wave * 16 + (lane & 15);
@@ -135,9 +155,19 @@ __global__ void __launch_bounds__(256) front_inverse_kernel(const FrontDesc* __r
         }
     }
     // diagonal block of the panel: Bc[m * LDP + c] = L11(j0 + m, j0 + c), m > c
-    for (int e = tid; e < IB * IB; e += 256) {
-      const int m = e & 63, c = e >> 6;
-      Bc[m * LDP + c] = (m > c && m < pw) ? l_entry(L, f, j0 + m, j0 + c, type) : 0.0;
+    {
+      double dr[IB * IB / 256];
+#pragma unroll
+      for (int q = 0; q < IB * IB / 256; ++q) {
+        const int e = tid + 256 * q;
+        const int m = e & 63, c = e >> 6;
+        dr[q] = (m > c && m < pw) ? l_entry(L, f, j0 + m, j0 + c, type) : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < IB * IB / 256; ++q) {
+        const int e = tid + 256 * q;
+        Bc[(e & 63) * LDP + (e >> 6)] = dr[q];
+      }
     }
     __syncthreads();
     // h(:, c) for c from the right: once h(i, m) is final, remove its share

@@ -176,7 +176,11 @@ __global__ void __launch_bounds__(256) top_inverse_kernel(
       tys[tid] = ty;
     }
     __syncthreads();
-    for (int e = tid; e < TB * TB; e += 256) {
+    // all 32 loads of this thread's share first, then the LDS stores
+    double av[TB * TB / 256], bvv[TB * TB / 256];
+#pragma unroll
+    for (int q8 = 0; q8 < TB * TB / 256; ++q8) {
+      const int e = tid + 256 * q8;
       const int rr = e & 63, uu = e >> 6;
       const int r = r0 + rr, u = u0 + uu;
       double a = 0.0;
@@ -184,19 +188,24 @@ __global__ void __launch_bounds__(256) top_inverse_kernel(
         if (r >= kP || (u < r && !(u == r - 1 && tys[uu] == 2)))
           a = (double)Hp[(int64_t)u * p.ldh + r];
       }
-      At[uu * TLD + rr] = a;
-      const int cc = e & 63, ub = e >> 6;
-      const int col = c0 + cc;
+      av[q8] = a;
+      const int col = c0 + rr;
       double bv = 0.0;
-      if (ub < uw && col < kF) {
+      if (uu < uw && col < kF) {
         if (self) {
-          bv = (u0 + ub == col) ? 1.0 : 0.0;
+          bv = (u0 + uu == col) ? 1.0 : 0.0;
         } else {
-          const int q = qs[ub];
+          const int q = qs[uu];
           bv = q >= 0 ? cb[p.cb_in + (int64_t)q * kF + col] : 0.0;
         }
       }
-      Bt[ub * TLD + cc] = bv;
+      bvv[q8] = bv;
+    }
+#pragma unroll
+    for (int q8 = 0; q8 < TB * TB / 256; ++q8) {
+      const int e = tid + 256 * q8;
+      At[(e >> 6) * TLD + (e & 63)] = av[q8];
+      Bt[(e >> 6) * TLD + (e & 63)] = bvv[q8];
     }
     __syncthreads();
     const int cl = wave * 16 + (lane & 15);

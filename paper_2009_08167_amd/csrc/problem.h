@@ -183,6 +183,7 @@ struct Factor {
   DBuf<double> d_diag, d_sub;          // D by pivot index: diagonal, (t+1, t) of 2x2 blocks
   DBuf<double> av;                     // K - sigma M values (refinement residuals)
   DBuf<int32_t> big_perm, big_lperm, big_state;  // blocked-factorisation scratch
+  DBuf<int32_t> big_pend;              // per level: fronts left unfinished (0 when complete)
   DBuf<double> trow64, tcol64;         // L_TT^{-1} by rows and by columns
   DBuf<float> trow32, tcol32;
   DBuf<int32_t> tmap, tdof;            // top gather maps in pivot order
@@ -277,10 +278,14 @@ void launch_front_inverse(riga_problem* pr, Factor& F, const T* pool, T* h, hipS
 size_t front_inverse_lds(int max_k);
 // Fronts above the LDS limit of one tree level (`fronts`, orders big_f,
 // fully-summed orders big_k): blocked LDL^T spread over many workgroups.
+// Without `checked`, the predicted number of panel steps plus one is
+// launched and the count of unfinished fronts is left in F.big_pend[level]
+// for the caller to test after its own synchronisation; with `checked`, the
+// host waits for that count and launches further steps until it is zero.
 template <class T>
 void factor_big_fronts(riga_problem* pr, Factor& F, T* pool, const int32_t* fronts,
                        const std::vector<int>& big_f, const std::vector<int>& big_k,
-                       double pivtol, hipStream_t s);
+                       double pivtol, int level, bool checked, hipStream_t s);
 int bigfront_max_k();
 // Allocates the blocked-factorisation scratch of F for every level (fronts
 // above lds_max_f), so that no level reallocates it mid-factorisation.

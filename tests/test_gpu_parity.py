@@ -278,3 +278,26 @@ def test_solve_multi_matches_solve():
             x = pr.solve(B[i].contiguous(), max_ir=ir)
             assert torch.equal(X[i], x), (prec, i)
     assert pr.solve_multi(B[:0]).shape[0] == 0
+
+
+@pytest.mark.parametrize("w", [workloads.small(2, 64, 3, 0, 10, 0.3), workloads.small(3, 10, 2, 0, 10, 0.3)],
+                         ids=lambda w: w.name)
+def test_blocked_fronts_checked_and_unchecked_agree(w, monkeypatch):
+    """The blocked (multi-workgroup) fronts run their predicted panel steps
+    without host checks; RIGA_FACTOR_CHECKED=1 makes the host check every
+    level.  Both give the same inertia and bitwise the same solve."""
+    riga = _riga()
+    _say("checked vs unchecked", w.name)
+    kappa, rho = w.coefficients()
+    pr = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
+    b = torch.randn(pr.n_dof, dtype=torch.float64, device="cuda")
+    for sigma in (0.0, 900.0):
+        for prec in (riga.RIGA_FP64, riga.RIGA_MIXED):
+            monkeypatch.delenv("RIGA_FACTOR_CHECKED", raising=False)
+            n0, _ = pr.factor(sigma, prec)
+            x0 = pr.solve(b)
+            monkeypatch.setenv("RIGA_FACTOR_CHECKED", "1")
+            n1, _ = pr.factor(sigma, prec)
+            x1 = pr.solve(b)
+            assert n0 == n1
+            assert torch.equal(x0, x1), (sigma, prec)
