@@ -64,6 +64,8 @@ struct Solver {
   int max_restarts;
   int precision;
   int max_ir;
+  int dim = 2;           // spatial dimension (eigenvalue-count growth)
+  int64_t nu_lo = 0;     // eigenvalues below lo
   DBuf<double> B, W, x, y, c1, c2, partial, dotp, alpha, beta, scal;
   DBuf<int32_t> flag;
   DBuf<double> chk, S, Sh, Ub, KU, MU, res3, rqn, lam, rpart;
@@ -416,6 +418,14 @@ struct Solver {
 // Moves cand to the middle of the gap between estimated eigenvalues above
 // top that contains it (estimates: the locked values and the Ritz values of
 // run r, made at shift sigma); clamps to hi.
+// Increase of lambda above `top` (n eigenvalues below it) that adds `add`
+// eigenvalues, with the count growing like lambda^{dim/2} (Weyl's law for
+// second-order operators); 0 when top or n is not positive.
+double weyl_step(double top, int64_t n, int add, int dim) {
+  if (!(top > 0) || n <= 0) return 0.0;
+  return top * (std::pow((double)(n + add) / (double)n, 2.0 / dim) - 1.0);
+}
+
 double place_in_gap(const Solver& sv, const Solver::Ritz& r, double sigma, double top, double cand,
                     double step, double hi) {
   std::vector<double> est;
@@ -430,18 +440,26 @@ double place_in_gap(const Solver& sv, const Solver::Ritz& r, double sigma, doubl
     if (e <= cand) below = std::max(below, e);
     else { above = std::min(above, e); }
   }
-  if (std::isfinite(above)) cand = 0.5 * (below + above);
-  else if (below > top) cand = std::max(cand, below + 0.5 * step);
+  if (std::isfinite(above)) {
+    // a wide gap (estimates missing, e.g. copies of a multiple eigenvalue
+    // that the last Krylov space did not resolve) is not crossed: cand only
+    // keeps half a step from its lower end
+    if (above - below <= 2.0 * step) cand = 0.5 * (below + above);
+    else cand = std::min(std::max(cand, below + 0.5 * step), above - 0.5 * step);
+  } else if (below > top) {
+    cand = std::max(cand, below + 0.5 * step);
+  }
   if (std::isfinite(hi) && cand >= hi) cand = hi;
   return cand;
 }
 
 
 // Places the next shift above the eigenvalues locked so far: far enough
-// that the new slice holds about `target` eigenvalues (eigenvalue density
-// estimated from the locked ones), then moved to the middle of the nearest
-// gap between estimated eigenvalues so that K - sigma M stays well
-// conditioned (the paper gives no rule for choosing shifts; Sec. 4.1).
+// that the new slice holds about `target` eigenvalues (the count below the
+// top locked eigenvalue extrapolated with Weyl's law, linearly in 2D), then
+// moved into the nearest gap between estimated eigenvalues so that
+// K - sigma M stays well conditioned (the paper gives no rule for choosing
+// shifts; Sec. 4.1).
 double next_shift(const Solver& sv, const Solver::Ritz& r, double sigma, double lo, double hi,
                   int target) {
   double top = sigma;
@@ -451,11 +469,11 @@ double next_shift(const Solver& sv, const Solver::Ritz& r, double sigma, double 
       top = std::max(top, L.lam);
       ++cnt;
     }
-  double width = top - lo;
-  double dens = (cnt > 0 && width > 0) ? cnt / width : 0.0;
-  double step;
-  if (dens > 0) step = target / dens;
-  else step = std::max(std::fabs(top), 1.0) * 0.5;
+  double step = weyl_step(top, sv.nu_lo + cnt, target, sv.dim);
+  if (!(step > 0)) {
+    const double width = top - lo;
+    step = (cnt > 0 && width > 0) ? target * width / cnt : std::max(std::fabs(top), 1.0) * 0.5;
+  }
   return place_in_gap(sv, r, sigma, top, top + step, step, hi);
 }
 
@@ -475,21 +493,25 @@ double predict_shift(const Solver& sv, const Solver::Ritz& r, double r_sigma, do
       top = std::max(top, L.lam);
       ++cnt;
     }
-  const double width = top - lo;
-  if (cnt == 0 || !(width > 0)) return std::numeric_limits<double>::quiet_NaN();
-  const double dens = cnt / width;
+  if (cnt == 0 || !(top > lo)) return std::numeric_limits<double>::quiet_NaN();
+  int64_t n_top = sv.nu_lo + cnt;
   // pairs locked above sigma already count towards the runs' target
-  if (sv.count_locked(sigma, hi) < per_above) top = std::max(top, sigma + per_above / dens);
-  const double step = target / dens;
+  const int64_t n_sigma = sv.nu_lo + sv.count_locked(lo, sigma);
+  if (sv.count_locked(sigma, hi) < per_above && n_sigma + per_above > n_top) {
+    const double up = weyl_step(sigma, n_sigma, per_above, sv.dim);
+    if (!(up > 0)) return std::numeric_limits<double>::quiet_NaN();
+    top = std::max(top, sigma + up);
+    n_top = n_sigma + per_above;
+  }
+  const double step = weyl_step(top, n_top, target, sv.dim);
+  if (!(step > 0)) return std::numeric_limits<double>::quiet_NaN();
   return place_in_gap(sv, r, r_sigma, top, top + step, step, hi);
 }
 
 // The same guess made during the first run at the lowest shift, before
 // anything is locked: the converged Ritz values of a convergence check
-// stand in for the locked eigenvalues.  Over this wider range the count
-// of eigenvalues below lambda is extrapolated with its asymptotic growth,
-// proportional to (lambda - lo)^{dim/2} (Weyl), not linearly.  NaN while
-// fewer than 8 have converged.
+// stand in for the locked eigenvalues.  NaN while fewer than 8 have
+// converged.
 double predict_from_ritz(const Solver& sv, const Solver::Ritz& r, double sigma, double lo, double hi,
                          int per_above, int target, int dim) {
   int cnt = 0, above = 0;
@@ -502,12 +524,11 @@ double predict_from_ritz(const Solver& sv, const Solver::Ritz& r, double sigma, 
     if (l >= sigma) ++above;
     top = std::max(top, l);
   }
-  const double width = top - lo;
-  if (cnt < 8 || !(width > 0)) return std::numeric_limits<double>::quiet_NaN();
-  const double want = cnt + std::max(0, per_above - above) + target;
-  const double cand = lo + width * std::pow(want / cnt, 2.0 / dim);
-  const double step = cand - top;
-  return place_in_gap(sv, r, sigma, top, cand, step, hi);
+  if (cnt < 8 || !(top > lo)) return std::numeric_limits<double>::quiet_NaN();
+  const int add = std::max(0, per_above - above) + target;
+  const double step = weyl_step(top, sv.nu_lo + cnt, add, dim);
+  if (!(step > 0)) return std::numeric_limits<double>::quiet_NaN();
+  return place_in_gap(sv, r, sigma, top, top + step, step, hi);
 }
 
 // A factorisation at a predicted shift made on a second host thread and
@@ -612,6 +633,8 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
     sv.factor(lo);
     nu_lo = sv.cur().inertia;
   }
+  sv.nu_lo = nu_lo;
+  sv.dim = pr->an.dim;
   sv.st.n_shift = 1;
   riga_status status = RIGA_OK;
   double sigma = lo;

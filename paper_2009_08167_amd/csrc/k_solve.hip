@@ -35,8 +35,7 @@ struct SolveArgs {
   const int32_t* piv_type;  // 1: 1x1 pivot, 2/3: first/second of a 2x2 block
   const int32_t* piv_dof;   // DOF of each pivot
   const int32_t* piv_gmap;  // children's update indices of each pivot
-  const double* dd;         // D diagonal by pivot index
-  const double* dsub;       // D(t+1, t) of 2x2 blocks, at the block's first pivot
+  const double* dc;         // [N * 3] D^{-1} by pivot: w_n = c0 z_n + c+ z_{n+1} + c- z_{n-1}
   double* cbvec;            // update vectors, one per front (f - k entries)
   double* fwd;              // z of the forward sweep, by new (pivot-order) index
 };
@@ -150,6 +149,8 @@ __global__ void __launch_bounds__(256) bwd_kernel(SolveArgs sa, const T* __restr
     acc[c] = 0.0;
   }
   double hv[RCH][CPW];
+  // the 2x2 slot (j + 1, j) holds D: loaded like the rest, zeroed at use,
+  // so that the loads do not wait for the pivot types
   auto load = [&](int i0) {
 #pragma unroll
     for (int r = 0; r < RCH; ++r) {
@@ -157,7 +158,7 @@ __global__ void __launch_bounds__(256) bwd_kernel(SolveArgs sa, const T* __restr
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
         const int j = jc[c];
-        const bool use = j < hi && i < f && i > j && !(two[c] && i == j + 1);
+        const bool use = j < hi && i < f && i > j;
         hv[r][c] = use ? (double)Hf[(int64_t)j * ldh + i] : 0.0;
       }
     }
@@ -169,18 +170,12 @@ __global__ void __launch_bounds__(256) bwd_kernel(SolveArgs sa, const T* __restr
   for (int i = lo + tid; i < f; i += 256) {
     double val;
     if (i < k) {
+      // neighbours inside the front's own pivots (a 2x2 block never
+      // crosses a front); their coefficient is zero otherwise
       const int n = start + i;
-      const int ty = sa.piv_type[n];
-      const double zi = sa.fwd[n];
-      if (ty == 1) {
-        val = zi / sa.dd[n];
-      } else if (ty == 2) {
-        const double d11 = sa.dd[n], d21 = sa.dsub[n], d22 = sa.dd[n + 1];
-        val = (d22 * zi - d21 * sa.fwd[n + 1]) / (d11 * d22 - d21 * d21);
-      } else {
-        const double d11 = sa.dd[n - 1], d21 = sa.dsub[n - 1], d22 = sa.dd[n];
-        val = (d11 * zi - d21 * sa.fwd[n - 1]) / (d11 * d22 - d21 * d21);
-      }
+      const double* c3 = sa.dc + 3 * (int64_t)n;
+      val = c3[0] * sa.fwd[n] + c3[1] * sa.fwd[start + min(i + 1, k - 1)] +
+            c3[2] * sa.fwd[start + max(i - 1, 0)];
     } else {
       val = -x[rows[i]];
     }
@@ -194,7 +189,7 @@ __global__ void __launch_bounds__(256) bwd_kernel(SolveArgs sa, const T* __restr
       const int i = i0 + 64 * r + lane;
       const double vv = (i > lo && i < f) ? v[i - lo] : 0.0;
 #pragma unroll
-      for (int c = 0; c < CPW; ++c) acc[c] += hv[r][c] * vv;
+      for (int c = 0; c < CPW; ++c) acc[c] += (two[c] && i == jc[c] + 1) ? 0.0 : hv[r][c] * vv;
     }
   }
 #pragma unroll
@@ -221,6 +216,32 @@ __global__ void pivot_maps_kernel(const FrontDesc* __restrict__ desc,
   for (int sl = 0; sl < gs; ++sl) piv_gmap[n * gs + sl] = gmap[d.gmap_off + (int64_t)pos * gs + sl];
 }
 
+// D^{-1} by pivot (per factorisation): w_n = c0 z_n + c+ z_{n+1} + c- z_{n-1},
+// the neighbours non-zero only inside a 2x2 block.
+__global__ void dinv_coef_kernel(const int32_t* __restrict__ piv_type, const double* __restrict__ dd,
+                                 const double* __restrict__ dsub, int64_t N, double* dc) {
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  const int ty = piv_type[n];
+  double c0, cp = 0.0, cm = 0.0;
+  if (ty == 1) {
+    c0 = 1.0 / dd[n];
+  } else if (ty == 2) {
+    const double d11 = dd[n], d21 = dsub[n], d22 = dd[n + 1];
+    const double det = d11 * d22 - d21 * d21;
+    c0 = d22 / det;
+    cp = -d21 / det;
+  } else {
+    const double d11 = dd[n - 1], d21 = dsub[n - 1], d22 = dd[n];
+    const double det = d11 * d22 - d21 * d21;
+    c0 = d11 / det;
+    cm = -d21 / det;
+  }
+  dc[3 * n] = c0;
+  dc[3 * n + 1] = cp;
+  dc[3 * n + 2] = cm;
+}
+
 SolveArgs solve_args(riga_problem* pr, const Factor& F) {
   SolveArgs sa{};
   sa.gmap = pr->d_gmap.p;
@@ -229,8 +250,7 @@ SolveArgs solve_args(riga_problem* pr, const Factor& F) {
   sa.piv_type = F.piv_type.p;
   sa.piv_dof = F.piv_dof.p;
   sa.piv_gmap = F.piv_gmap.p;
-  sa.dd = F.d_diag.p;
-  sa.dsub = F.d_sub.p;
+  sa.dc = F.dcoef.p;
   sa.cbvec = pr->cbvec.p;
   sa.fwd = pr->fwd.p;
   return sa;
@@ -284,6 +304,8 @@ void launch_pivot_maps(riga_problem* pr, Factor& F, hipStream_t s) {
   pivot_maps_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(
       pr->d_desc.p, pr->d_front_of.p, F.piv_perm.p, pr->d_rows.p, pr->d_gmap.p, pr->gstride, N,
       F.piv_dof.p, F.piv_gmap.p);
+  dinv_coef_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(F.piv_type.p, F.d_diag.p, F.d_sub.p, N,
+                                                             F.dcoef.p);
   HIPCHECK(hipGetLastError());
 }
 

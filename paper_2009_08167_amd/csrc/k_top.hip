@@ -314,59 +314,81 @@ __global__ void __launch_bounds__(256) top_fwd_kernel(const TopRowUnit* __restri
 }
 
 // x_T = L_TT^{-T} D^{-1} y_T by columns: the workgroup gathers w = D^{-1} y
-// over the stacked rows of its front into LDS, then each wave forms one
-// column's dot product.
+// over the stacked rows of its front into LDS (w_a = c0 y_a + c+ y_{a+1} +
+// c- y_{a-1}, coefficients of D^{-1} formed once per factorisation), then
+// each wave forms one column's dot product.  The column's first loads are
+// issued before the gather.
 template <class T>
 __global__ void __launch_bounds__(256) top_bwd_kernel(const TopColUnit* __restrict__ units,
                                                       const TopFront* __restrict__ fronts,
                                                       const TopAnc* __restrict__ anc, const T* __restrict__ L,
                                                       const double* __restrict__ y,
-                                                      const int32_t* __restrict__ piv_type,
-                                                      const double* __restrict__ dd,
-                                                      const double* __restrict__ dsub,
+                                                      const double* __restrict__ dc, int nT,
                                                       const int32_t* __restrict__ piv_dof, double* x) {
   extern __shared__ double v[];
   __shared__ TopAnc al[TOP_MAX_ANC];
   const TopColUnit u = units[blockIdx.x];
   const TopFront F = fronts[u.tf];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j = u.c0 + wave;
+  const bool col = j < u.c1;
+  const T* c = L + F.coff + (int64_t)F.ld * (col ? j : u.c0);
+  double cv[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) cv[q] = (col && lane + 64 * q < F.h) ? (double)c[lane + 64 * q] : 0.0;
   if (tid < F.n_anc) al[tid] = anc[F.anc_off + tid];
   __syncthreads();
   int e = 0;
   for (int i = tid; i < F.h; i += 256) {
     while (e + 1 < F.n_anc && al[e + 1].rowpos <= i) ++e;
-    const int t = i - al[e].rowpos;
-    const int a = al[e].tstart + t, n = al[e].start + t;
-    const int ty = piv_type[n];
-    const double ya = y[a];
-    double val;
-    if (ty == 1) {
-      val = ya / dd[n];
-    } else if (ty == 2) {
-      const double d11 = dd[n], d21 = dsub[n], d22 = dd[n + 1];
-      val = (d22 * ya - d21 * y[a + 1]) / (d11 * d22 - d21 * d21);
-    } else {
-      const double d11 = dd[n - 1], d21 = dsub[n - 1], d22 = dd[n];
-      val = (d11 * ya - d21 * y[a - 1]) / (d11 * d22 - d21 * d21);
-    }
-    v[i] = val;
+    const int a = al[e].tstart + (i - al[e].rowpos);
+    const double* k3 = dc + 3 * (int64_t)a;
+    v[i] = k3[0] * y[a] + k3[1] * y[min(a + 1, nT - 1)] + k3[2] * y[max(a - 1, 0)];
   }
   __syncthreads();
-  const int j = u.c0 + wave;
-  if (j >= u.c1) return;
-  const T* c = L + F.coff + (int64_t)F.ld * j;
+  if (!col) return;
   double s = 0.0;
-  int i = lane;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) s += cv[q] * ((lane + 64 * q < F.h) ? v[lane + 64 * q] : 0.0);
+  int i = lane + 8 * 64;
   for (; i + 7 * 64 < F.h; i += 8 * 64) {
-    double cv[8];
+    double cw[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) cv[q] = (double)c[i + 64 * q];
+    for (int q = 0; q < 8; ++q) cw[q] = (double)c[i + 64 * q];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) s += cv[q] * v[i + 64 * q];
+    for (int q = 0; q < 8; ++q) s += cw[q] * v[i + 64 * q];
   }
   for (; i < F.h; i += 64) s += (double)c[i] * v[i];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
   if (lane == 0) x[piv_dof[F.start + j]] = s;
+}
+
+// Coefficients of D^{-1} by top row (per factorisation): w_a = c0 y_a +
+// c+ y_{a+1} + c- y_{a-1}, non-zero neighbours only inside a 2x2 block.
+__global__ void top_dinv_kernel(const int32_t* __restrict__ n_of_j, const int32_t* __restrict__ piv_type,
+                                const double* __restrict__ dd, const double* __restrict__ dsub, int nT,
+                                double* dc) {
+  const int a = blockIdx.x * 256 + threadIdx.x;
+  if (a >= nT) return;
+  const int n = n_of_j[a];
+  const int ty = piv_type[n];
+  double c0, cp = 0.0, cm = 0.0;
+  if (ty == 1) {
+    c0 = 1.0 / dd[n];
+  } else if (ty == 2) {
+    const double d11 = dd[n], d21 = dsub[n], d22 = dd[n + 1];
+    const double det = d11 * d22 - d21 * d21;
+    c0 = d22 / det;
+    cp = -d21 / det;
+  } else {
+    const double d11 = dd[n - 1], d21 = dsub[n - 1], d22 = dd[n];
+    const double det = d11 * d22 - d21 * d21;
+    c0 = d11 / det;
+    cm = -d21 / det;
+  }
+  dc[3 * (int64_t)a] = c0;
+  dc[3 * (int64_t)a + 1] = cp;
+  dc[3 * (int64_t)a + 2] = cm;
 }
 
 }  // namespace
@@ -573,14 +595,18 @@ void top_reserve(riga_problem* pr, Factor& F, int precision, hipStream_t s) {
   }
   if (F.tmap.n < (size_t)T.nT * T.tgs) F.tmap.alloc((size_t)T.nT * T.tgs, s);
   if (F.tdof.n < (size_t)T.nT) F.tdof.alloc(T.nT, s);
+  if (F.tdc.n < (size_t)T.nT * 3) F.tdc.alloc((size_t)T.nT * 3, s);
 }
 
 template <class T>
 void build_top(riga_problem* pr, Factor& F, const T* h, T* trow, T* tcol, hipStream_t s) {
   const TopDev& TD = pr->top;
   if (TD.cut < 0) return;
-  if (!trow || !tcol || F.tmap.n < (size_t)TD.nT * TD.tgs || F.tdof.n < (size_t)TD.nT)
+  if (!trow || !tcol || F.tmap.n < (size_t)TD.nT * TD.tgs || F.tdof.n < (size_t)TD.nT ||
+      F.tdc.n < (size_t)TD.nT * 3)
     throw Error(RIGA_EINVAL, "top block buffers not reserved");
+  top_dinv_kernel<<<(TD.nT + 255) / 256, 256, 0, s>>>(TD.n_of_j.p, F.piv_type.p, F.d_diag.p, F.d_sub.p,
+                                                      TD.nT, F.tdc.p);
   top_maps_kernel<<<(TD.nT + 255) / 256, 256, 0, s>>>(TD.n_of_j.p, pr->d_front_of.p, pr->d_desc.p,
                                                       F.piv_perm.p, F.piv_dof.p, TD.slist.p, TD.nT,
                                                       TD.tgs, F.tmap.p, F.tdof.p);
@@ -603,8 +629,7 @@ void sweep_top(riga_problem* pr, const Factor& F, const T* trow, const T* tcol, 
   top_fwd_kernel<T><<<TD.n_fwd, 256, 0, s>>>(TD.fwd_units.p, TD.roff.p, TD.rlo.p, TD.rlen.p, trow, TD.r.p,
                                              TD.y.p);
   top_bwd_kernel<T><<<TD.n_bwd, 256, (size_t)TD.max_h * sizeof(double), s>>>(
-      TD.bwd_units.p, TD.fronts.p, TD.anc.p, tcol, TD.y.p, F.piv_type.p, F.d_diag.p, F.d_sub.p,
-      F.piv_dof.p, x);
+      TD.bwd_units.p, TD.fronts.p, TD.anc.p, tcol, TD.y.p, F.tdc.p, TD.nT, F.piv_dof.p, x);
   HIPCHECK(hipGetLastError());
 }
 

@@ -181,12 +181,14 @@ struct Factor {
   DBuf<int32_t> front_stat;            // [n_fronts * 4]: neg, perturbed, 2x2, spare
   DBuf<int32_t> piv_dof, piv_gmap;     // pivot-order gather maps of the sweeps
   DBuf<double> d_diag, d_sub;          // D by pivot index: diagonal, (t+1, t) of 2x2 blocks
+  DBuf<double> dcoef;                  // [N * 3] D^{-1} by pivot (see dinv_coef_kernel)
   DBuf<double> av;                     // K - sigma M values (refinement residuals)
   DBuf<int32_t> big_perm, big_lperm, big_state;  // blocked-factorisation scratch
   DBuf<int32_t> big_pend;              // per level: fronts left unfinished (0 when complete)
   DBuf<double> trow64, tcol64;         // L_TT^{-1} by rows and by columns
   DBuf<float> trow32, tcol32;
   DBuf<int32_t> tmap, tdof;            // top gather maps in pivot order
+  DBuf<double> tdc;                    // [nT * 3] D^{-1} coefficients of the top rows
   bool factored = false;
   int precision = 0;
   double sigma = 0.0;

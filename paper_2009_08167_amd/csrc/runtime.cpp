@@ -170,6 +170,7 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
       F.piv_gmap.alloc((size_t)N * gs, s);
       F.d_diag.alloc(N, s);
       F.d_sub.alloc(N, s);
+      F.dcoef.alloc((size_t)N * 3, s);
     }
   }
   pr->levels.clear();
