@@ -32,8 +32,22 @@ __global__ void __launch_bounds__(256) spmv_kernel(const int64_t* __restrict__ r
     const int64_t r = r0 + threadIdx.x / G;
     double s = 0.0;
     if (r < N) {
+      // four entries per thread in flight: indices and values first, then
+      // the gathers of x (a masked entry reads x[0] with value 0)
       const int64_t e1 = row_ptr[r + 1];
-      for (int64_t e = row_ptr[r] + sub; e < e1; e += G) s += val[e] * x[col[e]];
+      for (int64_t eb = row_ptr[r] + sub; eb < e1; eb += 4 * G) {
+        int c[4];
+        double v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t e = eb + q * G;
+          const bool ok = e < e1;
+          c[q] = ok ? col[e] : 0;
+          v[q] = ok ? val[e] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s += v[q] * x[c[q]];
+      }
     }
     for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if (sub == 0 && r < N) {
@@ -107,47 +121,53 @@ constexpr int GEMV_RB = 1024;  // rows per block of the column-pair reductions
 
 // Projection x -= B (W^T x) of one Gram-Schmidt pass, in two launches:
 // proj_t_kernel forms partial sums of c = W^T x over row blocks of PROJ_RB
-// rows (8 columns per workgroup, 2 per wave, x read once per wave); every
+// rows (2 columns per workgroup, the rows split over its 4 waves); every
 // workgroup of proj_n_kernel sums the partials of all columns in the same
 // fixed order, so c needs no launch of its own, and subtracts B c.
-constexpr int PROJ_RB = 4096;  // rows per partial sum
-constexpr int PROJ_CG = 8;     // columns per workgroup of the transposed product
+constexpr int PROJ_RB = 4096;  // rows per partial sum (1024 per wave)
 
 __global__ void __launch_bounds__(256) proj_t_kernel(const double* __restrict__ W, int64_t n, int m,
                                                    const double* __restrict__ x,
                                                    double* __restrict__ partial) {
+  // workgroup: 2 columns x PROJ_RB rows; wave w takes rows
+  // [rb * PROJ_RB + w * PROJ_RB / 4, ...), 16 per lane, all loads issued first
+  __shared__ double red[2][4];
   const int rb = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int j0 = blockIdx.y * PROJ_CG + 2 * wave;
-  if (j0 >= m) return;
+  const int j0 = blockIdx.y * 2;
   const bool two = j0 + 1 < m;
-  const int64_t r0 = (int64_t)rb * PROJ_RB, r1 = min(r0 + PROJ_RB, n);
+  const int64_t r0 = (int64_t)rb * PROJ_RB + (int64_t)wave * (PROJ_RB / 4);
+  const int64_t r1 = min((int64_t)rb * PROJ_RB + PROJ_RB, n);
   const double* c0 = W + (int64_t)j0 * n;
   const double* c1 = W + (int64_t)(two ? j0 + 1 : j0) * n;
+  constexpr int RPL = PROJ_RB / 4 / 64;
+  double xv[RPL], a0[RPL], a1[RPL];
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    const int64_t r = r0 + lane + 64 * u;
+    const bool ok = r < r1;
+    xv[u] = ok ? x[r] : 0.0;
+    a0[u] = ok ? c0[r] : 0.0;
+    a1[u] = ok ? c1[r] : 0.0;
+  }
   double s0 = 0.0, s1 = 0.0;
-  for (int64_t rc = r0; rc < r1; rc += 64 * 16) {
-    double xv[16], a0[16], a1[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int64_t r = rc + lane + 64 * u;
-      const bool ok = r < r1;
-      xv[u] = ok ? x[r] : 0.0;
-      a0[u] = ok ? c0[r] : 0.0;
-      a1[u] = ok ? c1[r] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      s0 += a0[u] * xv[u];
-      s1 += a1[u] * xv[u];
-    }
+  for (int u = 0; u < RPL; ++u) {
+    s0 += a0[u] * xv[u];
+    s1 += a1[u] * xv[u];
   }
   for (int off = 32; off > 0; off >>= 1) {
     s0 += __shfl_xor(s0, off);
     s1 += __shfl_xor(s1, off);
   }
   if (lane == 0) {
-    partial[(int64_t)rb * m + j0] = s0;
-    if (two) partial[(int64_t)rb * m + j0 + 1] = s1;
+    red[0][wave] = s0;
+    red[1][wave] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partial[(int64_t)rb * m + j0] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    if (two) partial[(int64_t)rb * m + j0 + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
   }
 }
 
@@ -478,7 +498,7 @@ void launch_project(const double* W, const double* B, int64_t n, int m, double* 
                     double* c, double* alpha_out, const double* addend, hipStream_t s) {
   if (m <= 0) return;
   const int nrb = proj_row_blocks(n);
-  dim3 grid(nrb, (m + PROJ_CG - 1) / PROJ_CG);
+  dim3 grid(nrb, (m + 1) / 2);
   proj_t_kernel<<<grid, 256, 0, s>>>(W, n, m, x, partial);
   proj_n_kernel<<<(unsigned)((n + 255) / 256), 256, (size_t)m * sizeof(double), s>>>(
       B, n, m, partial, nrb, c, alpha_out, addend, x);

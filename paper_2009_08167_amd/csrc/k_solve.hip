@@ -63,11 +63,12 @@ __global__ void __launch_bounds__(256) fwd_kernel(SolveArgs sa, const T* __restr
   const bool row = i < hi;
   const int jend = row ? (i < k ? i : k) : 0;
   const T* hc = H + u.h_off + i;
+  // the first 16 columns of this thread (predicated), before the gather
   double hv[16];
-  const bool first = g + 15 * G < jend;
-  if (first) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) hv[q] = (double)hc[(int64_t)(g + G * q) * ldh];
+  for (int q = 0; q < 16; ++q) {
+    const int j = g + G * q;
+    hv[q] = j < jend ? (double)hc[(int64_t)j * ldh] : 0.0;
   }
   // the (i, i-1) slot of a 2x2 pivot block holds D, not L11^{-1} (= 0)
   const int skip = (row && i < k && i > 0 && sa.piv_type[start + i] == 3) ? i - 1 : -1;
@@ -97,20 +98,20 @@ __global__ void __launch_bounds__(256) fwd_kernel(SolveArgs sa, const T* __restr
   }
   __syncthreads();
   double s = 0.0;
-  int j = g;
-  if (first) {
+  for (int jb = g;;) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) s += (g + G * q == skip ? 0.0 : hv[q]) * y[g + G * q];
-    j += 16 * G;
+    for (int q = 0; q < 16; ++q) {
+      const int j = jb + G * q;
+      if (j < jend && j != skip) s += hv[q] * y[j];
+    }
+    jb += 16 * G;
+    if (jb >= jend) break;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int j = jb + G * q;
+      hv[q] = j < jend ? (double)hc[(int64_t)j * ldh] : 0.0;
+    }
   }
-  for (; j + 15 * G < jend; j += 16 * G) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) hv[q] = (double)hc[(int64_t)(j + G * q) * ldh];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) s += (j + G * q == skip ? 0.0 : hv[q]) * y[j + G * q];
-  }
-  for (; j < jend; j += G)
-    if (j != skip) s += (double)hc[(int64_t)j * ldh] * y[j];
   psum[g * RW + rl] = s;
   __syncthreads();
   if (g == 0 && row) {

@@ -263,24 +263,34 @@ __global__ void top_rhs_kernel(const int32_t* __restrict__ tdof, const int32_t* 
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= nT) return;
   double v = b[tdof[j]];
-  for (int s = 0; s < tgs; ++s) {
-    const int m = tmap[(int64_t)j * tgs + s];
-    if (m >= 0) v += cbvec[m];
+  // eight map entries, then their update entries, in flight at a time
+  for (int s0 = 0; s0 < tgs; s0 += 8) {
+    int m[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) m[q] = s0 + q < tgs ? tmap[(int64_t)j * tgs + s0 + q] : -1;
+    double c[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) c[q] = m[q] >= 0 ? cbvec[m[q]] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v += c[q];
   }
   r[j] = v;
 }
 
-// y_T = L_TT^{-1} r_T by rows: tpr threads per row (16, 64 or 256), each
-// summing every tpr-th entry of the row's segment, then a reduction in a
-// fixed order.
+// y_T = L_TT^{-1} r_T by rows: workgroups of 1024 threads, tpr threads per
+// row (16, 64, 256 or 1024 by the row's length), each summing every tpr-th
+// entry of the row's segment, then a reduction in a fixed order.
+constexpr int TOP_FWD_THREADS = 1024;
+
 template <class T>
-__global__ void __launch_bounds__(256) top_fwd_kernel(const TopRowUnit* __restrict__ units,
-                                                      const int64_t* __restrict__ roff,
-                                                      const int32_t* __restrict__ rlo,
-                                                      const int32_t* __restrict__ rlen,
-                                                      const T* __restrict__ L, const double* __restrict__ r,
-                                                      double* y) {
-  __shared__ double red[4];
+__global__ void __launch_bounds__(TOP_FWD_THREADS) top_fwd_kernel(const TopRowUnit* __restrict__ units,
+                                                                  const int64_t* __restrict__ roff,
+                                                                  const int32_t* __restrict__ rlo,
+                                                                  const int32_t* __restrict__ rlen,
+                                                                  const T* __restrict__ L,
+                                                                  const double* __restrict__ r,
+                                                                  double* y) {
+  __shared__ double red[TOP_FWD_THREADS / 64];
   const TopRowUnit u = units[blockIdx.x];
   const int tid = threadIdx.x, tpr = u.tpr;
   const int row = u.r0 + tid / tpr, ph = tid % tpr;
@@ -304,10 +314,16 @@ __global__ void __launch_bounds__(256) top_fwd_kernel(const TopRowUnit* __restri
   }
   const int w = tpr < 64 ? tpr : 64;
   for (int off = w >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if (tpr == 256) {
+  if (tpr > 64) {
+    // rows of tpr / 64 waves: wave sums through LDS, in wave order
     if ((tid & 63) == 0) red[tid >> 6] = acc;
     __syncthreads();
-    if (tid == 0) y[u.r0] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (ph == 0 && row < u.r1) {
+      const int w0 = tid >> 6, nw = tpr >> 6;
+      double t = 0.0;
+      for (int q = 0; q < nw; ++q) t += red[w0 + q];
+      y[row] = t;
+    }
   } else if (ph == 0 && row < u.r1) {
     y[row] = acc;
   }
@@ -477,13 +493,14 @@ void setup_top(riga_problem* pr) {
   std::vector<int32_t> slist((size_t)nT * tgs, -1);
   for (int j = 0; j < nT; ++j)
     for (size_t q = 0; q < lists[j].size(); ++q) slist[(size_t)j * tgs + q] = lists[j][q];
-  // forward units: consecutive rows of one width class
+  // forward units: consecutive rows of one width class (up to 12 entries
+  // per thread below the widest class)
   std::vector<TopRowUnit> fu;
   for (int j = 0; j < nT;) {
-    auto cls = [&](int len) { return len <= 96 ? 16 : (len <= 768 ? 64 : 256); };
+    auto cls = [&](int len) { return len <= 192 ? 16 : (len <= 768 ? 64 : (len <= 3072 ? 256 : 1024)); };
     const int tpr = cls(rlen[j]);
     int j1 = j + 1;
-    while (j1 < nT && j1 - j < 256 / tpr && cls(rlen[j1]) == tpr) ++j1;
+    while (j1 < nT && j1 - j < 1024 / tpr && cls(rlen[j1]) == tpr) ++j1;
     fu.push_back(TopRowUnit{j, j1, tpr, 0});
     j = j1;
   }
@@ -626,8 +643,8 @@ void sweep_top(riga_problem* pr, const Factor& F, const T* trow, const T* tcol, 
   TopDev& TD = pr->top;
   top_rhs_kernel<<<(TD.nT + 255) / 256, 256, 0, s>>>(F.tdof.p, F.tmap.p, TD.nT, TD.tgs, b, pr->cbvec.p,
                                                      TD.r.p);
-  top_fwd_kernel<T><<<TD.n_fwd, 256, 0, s>>>(TD.fwd_units.p, TD.roff.p, TD.rlo.p, TD.rlen.p, trow, TD.r.p,
-                                             TD.y.p);
+  top_fwd_kernel<T><<<TD.n_fwd, TOP_FWD_THREADS, 0, s>>>(TD.fwd_units.p, TD.roff.p, TD.rlo.p, TD.rlen.p,
+                                                         trow, TD.r.p, TD.y.p);
   top_bwd_kernel<T><<<TD.n_bwd, 256, (size_t)TD.max_h * sizeof(double), s>>>(
       TD.bwd_units.p, TD.fronts.p, TD.anc.p, tcol, TD.y.p, F.tdc.p, TD.nT, F.piv_dof.p, x);
   HIPCHECK(hipGetLastError());
