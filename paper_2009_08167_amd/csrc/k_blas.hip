@@ -181,15 +181,13 @@ __global__ void __launch_bounds__(256) proj_n_kernel(const double* __restrict__ 
   extern __shared__ double cs[];
   for (int j = threadIdx.x; j < m; j += blockDim.x) {
     double sj = 0.0;
-    int rb = 0;
-    for (; rb + 8 <= nrb; rb += 8) {
+    for (int rb = 0; rb < nrb; rb += 8) {
       double v[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = partial[(int64_t)(rb + q) * m + j];
+      for (int q = 0; q < 8; ++q) v[q] = rb + q < nrb ? partial[(int64_t)(rb + q) * m + j] : 0.0;
 #pragma unroll
       for (int q = 0; q < 8; ++q) sj += v[q];
     }
-    for (; rb < nrb; ++rb) sj += partial[(int64_t)rb * m + j];
     cs[j] = sj;
     if (blockIdx.x == 0) {
       c_out[j] = sj;
@@ -199,17 +197,15 @@ __global__ void __launch_bounds__(256) proj_n_kernel(const double* __restrict__ 
   __syncthreads();
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  // 16 column loads in flight per thread
+  // 16 column loads in flight per thread (the last batch predicated)
   double s = 0.0;
-  int j = 0;
-  for (; j + 16 <= m; j += 16) {
+  for (int j = 0; j < m; j += 16) {
     double v[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = B[(int64_t)(j + u) * n + r];
+    for (int u = 0; u < 16; ++u) v[u] = j + u < m ? B[(int64_t)(j + u) * n + r] : 0.0;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) s += v[u] * cs[j + u];
+    for (int u = 0; u < 16; ++u) s += j + u < m ? v[u] * cs[j + u] : 0.0;
   }
-  for (; j < m; ++j) s += B[(int64_t)j * n + r] * cs[j];
   x[r] -= s;
 }
 
@@ -252,15 +248,13 @@ __global__ void __launch_bounds__(256) scale2_kernel(const double* x, const doub
   // every workgroup sums all partials: eight loads in flight per thread,
   // then the wave and workgroup reductions (fixed order)
   double t = 0.0;
-  int i0 = threadIdx.x;
-  for (; i0 + 7 * 256 < np; i0 += 8 * 256) {
+  for (int i0 = threadIdx.x; i0 < np; i0 += 8 * 256) {
     double pv[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) pv[q] = partial[i0 + q * 256];
+    for (int q = 0; q < 8; ++q) pv[q] = i0 + q * 256 < np ? partial[i0 + q * 256] : 0.0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) t += pv[q];
   }
-  for (; i0 < np; i0 += 256) t += partial[i0];
   for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
   if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = t;
   __syncthreads();

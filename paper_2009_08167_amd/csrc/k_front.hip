@@ -51,11 +51,13 @@ struct FrontArgs {
 };
 
 template <class T>
-__global__ void __launch_bounds__(256) front_assemble_kernel(FrontArgs fa, T* pool,
-                                                           const int32_t* fronts,
-                                                           const int64_t* col_prefix, int nf,
-                                                           double sigma) {
-  extern __shared__ double col[];
+__global__ void __launch_bounds__(64 * ASM_COLS) front_assemble_kernel(FrontArgs fa, T* pool,
+                                                                     const int32_t* fronts,
+                                                                     const int64_t* col_prefix,
+                                                                     int nf, int cpw, double sigma) {
+  // workgroup: cpw consecutive columns of one front, one wave each,
+  // lanes over rows; the column is built in LDS and written once
+  extern __shared__ double cols[];
   const int64_t gid = blockIdx.x;
   int lo = 0, hi = nf;
   while (hi - lo > 1) {
@@ -63,34 +65,65 @@ __global__ void __launch_bounds__(256) front_assemble_kernel(FrontArgs fa, T* po
     if (col_prefix[mid] <= gid) lo = mid; else hi = mid;
   }
   const int F = fronts[lo];
-  const int j = (int)(gid - col_prefix[lo]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = (int)(gid - col_prefix[lo]) * cpw + wave;
   const int f = fa.ff[F], k = fa.fk[F];
+  double* col = cols + (size_t)wave * f;
   T* front = pool + fa.pool_off[F];
-  for (int r = j + threadIdx.x; r < f; r += blockDim.x) {
-    double v = 0.0;
-    for (int ci = fa.child_ptr[F]; ci < fa.child_ptr[F + 1]; ++ci) {
-      const int32_t* inv = fa.inv + fa.inv_off[ci];
-      const int cc = inv[j];
-      const int cr = inv[r];
-      if (cc >= 0 && cr >= 0) {
-        const int C = fa.child_list[ci];
-        const int kc = fa.fk[C], fc = fa.ff[C];
-        v += (double)pool[fa.pool_off[C] + (int64_t)(kc + cc) * fc + (kc + cr)];
+  const int c0 = fa.child_ptr[F], nc = fa.child_ptr[F + 1] - c0;
+  if (j < f) {
+    // children's contributions: positions of column j in each child first
+    int cc[4], kc[4], fc[4];
+    int64_t po[4];
+    const int32_t* inv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      cc[q] = -1;
+      if (q < nc) {
+        inv[q] = fa.inv + fa.inv_off[c0 + q];
+        const int C = fa.child_list[c0 + q];
+        kc[q] = fa.fk[C];
+        fc[q] = fa.ff[C];
+        po[q] = fa.pool_off[C];
+        cc[q] = inv[q][j];
       }
     }
-    col[r] = v;
+    for (int r0 = j; r0 < f; r0 += 64 * 4) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = r0 + lane + 64 * u;
+        double t = 0.0;
+        if (r < f) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (cc[q] >= 0) {
+              const int cr = inv[q][r];
+              if (cr >= 0) t += (double)pool[po[q] + (int64_t)(kc[q] + cc[q]) * fc[q] + (kc[q] + cr)];
+            }
+          }
+        }
+        v[u] = t;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = r0 + lane + 64 * u;
+        if (r < f) col[r] = v[u];
+      }
+    }
   }
   __syncthreads();
   if (j < k) {
     const int g = fa.fstart[F] + j;
-    for (int64_t e = fa.amap_ptr[g] + threadIdx.x; e < fa.amap_ptr[g + 1]; e += blockDim.x) {
+    for (int64_t e = fa.amap_ptr[g] + lane; e < fa.amap_ptr[g + 1]; e += 64) {
       const int r = fa.amap_row[e];
       const int v = fa.amap_val[e];
       col[r] += fa.kv[v] - sigma * fa.mv[v];
     }
   }
   __syncthreads();
-  for (int r = j + threadIdx.x; r < f; r += blockDim.x) front[(int64_t)j * f + r] = (T)col[r];
+  if (j < f)
+    for (int r = j + lane; r < f; r += 64) front[(int64_t)j * f + r] = (T)col[r];
 }
 
 constexpr double BK_ALPHA = 0.6403882032022076;  // (1 + sqrt(17)) / 8
@@ -388,8 +421,9 @@ void factor_levels(riga_problem* pr, Factor& F, T* pool, T* hpool, double sigma,
   for (size_t h = 0; h < pr->levels.size(); ++h) {
     LevelDev& L = pr->levels[h];
     if (L.n == 0) continue;
-    front_assemble_kernel<T><<<(unsigned)L.cols, 256, (size_t)L.max_f * sizeof(double), s>>>(
-        fa, pool, L.fronts.p, L.col_prefix.p, L.n, sigma);
+    front_assemble_kernel<T><<<(unsigned)L.cols, 64 * L.asm_cols,
+                               (size_t)L.asm_cols * L.max_f * sizeof(double), s>>>(
+        fa, pool, L.fronts.p, L.col_prefix.p, L.n, L.asm_cols, sigma);
     HIPCHECK(hipGetLastError());
     const int ns = L.n_upto(MAXF);
     if (ns > 0) {
@@ -408,7 +442,12 @@ void factor_levels(riga_problem* pr, Factor& F, T* pool, T* hpool, double sigma,
 
 }  // namespace
 
-void set_front_attributes() {}
+void set_front_attributes() {
+  HIPCHECK(hipFuncSetAttribute((const void*)front_assemble_kernel<double>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, ASM_LDS));
+  HIPCHECK(hipFuncSetAttribute((const void*)front_assemble_kernel<float>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, ASM_LDS));
+}
 
 void factor_reserve(riga_problem* pr, Factor& F, int precision, hipStream_t s) {
   const Analysis& an = pr->an;

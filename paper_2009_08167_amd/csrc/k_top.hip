@@ -299,18 +299,17 @@ __global__ void __launch_bounds__(TOP_FWD_THREADS) top_fwd_kernel(const TopRowUn
     const int len = rlen[row];
     const T* a = L + roff[row];
     const double* x = r + rlo[row];
-    int c = ph;
-    for (; c + 7 * tpr < len; c += 8 * tpr) {
+    for (int c = ph; c < len; c += 8 * tpr) {
       double av[8], xv[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        av[q] = (double)a[c + q * tpr];
-        xv[q] = x[c + q * tpr];
+        const bool ok = c + q * tpr < len;
+        av[q] = ok ? (double)a[c + q * tpr] : 0.0;
+        xv[q] = ok ? x[c + q * tpr] : 0.0;
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) acc += av[q] * xv[q];
     }
-    for (; c < len; c += tpr) acc += (double)a[c] * x[c];
   }
   const int w = tpr < 64 ? tpr : 64;
   for (int off = w >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
@@ -354,27 +353,43 @@ __global__ void __launch_bounds__(256) top_bwd_kernel(const TopColUnit* __restri
   for (int q = 0; q < 8; ++q) cv[q] = (col && lane + 64 * q < F.h) ? (double)c[lane + 64 * q] : 0.0;
   if (tid < F.n_anc) al[tid] = anc[F.anc_off + tid];
   __syncthreads();
+  // four rows per thread at a time: indices, then all their loads
   int e = 0;
-  for (int i = tid; i < F.h; i += 256) {
-    while (e + 1 < F.n_anc && al[e + 1].rowpos <= i) ++e;
-    const int a = al[e].tstart + (i - al[e].rowpos);
-    const double* k3 = dc + 3 * (int64_t)a;
-    v[i] = k3[0] * y[a] + k3[1] * y[min(a + 1, nT - 1)] + k3[2] * y[max(a - 1, 0)];
+  for (int i0 = tid; i0 < F.h; i0 += 4 * 256) {
+    int av[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = min(i0 + 256 * q, F.h - 1);
+      while (e + 1 < F.n_anc && al[e + 1].rowpos <= i) ++e;
+      av[q] = al[e].tstart + (i - al[e].rowpos);
+    }
+    double k0[4], k1[4], k2[4], y0[4], y1[4], y2[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double* k3 = dc + 3 * (int64_t)av[q];
+      k0[q] = k3[0];
+      k1[q] = k3[1];
+      k2[q] = k3[2];
+      y0[q] = y[av[q]];
+      y1[q] = y[min(av[q] + 1, nT - 1)];
+      y2[q] = y[max(av[q] - 1, 0)];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (i0 + 256 * q < F.h) v[i0 + 256 * q] = k0[q] * y0[q] + k1[q] * y1[q] + k2[q] * y2[q];
   }
   __syncthreads();
   if (!col) return;
   double s = 0.0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) s += cv[q] * ((lane + 64 * q < F.h) ? v[lane + 64 * q] : 0.0);
-  int i = lane + 8 * 64;
-  for (; i + 7 * 64 < F.h; i += 8 * 64) {
+  for (int i = lane + 8 * 64; i < F.h; i += 8 * 64) {
     double cw[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) cw[q] = (double)c[i + 64 * q];
+    for (int q = 0; q < 8; ++q) cw[q] = i + 64 * q < F.h ? (double)c[i + 64 * q] : 0.0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) s += cw[q] * v[i + 64 * q];
+    for (int q = 0; q < 8; ++q) s += i + 64 * q < F.h ? cw[q] * v[i + 64 * q] : 0.0;
   }
-  for (; i < F.h; i += 64) s += (double)c[i] * v[i];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
   if (lane == 0) x[piv_dof[F.start + j]] = s;
 }

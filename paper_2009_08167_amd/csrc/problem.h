@@ -64,6 +64,11 @@ struct DBuf {
   }
 };
 
+// Front columns assembled per workgroup (one wave each), at most; fewer
+// where ASM_COLS columns of the level's largest front exceed ASM_LDS bytes.
+constexpr int ASM_COLS = 8;
+constexpr int ASM_LDS = 150 * 1024;
+
 // Fronts at or below this order are factorised in LDS by one workgroup.
 constexpr int LDS_FRONT_MAX_F64 = 128;
 constexpr int LDS_FRONT_MAX_F32 = 176;
@@ -97,12 +102,13 @@ struct WorkUnit {
 
 struct LevelDev {
   int n = 0;                 // fronts at this height
-  int64_t cols = 0;          // sum of front orders (assembly grid)
+  int64_t cols = 0;          // assembly workgroups: sum of ceil(f / asm_cols)
+  int asm_cols = 1;          // columns per assembly workgroup
   int max_f = 0, max_k = 0;
   std::vector<int> host_f;   // front orders, ascending (same order as `fronts`)
   std::vector<int> host_k;   // their fully-summed orders
   DBuf<int32_t> fronts;      // front ids sorted by order
-  DBuf<int64_t> col_prefix;  // [n+1] prefix sums of front orders
+  DBuf<int64_t> col_prefix;  // [n+1] prefix sums of ceil(f / asm_cols)
   DBuf<WorkUnit> fwd_units;  // forward sweep: row blocks of this level's fronts
   DBuf<WorkUnit> bwd_units;  // backward sweep: column blocks
   int n_fwd = 0, n_bwd = 0;

@@ -184,8 +184,13 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
     std::vector<int64_t> pref(fr.size() + 1, 0);
     L.host_f.clear();
     L.host_k.clear();
+    int lvl_max_f = 1;
+    for (int F : fr) lvl_max_f = std::max(lvl_max_f, an.f_f[F]);
+    L.asm_cols = std::max(1, std::min(ASM_COLS, ASM_LDS / (lvl_max_f * (int)sizeof(double))));
+    if ((size_t)lvl_max_f * sizeof(double) > (size_t)ASM_LDS)
+      throw Error(RIGA_EUNSUPPORTED, "front too large for the assembly kernel's LDS");
     for (size_t i = 0; i < fr.size(); ++i) {
-      pref[i + 1] = pref[i] + an.f_f[fr[i]];
+      pref[i + 1] = pref[i] + (an.f_f[fr[i]] + L.asm_cols - 1) / L.asm_cols;
       L.max_f = std::max(L.max_f, an.f_f[fr[i]]);
       L.max_k = std::max(L.max_k, an.f_k[fr[i]]);
       L.host_f.push_back(an.f_f[fr[i]]);
