@@ -348,6 +348,7 @@ __global__ void __launch_bounds__(256) top_bwd_kernel(const TopColUnit* __restri
   const int j = u.c0 + wave;
   const bool col = j < u.c1;
   const T* c = L + F.coff + (int64_t)F.ld * (col ? j : u.c0);
+  const int dof = col ? piv_dof[F.start + j] : 0;  // output index, loaded early
   double cv[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) cv[q] = (col && lane + 64 * q < F.h) ? (double)c[lane + 64 * q] : 0.0;
@@ -391,7 +392,7 @@ __global__ void __launch_bounds__(256) top_bwd_kernel(const TopColUnit* __restri
     for (int q = 0; q < 8; ++q) s += i + 64 * q < F.h ? cw[q] * v[i + 64 * q] : 0.0;
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if (lane == 0) x[piv_dof[F.start + j]] = s;
+  if (lane == 0) x[dof] = s;
 }
 
 // Coefficients of D^{-1} by top row (per factorisation): w_a = c0 y_a +
