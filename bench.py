@@ -239,9 +239,21 @@ def trace_summary(trace_csv, stats_csv):
     pairs = sweep_pairs(rows)
     dur = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows if sweep_kernel(r["Kernel_Name"]))
     n_sw = sum(1 for r in rows if sweep_kernel(r["Kernel_Name"]))
+    # the sweeps that bench.py times with events: the last 30 sweep pairs
+    # (riga_solve_multi, queued back to back after a factorisation)
+    sw = [r for r in rows if sweep_kernel(r["Kernel_Name"])]
+    starts = [i for i, r in enumerate(sw) if "::fwd_kernel<" in r["Kernel_Name"]
+              and (i == 0 or "::fwd_kernel<" not in sw[i - 1]["Kernel_Name"])]
+    last = sw[starts[-30]:] if len(starts) >= 30 else []
     print("| quantity | value |\n|---|---|")
     print("| sweep pairs in the trace | %d (%d sweep-kernel launches) |" % (pairs, n_sw))
-    print("| summed sweep-kernel durations / sweep pairs | %.1f us |" % (dur / 1e3 / max(pairs, 1)))
+    print("| summed sweep-kernel durations / sweep pairs (all, incl. those beside a factorisation) | %.1f us |"
+          % (dur / 1e3 / max(pairs, 1)))
+    if last:
+        span = (max(int(r["End_Timestamp"]) for r in last) - int(last[0]["Start_Timestamp"])) / 1e3 / 30
+        busy = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in last) / 1e3 / 30
+        print("| the 30 timed sweep pairs: span / 30 | %.1f us |" % span)
+        print("| the 30 timed sweep pairs: summed kernel durations / 30 | %.1f us |" % busy)
     st = list(csv.DictReader(open(stats_csv)))
     tot = sum(float(r["TotalDurationNs"]) for r in st)
     print("\n## All kernels (kernel_stats.csv, total %.1f ms)\n" % (tot / 1e6))
