@@ -99,6 +99,9 @@ typedef struct {
   int32_t n_ir;           /* iterative-refinement corrections (mixed precision) */
   int32_t n_perturbed_pivots; /* pivots replaced by a perturbation (static pivoting) */
   int32_t n_2x2_pivots;   /* Bunch-Kaufman 2x2 pivots taken */
+  /* host wall times; t_fact counts only the time the solve waited for a
+   * factorisation (one made ahead on a second stream while the Lanczos runs
+   * at the current shift proceed counts only the wait at its end) */
   double t_fact, t_fb, t_mv, t_orth, t_proj, t_ritz, t_total;
   double flops_fact;      /* algorithmic flops of one factorisation */
   double bytes_fb;        /* algorithmic bytes of one forward+backward elimination */
@@ -203,6 +206,11 @@ riga_status riga_solve_multi(riga_problem* pr, const double* B_dev, double* X_de
                              int64_t ld, int32_t max_ir, void* stream);
 
 /* riga_eigs: the nev lowest eigenpairs with lambda in [lo, hi) (Sec. 4).
+ * Spectrum slicing with inertia counts (Sec. 4.1): the factorisation at a
+ * guess of the next shift runs on a second HIP stream of the library's own
+ * (and a second host thread) while the Lanczos runs at the current shift
+ * proceed; the call returns only after both are done.  Not reentrant for
+ * one problem: calls on the same problem must not overlap.
  * evals_host[nev]: ascending eigenvalues (Rayleigh quotients).
  * evecs_dev: [n_dof * nev] column-major device buffer for M-normalised
  * eigenvectors, or NULL.  resid_host[nev] (or NULL): relative residuals
