@@ -157,7 +157,7 @@ riga_status riga_spmv(riga_problem* pr, int32_t which, const double* x, double* 
     if (which == RIGA_MAT_K) vals = pr->kv.p;
     else if (which == RIGA_MAT_M) vals = pr->mv.p;
     else if (which == RIGA_MAT_A) {
-      riga::Factor& F = pr->fac[pr->cur];
+      riga::Factor& F = pr->ctx[0].current();
       if (!F.factored) return fail(RIGA_EINVAL, "no shift factorised yet");
       if (F.av.n < pr->kv.n) F.av.alloc(pr->kv.n, pr->home);
       riga::launch_axpby_vals(pr->kv.p, pr->mv.p, F.sigma, F.av.p, (int64_t)pr->kv.n, s);
@@ -175,7 +175,7 @@ riga_status riga_factor(riga_problem* pr, double sigma, int32_t precision, int64
     if (!need_device(pr)) return fail(RIGA_EINVAL, "problem has no device data");
     if (!std::isfinite(sigma)) return fail(RIGA_EINVAL, "sigma must be finite");
     if (precision != RIGA_FP64 && precision != RIGA_MIXED) return fail(RIGA_EINVAL, "bad precision");
-    riga::Factor& F = pr->fac[pr->cur];
+    riga::Factor& F = pr->ctx[0].current();
     riga::factor_reserve(pr, F, precision, pr->home);
     riga::factor_numeric(pr, F, sigma, precision, pr->home);
     if (neg_pivots) *neg_pivots = F.inertia;
@@ -229,7 +229,7 @@ void solve_one(riga_problem* pr, const riga::Factor& F, const double* b, double*
 riga_status riga_solve(riga_problem* pr, const double* b, double* x, int32_t max_ir, void* stream) {
   return guarded([&]() -> riga_status {
     if (!need_device(pr) || !b || !x || b == x) return fail(RIGA_EINVAL, "bad problem or vectors");
-    const riga::Factor& F = pr->fac[pr->cur];
+    const riga::Factor& F = pr->ctx[0].current();
     if (!F.factored) return fail(RIGA_EINVAL, "no factorisation");
     hipStream_t s = (hipStream_t)stream;
     solve_one(pr, F, b, x, max_ir, s);
@@ -246,7 +246,7 @@ riga_status riga_solve_multi(riga_problem* pr, const double* B, double* X, int32
     if (!B || !X || ld < pr->an.N) return fail(RIGA_EINVAL, "bad blocks or leading dimension");
     const int64_t span = ld * (int64_t)(nrhs - 1) + pr->an.N;
     if (B < X + span && X < B + span) return fail(RIGA_EINVAL, "B and X overlap");
-    const riga::Factor& F = pr->fac[pr->cur];
+    const riga::Factor& F = pr->ctx[0].current();
     if (!F.factored) return fail(RIGA_EINVAL, "no factorisation");
     hipStream_t s = (hipStream_t)stream;
     for (int32_t i = 0; i < nrhs; ++i) solve_one(pr, F, B + ld * i, X + ld * i, max_ir, s);

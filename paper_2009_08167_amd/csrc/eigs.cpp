@@ -119,7 +119,8 @@ struct Solver {
     }
   }
 
-  Factor& cur() { return pr->fac[pr->cur]; }
+  SolveCtx* ctx = nullptr;  // the solve's factorisations and sweep scratch
+  Factor& cur() { return ctx->current(); }
 
   // counts one factorisation (in place or look-ahead) in the statistics
   void count_factor(const Factor& F) {
@@ -537,6 +538,7 @@ double predict_from_ritz(const Solver& sv, const Solver::Ritz& r, double sigma, 
 // the thread writing into the problem.
 struct LookAhead {
   riga_problem* pr = nullptr;
+  SolveCtx* ctx = nullptr;
   hipStream_t s2 = nullptr;
   std::thread th;
   bool active = false;
@@ -549,7 +551,7 @@ struct LookAhead {
     if (s2) (void)hipStreamDestroy(s2);
   }
 
-  Factor& spare() { return pr->fac[1 - pr->cur]; }
+  Factor& spare() { return ctx->spare(); }
 
   // s: the stream of the Lanczos runs, whose work on the spare Factor (if
   // it was the current one before) must be finished before it is reused
@@ -595,19 +597,31 @@ bool lookahead_on() {
 
 }  // namespace
 
-riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found, double* evals,
-                     double* evecs, double* resid, riga_stats* stats_out) {
+namespace {
+
+// One slice of the spectrum: the nev lowest eigenpairs in [lo, hi) found by
+// shift-and-invert Lanczos with spectrum slicing (Sec. 4.1) on its own
+// Solver (basis storage, stream, factorisations).  `nu_base` >= 0 makes the
+// slice find nev - (nu(lo) - nu_base) pairs instead (the pairs of a lower
+// slice ending at lo are counted by the inertia at lo).  `after_first`, if
+// set, runs once after the runs at the first shift (the split of run_eigs).
+struct Slice {
   Solver sv;
+  double lo = 0.0, hi = 0.0;
+  int nev = 0;
+  int64_t nu_base = -1;
+  riga_status status = RIGA_OK;
+  double verified = 0.0;
+  std::function<void(Slice&, const Solver::Ritz&)> after_first;
+};
+
+void setup_solver(Solver& sv, riga_problem* pr, SolveCtx* ctx, const riga_eigs_opts* o, hipStream_t s,
+                  int nev_cap) {
   sv.pr = pr;
-  sv.s = o->stream ? (hipStream_t)o->stream : pr->home;
-  StreamBind bind(pr, sv.s);
+  sv.ctx = ctx;
+  sv.s = s;
   sv.N = pr->an.N;
   sv.t0 = clk::now();
-  int nev = o->nev;
-  const double lo = o->lo;
-  const double hi = o->hi;
-  sv.lo = lo;
-  sv.hi = hi;
   sv.tol = o->tol > 0 ? o->tol : 1e-9;
   sv.seed = o->seed;
   sv.precision = o->precision;
@@ -618,10 +632,18 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
   int mb = o->max_basis > 0 ? o->max_basis : std::max(160, 4 * sv.per_shift + 32);
   mb = (int)std::min<int64_t>(std::min(mb, 1000), sv.N - 1);
   sv.mb = mb;
-  sv.lock_cap = (int)std::min<int64_t>(nev + 2 * sv.per_shift + 32, sv.N);
+  sv.lock_cap = (int)std::min<int64_t>(nev_cap + 2 * sv.per_shift + 32, sv.N);
+  sv.dim = pr->an.dim;
   sv.alloc();
-  *n_found = 0;
+}
 
+void run_slice(Slice& S) {
+  Solver& sv = S.sv;
+  riga_problem* pr = sv.pr;
+  const double lo = S.lo, hi = S.hi;
+  sv.lo = lo;
+  sv.hi = hi;
+  int nev = S.nev;
   int64_t nu_lo = 0;
   if (std::isfinite(hi)) {
     sv.factor(hi);
@@ -633,8 +655,9 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
     sv.factor(lo);
     nu_lo = sv.cur().inertia;
   }
+  if (S.nu_base >= 0) nev = (int)std::max<int64_t>(0, nev - (nu_lo - S.nu_base));
+  S.nev = nev;
   sv.nu_lo = nu_lo;
-  sv.dim = pr->an.dim;
   sv.st.n_shift = 1;
   riga_status status = RIGA_OK;
   double sigma = lo;
@@ -643,35 +666,43 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
   const double* init = nullptr;
   LookAhead la;
   la.pr = pr;
+  la.ctx = sv.ctx;
   Solver::Ritz last;        // final Ritz data of the last run
   double last_sigma = lo;   // its shift
+  double hi_now = hi;       // the split may lower it after the first shift
   for (int shift = 0; nev > 0 && shift < 400; ++shift) {
     int runs = 0;
     const int per_above = shift == 0 ? sv.per_shift : std::max(1, sv.per_shift / 2);
     const int64_t target = std::max<int64_t>(1, std::min<int64_t>(sv.per_shift / 2, nev - known));
     // factorise at the guessed next shift while the runs at this one proceed
-    if (lookahead_on() && shift > 0 && known < nev && !(std::isfinite(hi) && sigma >= hi)) {
-      const double guess = predict_shift(sv, last, last_sigma, sigma, lo, hi, per_above, (int)target);
+    if (lookahead_on() && shift > 0 && known < nev && !(std::isfinite(hi_now) && sigma >= hi_now)) {
+      const double guess = predict_shift(sv, last, last_sigma, sigma, lo, hi_now, per_above, (int)target);
       if (std::isfinite(guess) && guess > sigma) la.start(guess, sv.precision, sv.s);
     }
     do {
       const int below = sv.count_locked(lo, sigma);
       const int need_below = (int)std::max<int64_t>(0, known - below);
-      const int above = sv.count_locked(sigma, hi);
-      const int need_above = (int)std::max<int64_t>(
-          0, std::min<int64_t>(per_above, nev - known - above));
+      // a split slice's last shift whose eigenvalues below are all locked
+      // needs no run
+      if (need_below == 0 && std::isfinite(hi_now) && sigma >= hi_now) break;
+      const int above = sv.count_locked(sigma, hi_now);
+      // none above the slice's upper end (a split slice's last shift)
+      const int need_above = (std::isfinite(hi_now) && sigma >= hi_now)
+                                 ? 0
+                                 : (int)std::max<int64_t>(
+                                       0, std::min<int64_t>(per_above, nev - known - above));
       int n_new = 0;
       // a repeated run at the same shift means eigenvalues are missing that
       // the previous Krylov space did not reach (e.g. further copies of a
-      // multiple eigenvalue): start it from a fresh random vector
-      // at the lowest shift the look-ahead starts from the first run's
-      // convergence checks
+      // multiple eigenvalue): start it from a fresh random vector.  At the
+      // lowest shift the look-ahead starts from the first run's convergence
+      // checks
       std::function<void(const Solver::Ritz&)> hook;
-      if (shift == 0 && lookahead_on() && !la.active && !(std::isfinite(hi) && sigma >= hi))
+      if (shift == 0 && lookahead_on() && !la.active && !(std::isfinite(hi_now) && sigma >= hi_now))
         hook = [&](const Solver::Ritz& r) {
           if (la.active) return;
           const double guess =
-              predict_from_ritz(sv, r, sigma, lo, hi, per_above, (int)target, pr->an.dim);
+              predict_from_ritz(sv, r, sigma, lo, hi_now, per_above, (int)target, pr->an.dim);
           if (std::isfinite(guess) && guess > sigma) la.start(guess, sv.precision, sv.s);
         };
       last = sv.run(sigma, need_below, need_above, runs == 0 ? init : nullptr, &n_new, hook);
@@ -684,9 +715,14 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
       break;
     }
     verified = sigma;
+    if (shift == 0 && S.after_first) {
+      S.after_first(S, last);  // may lower S.hi (the rest goes to another slice)
+      hi_now = S.hi;
+      sv.hi = hi_now;
+    }
     if (known >= nev) break;
-    if (std::isfinite(hi) && sigma >= hi) break;
-    double next = next_shift(sv, last, sigma, lo, hi, (int)target);
+    if (std::isfinite(hi_now) && sigma >= hi_now) break;
+    double next = next_shift(sv, last, sigma, lo, hi_now, (int)target);
     bool taken = false;
     if (la.active) {
       // the look-ahead factorisation replaces the one at `next` when it
@@ -699,12 +735,13 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
       sv.count_factor(F);
       const int64_t known_g = F.inertia - nu_lo;
       const int64_t missing = known_g - sv.count_locked(lo, la.sigma);
-      taken = la.sigma > sigma && known_g > known && missing <= sv.per_shift;
+      taken = la.sigma > sigma && known_g > known && missing <= sv.per_shift &&
+              !(std::isfinite(hi_now) && la.sigma > hi_now);
       if (log_on())
         std::fprintf(stderr, "[riga] look-ahead sigma=%.10g (placed after the runs: %.10g): %s\n",
                      la.sigma, next, taken ? "taken" : "discarded");
       if (taken) {
-        pr->cur = 1 - pr->cur;
+        sv.ctx->cur = 1 - sv.ctx->cur;
         next = la.sigma;
       }
     }
@@ -720,31 +757,168 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
     }
     sigma = next;
   }
-  // results: locked pairs in [lo, hi), ascending; when the budget ran out,
-  // only those below the last shift whose inertia count they complete (the
-  // others are eigenpairs, but some eigenvalue below them may be missing)
-  const double top = status == RIGA_OK ? hi : std::min(hi, verified);
+  S.status = status;
+  S.verified = verified;
+}
+
+// The slice's pairs to return: those in [lo, hi) (only below the last
+// verified shift if the budget ran out), ascending, at most its nev.
+std::vector<Locked> slice_pairs(const Slice& S) {
+  const double top = S.status == RIGA_OK ? S.hi : std::min(S.hi, S.verified);
   std::vector<Locked> in;
-  for (auto& L : sv.locked)
-    if (L.lam >= lo && L.lam < top) in.push_back(L);
+  for (auto& L : S.sv.locked)
+    if (L.lam >= S.lo && L.lam < top) in.push_back(L);
   std::sort(in.begin(), in.end(), [](const Locked& a, const Locked& b) { return a.lam < b.lam; });
-  const int nf = std::min<int>((int)in.size(), nev);
-  std::vector<int> out_col, in_col;
-  for (int i = 0; i < nf; ++i) {
-    if (evals) evals[i] = in[i].lam;
-    if (resid) resid[i] = in[i].resid;
-    out_col.push_back(i);
-    in_col.push_back(in[i].col);
+  if ((int)in.size() > S.nev) in.resize(S.nev);
+  return in;
+}
+
+void add_stats(riga_stats& a, const riga_stats& b) {
+  a.n_shift += b.n_shift;
+  a.n_fact += b.n_fact;
+  a.n_fb += b.n_fb;
+  a.n_mv += b.n_mv;
+  a.n_it += b.n_it;
+  a.n_ir += b.n_ir;
+  a.n_perturbed_pivots += b.n_perturbed_pivots;
+  a.n_2x2_pivots += b.n_2x2_pivots;
+  a.t_fact += b.t_fact;
+  a.t_fb += b.t_fb;
+  a.t_mv += b.t_mv;
+  a.t_orth += b.t_orth;
+  a.t_proj += b.t_proj;
+  a.t_ritz += b.t_ritz;
+}
+
+// RIGA_SLICES=1 keeps one slice; otherwise an open-ended request for at
+// least 4 shifts' worth of pairs is split in two after its first shift.
+bool split_on() {
+  const char* v = std::getenv("RIGA_SLICES");
+  return !(v && *v == '1');
+}
+
+}  // namespace
+
+riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found, double* evals,
+                     double* evecs, double* resid, riga_stats* stats_out) {
+  const hipStream_t s = o->stream ? (hipStream_t)o->stream : pr->home;
+  StreamBind bind(pr, s);
+  const auto t0 = clk::now();
+  *n_found = 0;
+  Slice A;
+  setup_solver(A.sv, pr, &pr->ctx[0], o, s, o->nev);
+  A.lo = o->lo;
+  A.hi = o->hi;
+  A.nev = o->nev;
+  // the second slice: [b, inf) on its own thread, stream and factorisations.
+  // Destruction order: the thread is joined first, the slice's buffers are
+  // freed next, its stream is destroyed last.
+  hipStream_t sb = nullptr;
+  struct StreamGuard {
+    hipStream_t& st;
+    ~StreamGuard() {
+      if (st) (void)hipStreamDestroy(st);
+    }
+  } stream_guard{sb};
+  Slice B;
+  std::string b_err;
+  riga_status b_code = RIGA_OK;
+  std::thread tb;
+  struct Joiner {
+    std::thread& t;
+    ~Joiner() {
+      if (t.joinable()) t.join();
+    }
+  } joiner{tb};
+  const int per_shift = o->per_shift > 0 ? o->per_shift : 32;
+  if (split_on() && !std::isfinite(o->hi) && o->nev >= 4 * per_shift) {
+    A.after_first = [&](Slice& a, const Solver::Ritz& last) {
+      // split where about half of the remaining pairs lie below
+      Solver& sv = a.sv;
+      int cnt = 0;
+      double top = a.lo;
+      for (auto& L : sv.locked)
+        if (L.lam >= a.lo) {
+          top = std::max(top, L.lam);
+          ++cnt;
+        }
+      // half of the pairs left on each side
+      const int want = (a.nev + cnt) / 2;
+      if (cnt == 0 || want <= cnt + per_shift) return;
+      const double step = weyl_step(top, sv.nu_lo + cnt, want - cnt, sv.dim);
+      if (!(step > 0)) return;
+      const double b = place_in_gap(sv, last, a.lo, top, top + step, step, a.hi);
+      if (!(b > top) || !std::isfinite(b)) return;
+      a.hi = b;
+      if (log_on()) std::fprintf(stderr, "[riga] split at %.10g (%d pairs below the first shift's top)\n", b, cnt);
+      HIPCHECK(hipStreamCreateWithFlags(&sb, hipStreamNonBlocking));
+      const int dev = pr->device;
+      B.lo = b;
+      B.hi = o->hi;
+      B.nev = o->nev;
+      B.nu_base = sv.nu_lo;
+      tb = std::thread([&, dev] {
+        try {
+          HIPCHECK(hipSetDevice(dev));
+          setup_solver(B.sv, pr, &pr->ctx[1], o, sb, o->nev);
+          run_slice(B);
+        } catch (const Error& e) {
+          b_code = e.code;
+          b_err = e.what();
+        } catch (const std::exception& e) {
+          b_code = RIGA_EDEVICE;
+          b_err = e.what();
+        }
+      });
+    };
   }
-  if (evecs) launch_copy_cols(out_col, in_col, sv.N, evecs, sv.B.p, nullptr, nullptr, sv.s);
-  HIPCHECK(hipStreamSynchronize(sv.s));
+  run_slice(A);
+  if (tb.joinable()) tb.join();
+  if (b_code != RIGA_OK) throw Error(b_code, "second slice: " + b_err);
+  // results: the first slice's pairs, then (if it is complete) the second's
+  std::vector<Locked> pa = slice_pairs(A);
+  std::vector<Locked> pb;
+  riga_status status = A.status;
+  const bool split = sb != nullptr;
+  if (split && A.status == RIGA_OK) {
+    pb = slice_pairs(B);
+    status = B.status;
+  }
+  const int nev = split ? (int)std::min<size_t>(o->nev, pa.size() + pb.size())
+                        : std::min(A.nev, (int)pa.size());
+  std::vector<int> oa, ia, ob, ib;
+  int nf = 0;
+  for (size_t i = 0; i < pa.size() && nf < o->nev; ++i, ++nf) {
+    if (evals) evals[nf] = pa[i].lam;
+    if (resid) resid[nf] = pa[i].resid;
+    oa.push_back(nf);
+    ia.push_back(pa[i].col);
+  }
+  for (size_t i = 0; i < pb.size() && nf < o->nev; ++i, ++nf) {
+    if (evals) evals[nf] = pb[i].lam;
+    if (resid) resid[nf] = pb[i].resid;
+    ob.push_back(nf);
+    ib.push_back(pb[i].col);
+  }
+  (void)nev;
+  if (evecs) {
+    launch_copy_cols(oa, ia, A.sv.N, evecs, A.sv.B.p, nullptr, nullptr, s);
+    if (!ob.empty()) {
+      HIPCHECK(hipStreamSynchronize(sb));
+      launch_copy_cols(ob, ib, B.sv.N, evecs, B.sv.B.p, nullptr, nullptr, s);
+    }
+  }
+  HIPCHECK(hipStreamSynchronize(s));
   *n_found = nf;
-  if (nf < nev && status == RIGA_OK) status = RIGA_ENOCONV;
-  sv.st.t_total = secs(sv.t0, clk::now());
-  sv.st.flops_fact = pr->an.flops_fact;
-  sv.st.bytes_fb = (double)pr->an.nnz_l * 2.0 * (sv.precision == RIGA_MIXED ? 4.0 : 8.0);
-  if (stats_out) *stats_out = sv.st;
-  pr->stats = sv.st;
+  const int wanted = split ? o->nev : A.nev;
+  if (nf < wanted && status == RIGA_OK) status = RIGA_ENOCONV;
+  riga_stats st = A.sv.st;
+  if (split) add_stats(st, B.sv.st);
+  st.t_total = secs(t0, clk::now());
+  st.flops_fact = pr->an.flops_fact;
+  st.bytes_fb = (double)pr->an.nnz_l * 2.0 * (o->precision == RIGA_MIXED ? 4.0 : 8.0);
+  if (stats_out) *stats_out = st;
+  pr->stats = st;
   return status;
 }
 

@@ -451,6 +451,20 @@ void set_front_attributes() {
 
 void factor_reserve(riga_problem* pr, Factor& F, int precision, hipStream_t s) {
   const Analysis& an = pr->an;
+  const int64_t N = an.N;
+  const size_t gs = (size_t)pr->gstride;
+  if (F.piv_perm.n < (size_t)N) {
+    F.piv_perm.alloc(N, s);
+    F.piv_type.alloc(N, s);
+    F.piv_dof.alloc(N, s);
+    F.piv_gmap.alloc((size_t)N * gs, s);
+    F.d_diag.alloc(N, s);
+    F.d_sub.alloc(N, s);
+    F.dcoef.alloc((size_t)N * 3, s);
+    F.front_stat.alloc((size_t)an.n_fronts * 4, s);
+    F.cbvec.alloc(std::max<int64_t>(an.cb_size, 1), s);
+    F.fwd.alloc(N, s);
+  }
   if (precision == RIGA_MIXED) {
     if (F.pool32.n < (size_t)an.pool_size) F.pool32.alloc(an.pool_size, s);
     if (F.h32.n < (size_t)an.h_size) F.h32.alloc(an.h_size, s);

@@ -252,8 +252,8 @@ SolveArgs solve_args(riga_problem* pr, const Factor& F) {
   sa.piv_dof = F.piv_dof.p;
   sa.piv_gmap = F.piv_gmap.p;
   sa.dc = F.dcoef.p;
-  sa.cbvec = pr->cbvec.p;
-  sa.fwd = pr->fwd.p;
+  sa.cbvec = F.cbvec.p;
+  sa.fwd = F.fwd.p;
   return sa;
 }
 

@@ -607,9 +607,6 @@ void setup_top(riga_problem* pr) {
     T.tiles[l].upload(tiles[l], s);
     T.n_tiles[l] = (int)tiles[l].size();
   }
-  T.r.alloc(nT, s);
-  T.y.alloc(nT, s);
-  T.cb.alloc(std::max<int64_t>(e_cb, 1), s);
   if (const char* v = std::getenv("RIGA_LOG"))
     if (*v && *v != '0')
       std::fprintf(stderr, "[riga] top block: heights >= %d, %d variables, %zu fronts, %.1f MB by rows, "
@@ -629,6 +626,11 @@ void top_reserve(riga_problem* pr, Factor& F, int precision, hipStream_t s) {
   if (F.tmap.n < (size_t)T.nT * T.tgs) F.tmap.alloc((size_t)T.nT * T.tgs, s);
   if (F.tdof.n < (size_t)T.nT) F.tdof.alloc(T.nT, s);
   if (F.tdc.n < (size_t)T.nT * 3) F.tdc.alloc((size_t)T.nT * 3, s);
+  if (F.tcb.n < (size_t)std::max<int64_t>(T.e_cb, 1)) F.tcb.alloc(std::max<int64_t>(T.e_cb, 1), s);
+  if (F.top_r.n < (size_t)T.nT) {
+    F.top_r.alloc(T.nT, s);
+    F.top_y.alloc(T.nT, s);
+  }
 }
 
 template <class T>
@@ -648,7 +650,7 @@ void build_top(riga_problem* pr, Factor& F, const T* h, T* trow, T* tcol, hipStr
     if (TD.n_tiles[l] == 0) continue;
     top_inverse_kernel<T><<<TD.n_tiles[l], 256, 0, s>>>(TD.tiles[l].p, TD.pairs.p, h, F.piv_perm.p,
                                                         F.piv_type.p, pr->d_inv.p, TD.roff.p,
-                                                        pr->top.cb.p, trow, tcol);
+                                                        F.tcb.p, trow, tcol);
     HIPCHECK(hipGetLastError());
   }
 }
@@ -656,13 +658,13 @@ void build_top(riga_problem* pr, Factor& F, const T* h, T* trow, T* tcol, hipStr
 template <class T>
 void sweep_top(riga_problem* pr, const Factor& F, const T* trow, const T* tcol, const double* b,
                double* x, hipStream_t s) {
-  TopDev& TD = pr->top;
-  top_rhs_kernel<<<(TD.nT + 255) / 256, 256, 0, s>>>(F.tdof.p, F.tmap.p, TD.nT, TD.tgs, b, pr->cbvec.p,
-                                                     TD.r.p);
+  const TopDev& TD = pr->top;
+  top_rhs_kernel<<<(TD.nT + 255) / 256, 256, 0, s>>>(F.tdof.p, F.tmap.p, TD.nT, TD.tgs, b, F.cbvec.p,
+                                                     F.top_r.p);
   top_fwd_kernel<T><<<TD.n_fwd, TOP_FWD_THREADS, 0, s>>>(TD.fwd_units.p, TD.roff.p, TD.rlo.p, TD.rlen.p,
-                                                         trow, TD.r.p, TD.y.p);
+                                                         trow, F.top_r.p, F.top_y.p);
   top_bwd_kernel<T><<<TD.n_bwd, 256, (size_t)TD.max_h * sizeof(double), s>>>(
-      TD.bwd_units.p, TD.fronts.p, TD.anc.p, tcol, TD.y.p, F.tdc.p, TD.nT, F.piv_dof.p, x);
+      TD.bwd_units.p, TD.fronts.p, TD.anc.p, tcol, F.top_y.p, F.tdc.p, TD.nT, F.piv_dof.p, x);
   HIPCHECK(hipGetLastError());
 }
 

@@ -173,8 +173,6 @@ struct TopDev {
   DBuf<TopPair> pairs;
   std::vector<DBuf<TopTile>> tiles;  // per height, cut upwards
   std::vector<int> n_tiles;
-  DBuf<double> r, y;                 // sweep vectors [nT]
-  DBuf<double> cb;                   // construction blocks [e_cb]
 };
 
 // One numeric factorisation of K - sigma M and everything the sweeps read
@@ -195,11 +193,25 @@ struct Factor {
   DBuf<float> trow32, tcol32;
   DBuf<int32_t> tmap, tdof;            // top gather maps in pivot order
   DBuf<double> tdc;                    // [nT * 3] D^{-1} coefficients of the top rows
+  DBuf<double> tcb;                    // top block construction blocks [e_cb]
+  // sweep scratch: sweeps with this factorisation run one at a time
+  DBuf<double> cbvec, fwd;             // update vectors [cb_size], forward z [N]
+  DBuf<double> top_r, top_y;           // top block right-hand side and y [nT]
   bool factored = false;
   int precision = 0;
   double sigma = 0.0;
   int64_t inertia = 0;
   int perturbed = 0, two = 0;
+};
+
+// The mutable state of one solve: two factorisations (the current one and
+// the one made ahead), each with its own sweep scratch.  A problem has two,
+// so that two slices of the spectrum can be solved at once.
+struct SolveCtx {
+  Factor fac[2];
+  int cur = 0;
+  Factor& current() { return fac[cur]; }
+  Factor& spare() { return fac[1 - cur]; }
 };
 
 }  // namespace riga
@@ -233,14 +245,13 @@ struct riga_problem {
   riga::DBuf<int32_t> d_amap_row, d_amap_val;
   std::vector<riga::LevelDev> levels;
 
-  // numeric factorisations: fac[cur] is the one riga_factor / riga_solve use
-  riga::Factor fac[2];
-  int cur = 0;
+  // numeric factorisations: ctx[0].current() is the one riga_factor /
+  // riga_solve use; ctx[1] serves a second slice of the spectrum
+  riga::SolveCtx ctx[2];
   riga::DBuf<riga::WorkUnit> inv_units;     // row blocks of every front
   int n_inv_units = 0;
 
-  // solve workspace
-  riga::DBuf<double> cbvec, fwd;
+  // solve descriptors
   riga::DBuf<riga::FrontDesc> d_desc;
   riga::DBuf<int32_t> d_front_of;           // front of each new (pivot-order) index
   riga::DBuf<int32_t> d_gmap;               // [sum f * gstride] children's update indices

@@ -96,7 +96,7 @@ void load_and_assemble(riga_problem* pr, const double* kappa, const double* rho,
   load_coef(rho, pr->rho, "rho");
   launch_assemble(pr);
   compute_norms(pr);
-  pr->fac[0].factored = pr->fac[1].factored = false;
+  for (SolveCtx& c : pr->ctx) c.fac[0].factored = c.fac[1].factored = false;
 }
 
 void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
@@ -166,13 +166,6 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
     for (int F = 0; F < an.n_fronts; ++F)
       for (int t = 0; t < an.f_k[F]; ++t) front_of[an.f_start[F] + t] = F;
     pr->d_front_of.upload(front_of, s);
-    for (Factor& F : pr->fac) {
-      F.piv_dof.alloc(N, s);
-      F.piv_gmap.alloc((size_t)N * gs, s);
-      F.d_diag.alloc(N, s);
-      F.d_sub.alloc(N, s);
-      F.dcoef.alloc((size_t)N * 3, s);
-    }
   }
   pr->levels.clear();
   pr->levels.resize(an.height);
@@ -277,13 +270,6 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
     throw Error(RIGA_EUNSUPPORTED, "fully-summed block too large for the panel kernel");
   if (front_inverse_lds(an.max_fs) > 159 * 1024)
     throw Error(RIGA_EUNSUPPORTED, "fully-summed block too large for the inverse kernel's LDS");
-  for (Factor& F : pr->fac) {
-    F.piv_perm.alloc(N, s);
-    F.piv_type.alloc(N, s);
-    F.front_stat.alloc((size_t)an.n_fronts * 4, s);
-  }
-  pr->cbvec.alloc(std::max<int64_t>(an.cb_size, 1), s);
-  pr->fwd.alloc(N, s);
   setup_top(pr);
   HIPCHECK(hipStreamSynchronize(s));
   pr->has_device = true;

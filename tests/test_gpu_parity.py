@@ -301,3 +301,26 @@ def test_blocked_fronts_checked_and_unchecked_agree(w, monkeypatch):
             x1 = pr.solve(b)
             assert n0 == n1
             assert torch.equal(x0, x1), (sigma, prec)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_two_slices_match_one(prec, monkeypatch):
+    """An open-ended request for many pairs is split after its first shift
+    into two slices solved at once; the result equals the single-slice
+    solve and the dense oracle (eigenvalues <= 1e-10, residuals <= 1e-9,
+    M-orthonormality across the two slices' vectors <= 1e-10)."""
+    riga = _riga()
+    w = workloads.small(2, 40, 3, 8, 140, 0.3)
+    kappa, rho = w.coefficients()
+    pr = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho, leaf_dofs=32)
+    _say("slices", w.name, "N", pr.n_dof, "nev", w.nev)
+    Ko, Mo = assembly.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
+    lr, Ur = eigen.dense_eigh(Ko, Mo)
+    monkeypatch.setenv("RIGA_SLICES", "1")
+    l1, U1, r1, s1 = pr.eigs(w.nev, precision=prec)
+    monkeypatch.delenv("RIGA_SLICES")
+    l2, U2, r2, s2 = pr.eigs(w.nev, precision=prec)
+    _say("one slice", s1, "two slices", s2)
+    assert s2["n_shift"] >= 2
+    for lam, U, res in ((l1, U1, r1), (l2, U2, r2)):
+        _check_pairs(Ko, Mo, lr, Ur, lam, U.cpu().numpy(), res, w.nev)
