@@ -42,12 +42,14 @@ namespace riga {
 namespace {
 
 // Cost model for the choice of the cut (sweep pair, seconds): a tree level
-// costs one launch per direction, bounded below by its latency; the top
-// block costs three launches and one pass over each of its two copies.
-constexpr double LEVEL_LATENCY = 5.5e-6;
-constexpr double LEVEL_BW = 3.5e12;
+// costs one launch per direction, a fixed latency plus its factor bytes at
+// the rate its kernels reach; the top block costs three launches and one
+// pass over each of its two copies. Fitted to measured sweep pairs over
+// forced cuts of the 2D and 3D workloads.
+constexpr double LEVEL_LATENCY = 5.0e-6;
+constexpr double LEVEL_BW = 2.0e12;
 constexpr double TOP_LATENCY = 5.0e-6;
-constexpr double TOP_BW = 4.5e12;
+constexpr double TOP_BW = 2.75e12;
 constexpr int64_t TOP_MAX_ENTRIES = int64_t(1) << 27;  // rows + columns + construction blocks
 constexpr int TOP_MAX_STACK = 16384;  // stacked rows of a column block (backward kernel's LDS)
 constexpr int TOP_MAX_ANC = 64;       // fronts in one ancestor chain
@@ -106,7 +108,7 @@ int choose_cut(const Analysis& an) {
     const double f = an.f_f[F], k = an.f_k[F];
     bytes[an.f_height[F]] += (k * (k - 1) / 2 + (f - k) * k) * 8.0;
   }
-  auto level = [&](int h) { return 2.0 * std::max(LEVEL_LATENCY, bytes[h] / LEVEL_BW); };
+  auto level = [&](int h) { return 2.0 * (LEVEL_LATENCY + bytes[h] / LEVEL_BW); };
   double all = 0.0;
   for (int h = 0; h < H; ++h) all += level(h);
   double best = 0.95 * all;  // take the top block only for a clear gain
