@@ -79,7 +79,8 @@ typedef struct {
   double lo;              /* interval start (inclusive) */
   double hi;              /* interval end (exclusive); +INFINITY -> the nev lowest >= lo */
   int32_t nev;            /* number of pairs wanted, returned ascending */
-  int32_t precision;      /* RIGA_FP64, or RIGA_MIXED: FP32 fronts and solves refined in FP64 */
+  int32_t precision;      /* RIGA_FP64, or RIGA_MIXED: FP32 fronts and solves refined in FP64
+                             (2 steps per solve, doubled up to 8 when a run stalls) */
   double tol;             /* accept a pair when ||K u - lambda M u||_2 / (||K||_1 ||u||_2) <= tol;
                              0 -> 1e-9 */
   int32_t max_basis;      /* Lanczos basis size per run; 0 -> max(160, 4 per_shift + 32) */

@@ -35,6 +35,9 @@ namespace {
 
 using clk = std::chrono::steady_clock;
 
+// refinement steps per mixed-precision solve after escalation (2 at start)
+constexpr int MAX_IR_ESCALATED = 8;
+
 // RIGA_LOG=1 prints one line per Lanczos run and per shift to stderr.
 bool log_on() {
   static const bool on = [] {
@@ -706,6 +709,14 @@ void run_slice(Slice& S) {
           if (std::isfinite(guess) && guess > sigma) la.start(guess, sv.precision, sv.s);
         };
       last = sv.run(sigma, need_below, need_above, runs == 0 ? init : nullptr, &n_new, hook);
+      // mixed precision: a run that locks under an eighth of what is missing
+      // has reached the accuracy the refined FP32 solve allows (Ritz values
+      // converge, their FP64 residuals do not); refine more from here on
+      if (sv.precision == RIGA_MIXED && sv.max_ir < MAX_IR_ESCALATED &&
+          8 * n_new < need_below + need_above) {
+        sv.max_ir = std::min(MAX_IR_ESCALATED, std::max(1, 2 * sv.max_ir));
+        if (log_on()) std::fprintf(stderr, "[riga] refinement steps raised to %d\n", sv.max_ir);
+      }
       last_sigma = sigma;
       init = sv.restart_valid ? sv.y.p : nullptr;
       ++runs;

@@ -8,8 +8,8 @@ can compute one piece at a time (see the oracle's pins in test_oracle_*.py):
   K and M; the oracle's inertia count (Remark on inertia) between sampled
   consecutive eigenvalues equals the number of pairs below it (no pair missed
   or repeated); the 20 lowest against ARPACK shift-and-invert.
-* 3D 32^3 p=2 rIGA (blocks of 8), kappa = rho = 1, 100 lowest, FP64 and
-  mixed precision: every eigenvalue against the exact discrete spectrum of
+* 3D 32^3 p=2 rIGA (blocks of 8) and IGA, kappa = rho = 1, 100 lowest, FP64
+  and mixed precision: every eigenvalue against the exact discrete spectrum of
   Kronecker sums (Eq. 2Dmatrix and its 3D analogue), compared as a sorted
   multiset (the 100th cuts a six-fold cluster), residuals with the
   oracle's Kronecker K and M.
@@ -93,9 +93,12 @@ def _kron_spectrum(dim, ne, p, s, count):
 
 
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
-def test_3d_32_p2_riga8_full_size(precision):
+@pytest.mark.parametrize("refined", [True, False], ids=["riga8", "iga"])
+def test_3d_32_p2_full_size(refined, precision):
+    """IGA in mixed precision stalls with two refinement steps per solve and
+    needs the solver's escalation to finish."""
     riga = _riga()
-    w = workloads.c3(True)
+    w = workloads.c3(refined)
     _say("full size", w.name, "precision", precision)
     pr = riga.assemble(w.dim, w.ne, w.p, w.s)
     lam, U, res, st = pr.eigs(w.nev, precision=precision)
