@@ -11,8 +11,8 @@
 //     r_T = b_T + (the extend-add of every lower front's update entries that
 //           lands on a variable of T)
 // the top part of a sweep is three launches:
-//     forward   y_T = L_TT^{-1} r_T                 (rows of L_TT^{-1})
-//     backward  x_T = L_TT^{-T} D_TT^{-1} y_T       (columns of L_TT^{-1})
+//     forward   w_T = D_TT^{-1} L_TT^{-1} r_T       (rows of D_TT^{-1} L_TT^{-1})
+//     backward  x_T = L_TT^{-T} w_T                 (columns of L_TT^{-1})
 // after which the lower levels continue as before, reading x_T through
 // their update rows.  This extends the per-front partitioned inverse
 // H = [I; L21] L11^{-1} over several tree levels (a partitioned inverse of
@@ -28,7 +28,8 @@
 //     X_P  = L11^{-1}(P) R_FS         -> rows of P in L_TT^{-1}(:, F)
 //     R_CB = R_CB - (L21 L11^{-1})(P) R_FS   -> passed to P's parent
 // with P's partitioned inverse.  Every (P, F) pair of one height is one
-// launch of 64 x 64 output tiles on the FP64 matrix units.
+// launch of 64 x 64 output tiles on the FP64 matrix units; a last launch
+// folds D_TT^{-1} (1x1 and 2x2 blocks) into the row copy.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -279,7 +280,7 @@ __global__ void top_rhs_kernel(const int32_t* __restrict__ tdof, const int32_t* 
   r[j] = v;
 }
 
-// y_T = L_TT^{-1} r_T by rows: workgroups of 1024 threads, tpr threads per
+// w_T = D^{-1} L_TT^{-1} r_T by rows: workgroups of 1024 threads, tpr threads per
 // row (16, 64, 256 or 1024 by the row's length), each summing every tpr-th
 // entry of the row's segment, then a reduction in a fixed order.
 constexpr int TOP_FWD_THREADS = 1024;
@@ -330,17 +331,15 @@ __global__ void __launch_bounds__(TOP_FWD_THREADS) top_fwd_kernel(const TopRowUn
   }
 }
 
-// x_T = L_TT^{-T} D^{-1} y_T by columns: the workgroup gathers w = D^{-1} y
-// over the stacked rows of its front into LDS (w_a = c0 y_a + c+ y_{a+1} +
-// c- y_{a-1}, coefficients of D^{-1} formed once per factorisation), then
-// each wave forms one column's dot product.  The column's first loads are
-// issued before the gather.
+// x_T = L_TT^{-T} w_T by columns (w = D^{-1} y from the forward sweep, whose
+// rows carry D^{-1}): the workgroup gathers w over the stacked rows of its
+// front into LDS, then each wave forms one column's dot product.  The
+// column's first loads are issued before the gather.
 template <class T>
 __global__ void __launch_bounds__(256) top_bwd_kernel(const TopColUnit* __restrict__ units,
                                                       const TopFront* __restrict__ fronts,
                                                       const TopAnc* __restrict__ anc, const T* __restrict__ L,
-                                                      const double* __restrict__ y,
-                                                      const double* __restrict__ dc, int nT,
+                                                      const double* __restrict__ w,
                                                       const int32_t* __restrict__ piv_dof, double* x) {
   extern __shared__ double v[];
   __shared__ TopAnc al[TOP_MAX_ANC];
@@ -356,30 +355,22 @@ __global__ void __launch_bounds__(256) top_bwd_kernel(const TopColUnit* __restri
   for (int q = 0; q < 8; ++q) cv[q] = (col && lane + 64 * q < F.h) ? (double)c[lane + 64 * q] : 0.0;
   if (tid < F.n_anc) al[tid] = anc[F.anc_off + tid];
   __syncthreads();
-  // four rows per thread at a time: indices, then all their loads
+  // eight rows per thread at a time: indices, then all their loads
   int e = 0;
-  for (int i0 = tid; i0 < F.h; i0 += 4 * 256) {
-    int av[4];
+  for (int i0 = tid; i0 < F.h; i0 += 8 * 256) {
+    int av[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       const int i = min(i0 + 256 * q, F.h - 1);
       while (e + 1 < F.n_anc && al[e + 1].rowpos <= i) ++e;
       av[q] = al[e].tstart + (i - al[e].rowpos);
     }
-    double k0[4], k1[4], k2[4], y0[4], y1[4], y2[4];
+    double wv[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const double* k3 = dc + 3 * (int64_t)av[q];
-      k0[q] = k3[0];
-      k1[q] = k3[1];
-      k2[q] = k3[2];
-      y0[q] = y[av[q]];
-      y1[q] = y[min(av[q] + 1, nT - 1)];
-      y2[q] = y[max(av[q] - 1, 0)];
-    }
+    for (int q = 0; q < 8; ++q) wv[q] = w[av[q]];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (i0 + 256 * q < F.h) v[i0 + 256 * q] = k0[q] * y0[q] + k1[q] * y1[q] + k2[q] * y2[q];
+    for (int q = 0; q < 8; ++q)
+      if (i0 + 256 * q < F.h) v[i0 + 256 * q] = wv[q];
   }
   __syncthreads();
   if (!col) return;
@@ -425,6 +416,47 @@ __global__ void top_dinv_kernel(const int32_t* __restrict__ n_of_j, const int32_
   dc[3 * (int64_t)a + 2] = cm;
 }
 
+// Rows of D^{-1} L_TT^{-1} in place of those of L_TT^{-1} (per
+// factorisation, after the construction), so that the forward sweep yields
+// w = D^{-1} y directly.  One workgroup per row: a 1x1 pivot's row is
+// scaled; the first row a of a 2x2 block combines rows a and a + 1 into both
+// (L_TT^{-1} has a zero at (a, a + 1) and (a + 1, a) and a unit diagonal;
+// the column a + 1 of row a is its spare slot).  A spare slot not taken is
+// cleared.
+template <class T>
+__global__ void __launch_bounds__(256) top_fold_kernel(const int32_t* __restrict__ n_of_j,
+                                                       const int32_t* __restrict__ piv_type,
+                                                       const double* __restrict__ dc,
+                                                       const int64_t* __restrict__ roff,
+                                                       const int32_t* __restrict__ rlo,
+                                                       const int32_t* __restrict__ rlen, T* trow) {
+  const int j = blockIdx.x;
+  const int ty = piv_type[n_of_j[j]];
+  const int len = j - rlo[j] + 1;                // entries up to the diagonal
+  const bool spare = rlen[j] > len;
+  T* a = trow + roff[j];
+  if (ty == 3) {  // second row of a 2x2 block: rewritten with the first
+    if (spare && threadIdx.x == 0) a[len] = (T)0.0;
+    return;
+  }
+  const double c0 = dc[3 * (int64_t)j];
+  if (ty == 1) {
+    for (int e = threadIdx.x; e < len; e += 256) a[e] = (T)(c0 * (double)a[e]);
+    if (spare && threadIdx.x == 0) a[len] = (T)0.0;
+    return;
+  }
+  // 2x2 block (j, j + 1): w_j = c0 y_j + cp y_{j+1}, w_{j+1} = cm' y_j + c0' y_{j+1}
+  const double cp = dc[3 * (int64_t)j + 1];
+  const double c0b = dc[3 * (int64_t)(j + 1)], cmb = dc[3 * (int64_t)(j + 1) + 2];
+  T* b = trow + roff[j + 1];
+  for (int e = threadIdx.x; e <= len; e += 256) {
+    const double va = e < len ? (double)a[e] : 0.0;  // L_TT^{-1}(j, j + 1) = 0
+    const double vb = (double)b[e];                  // L_TT^{-1}(j + 1, j + 1) = 1
+    a[e] = (T)(c0 * va + cp * vb);
+    b[e] = (T)(cmb * va + c0b * vb);
+  }
+}
+
 }  // namespace
 
 void setup_top(riga_problem* pr) {
@@ -456,7 +488,10 @@ void setup_top(riga_problem* pr) {
       const int j = tstart[F] + t;
       n_of_j[j] = an.f_start[F] + t;
       rlo[j] = sub_lo[F];
-      rlen[j] = j - sub_lo[F] + 1;
+      // one slot beyond the diagonal when the next pivot is in the same
+      // front: the first row of a 2x2 block takes its partner's column
+      // once D^{-1} is folded in
+      rlen[j] = j - sub_lo[F] + 1 + (t + 1 < an.f_k[F] ? 1 : 0);
       roff[j] = e_row;
       e_row += ((int64_t)rlen[j] + 15) & ~int64_t(15);
     }
@@ -655,6 +690,9 @@ void build_top(riga_problem* pr, Factor& F, const T* h, T* trow, T* tcol, hipStr
                                                         F.tcb.p, trow, tcol);
     HIPCHECK(hipGetLastError());
   }
+  top_fold_kernel<T><<<TD.nT, 256, 0, s>>>(TD.n_of_j.p, F.piv_type.p, F.tdc.p, TD.roff.p, TD.rlo.p,
+                                           TD.rlen.p, trow);
+  HIPCHECK(hipGetLastError());
 }
 
 template <class T>
@@ -666,7 +704,7 @@ void sweep_top(riga_problem* pr, const Factor& F, const T* trow, const T* tcol, 
   top_fwd_kernel<T><<<TD.n_fwd, TOP_FWD_THREADS, 0, s>>>(TD.fwd_units.p, TD.roff.p, TD.rlo.p, TD.rlen.p,
                                                          trow, F.top_r.p, F.top_y.p);
   top_bwd_kernel<T><<<TD.n_bwd, 256, (size_t)TD.max_h * sizeof(double), s>>>(
-      TD.bwd_units.p, TD.fronts.p, TD.anc.p, tcol, F.top_y.p, F.tdc.p, TD.nT, F.piv_dof.p, x);
+      TD.bwd_units.p, TD.fronts.p, TD.anc.p, tcol, F.top_y.p, F.piv_dof.p, x);
   HIPCHECK(hipGetLastError());
 }
 

@@ -196,7 +196,7 @@ struct Factor {
   DBuf<double> tcb;                    // top block construction blocks [e_cb]
   // sweep scratch: sweeps with this factorisation run one at a time
   DBuf<double> cbvec, fwd;             // update vectors [cb_size], forward z [N]
-  DBuf<double> top_r, top_y;           // top block right-hand side and y [nT]
+  DBuf<double> top_r, top_y;           // top block right-hand side and w = D^{-1} y [nT]
   bool factored = false;
   int precision = 0;
   double sigma = 0.0;
