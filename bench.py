@@ -348,6 +348,99 @@ def cpu_baseline():
                       "pairs; %.1f s" % (w.name, k, dt)}, lam
 
 
+# Separator-spacing study (the blocksize study of Sec. 6: total time and the
+# times of the costly operations against the macroelement size BS = 2^(s-l),
+# l = 0 ... s).  kappa = rho = 1 (the Laplace problem of the study); FP64.
+SPACING_GRID = {2: (256, (2, 3, 4, 5), (256, 128, 64, 32, 16, 8, 4, 2, 1), 200),
+                3: (32, (2, 3), (32, 16, 8, 4, 2, 1), 100)}
+SPACING_MAX_FRONT = 6000   # larger fronts are left out of the sweep
+SPACING_MAX_DOF = 2000000
+
+
+def time_spmv(pr, reps, torch):
+    """Average duration of y = M x on the library's default stream."""
+    x = torch.randn(pr.n_dof, dtype=torch.float64, device="cuda")
+    pr.spmv(1, x)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        pr.spmv(1, x)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def spacing_sweep(riga, torch, out_path):
+    """One JSON line per (dim, p, BS): whole-solve wall time, operation
+    counts, and the event-timed cost of one factorisation, one sweep pair
+    and one M product; BS = ne is IGA (no separators)."""
+    fout = open(out_path, "w") if out_path else None
+    for dim in (2, 3):
+        ne, degrees, sizes, nev = SPACING_GRID[dim]
+        for p in degrees:
+            for bs in sizes:
+                s = 0 if bs >= ne else bs
+                rec = {"dim": dim, "ne": ne, "p": p, "bs": bs, "sep_spacing": s, "nev": nev}
+                an = riga.analyze(dim, ne, p, s)
+                inf = an.info
+                rec.update(n_dof=inf["n_dof"], max_front=inf["max_front"], nnz_l=inf["nnz_l"],
+                           flops_fact=inf["flops_fact"])
+                del an
+                if inf["max_front"] > SPACING_MAX_FRONT or inf["n_dof"] > SPACING_MAX_DOF:
+                    rec["skipped"] = "front or size above the sweep's limits"
+                else:
+                    try:
+                        pr = riga.assemble(dim, ne, p, s)
+                        wall, lam, U, res, st = timed_eigs(pr, nev, riga.RIGA_FP64, torch)
+                        del U
+                        sigma_mid = 0.5 * (lam[nev // 2] + lam[nev // 2 + 1])
+                        t_fb, t_fact = time_solves(pr, sigma_mid, riga.RIGA_FP64, 10, torch)
+                        t_mv = time_spmv(pr, 20, torch)
+                        rec.update(wall=wall, rate=nev / wall, max_res=float(max(res)),
+                                   n_fact=st["n_fact"], n_fb=st["n_fb"], n_mv=st["n_mv"],
+                                   n_shift=st["n_shift"], t_fact=t_fact, t_fb=t_fb, t_mv=t_mv,
+                                   T_fact=st["n_fact"] * t_fact, T_fb=st["n_fb"] * t_fb,
+                                   T_mv=st["n_mv"] * t_mv)
+                        del pr
+                    except riga.RigaError as e:
+                        rec["error"] = str(e)
+                    torch.cuda.empty_cache()
+                line = json.dumps(rec)
+                print(line, flush=True)
+                if fout:
+                    fout.write(line + "\n")
+                    fout.flush()
+    if fout:
+        fout.close()
+
+
+def spacing_summary(path):
+    """Markdown tables of a spacing sweep's JSON lines."""
+    recs = [json.loads(l) for l in open(path) if l.strip()]
+    for dim in (2, 3):
+        rs = [r for r in recs if r["dim"] == dim]
+        if not rs:
+            continue
+        print("\n### %dD, %d^%d elements, %d lowest eigenpairs\n" % (dim, rs[0]["ne"], dim, rs[0]["nev"]))
+        print("| p | BS | N | max front | nnz(L) | eigenpairs/s | N_fa | N_fb | N_mv | "
+              "t_fa ms | t_fb us | t_mv us | T_fa s | T_fb s | T_mv s | wall s |")
+        print("|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|")
+        for r in rs:
+            bs = "%d (IGA)" % r["bs"] if r["sep_spacing"] == 0 else str(r["bs"])
+            head = "| %d | %s | %d | %d | %.1fM |" % (r["p"], bs, r["n_dof"], r["max_front"], r["nnz_l"] / 1e6)
+            if "wall" not in r:
+                print(head + " %s |" % r.get("skipped", r.get("error")) + " |" * 10)
+                continue
+            print(head + " %.0f | %d | %d | %d | %.2f | %.0f | %.1f | %.3f | %.3f | %.3f | %.3f |" % (
+                r["rate"], r["n_fact"], r["n_fb"], r["n_mv"], r["t_fact"] * 1e3, r["t_fb"] * 1e6,
+                r["t_mv"] * 1e6, r["T_fact"], r["T_fb"], r["T_mv"], r["wall"]))
+        print("\nFastest BS per degree (whole solve): " + ", ".join(
+            "p=%d: %s" % (p, min((r for r in rs if r["p"] == p and "wall" in r), key=lambda r: r["wall"])["bs"])
+            for p in sorted({r["p"] for r in rs if "wall" in r})))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -363,7 +456,14 @@ def main():
                     help="summarise two rocprofv3 counter runs into profiles/fb_traffic.json and exit")
     ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_CSV", "STATS_CSV"),
                     help="print a markdown summary of a rocprofv3 kernel trace and exit")
+    ap.add_argument("--spacing-sweep", metavar="OUT_JSONL", nargs="?", const="",
+                    help="time the solve over separator spacings (2D 256^2, 3D 32^3) and exit")
+    ap.add_argument("--spacing-summary", metavar="JSONL",
+                    help="print markdown tables of a spacing sweep and exit")
     args = ap.parse_args()
+    if args.spacing_summary:
+        spacing_summary(args.spacing_summary)
+        return
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)
         return
@@ -385,6 +485,9 @@ def main():
         sys.exit(1)
     riga.lib()
     torch.cuda.set_device(0)
+    if args.spacing_sweep is not None:
+        spacing_sweep(riga, torch, args.spacing_sweep)
+        return
     if args.calibrate_copy:
         calibrate_copy(torch)
 
