@@ -20,6 +20,8 @@ arXiv 2009.08167, that it follows):
 * ``eigen``    -- the generalized eigenproblem (Eq. GHEP): dense
   Cholesky-reduced solve (Sec. 4.1), sparse shift-and-invert solve (Eq.
   ST_GHEP), inertia counts (Remark on inertia), residuals, normalisation.
+* ``accuracy`` -- EVerr, EFerr_L2, EFerr_E against the exact eigenpairs
+  (Eqs. exact, norms, eigerrors; diagonal modes as in Sec. 7).
 * ``grad``     -- adjoint eigenvalue gradient with respect to per-element
   coefficients (not in the paper: first-order perturbation theory of a
   simple eigenpair of a symmetric pencil).
