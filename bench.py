@@ -441,6 +441,84 @@ def spacing_summary(path):
             for p in sorted({r["p"] for r in rs if "wall" in r})))
 
 
+# Accuracy study (Sec. 7, Eq. eigerrors): 2D 64^2, p = 2..5, IGA against rIGA
+# of several macroelement sizes, the first N0 = N_IGA eigenpairs of each;
+# EVerr over all of them against the sorted exact spectrum, EFerr_L2 and
+# EFerr_E of the diagonal modes.  kappa = rho = 1, FP64.
+ACCURACY_NE = 64
+ACCURACY_DEGREES = (2, 3, 4, 5)
+ACCURACY_SPACINGS = (0, 16, 8, 4)
+
+
+def accuracy_study(riga, torch, out_path):
+    import numpy as np
+    fout = open(out_path, "w") if out_path else None
+    ne = ACCURACY_NE
+    for p in ACCURACY_DEGREES:
+        n_iga = (ne + p - 2) ** 2
+        for s in ACCURACY_SPACINGS:
+            pr = riga.assemble(2, ne, p, s)
+            t0 = time.perf_counter()
+            lam, U, res, st = pr.eigs(n_iga, allow_partial=True)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            n = len(lam)
+            exact = riga.exact_eigenvalues(2, n)
+            ev = (lam - exact) / exact
+            # diagonal modes (i, i) whose exact eigenvalue is among the first n
+            top = exact[-1] / math.pi ** 2
+            nd = int(math.floor(math.sqrt(top / 2.0)))
+            modes = np.array([[i, i] for i in range(1, nd + 1)], dtype=np.int32)
+            me = pr.mode_errors(lam, U, modes)
+            rec = {"ne": ne, "p": p, "sep_spacing": s, "n_dof": pr.n_dof, "n0": n_iga, "found": n,
+                   "wall": wall, "max_res": float(max(res)), "n_fb": st["n_fb"],
+                   "everr": ev.tolist(),
+                   "modes": modes[:, 0].tolist(), "mode_match": me["match"].tolist(),
+                   "mode_overlap": me["overlap"].tolist(), "mode_ev": me["ev"].tolist(),
+                   "ef_l2": me["l2"].tolist(), "ef_e": me["energy"].tolist()}
+            log("accuracy p=%d s=%d: %d of %d pairs in %.2f s, max EVerr %.3e, %d diagonal modes"
+                % (p, s, n, n_iga, wall, ev.max(), nd))
+            line = json.dumps(rec)
+            print(json.dumps({k: rec[k] for k in ("ne", "p", "sep_spacing", "n_dof", "found", "wall")}),
+                  flush=True)
+            if fout:
+                fout.write(line + "\n")
+                fout.flush()
+            del pr, U
+            torch.cuda.empty_cache()
+    if fout:
+        fout.close()
+
+
+def accuracy_summary(path):
+    """Markdown tables of an accuracy study's JSON lines."""
+    import numpy as np
+    recs = [json.loads(l) for l in open(path) if l.strip()]
+    fr = (0.1, 0.25, 0.5, 0.75, 0.9, 1.0)
+    print("\n### EVerr against the sorted exact spectrum, at mode number i / N0\n")
+    print("| p | discretisation | N | pairs | " + " | ".join("i/N0=%.2g" % f for f in fr) + " | max |")
+    print("|---|---|---|---|" + "---|" * (len(fr) + 1))
+    for r in recs:
+        ev = np.array(r["everr"])
+        name = "IGA" if r["sep_spacing"] == 0 else "rIGA BS=%d" % r["sep_spacing"]
+        cells = " | ".join("%.2e" % ev[max(0, int(round(f * r["n0"])) - 1)] if int(round(f * r["n0"])) <= len(ev)
+                           else "-" for f in fr)
+        print("| %d | %s | %d | %d | %s | %.2e |" % (r["p"], name, r["n_dof"], r["found"], cells, ev.max()))
+    print("\n### Diagonal modes (i, i): EFerr_L2 / EFerr_E\n")
+    picks = (1, 4, 8, 16, 24, 32, 40)
+    print("| p | discretisation | " + " | ".join("i=%d" % i for i in picks) + " |")
+    print("|---|---|" + "---|" * len(picks))
+    for r in recs:
+        name = "IGA" if r["sep_spacing"] == 0 else "rIGA BS=%d" % r["sep_spacing"]
+        cells = []
+        for i in picks:
+            if i <= len(r["modes"]):
+                cells.append("%.1e / %.1e" % (r["ef_l2"][i - 1], r["ef_e"][i - 1]))
+            else:
+                cells.append("-")
+        print("| %d | %s | %s |" % (r["p"], name, " | ".join(cells)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -460,7 +538,14 @@ def main():
                     help="time the solve over separator spacings (2D 256^2, 3D 32^3) and exit")
     ap.add_argument("--spacing-summary", metavar="JSONL",
                     help="print markdown tables of a spacing sweep and exit")
+    ap.add_argument("--accuracy-study", metavar="OUT_JSONL", nargs="?", const="",
+                    help="EVerr / EFerr of IGA and rIGA on 2D 64^2 (first N_IGA pairs) and exit")
+    ap.add_argument("--accuracy-summary", metavar="JSONL",
+                    help="print markdown tables of an accuracy study and exit")
     args = ap.parse_args()
+    if args.accuracy_summary:
+        accuracy_summary(args.accuracy_summary)
+        return
     if args.spacing_summary:
         spacing_summary(args.spacing_summary)
         return
@@ -487,6 +572,9 @@ def main():
     torch.cuda.set_device(0)
     if args.spacing_sweep is not None:
         spacing_sweep(riga, torch, args.spacing_sweep)
+        return
+    if args.accuracy_study is not None:
+        accuracy_study(riga, torch, args.accuracy_study)
         return
     if args.calibrate_copy:
         calibrate_copy(torch)

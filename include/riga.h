@@ -249,6 +249,35 @@ riga_status riga_eig_grad(riga_problem* pr, int32_t k, const double* evals_host,
                           const double* evecs_dev, const double* w_host, double* dkappa_dev,
                           double* drho_dev, void* stream);
 
+/* riga_mode_errors: eigenfunction errors of computed eigenpairs against the
+ * exact eigenpairs of the Dirichlet Laplacian on the unit square or cube
+ * (Eq. exact: lambda_e = pi^2 (i^2 + j^2 [+ k^2]), u_e = 2^(d/2) prod
+ * sin(i pi x)), as the accuracy study of Sec. 7 uses them (Eqs. norms,
+ * eigerrors).  Meaningful for a problem assembled with kappa = rho = 1.
+ * n_vec computed pairs: lam_host [n_vec] (host), U_dev [n_vec][n_dof]
+ * device FP64, M-normalised (the layout riga_eigs returns).  modes_host
+ * [n_modes][dim] 1-based mode indices (Sec. 7 uses the diagonal ones).
+ * nquad: Gauss points per direction and element for the integrals (0 ->
+ * p + 6, at most 16).  Outputs per mode, host [n_modes]:
+ *   match    index of the computed eigenvector with the largest |(u_h, u_e)|
+ *   overlap  that (u_h, u_e) (L2 inner product)
+ *   ef_l2    EFerr_L2 = ||u_h - s u_e||^2, s = +-1 giving the smaller value
+ *   ef_e     EFerr_E = a(u_h - s u_e, u_h - s u_e) / lambda_e (integrated
+ *            directly; equals EVerr + EFerr_L2 for a Galerkin pair)
+ *   ev       (lam_host[match] - lambda_e) / lambda_e
+ * Runs on `stream` (U_dev must be ready there) and returns when the results
+ * are on the host.  RIGA_EINVAL on a mode index below 1 or nquad above 16. */
+riga_status riga_mode_errors(riga_problem* pr, int32_t n_vec, const double* lam_host,
+                             const double* U_dev, int32_t n_modes, const int32_t* modes_host,
+                             int32_t nquad, int32_t* match, double* overlap, double* ef_l2,
+                             double* ef_e, double* ev, void* stream);
+
+/* riga_exact_eigenvalues: the `count` smallest exact eigenvalues of the
+ * Dirichlet Laplacian on the unit square (dim 2) or cube (dim 3), Eq. exact,
+ * ascending with multiplicity, into out_host [count].  Host only; EVerr of
+ * the n-th computed eigenvalue is (lambda_h,n - out_host[n]) / out_host[n]. */
+riga_status riga_exact_eigenvalues(int32_t dim, int32_t count, double* out_host);
+
 void riga_destroy(riga_problem* pr);
 const char* riga_status_string(riga_status s);
 const char* riga_last_error(void);

@@ -313,6 +313,29 @@ riga_status riga_eig_grad(riga_problem* pr, int32_t k, const double* evals, cons
   });
 }
 
+riga_status riga_mode_errors(riga_problem* pr, int32_t n_vec, const double* lam_host,
+                             const double* U_dev, int32_t n_modes, const int32_t* modes_host,
+                             int32_t nquad, int32_t* match, double* overlap, double* ef_l2,
+                             double* ef_e, double* ev, void* stream) {
+  return guarded([&]() -> riga_status {
+    if (!need_device(pr) || n_vec < 1 || n_modes < 1 || !lam_host || !U_dev || !modes_host || !match ||
+        !overlap || !ef_l2 || !ef_e || !ev || nquad < 0)
+      return fail(RIGA_EINVAL, "bad arguments");
+    riga::mode_errors(pr, n_vec, lam_host, U_dev, n_modes, modes_host, nquad, match, overlap, ef_l2,
+                      ef_e, ev, (hipStream_t)stream);
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_exact_eigenvalues(int32_t dim, int32_t count, double* out_host) {
+  return guarded([&]() -> riga_status {
+    if ((dim != 2 && dim != 3) || count < 1 || count > (1 << 24) || !out_host)
+      return fail(RIGA_EINVAL, "bad arguments");
+    riga::exact_eigenvalues(dim, count, out_host);
+    return RIGA_OK;
+  });
+}
+
 void riga_destroy(riga_problem* pr) {
   if (!pr) return;
   try {

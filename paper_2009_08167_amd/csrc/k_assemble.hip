@@ -245,27 +245,22 @@ __global__ void max_reduce_kernel(const double* x, int64_t n, double* out) {
 
 }  // namespace
 
-void launch_basis_tables(riga_problem* pr) {
+namespace {
+
+// Knot values and first functions per direction, and the Gauss rule of q
+// points, on the device; the tables (and, with ke1/me1, the 1D element
+// matrices) at those points.
+void basis_tables_at(riga_problem* pr, int q, double* val, double* der, double* ke1, double* me1) {
   const Analysis& an = pr->an;
-  const int dim = an.dim, p = an.p, q = an.nquad, np = p + 1;
+  const int dim = an.dim, p = an.p, np = p + 1;
   hipStream_t s = pr->stream;
-  // host-side constants: knot values, first functions, supports, Gauss rule
   std::vector<double> kvv;
   std::vector<int> kvoff(3, 0);
-  std::vector<int32_t> ff, fe, le;
-  int total_el = 0, total_fn = 0;
+  int total_el = 0;
   for (int d = 0; d < dim; ++d) {
     kvoff[d] = (int)kvv.size();
     for (int k : an.sp[d].kv) kvv.push_back((double)k / an.ne[d]);
-    pr->tab_off[d] = total_el;
-    pr->fn_off[d] = total_fn;
-    for (int e = 0; e < an.ne[d]; ++e) ff.push_back(an.sp[d].first_fn[e]);
-    for (int i = 0; i < an.sp[d].n; ++i) {
-      fe.push_back(an.sp[d].fe[i]);
-      le.push_back(an.sp[d].le[i]);
-    }
     total_el += an.ne[d];
-    total_fn += an.sp[d].n;
   }
   std::vector<double> gx, gw;
   gauss_legendre(q, gx, gw);
@@ -273,13 +268,6 @@ void launch_basis_tables(riga_problem* pr) {
   d_kv.upload(kvv, s);
   d_gx.upload(gx, s);
   d_gw.upload(gw, s);
-  pr->first_fn.upload(ff, s);
-  pr->fe.upload(fe, s);
-  pr->le.upload(le, s);
-  pr->tab_val.alloc((size_t)total_el * q * np, s);
-  pr->tab_der.alloc((size_t)total_el * q * np, s);
-  pr->ke1.alloc((size_t)total_el * np * np, s);
-  pr->me1.alloc((size_t)total_el * np * np, s);
   TabArgs a{};
   for (int d = 0; d < 3; ++d) {
     a.kv[d] = d < dim ? d_kv.p + kvoff[d] : nullptr;
@@ -292,17 +280,58 @@ void launch_basis_tables(riga_problem* pr) {
   a.q = q;
   a.gx = d_gx.p;
   a.gw = d_gw.p;
-  a.val = pr->tab_val.p;
-  a.der = pr->tab_der.p;
-  a.ke1 = pr->ke1.p;
-  a.me1 = pr->me1.p;
+  a.val = val;
+  a.der = der;
+  a.ke1 = ke1;
+  a.me1 = me1;
   const int n1 = total_el * q;
   basis_tables_kernel<<<(n1 + 127) / 128, 128, 0, s>>>(a);
   HIPCHECK(hipGetLastError());
-  const int n2 = total_el * np * np;
-  element_1d_kernel<<<(n2 + 127) / 128, 128, 0, s>>>(a, total_el);
-  HIPCHECK(hipGetLastError());
+  if (ke1) {
+    const int n2 = total_el * np * np;
+    element_1d_kernel<<<(n2 + 127) / 128, 128, 0, s>>>(a, total_el);
+    HIPCHECK(hipGetLastError());
+  }
   HIPCHECK(hipStreamSynchronize(s));  // d_kv/d_gx/d_gw are freed on return
+}
+
+}  // namespace
+
+void launch_basis_tables(riga_problem* pr) {
+  const Analysis& an = pr->an;
+  const int dim = an.dim, p = an.p, q = an.nquad, np = p + 1;
+  hipStream_t s = pr->stream;
+  // first functions and supports per direction
+  std::vector<int32_t> ff, fe, le;
+  int total_el = 0, total_fn = 0;
+  for (int d = 0; d < dim; ++d) {
+    pr->tab_off[d] = total_el;
+    pr->fn_off[d] = total_fn;
+    for (int e = 0; e < an.ne[d]; ++e) ff.push_back(an.sp[d].first_fn[e]);
+    for (int i = 0; i < an.sp[d].n; ++i) {
+      fe.push_back(an.sp[d].fe[i]);
+      le.push_back(an.sp[d].le[i]);
+    }
+    total_el += an.ne[d];
+    total_fn += an.sp[d].n;
+  }
+  pr->first_fn.upload(ff, s);
+  pr->fe.upload(fe, s);
+  pr->le.upload(le, s);
+  pr->tab_val.alloc((size_t)total_el * q * np, s);
+  pr->tab_der.alloc((size_t)total_el * q * np, s);
+  pr->ke1.alloc((size_t)total_el * np * np, s);
+  pr->me1.alloc((size_t)total_el * np * np, s);
+  basis_tables_at(pr, q, pr->tab_val.p, pr->tab_der.p, pr->ke1.p, pr->me1.p);
+}
+
+void basis_tables_q(riga_problem* pr, int q, DBuf<double>& val, DBuf<double>& der) {
+  const Analysis& an = pr->an;
+  int total_el = 0;
+  for (int d = 0; d < an.dim; ++d) total_el += an.ne[d];
+  val.alloc((size_t)total_el * q * (an.p + 1), pr->stream);
+  der.alloc((size_t)total_el * q * (an.p + 1), pr->stream);
+  basis_tables_at(pr, q, val.p, der.p, nullptr, nullptr);
 }
 
 void launch_assemble(riga_problem* pr) {

@@ -388,6 +388,14 @@ void launch_ritz_vectors(const double* alpha, const double* beta, int m, const d
                          const int32_t* sel, const int32_t* cl_start, int ncl, double* S,
                          hipStream_t s);
 
+// basis values and derivatives at a q-point Gauss rule per element and
+// direction (same layout as tab_val/tab_der); synchronises pr->stream
+void basis_tables_q(riga_problem* pr, int q, DBuf<double>& val, DBuf<double>& der);
+// eigenfunction errors against the exact Laplace modes (k_accuracy.hip)
+void mode_errors(riga_problem* pr, int n_vec, const double* lam, const double* U, int nm,
+                 const int32_t* modes, int nquad, int32_t* match, double* overlap, double* ef_l2,
+                 double* ef_e, double* ev, hipStream_t s);
+void exact_eigenvalues(int dim, int count, double* out);
 void launch_eig_grad(const riga_problem* pr, int k, const double* U, const double* lam_w_dev,
                      const double* w_dev, double* gk, double* gr, hipStream_t s);
 

@@ -22,7 +22,8 @@ RIGA_MAT_K, RIGA_MAT_M, RIGA_MAT_A = 0, 1, 2
 EXPORTED = ["riga_set_allocator", "riga_analyze", "riga_assemble", "riga_update_coefficients",
             "riga_problem_info",
             "riga_tree_export", "riga_get_matrices", "riga_spmv", "riga_factor", "riga_solve",
-            "riga_solve_multi", "riga_eigs", "riga_eigs_batched", "riga_eig_grad", "riga_destroy", "riga_status_string",
+            "riga_solve_multi", "riga_eigs", "riga_eigs_batched", "riga_eig_grad", "riga_mode_errors",
+            "riga_exact_eigenvalues", "riga_destroy", "riga_status_string",
             "riga_last_error"]
 
 
@@ -89,6 +90,8 @@ def lib():
         L.riga_eigs.argtypes = [P, C.POINTER(EigsOpts), C.POINTER(C.c_int32), P, P, P,
                                 C.POINTER(Stats)]
         L.riga_eig_grad.argtypes = [P, C.c_int32, P, P, P, P, P, P]
+        L.riga_mode_errors.argtypes = [P, C.c_int32, P, P, C.c_int32, P, C.c_int32, P, P, P, P, P, P]
+        L.riga_exact_eigenvalues.argtypes = [C.c_int32, C.c_int32, P]
         L.riga_eigs_batched.argtypes = [P, C.c_int32, C.POINTER(EigsOpts), C.c_int32,
                                         C.POINTER(C.c_int32), P, P, P, P]
         L.riga_destroy.argtypes = [P]
@@ -98,7 +101,8 @@ def lib():
         for name in ["riga_analyze", "riga_assemble", "riga_update_coefficients",
                      "riga_problem_info", "riga_tree_export",
                      "riga_get_matrices", "riga_spmv", "riga_factor", "riga_solve", "riga_solve_multi",
-                     "riga_eigs", "riga_eig_grad", "riga_set_allocator", "riga_eigs_batched"]:
+                     "riga_eigs", "riga_eig_grad", "riga_set_allocator", "riga_eigs_batched",
+                     "riga_mode_errors", "riga_exact_eigenvalues"]:
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -265,6 +269,38 @@ class Problem:
         _check(lib().riga_eig_grad(self._h, k, lam.ctypes.data, _ptr(Uc), w.ctypes.data,
                                    _ptr(gk), _ptr(gr), _stream(stream)))
         return gk, gr
+
+
+    def mode_errors(self, lam, U, modes, nquad=0, stream=None):
+        """Eigenfunction errors against the exact Laplace modes
+        (riga_mode_errors).  lam [n] ascending; U [n_dof, n] M-normalised
+        eigenvectors (as eigs returns them; a NumPy array is copied to the
+        device); modes [n_modes, dim], 1-based.  Returns a dict of arrays:
+        match, overlap, l2 (EFerr_L2), energy (EFerr_E), ev (EVerr)."""
+        import torch
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        if isinstance(U, np.ndarray):
+            U = torch.tensor(U, dtype=torch.float64, device=self.device)
+        Uc = U.T.contiguous()  # [n][n_dof]
+        modes = np.ascontiguousarray(np.atleast_2d(modes), dtype=np.int32)
+        nm = modes.shape[0]
+        out = {k: np.zeros(nm) for k in ("overlap", "l2", "energy", "ev")}
+        match = np.zeros(nm, dtype=np.int32)
+        _check(lib().riga_mode_errors(self._h, len(lam), lam.ctypes.data, _ptr(Uc), nm,
+                                      modes.ctypes.data, nquad, match.ctypes.data,
+                                      out["overlap"].ctypes.data, out["l2"].ctypes.data,
+                                      out["energy"].ctypes.data, out["ev"].ctypes.data,
+                                      _stream(stream)))
+        out["match"] = match.astype(np.int64)
+        return out
+
+
+def exact_eigenvalues(dim, count):
+    """The `count` smallest exact eigenvalues of the Dirichlet Laplacian on
+    the unit square/cube, ascending with multiplicity (riga_exact_eigenvalues)."""
+    out = np.zeros(count)
+    _check(lib().riga_exact_eigenvalues(dim, count, out.ctypes.data))
+    return out
 
 
 def _desc(dim, ne, p, s, kappa, rho, nquad, leaf_dofs, stream, keep):

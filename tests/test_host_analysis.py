@@ -156,3 +156,15 @@ def test_analysis_is_deterministic():
     b = riga.analyze(2, 40, 3, 8).tree()
     for k in a:
         assert np.array_equal(a[k], b[k])
+
+
+def test_exact_eigenvalues_host_enumeration_matches_oracle():
+    """riga_exact_eigenvalues (host code of the library) against the
+    oracle's enumeration of Eq. exact, 2D and 3D, with multiplicities."""
+    from oracle import accuracy
+    for dim, count in ((2, 1), (2, 37), (2, 5000), (3, 1), (3, 400)):
+        got = riga.exact_eigenvalues(dim, count)
+        ref = accuracy.exact_eigenvalues(dim, count)
+        assert np.array_equal(got, ref), (dim, count)
+    with pytest.raises(riga.RigaError):
+        riga.exact_eigenvalues(1, 5)
