@@ -519,6 +519,77 @@ def accuracy_summary(path):
         print("| %d | %s | %s |" % (r["p"], name, " | ".join(cells)))
 
 
+# Large N0 (the operation counts of Sec. 6's tables for N0 = 4096 eigenpairs
+# in 2D): per mesh, degree and method the solve's shifts, factorisations,
+# sweeps and products, the event-timed cost of one of each, and the average
+# time per eigenpair.  kappa = rho = 1, FP64, rIGA with BS = 16.
+LARGE_N0 = 4096
+LARGE_CASES = [(256, p) for p in (2, 3, 4, 5)] + [(512, p) for p in (2, 3, 4, 5)] + [(1024, 3)]
+
+
+def large_n0(riga, torch, out_path):
+    fout = open(out_path, "w") if out_path else None
+    for ne, p in LARGE_CASES:
+        for s in (0, 16):
+            rec = {"dim": 2, "ne": ne, "p": p, "sep_spacing": s, "n0": LARGE_N0}
+            try:
+                pr = riga.assemble(2, ne, p, s)
+                rec.update(n_dof=pr.n_dof, nnz_l=pr.info["nnz_l"], max_front=pr.info["max_front"])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                lam, U, res, st = pr.eigs(LARGE_N0)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                del U
+                torch.cuda.empty_cache()
+                sigma_mid = 0.5 * (lam[len(lam) // 2] + lam[len(lam) // 2 + 1])
+                t_fb, t_fact = time_solves(pr, sigma_mid, riga.RIGA_FP64, 10, torch)
+                t_mv = time_spmv(pr, 20, torch)
+                rec.update(wall=wall, t_av=wall / LARGE_N0, max_res=float(max(res)),
+                           n_shift=st["n_shift"], n_fact=st["n_fact"], n_fb=st["n_fb"], n_mv=st["n_mv"],
+                           t_fact=t_fact, t_fb=t_fb, t_mv=t_mv)
+                del pr
+            except riga.RigaError as e:
+                rec["error"] = str(e)
+            torch.cuda.empty_cache()
+            line = json.dumps(rec)
+            print(line, flush=True)
+            if fout:
+                fout.write(line + "\n")
+                fout.flush()
+    if fout:
+        fout.close()
+
+
+def large_n0_summary(path):
+    """Markdown table in the shape of the paper's large-N0 tables: per
+    operation its count and its time per eigenpair (count x event-timed
+    cost / N0), and the measured average time per eigenpair."""
+    recs = [json.loads(l) for l in open(path) if l.strip()]
+    print("| mesh | p | method | N | N_sh | N_fa | t_fa/N0 ms | N_fb | t_fb/N0 ms | N_mv | t_mv/N0 ms | "
+          "T_av ms (measured) | rIGA gain |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|---|---|")
+    by = {}
+    for r in recs:
+        by[(r["ne"], r["p"], r["sep_spacing"])] = r
+    for r in recs:
+        name = "IGA" if r["sep_spacing"] == 0 else "rIGA"
+        head = "| %d^2 | %d | %s |" % (r["ne"], r["p"], name)
+        if "wall" not in r:
+            print(head + " %s |" % r.get("error", "") + " |" * 9)
+            continue
+        n0 = r["n0"]
+        gain = ""
+        if r["sep_spacing"] != 0:
+            iga = by.get((r["ne"], r["p"], 0))
+            if iga and "wall" in iga:
+                gain = "%.2f" % (iga["wall"] / r["wall"])
+        print(head + " %d | %d | %d | %.4f | %d | %.4f | %d | %.4f | %.4f | %s |" % (
+            r["n_dof"], r["n_shift"], r["n_fact"], r["n_fact"] * r["t_fact"] / n0 * 1e3,
+            r["n_fb"], r["n_fb"] * r["t_fb"] / n0 * 1e3, r["n_mv"], r["n_mv"] * r["t_mv"] / n0 * 1e3,
+            r["t_av"] * 1e3, gain))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -542,7 +613,14 @@ def main():
                     help="EVerr / EFerr of IGA and rIGA on 2D 64^2 (first N_IGA pairs) and exit")
     ap.add_argument("--accuracy-summary", metavar="JSONL",
                     help="print markdown tables of an accuracy study and exit")
+    ap.add_argument("--large-n0", metavar="OUT_JSONL", nargs="?", const="",
+                    help="4096 lowest eigenpairs of 2D 256^2-1024^2 IGA and rIGA, operation counts, and exit")
+    ap.add_argument("--large-n0-summary", metavar="JSONL",
+                    help="print the markdown table of a --large-n0 run and exit")
     args = ap.parse_args()
+    if args.large_n0_summary:
+        large_n0_summary(args.large_n0_summary)
+        return
     if args.accuracy_summary:
         accuracy_summary(args.accuracy_summary)
         return
@@ -575,6 +653,9 @@ def main():
         return
     if args.accuracy_study is not None:
         accuracy_study(riga, torch, args.accuracy_study)
+        return
+    if args.large_n0 is not None:
+        large_n0(riga, torch, args.large_n0)
         return
     if args.calibrate_copy:
         calibrate_copy(torch)

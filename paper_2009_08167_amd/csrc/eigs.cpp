@@ -38,6 +38,19 @@ using clk = std::chrono::steady_clock;
 // refinement steps per mixed-precision solve after escalation (2 at start)
 constexpr int MAX_IR_ESCALATED = 8;
 
+// refinement steps per FP64 solve after escalation (none at start)
+constexpr int MAX_IR_FP64 = 2;
+
+// deflation window, in intervals between consecutive shifts below the shift
+constexpr double DEFLATE_SPACINGS = 4.0;
+
+// RIGA_DEFLATE_ALL=1 projects every Lanczos vector against all locked pairs
+// (no window); read per call
+bool deflate_window_on() {
+  const char* v = std::getenv("RIGA_DEFLATE_ALL");
+  return !(v && *v && *v != '0');
+}
+
 // RIGA_LOG=1 prints one line per Lanczos run and per shift to stderr.
 bool log_on() {
   static const bool on = [] {
@@ -67,6 +80,7 @@ struct Solver {
   int max_restarts;
   int precision;
   int max_ir;
+  int max_ir_fp64 = 0;   // refinement steps of an FP64 solve (raised on a stall)
   int dim = 2;           // spatial dimension (eigenvalue-count growth)
   int64_t nu_lo = 0;     // eigenvalues below lo
   DBuf<double> B, W, x, y, c1, c2, partial, dotp, alpha, beta, scal;
@@ -79,6 +93,11 @@ struct Solver {
   DBuf<double> ir_r, ir_d;
   std::vector<Locked> locked;
   int nl = 0;            // locked columns
+  // deflation window of the current run: the locked columns from c_win on
+  // hold every locked pair with eigenvalue >= win_lo; only they are
+  // projected out, and only candidates >= win_lo are locked
+  int c_win = 0;
+  double win_lo = -INFINITY;
   int n_evicted = 0;
   uint64_t run_id = 0;
   riga_stats st{};
@@ -116,10 +135,8 @@ struct Solver {
     res3.alloc(3 * (size_t)umax, s);  // u^T M u, ||K u - lam M u||^2, ||u||^2
     lam.alloc(umax, s);
     rpart.alloc(residual_partials(N, umax), s);
-    if (precision == RIGA_MIXED) {
-      ir_r.alloc(N, s);
-      ir_d.alloc(N, s);
-    }
+    ir_r.alloc(N, s);
+    ir_d.alloc(N, s);
   }
 
   SolveCtx* ctx = nullptr;  // the solve's factorisations and sweep scratch
@@ -141,13 +158,15 @@ struct Solver {
     count_factor(cur());
   }
 
-  // x = A^{-1} b (FP64), or FP32 solve + fixed FP64 refinement (mixed)
+  // x = A^{-1} b (FP64), or FP32 solve + FP64 refinement (mixed); FP64
+  // solves are refined too once a stall has raised max_ir_fp64
   void apply_inverse(const double* b, double* out) {
     const Factor& F = cur();
     solve_fb(pr, F, b, out, s);
     st.n_fb++;
-    if (precision == RIGA_MIXED) {
-      for (int it = 0; it < max_ir; ++it) {
+    const int nir = precision == RIGA_MIXED ? max_ir : max_ir_fp64;
+    {
+      for (int it = 0; it < nir; ++it) {
         // r = b - A x
         launch_spmv(pr, F.av.p, out, ir_r.p, nullptr, s);
         st.n_mv++;
@@ -184,6 +203,11 @@ struct Solver {
     HIPCHECK(hipMemsetAsync(flag.p, 0, 4 * sizeof(int32_t), s));
     if (init) launch_copy(x.p, init, N, s);
     else launch_fill_random(x.p, N, seed, ++run_id, s);
+    // against every locked pair, window or not: a start vector with
+    // components along the pairs below the window would pass them into the
+    // Ritz vectors (inside a multiple eigenvalue's eigenspace no residual
+    // shows them), while the steps only keep the Krylov space clear of the
+    // pairs near the shift, whose components the operator amplifies
     if (nl > 0) {
       project_out(nl, c1.p);
       project_out(nl, c2.p);
@@ -196,13 +220,13 @@ struct Solver {
     const int col = nl + j;
     apply_inverse(Wc(col), x.p);
     auto a = clk::now();
-    // Classical Gram-Schmidt against [U_locked | V], then a second pass
-    // against V only: x = (K - sigma M)^{-1} M v_j starts M-orthogonal to the
-    // locked eigenvectors up to rounding and their residuals, so the first
-    // pass removes those components without cancellation; the cancellation
-    // the second pass repairs comes from the large components along v_j and
-    // v_{j-1}.
-    project_out(col + 1, c1.p);
+    // Classical Gram-Schmidt against [U_locked (window) | V], then a second
+    // pass against V only: x = (K - sigma M)^{-1} M v_j starts M-orthogonal
+    // to the locked eigenvectors up to rounding and their residuals, so the
+    // first pass removes those components without cancellation; the
+    // cancellation the second pass repairs comes from the large components
+    // along v_j and v_{j-1}.
+    project_out(col + 1, c1.p, c_win);
     project_out(col + 1, c2.p, nl, alpha.p + j, c1.p + col);
     normalize_into(col + 1, beta.p + j + 1);
     st.t_orth += secs(a, clk::now());
@@ -312,7 +336,9 @@ struct Solver {
       std::vector<int> cand;
       for (int i = 0; i < nw; ++i) {
         const double res = std::sqrt(h_rn2[i]) / (pr->normK1 * std::sqrt(h_un2[i]));
-        if (res <= tol && h_lam[i] >= lo && h_lam[i] < hi) cand.push_back(i);
+        if (res <= tol && h_lam[i] >= lo && h_lam[i] >= win_lo && h_lam[i] < hi) cand.push_back(i);
+        else if (std::getenv("RIGA_LOG_LOCKS"))
+          std::fprintf(stderr, "[riga] not locked lambda=%.12g res=%.3e sigma=%.6g\n", h_lam[i], res, sigma);
       }
       std::sort(cand.begin(), cand.end(), [&](int a, int b) { return h_lam[a] < h_lam[b]; });
       if (*have_restart) launch_copy(y.p, Ub.p + (int64_t)nw * N, N, s);
@@ -334,6 +360,8 @@ struct Solver {
           locked[worst] = Locked{h_lam[i], res, col};
           ++n_evicted;
         }
+        if (std::getenv("RIGA_LOG_LOCKS"))
+          std::fprintf(stderr, "[riga] lock lambda=%.12g col=%d sigma=%.6g\n", h_lam[i], col, sigma);
         const auto it = std::find(dst_col.begin(), dst_col.end(), col);
         if (it != dst_col.end()) src_col[it - dst_col.begin()] = i;
         else {
@@ -352,6 +380,25 @@ struct Solver {
     (void)sigma;
     st.t_ritz += secs(a, clk::now());
     return nlocked;
+  }
+
+  // Deflation window of the Lanczos steps for runs at sigma when every
+  // eigenvalue below `verified` (the previous shift) is locked: the locked
+  // pairs above sigma - DEFLATE_SPACINGS (sigma - verified), i.e. those of
+  // the last few shift intervals and all above sigma (the clusters that
+  // straddle shifts).  A locked pair further down has |1 / (lambda - sigma)|
+  // below 1 / DEFLATE_SPACINGS of every missing pair's, so the operator does
+  // not amplify its components (the start vector is cleared of all locked
+  // pairs); were one to converge, it lies below win_lo and is not locked
+  // again.
+  void set_window(double sigma, double verified) {
+    win_lo = -INFINITY;
+    c_win = 0;
+    if (!deflate_window_on() || !(sigma > verified)) return;
+    win_lo = sigma - DEFLATE_SPACINGS * (sigma - verified);
+    c_win = nl;
+    for (auto& L : locked)
+      if (L.lam >= win_lo) c_win = std::min(c_win, L.col);
   }
 
   int count_locked(double a, double b) const {
@@ -411,8 +458,9 @@ struct Solver {
     *n_new = lock_pairs(r, sigma, Sv, which, rest, r.theta, &have_restart);
     restart_valid = have_restart && r.beta_m != 0.0;
     if (log_on())
-      std::fprintf(stderr, "[riga] run sigma=%.6g steps=%d need=(%d,%d) converged=%zu locked=%d total_locked=%d\n",
-                   sigma, j, need_below, need_above, which.size(), *n_new, nl);
+      std::fprintf(stderr, "[riga] run sigma=%.6g steps=%d need=(%d,%d) converged=%zu locked=%d total_locked=%d "
+                   "window=[%.6g, from column %d]\n",
+                   sigma, j, need_below, need_above, which.size(), *n_new, nl, win_lo, c_win);
     return r;
   }
   bool restart_valid = false;
@@ -708,14 +756,24 @@ void run_slice(Slice& S) {
               predict_from_ritz(sv, r, sigma, lo, hi_now, per_above, (int)target, pr->an.dim);
           if (std::isfinite(guess) && guess > sigma) la.start(guess, sv.precision, sv.s);
         };
+      sv.set_window(sigma, verified);
       last = sv.run(sigma, need_below, need_above, runs == 0 ? init : nullptr, &n_new, hook);
-      // mixed precision: a run that locks under an eighth of what is missing
-      // has reached the accuracy the refined FP32 solve allows (Ritz values
-      // converge, their FP64 residuals do not); refine more from here on
-      if (sv.precision == RIGA_MIXED && sv.max_ir < MAX_IR_ESCALATED &&
-          8 * n_new < need_below + need_above) {
-        sv.max_ir = std::min(MAX_IR_ESCALATED, std::max(1, 2 * sv.max_ir));
-        if (log_on()) std::fprintf(stderr, "[riga] refinement steps raised to %d\n", sv.max_ir);
+      // A run that locks under an eighth of what is missing, or a repeated
+      // run at this shift that locks none of the pairs missing below it, has
+      // reached the accuracy the solve allows: the Ritz values converge but
+      // their FP64 residuals stay above the tolerance (an FP32 factor, or an
+      // FP64 one of an ill-conditioned K - sigma M).  Refine the solves more
+      // from here on.
+      const bool stalled = 8 * n_new < need_below + need_above ||
+                           (runs >= 1 && need_below > 0 && sv.count_locked(lo, sigma) == below);
+      if (stalled) {
+        if (sv.precision == RIGA_MIXED && sv.max_ir < MAX_IR_ESCALATED) {
+          sv.max_ir = std::min(MAX_IR_ESCALATED, std::max(1, 2 * sv.max_ir));
+          if (log_on()) std::fprintf(stderr, "[riga] refinement steps raised to %d\n", sv.max_ir);
+        } else if (sv.precision != RIGA_MIXED && sv.max_ir_fp64 < MAX_IR_FP64) {
+          ++sv.max_ir_fp64;
+          if (log_on()) std::fprintf(stderr, "[riga] FP64 refinement steps raised to %d\n", sv.max_ir_fp64);
+        }
       }
       last_sigma = sigma;
       init = sv.restart_valid ? sv.y.p : nullptr;
@@ -868,10 +926,13 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
       B.hi = o->hi;
       B.nev = o->nev;
       B.nu_base = sv.nu_lo;
-      tb = std::thread([&, dev] {
+      // the first slice returns at least the cnt pairs it has locked, all
+      // below b: the second never needs room for more than nev - cnt
+      const int cap_b = std::max(1, o->nev - cnt);
+      tb = std::thread([&, dev, cap_b] {
         try {
           HIPCHECK(hipSetDevice(dev));
-          setup_solver(B.sv, pr, &pr->ctx[1], o, sb, o->nev);
+          setup_solver(B.sv, pr, &pr->ctx[1], o, sb, cap_b);
           run_slice(B);
         } catch (const Error& e) {
           b_code = e.code;

@@ -465,10 +465,10 @@ void factor_reserve(riga_problem* pr, Factor& F, int precision, hipStream_t s) {
     F.cbvec.alloc(std::max<int64_t>(an.cb_size, 1), s);
     F.fwd.alloc(N, s);
   }
+  if (F.av.n < pr->kv.n) F.av.alloc(pr->kv.n, s);
   if (precision == RIGA_MIXED) {
     if (F.pool32.n < (size_t)an.pool_size) F.pool32.alloc(an.pool_size, s);
     if (F.h32.n < (size_t)an.h_size) F.h32.alloc(an.h_size, s);
-    if (F.av.n < pr->kv.n) F.av.alloc(pr->kv.n, s);
     bigfront_reserve(pr, F, LDS_FRONT_MAX_F32, s);
   } else {
     if (F.pool64.n < (size_t)an.pool_size) F.pool64.alloc(an.pool_size, s);
@@ -481,8 +481,9 @@ void factor_reserve(riga_problem* pr, Factor& F, int precision, hipStream_t s) {
 void factor_numeric(riga_problem* pr, Factor& F, double sigma, int precision, hipStream_t s) {
   const Analysis& an = pr->an;
   F.factored = false;
+  if (F.av.n < pr->kv.n) throw Error(RIGA_EINVAL, "factorisation buffers not reserved");
   if (precision == RIGA_MIXED) {
-    if (F.pool32.n < (size_t)an.pool_size || F.h32.n < (size_t)an.h_size || F.av.n < pr->kv.n)
+    if (F.pool32.n < (size_t)an.pool_size || F.h32.n < (size_t)an.h_size)
       throw Error(RIGA_EINVAL, "factorisation buffers not reserved");
   } else if (F.pool64.n < (size_t)an.pool_size || F.h64.n < (size_t)an.h_size) {
     throw Error(RIGA_EINVAL, "factorisation buffers not reserved");
@@ -501,12 +502,13 @@ void factor_numeric(riga_problem* pr, Factor& F, double sigma, int precision, hi
     if (precision == RIGA_MIXED) {
       factor_levels<float, LDS_FRONT_MAX_F32>(pr, F, F.pool32.p, F.h32.p, sigma, checked, s);
       build_top<float>(pr, F, F.h32.p, F.trow32.p, F.tcol32.p, s);
-      // K - sigma M for the refinement residuals
-      launch_axpby_vals(pr->kv.p, pr->mv.p, sigma, F.av.p, (int64_t)pr->kv.n, s);
     } else {
       factor_levels<double, LDS_FRONT_MAX_F64>(pr, F, F.pool64.p, F.h64.p, sigma, checked, s);
       build_top<double>(pr, F, F.h64.p, F.trow64.p, F.tcol64.p, s);
     }
+    // K - sigma M for the refinement residuals (mixed precision, and FP64
+    // solves refined after a stall)
+    launch_axpby_vals(pr->kv.p, pr->mv.p, sigma, F.av.p, (int64_t)pr->kv.n, s);
     HIPCHECK(hipMemcpyAsync(st.data(), F.front_stat.p, st.size() * sizeof(int32_t),
                             hipMemcpyDeviceToHost, s));
     if (nlev)

@@ -183,14 +183,21 @@ def test_gradient_matches_oracle():
     _say("grad", w.name)
     kappa, rho = w.coefficients()
     pr = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
-    lam, U, res, st = pr.eigs(w.nev)
     wts = np.linspace(0.3, 1.0, w.nev)
-    gk, gr = pr.eig_grad(lam, U, wts)
-    gko, gro = grad.eig_grad(w.dim, w.ne, w.p, w.s, lam, U.cpu().numpy(), wts)
+    # the oracle's own eigenpairs go to both sides
+    Ko, Mo = assembly.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
+    lo, Uo = eigen.dense_eigh(Ko, Mo)
+    lo, Uo = lo[:w.nev], Uo[:, :w.nev]
+    gk, gr = pr.eig_grad(lo, torch.tensor(Uo, device="cuda"), wts)
+    gko, gro = grad.eig_grad(w.dim, w.ne, w.p, w.s, lo, Uo, wts)
     gk, gr = gk.cpu().numpy(), gr.cpu().numpy()
     assert np.abs(gk - gko).max() <= 1e-12 * np.abs(gko).max()
     assert np.abs(gr - gro).max() <= 1e-12 * np.abs(gro).max()
-    # Euler identities (degree-1 homogeneity in kappa, -1 in rho)
+    # the solver's own pairs: Euler identities (degree-1 homogeneity in
+    # kappa, -1 in rho), which hold at any size
+    lam, U, res, st = pr.eigs(w.nev)
+    gk, gr = pr.eig_grad(lam, U, wts)
+    gk, gr = gk.cpu().numpy(), gr.cpu().numpy()
     assert abs(kappa @ gk - wts @ lam) <= 1e-10 * (wts @ lam)
     assert abs(rho @ gr + wts @ lam) <= 1e-10 * (wts @ lam)
 
