@@ -177,6 +177,22 @@ def test_eigs_deterministic():
     assert torch.equal(a[1], b[1])
 
 
+def test_eigs_deterministic_with_two_slices_and_lookahead():
+    """A request large enough to split into two spectrum slices (two host
+    threads, two streams, each with its look-ahead factorisation): repeated
+    solves return bitwise the same eigenvalues and vectors."""
+    riga = _riga()
+    w = workloads.small(2, 64, 3, 16, 160, 0.3)
+    kappa, rho = w.coefficients()
+    pr = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
+    a = pr.eigs(w.nev)
+    b = pr.eigs(w.nev)
+    c = pr.eigs(w.nev)
+    _say("two slices", a[3]["n_shift"], a[3]["n_fb"])
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[0], c[0])
+    assert torch.equal(a[1], b[1]) and torch.equal(a[1], c[1])
+
+
 def test_gradient_matches_oracle():
     riga = _riga()
     w = workloads.small(2, 16, 3, 8, 8, 0.5)
