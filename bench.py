@@ -524,45 +524,50 @@ def accuracy_summary(path):
 # sweeps and products, the event-timed cost of one of each, and the average
 # time per eigenpair.  kappa = rho = 1, FP64, rIGA with BS = 16.
 LARGE_N0 = 4096
-LARGE_CASES = [(256, p) for p in (2, 3, 4, 5)] + [(512, p) for p in (2, 3, 4, 5)] + [(1024, 3)]
+LARGE_CASES = ([(2, 256, p, s, 4096) for p in (2, 3, 4, 5) for s in (0, 16)]
+               + [(2, 512, p, s, 4096) for p in (2, 3, 4, 5) for s in (0, 16)]
+               + [(2, 1024, 3, s, 4096) for s in (0, 16)])
+# 3D: 64^3, N0 = 1024 (the paper's 3D table); rIGA only (64^3 IGA fronts reach 12,160)
+LARGE_CASES_3D = [(3, 64, 2, s, 1024) for s in (16, 8)]
 
 
-def large_n0(riga, torch, out_path):
+def large_n0(riga, torch, out_path, dims=(2,)):
     fout = open(out_path, "w") if out_path else None
-    for ne, p in LARGE_CASES:
-        for s in (0, 16):
-            rec = {"dim": 2, "ne": ne, "p": p, "sep_spacing": s, "n0": LARGE_N0}
-            try:
-                pr = riga.assemble(2, ne, p, s)
-                rec.update(n_dof=pr.n_dof, nnz_l=pr.info["nnz_l"], max_front=pr.info["max_front"])
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                lam, U, res, st = pr.eigs(LARGE_N0)
-                torch.cuda.synchronize()
-                wall = time.perf_counter() - t0
-                del U
-                torch.cuda.empty_cache()
-                sigma_mid = 0.5 * (lam[len(lam) // 2] + lam[len(lam) // 2 + 1])
-                t_fb, t_fact = time_solves(pr, sigma_mid, riga.RIGA_FP64, 10, torch)
-                t_mv = time_spmv(pr, 20, torch)
-                rec.update(wall=wall, t_av=wall / LARGE_N0, max_res=float(max(res)),
-                           n_shift=st["n_shift"], n_fact=st["n_fact"], n_fb=st["n_fb"], n_mv=st["n_mv"],
-                           t_fact=t_fact, t_fb=t_fb, t_mv=t_mv)
-                del pr
-            except riga.RigaError as e:
-                rec["error"] = str(e)
+    cases = [c for c in LARGE_CASES + LARGE_CASES_3D if c[0] in dims]
+    for dim, ne, p, s, n0 in cases:
+        rec = {"dim": dim, "ne": ne, "p": p, "sep_spacing": s, "n0": n0}
+        try:
+            pr = riga.assemble(dim, ne, p, s)
+            rec.update(n_dof=pr.n_dof, nnz_l=pr.info["nnz_l"], max_front=pr.info["max_front"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lam, U, res, st = pr.eigs(n0)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            del U
             torch.cuda.empty_cache()
-            line = json.dumps(rec)
-            print(line, flush=True)
-            if fout:
-                fout.write(line + "\n")
-                fout.flush()
+            sigma_mid = 0.5 * (lam[len(lam) // 2] + lam[len(lam) // 2 + 1])
+            t_fb, t_fact = time_solves(pr, sigma_mid, riga.RIGA_FP64, 10, torch)
+            t_mv = time_spmv(pr, 20, torch)
+            rec.update(wall=wall, t_av=wall / n0, max_res=float(max(res)),
+                       n_shift=st["n_shift"], n_fact=st["n_fact"], n_fb=st["n_fb"], n_mv=st["n_mv"],
+                       t_fact=t_fact, t_fb=t_fb, t_mv=t_mv)
+            del pr
+        except riga.RigaError as e:
+            rec["error"] = str(e)
+        torch.cuda.empty_cache()
+        line = json.dumps(rec)
+        print(line, flush=True)
+        if fout:
+            fout.write(line + "\n")
+            fout.flush()
     if fout:
         fout.close()
 
 
 def large_n0_summary(path):
-    """Markdown table in the shape of the paper's large-N0 tables: per
+    """Markdown table in the shape of the paper's large-N0 tables (T_av per
+    eigenpair of each row's own N0): per
     operation its count and its time per eigenpair (count x event-timed
     cost / N0), and the measured average time per eigenpair."""
     recs = [json.loads(l) for l in open(path) if l.strip()]
@@ -571,17 +576,18 @@ def large_n0_summary(path):
     print("|---|---|---|---|---|---|---|---|---|---|---|---|---|")
     by = {}
     for r in recs:
-        by[(r["ne"], r["p"], r["sep_spacing"])] = r
+        by[(r.get("dim", 2), r["ne"], r["p"], r["sep_spacing"])] = r
     for r in recs:
-        name = "IGA" if r["sep_spacing"] == 0 else "rIGA"
-        head = "| %d^2 | %d | %s |" % (r["ne"], r["p"], name)
+        name = "IGA" if r["sep_spacing"] == 0 else (
+            "rIGA" if r.get("dim", 2) == 2 else "rIGA BS=%d" % r["sep_spacing"])
+        head = "| %d^%d | %d | %s |" % (r["ne"], r.get("dim", 2), r["p"], name)
         if "wall" not in r:
             print(head + " %s |" % r.get("error", "") + " |" * 9)
             continue
         n0 = r["n0"]
         gain = ""
         if r["sep_spacing"] != 0:
-            iga = by.get((r["ne"], r["p"], 0))
+            iga = by.get((r.get("dim", 2), r["ne"], r["p"], 0))
             if iga and "wall" in iga:
                 gain = "%.2f" % (iga["wall"] / r["wall"])
         print(head + " %d | %d | %d | %.4f | %d | %.4f | %d | %.4f | %.4f | %s |" % (
@@ -615,6 +621,8 @@ def main():
                     help="print markdown tables of an accuracy study and exit")
     ap.add_argument("--large-n0", metavar="OUT_JSONL", nargs="?", const="",
                     help="4096 lowest eigenpairs of 2D 256^2-1024^2 IGA and rIGA, operation counts, and exit")
+    ap.add_argument("--large-n0-dims", default="2",
+                    help="dimensions for --large-n0: 2, 3 or 2,3 (3: 64^3 rIGA, N0 = 1024)")
     ap.add_argument("--large-n0-summary", metavar="JSONL",
                     help="print the markdown table of a --large-n0 run and exit")
     args = ap.parse_args()
@@ -655,7 +663,7 @@ def main():
         accuracy_study(riga, torch, args.accuracy_study)
         return
     if args.large_n0 is not None:
-        large_n0(riga, torch, args.large_n0)
+        large_n0(riga, torch, args.large_n0, tuple(int(d) for d in args.large_n0_dims.split(",")))
         return
     if args.calibrate_copy:
         calibrate_copy(torch)
