@@ -270,12 +270,15 @@ struct Solver {
     std::vector<double> Sv((size_t)m * n);
     if (n == 0) return Sv;
     std::vector<int32_t> ix(idx.begin(), idx.end());
-    // clusters: adjacent selected eigenvalues closer than 1e-3 relative
+    // clusters: consecutive selected eigenvalues closer than 1e-3 relative
+    // when adjacent in T's spectrum, or closer than 1e-8 relative across
+    // unselected ones (copies of a multiple eigenvalue, some not converged
+    // and left out, must still be orthogonalised against each other)
     std::vector<int32_t> cl{0};
     for (int i = 1; i < n; ++i) {
       const double t0 = r.theta[idx[i - 1]], t1 = r.theta[idx[i]];
-      const bool close = idx[i] == idx[i - 1] + 1 &&
-                         std::fabs(t1 - t0) <= 1e-3 * std::max(std::fabs(t0), std::fabs(t1));
+      const double gap = std::fabs(t1 - t0), scale = std::max(std::fabs(t0), std::fabs(t1));
+      const bool close = (idx[i] == idx[i - 1] + 1 && gap <= 1e-3 * scale) || gap <= 1e-8 * scale;
       if (!close) cl.push_back(i);
     }
     cl.push_back(n);
