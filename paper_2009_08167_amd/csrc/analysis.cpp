@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <functional>
 #include <numeric>
 
@@ -108,6 +109,17 @@ struct NodeTmp {
   Box slab;                   // the node's own variables
   std::vector<int> children;
 };
+
+// Largest fully-summed block of one front; larger separators are split into
+// chains.  288 is the largest block whose panels get the full 64 columns
+// (the panel kernel's LDS holds 18,432 doubles of remaining rows x panel
+// columns).  RIGA_SPLIT_FS overrides (0: no splitting).
+constexpr int SPLIT_FS = 288;
+int split_fs() {
+  if (const char* v = std::getenv("RIGA_SPLIT_FS"))
+    if (*v) return std::max(0, std::atoi(v));
+  return SPLIT_FS;
+}
 
 }  // namespace
 
@@ -247,7 +259,7 @@ std::string analyze(int dim, const int ne_in[3], int p, int s, int nquad, int le
     root.e1[d] = A.ne[d];
   }
   std::vector<int> roots = build(root);
-  const int nf = (int)nodes.size();
+  int nf = (int)nodes.size();
   A.n_fronts = nf;
 
   // ---- Elimination order: nodes are created in post-order; each node's
@@ -289,6 +301,66 @@ std::string analyze(int dim, const int ne_in[3], int p, int s, int nquad, int le
     for (int c : nodes[f].children) h = std::max(h, A.f_height[c] + 1);
     A.f_height[f] = h;
   }
+
+  // ---- Supernode splitting: a separator with more than `split` variables
+  // becomes a chain of fronts of at most `split` each, in the same
+  // elimination order (same fill, same flops).  The panel kernel holds a
+  // front's remaining fully-summed rows of its panel columns in LDS, so a
+  // smaller fully-summed block allows wider panels, and the trailing
+  // updates become dense rank-(panel width) contractions instead of
+  // streaming the update block through HBM a few columns at a time.
+  const int split = split_fs();
+  if (split > 0) {
+    int nn = 0;
+    std::vector<int> first_new(A.n_fronts), nchunk(A.n_fronts);
+    for (int f = 0; f < A.n_fronts; ++f) {
+      nchunk[f] = std::max(1, (A.f_k[f] + split - 1) / split);
+      first_new[f] = nn;
+      nn += nchunk[f];
+    }
+    if (nn != A.n_fronts) {
+      std::vector<int32_t> start(nn), kk(nn), parent(nn, -1);
+      std::vector<std::vector<int>> kids(nn);
+      for (int f = 0; f < A.n_fronts; ++f) {
+        for (int c = 0; c < nchunk[f]; ++c) {
+          const int i = first_new[f] + c;
+          start[i] = A.f_start[f] + c * split;
+          kk[i] = std::min(split, A.f_k[f] - c * split);
+          if (c + 1 < nchunk[f]) {
+            parent[i] = i + 1;
+            kids[i + 1].push_back(i);
+          }
+        }
+        const int last = first_new[f] + nchunk[f] - 1;
+        if (A.f_parent[f] >= 0) {
+          parent[last] = first_new[A.f_parent[f]];
+          kids[first_new[A.f_parent[f]]].push_back(last);
+        }
+      }
+      A.n_fronts = nn;
+      A.f_start = start;
+      A.f_k = kk;
+      A.f_parent = parent;
+      A.child_ptr.assign(nn + 1, 0);
+      A.child_list.clear();
+      for (int i = 0; i < nn; ++i) {
+        std::sort(kids[i].begin(), kids[i].end());
+        A.child_ptr[i + 1] = A.child_ptr[i] + (int)kids[i].size();
+        for (int c : kids[i]) {
+          if (c >= i) return "internal: split tree not in post-order";
+          A.child_list.push_back(c);
+        }
+      }
+      A.f_height.assign(nn, 0);
+      for (int i = 0; i < nn; ++i) {
+        int h = 0;
+        for (int ci = A.child_ptr[i]; ci < A.child_ptr[i + 1]; ++ci)
+          h = std::max(h, A.f_height[A.child_list[ci]] + 1);
+        A.f_height[i] = h;
+      }
+    }
+  }
+  nf = A.n_fronts;
 
   // ---- Supernodal symbolic factorisation.  struct(P) = the variables
   // eliminated after P that are adjacent to P's variables or in a child's
