@@ -104,13 +104,18 @@ def test_tree_is_a_valid_elimination_tree(dim, ne, p, s):
             assert b in fsets[owner[a]]
 
 
-@pytest.mark.parametrize("dim,ne,p,s", [(2, 12, 2, 0), (2, 16, 3, 4), (3, 6, 2, 3), (2, 10, 4, 5)])
-def test_fronts_contain_exact_fill(dim, ne, p, s):
+@pytest.mark.parametrize("dim,ne,p,s,split", [(2, 12, 2, 0, 0), (2, 16, 3, 4, 0), (3, 6, 2, 3, 0),
+                                               (2, 10, 4, 5, 0), (2, 16, 3, 4, 6), (3, 6, 2, 3, 8)])
+def test_fronts_contain_exact_fill(dim, ne, p, s, split, monkeypatch):
     """Brute force: the symbolic Cholesky of P A P^T (SuperLU, natural order
     on the permuted matrix, no pivoting) never fills outside the fronts, and
-    the supernodal count nnz(L) is at least the exact fill."""
+    the supernodal count nnz(L) is at least the exact fill; also with
+    separators split into chains (split > 0)."""
     _lib_or_skip()
+    monkeypatch.setenv("RIGA_SPLIT_FS", str(split))
     pr = riga.analyze(dim, ne, p, s, leaf_dofs=24)
+    if split:
+        assert pr.tree()["k"].max() <= split
     t = pr.tree()
     perm = t["perm"]
     K, M = assembly.assemble(dim, ne, p, s)
@@ -168,3 +173,32 @@ def test_exact_eigenvalues_host_enumeration_matches_oracle():
         assert np.array_equal(got, ref), (dim, count)
     with pytest.raises(riga.RigaError):
         riga.exact_eigenvalues(1, 5)
+
+
+@pytest.mark.parametrize("dim,ne,p,s,split", [(2, 128, 3, 0, 288), (3, 12, 2, 0, 64), (2, 40, 3, 8, 16)])
+def test_supernode_splitting_keeps_order_fill_and_flops(dim, ne, p, s, split, monkeypatch):
+    """Separators larger than the split size become chains: the elimination
+    order is that of the unsplit tree; nnz(L) and the factorisation flops are
+    at most its (a supernode counts its fully-summed block as dense, the
+    chain pieces only the structure elimination creates); every
+    fully-summed block is at most the split size; a split front's parent is
+    the next piece of the same separator (consecutive pivots)."""
+    _lib_or_skip()
+    monkeypatch.setenv("RIGA_SPLIT_FS", "0")
+    whole = riga.analyze(dim, ne, p, s)
+    tw = whole.tree()
+    monkeypatch.setenv("RIGA_SPLIT_FS", str(split))
+    part = riga.analyze(dim, ne, p, s)
+    tp = part.tree()
+    assert tw["k"].max() > split  # the case exercises the split
+    assert tp["k"].max() <= split
+    assert np.array_equal(tw["perm"], tp["perm"])
+    assert part.info["nnz_l"] <= whole.info["nnz_l"]
+    assert part.info["flops_fact"] <= whole.info["flops_fact"] * (1 + 1e-12)
+    assert len(tp["k"]) > len(tw["k"])
+    # pieces of one separator: consecutive pivot ranges linked child -> parent
+    starts = np.concatenate(([0], np.cumsum(tp["k"])[:-1]))
+    for F in range(len(tp["k"])):
+        P = tp["parent"][F]
+        if P == F + 1 and tp["k"][F] == split:
+            assert starts[P] == starts[F] + split
