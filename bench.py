@@ -531,9 +531,9 @@ LARGE_CASES = ([(2, 256, p, s, 4096) for p in (2, 3, 4, 5) for s in (0, 16)]
 LARGE_CASES_3D = [(3, 64, 2, s, 1024) for s in (16, 8)]
 
 
-def large_n0(riga, torch, out_path, dims=(2,)):
+def large_n0(riga, torch, out_path, dims=(2,), mesh=0):
     fout = open(out_path, "w") if out_path else None
-    cases = [c for c in LARGE_CASES + LARGE_CASES_3D if c[0] in dims]
+    cases = [c for c in LARGE_CASES + LARGE_CASES_3D if c[0] in dims and (mesh == 0 or c[1] == mesh)]
     for dim, ne, p, s, n0 in cases:
         rec = {"dim": dim, "ne": ne, "p": p, "sep_spacing": s, "n0": n0}
         try:
@@ -623,6 +623,8 @@ def main():
                     help="4096 lowest eigenpairs of 2D 256^2-1024^2 IGA and rIGA, operation counts, and exit")
     ap.add_argument("--large-n0-dims", default="2",
                     help="dimensions for --large-n0: 2, 3 or 2,3 (3: 64^3 rIGA, N0 = 1024)")
+    ap.add_argument("--large-n0-mesh", type=int, default=0,
+                    help="with --large-n0: only the meshes with this many elements per direction")
     ap.add_argument("--large-n0-summary", metavar="JSONL",
                     help="print the markdown table of a --large-n0 run and exit")
     args = ap.parse_args()
@@ -663,7 +665,8 @@ def main():
         accuracy_study(riga, torch, args.accuracy_study)
         return
     if args.large_n0 is not None:
-        large_n0(riga, torch, args.large_n0, tuple(int(d) for d in args.large_n0_dims.split(",")))
+        large_n0(riga, torch, args.large_n0, tuple(int(d) for d in args.large_n0_dims.split(",")),
+                 args.large_n0_mesh)
         return
     if args.calibrate_copy:
         calibrate_copy(torch)
