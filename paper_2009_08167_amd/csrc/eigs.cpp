@@ -921,6 +921,28 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
       if (!(step > 0)) return;
       const double b = place_in_gap(sv, last, a.lo, top, top + step, step, a.hi);
       if (!(b > top) || !std::isfinite(b)) return;
+      // the second slice brings its own Lanczos storage and two more
+      // factorisations: split only when the device holds them with room
+      // to spare (the one-slice solve is the same computation, serial)
+      const int cap_b = std::max(1, o->nev - cnt);
+      const double n = (double)sv.N;
+      const double cols = (double)std::min<int64_t>(cap_b + 2 * sv.per_shift + 32, sv.N) + sv.mb + 1;
+      const double umax = (double)sv.mb + 1.0;
+      const Analysis& an = pr->an;
+      const TopDev& td = pr->top;
+      const double fact = (double)an.pool_size + (double)an.h_size + (double)td.e_row + (double)td.e_col +
+                          (double)td.e_cb + 4.0 * (double)n + (double)pr->kv.n;
+      // (a third factorisation's worth of margin: the first slice's
+      // look-ahead factorisation may not be allocated yet)
+      const double need = 8.0 * (2.0 * n * cols + 3.0 * n * umax + 3.0 * fact);
+      size_t free_b = 0, total_b = 0;
+      HIPCHECK(hipMemGetInfo(&free_b, &total_b));
+      if (need * 1.15 > (double)free_b) {
+        if (log_on())
+          std::fprintf(stderr, "[riga] no split: the second slice needs %.1f GB, %.1f GB free\n", need * 1e-9,
+                       (double)free_b * 1e-9);
+        return;
+      }
       a.hi = b;
       if (log_on()) std::fprintf(stderr, "[riga] split at %.10g (%d pairs below the first shift's top)\n", b, cnt);
       HIPCHECK(hipStreamCreateWithFlags(&sb, hipStreamNonBlocking));
@@ -931,7 +953,6 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
       B.nu_base = sv.nu_lo;
       // the first slice returns at least the cnt pairs it has locked, all
       // below b: the second never needs room for more than nev - cnt
-      const int cap_b = std::max(1, o->nev - cnt);
       tb = std::thread([&, dev, cap_b] {
         try {
           HIPCHECK(hipSetDevice(dev));
