@@ -532,6 +532,42 @@ double next_shift(const Solver& sv, const Solver::Ritz& r, double sigma, double 
   return place_in_gap(sv, r, sigma, top, top + step, step, hi);
 }
 
+// Once at least nev pairs of the slice are locked, a shift just above the
+// nev-th lowest of them, v, verifies them by inertia alone: with nothing
+// missing below it, it needs no run.  The shift goes to the middle of the
+// gap above v to the next estimate (a locked value or a Ritz value of run r,
+// made at shift r_sigma), gaps narrower than a relative 1e-4 (copies of a
+// multiple eigenvalue) skipped, and at most half of Weyl's spacing for one
+// more eigenvalue above the gap's lower end.  NaN when fewer are locked or
+// the shift would leave (sigma, hi).
+double verify_shift(const Solver& sv, const Solver::Ritz& r, double r_sigma, double lo, double hi,
+                    int nev, double sigma) {
+  const double none = std::numeric_limits<double>::quiet_NaN();
+  std::vector<double> lk;
+  for (auto& L : sv.locked)
+    if (L.lam >= lo && L.lam < hi) lk.push_back(L.lam);
+  if (nev < 1 || (int)lk.size() < nev) return none;
+  std::sort(lk.begin(), lk.end());
+  const double v = lk[nev - 1];
+  std::vector<double> est(lk.begin() + (nev - 1), lk.end());
+  for (int i = 0; i < (int)r.theta.size(); ++i)
+    if (r.theta[i] != 0.0) {
+      const double e = r_sigma + 1.0 / r.theta[i];
+      if (e > v) est.push_back(e);
+    }
+  std::sort(est.begin(), est.end());
+  for (size_t i = 1; i < est.size(); ++i) {
+    const double a = est[i - 1], b = est[i];
+    if (b - a < 1e-4 * std::fabs(a)) continue;
+    double cand = 0.5 * (a + b);
+    const double space = weyl_step(a, sv.nu_lo + nev + (int64_t)(i - 1), 1, sv.dim);
+    if (space > 0) cand = std::min(cand, a + 0.5 * space);
+    if (!(cand > sigma) || (std::isfinite(hi) && cand >= hi)) return none;
+    return cand;
+  }
+  return none;
+}
+
 // Look-ahead guess of the shift that next_shift will choose once the runs at
 // sigma have finished, made before they start: those runs lock about
 // `per_above` eigenvalues above sigma, so the top of the locked set moves to
@@ -657,16 +693,19 @@ namespace {
 // shift-and-invert Lanczos with spectrum slicing (Sec. 4.1) on its own
 // Solver (basis storage, stream, factorisations).  `nu_base` >= 0 makes the
 // slice find nev - (nu(lo) - nu_base) pairs instead (the pairs of a lower
-// slice ending at lo are counted by the inertia at lo).  `after_first`, if
-// set, runs once after the runs at the first shift (the split of run_eigs).
+// slice ending at lo are counted by the inertia at lo).  `after_lo`, if
+// set, runs once the inertia at lo is known and may lower hi (the split of
+// run_eigs: the rest goes to another slice).  A finite `first_shift` above
+// lo makes the first runs start there, inside the slice, rather than at lo.
 struct Slice {
   Solver sv;
   double lo = 0.0, hi = 0.0;
   int nev = 0;
   int64_t nu_base = -1;
+  double first_shift = std::numeric_limits<double>::quiet_NaN();
   riga_status status = RIGA_OK;
   double verified = 0.0;
-  std::function<void(Slice&, const Solver::Ritz&)> after_first;
+  std::function<void(Slice&)> after_lo;
 };
 
 void setup_solver(Solver& sv, riga_problem* pr, SolveCtx* ctx, const riga_eigs_opts* o, hipStream_t s,
@@ -713,20 +752,45 @@ void run_slice(Slice& S) {
   S.nev = nev;
   sv.nu_lo = nu_lo;
   sv.st.n_shift = 1;
+  double hi_now = hi;  // the split may lower it
+  if (S.after_lo) {
+    S.after_lo(S);
+    hi_now = S.hi;
+    sv.hi = hi_now;
+  }
   riga_status status = RIGA_OK;
   double sigma = lo;
   int64_t known = 0;  // eigenvalues in [lo, sigma)
+  // a first shift inside the slice locks pairs on both of its sides; one
+  // that turns out to lie past more eigenvalues than a run is sized for
+  // (a poor estimate) is given up for lo
+  bool inside = false;
+  if (nev > 0 && std::isfinite(S.first_shift) && S.first_shift > lo && S.first_shift < hi_now) {
+    sv.factor(S.first_shift);
+    sv.st.n_shift++;
+    const int64_t k = sv.cur().inertia - nu_lo;
+    if (k <= sv.per_shift) {
+      sigma = S.first_shift;
+      known = k;
+      inside = true;
+    } else {
+      sv.factor(lo);
+      sv.st.n_shift++;
+    }
+    if (log_on())
+      std::fprintf(stderr, "[riga] first shift %.10g: count above lo=%lld (%s)\n", S.first_shift,
+                   (long long)k, inside ? "kept" : "given up");
+  }
   double verified = lo;  // every eigenvalue in [lo, verified) is locked
   const double* init = nullptr;
   LookAhead la;
   la.pr = pr;
   la.ctx = sv.ctx;
   Solver::Ritz last;        // final Ritz data of the last run
-  double last_sigma = lo;   // its shift
-  double hi_now = hi;       // the split may lower it after the first shift
+  double last_sigma = sigma;  // its shift
   for (int shift = 0; nev > 0 && shift < 400; ++shift) {
     int runs = 0;
-    const int per_above = shift == 0 ? sv.per_shift : std::max(1, sv.per_shift / 2);
+    const int per_above = (shift == 0 && !inside) ? sv.per_shift : std::max(1, sv.per_shift / 2);
     const int64_t target = std::max<int64_t>(1, std::min<int64_t>(sv.per_shift / 2, nev - known));
     // factorise at the guessed next shift while the runs at this one proceed
     if (lookahead_on() && shift > 0 && known < nev && !(std::isfinite(hi_now) && sigma >= hi_now)) {
@@ -736,15 +800,15 @@ void run_slice(Slice& S) {
     do {
       const int below = sv.count_locked(lo, sigma);
       const int need_below = (int)std::max<int64_t>(0, known - below);
-      // a split slice's last shift whose eigenvalues below are all locked
-      // needs no run
-      if (need_below == 0 && std::isfinite(hi_now) && sigma >= hi_now) break;
       const int above = sv.count_locked(sigma, hi_now);
       // none above the slice's upper end (a split slice's last shift)
       const int need_above = (std::isfinite(hi_now) && sigma >= hi_now)
                                  ? 0
                                  : (int)std::max<int64_t>(
                                        0, std::min<int64_t>(per_above, nev - known - above));
+      // a shift with every eigenvalue below it locked and enough locked
+      // above (a split slice's last shift, a verifying shift) needs no run
+      if (need_below == 0 && need_above == 0) break;
       int n_new = 0;
       // a repeated run at the same shift means eigenvalues are missing that
       // the previous Krylov space did not reach (e.g. further copies of a
@@ -787,14 +851,12 @@ void run_slice(Slice& S) {
       break;
     }
     verified = sigma;
-    if (shift == 0 && S.after_first) {
-      S.after_first(S, last);  // may lower S.hi (the rest goes to another slice)
-      hi_now = S.hi;
-      sv.hi = hi_now;
-    }
     if (known >= nev) break;
     if (std::isfinite(hi_now) && sigma >= hi_now) break;
     double next = next_shift(sv, last, sigma, lo, hi_now, (int)target);
+    const double check = verify_shift(sv, last, last_sigma, lo, hi_now, nev, sigma);
+    const bool verify = std::isfinite(check);
+    if (verify) next = check;
     bool taken = false;
     if (la.active) {
       // the look-ahead factorisation replaces the one at `next` when it
@@ -807,8 +869,9 @@ void run_slice(Slice& S) {
       sv.count_factor(F);
       const int64_t known_g = F.inertia - nu_lo;
       const int64_t missing = known_g - sv.count_locked(lo, la.sigma);
+      // (a verifying shift is preferred unless this one verifies as well)
       taken = la.sigma > sigma && known_g > known && missing <= sv.per_shift &&
-              !(std::isfinite(hi_now) && la.sigma > hi_now);
+              !(std::isfinite(hi_now) && la.sigma > hi_now) && (!verify || (missing == 0 && known_g >= nev));
       if (log_on())
         std::fprintf(stderr, "[riga] look-ahead sigma=%.10g (placed after the runs: %.10g): %s\n",
                      la.sigma, next, taken ? "taken" : "discarded");
@@ -862,8 +925,35 @@ void add_stats(riga_stats& a, const riga_stats& b) {
   a.t_ritz += b.t_ritz;
 }
 
+// Estimates of the `count` lowest eigenvalues made before any shift: those
+// of the Dirichlet Laplacian on the unit square or cube (pi^2 times sums of
+// squared integers) divided by the mean of (rho/kappa)^(dim/2) to the power
+// 2/dim, the factor by which variable coefficients scale the leading term of
+// Weyl's law for -div(kappa grad u) = lambda rho u.
+std::vector<double> spectrum_estimates(riga_problem* pr, int count, hipStream_t s) {
+  const int64_t ne = pr->an.n_elem;
+  const int dim = pr->an.dim;
+  std::vector<double> kap(pr->kappa.p ? ne : 0), rho(pr->rho.p ? ne : 0);
+  if (!kap.empty())
+    HIPCHECK(hipMemcpyAsync(kap.data(), pr->kappa.p, ne * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (!rho.empty())
+    HIPCHECK(hipMemcpyAsync(rho.data(), pr->rho.p, ne * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  double acc = 0.0;
+  for (int64_t e = 0; e < ne; ++e) {
+    const double q = (rho.empty() ? 1.0 : rho[e]) / (kap.empty() ? 1.0 : kap[e]);
+    acc += std::pow(q, 0.5 * dim);
+  }
+  const double scale = std::pow(acc / (double)ne, 2.0 / dim);
+  std::vector<double> est(count);
+  exact_eigenvalues(dim, count, est.data());
+  for (double& v : est) v /= scale;
+  return est;
+}
+
 // RIGA_SLICES=1 keeps one slice; otherwise an open-ended request for at
-// least 4 shifts' worth of pairs is split in two after its first shift.
+// least 4 runs' worth of pairs is split in two once the inertia at its
+// lower end is known.
 bool split_on() {
   const char* v = std::getenv("RIGA_SLICES");
   return !(v && *v == '1');
@@ -904,27 +994,30 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
   } joiner{tb};
   const int per_shift = o->per_shift > 0 ? o->per_shift : 32;
   if (split_on() && !std::isfinite(o->hi) && o->nev >= 4 * per_shift) {
-    A.after_first = [&](Slice& a, const Solver::Ritz& last) {
-      // split where about half of the remaining pairs lie below
+    A.after_lo = [&](Slice& a) {
+      // split where the estimates put half of the pairs below; the second
+      // slice's first runs start half a run's worth of pairs above its
+      // lower end, so that they lock pairs on both sides of their shift
       Solver& sv = a.sv;
-      int cnt = 0;
-      double top = a.lo;
-      for (auto& L : sv.locked)
-        if (L.lam >= a.lo) {
-          top = std::max(top, L.lam);
-          ++cnt;
-        }
-      // half of the pairs left on each side
-      const int want = (a.nev + cnt) / 2;
-      if (cnt == 0 || want <= cnt + per_shift) return;
-      const double step = weyl_step(top, sv.nu_lo + cnt, want - cnt, sv.dim);
-      if (!(step > 0)) return;
-      const double b = place_in_gap(sv, last, a.lo, top, top + step, step, a.hi);
-      if (!(b > top) || !std::isfinite(b)) return;
-      // the second slice brings its own Lanczos storage and two more
-      // factorisations: split only when the device holds them with room
-      // to spare (the one-slice solve is the same computation, serial)
-      const int cap_b = std::max(1, o->nev - cnt);
+      const int w = std::max(2, per_shift / 8);
+      const int64_t t = sv.nu_lo + a.nev / 2, t1 = t + per_shift / 2;
+      if (t1 + w + 1 > (int64_t)1 << 22) return;
+      const std::vector<double> est = spectrum_estimates(pr, (int)(t1 + w + 1), s);
+      // the middle of the widest gap between neighbouring estimates around
+      // index c (the count of estimates below it lies within c -/+ w)
+      auto gap_mid = [&](int64_t c) {
+        int64_t best = std::max<int64_t>(1, c - w);
+        for (int64_t i = best + 1; i <= c + w; ++i)
+          if (est[i] - est[i - 1] > est[best] - est[best - 1]) best = i;
+        return 0.5 * (est[best] + est[best - 1]);
+      };
+      const double b = gap_mid(t), s1 = gap_mid(t1);
+      if (!(b > a.lo) || !(s1 > b) || !std::isfinite(s1)) return;
+      // the second slice brings its own Lanczos storage (room for all nev
+      // pairs: how many lie below b is not known yet) and two more
+      // factorisations: split only when the device holds them with room to
+      // spare (the one-slice solve is the same computation, serial)
+      const int cap_b = o->nev;
       const double n = (double)sv.N;
       const double cols = (double)std::min<int64_t>(cap_b + 2 * sv.per_shift + 32, sv.N) + sv.mb + 1;
       const double umax = (double)sv.mb + 1.0;
@@ -944,15 +1037,14 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
         return;
       }
       a.hi = b;
-      if (log_on()) std::fprintf(stderr, "[riga] split at %.10g (%d pairs below the first shift's top)\n", b, cnt);
+      if (log_on()) std::fprintf(stderr, "[riga] split at %.10g, second slice's first shift %.10g\n", b, s1);
       HIPCHECK(hipStreamCreateWithFlags(&sb, hipStreamNonBlocking));
       const int dev = pr->device;
       B.lo = b;
       B.hi = o->hi;
       B.nev = o->nev;
       B.nu_base = sv.nu_lo;
-      // the first slice returns at least the cnt pairs it has locked, all
-      // below b: the second never needs room for more than nev - cnt
+      B.first_shift = s1;
       tb = std::thread([&, dev, cap_b] {
         try {
           HIPCHECK(hipSetDevice(dev));
