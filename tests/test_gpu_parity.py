@@ -328,8 +328,9 @@ def test_blocked_fronts_checked_and_unchecked_agree(w, monkeypatch):
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
 def test_two_slices_match_one(prec, monkeypatch):
-    """An open-ended request for many pairs is split after its first shift
-    into two slices solved at once; the result equals the single-slice
+    """An open-ended request for many pairs is split, once the inertia at its
+    lower end is known, into two slices solved at once (the second starting
+    inside its interval); the result equals the single-slice
     solve and the dense oracle (eigenvalues <= 1e-10, residuals <= 1e-9,
     M-orthonormality across the two slices' vectors <= 1e-10)."""
     riga = _riga()
@@ -347,3 +348,43 @@ def test_two_slices_match_one(prec, monkeypatch):
     assert s2["n_shift"] >= 2
     for lam, U, res in ((l1, U1, r1), (l2, U2, r2)):
         _check_pairs(Ko, Mo, lr, Ur, lam, U.cpu().numpy(), res, w.nev)
+
+
+def test_two_slices_above_a_lower_bound():
+    """An open-ended request above lo > 0: the split estimate counts from the
+    inertia at lo, and the pairs returned are the oracle's 31st to 170th."""
+    riga = _riga()
+    w = workloads.small(2, 40, 3, 8, 140, 0.3)
+    kappa, rho = w.coefficients()
+    Ko, Mo = assembly.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
+    lr, Ur = eigen.dense_eigh(Ko, Mo)
+    k = 30
+    lo = 0.5 * (lr[k - 1] + lr[k])
+    pr = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho, leaf_dofs=32)
+    _say("lower bound", w.name, "lo", lo)
+    lam, U, res, st = pr.eigs(w.nev, lo=lo)
+    _say("stats", st)
+    assert st["n_shift"] >= 3
+    _check_pairs(Ko, Mo, lr[k:], Ur[:, k:], lam, U.cpu().numpy(), res, w.nev)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_two_slices_with_high_contrast_coefficients(prec):
+    """rho = 1e4 on a 4 x 4 block of elements in a corner, 1 elsewhere
+    (kappa = 1): the block holds most of the weight in Weyl's leading term
+    but, being small, few of the low modes, so the split's estimate (the
+    scaled Dirichlet-Laplace spectrum) puts 65 pairs below the split point
+    where the oracle has 25.  Each slice counts its own pairs by inertia, so
+    the result still equals the oracle's."""
+    riga = _riga()
+    dim, ne, p, s, nev = 2, 40, 3, 8, 130
+    e = np.arange(ne * ne)
+    kappa = np.ones(ne * ne)
+    rho = np.where((e % ne < 4) & (e // ne < 4), 1e4, 1.0)
+    Ko, Mo = assembly.assemble(dim, ne, p, s, kappa, rho)
+    lr, Ur = eigen.dense_eigh(Ko, Mo)
+    pr = riga.assemble(dim, ne, p, s, kappa, rho, leaf_dofs=32)
+    _say("high contrast", prec)
+    lam, U, res, st = pr.eigs(nev, precision=prec)
+    _say("stats", st)
+    _check_pairs(Ko, Mo, lr, Ur, lam, U.cpu().numpy(), res, nev)
