@@ -210,8 +210,13 @@ riga_status riga_solve_multi(riga_problem* pr, const double* B_dev, double* X_de
  * Spectrum slicing with inertia counts (Sec. 4.1): the factorisation at a
  * guess of the next shift runs on a second HIP stream of the library's own
  * (and a second host thread) while the Lanczos runs at the current shift
- * proceed; the call returns only after both are done.  Not reentrant for
- * one problem: calls on the same problem must not overlap.
+ * proceed; the call returns only after both are done.  An open-ended
+ * request (hi = +inf) for at least 4 * per_shift pairs is split in two
+ * spectrum slices solved at once, the upper one on a further host thread
+ * and HIP stream with its own factorisations, when the device's free memory
+ * holds its storage; the split point only balances the work, each slice
+ * counts its own pairs by inertia.  Not reentrant for one problem: calls on
+ * the same problem must not overlap.
  * evals_host[nev]: ascending eigenvalues (Rayleigh quotients).
  * evecs_dev: [n_dof * nev] column-major device buffer for M-normalised
  * eigenvectors, or NULL.  resid_host[nev] (or NULL): relative residuals
