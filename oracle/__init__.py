@@ -22,6 +22,9 @@ arXiv 2009.08167, that it follows):
   ST_GHEP), inertia counts (Remark on inertia), residuals, normalisation.
 * ``accuracy`` -- EVerr, EFerr_L2, EFerr_E against the exact eigenpairs
   (Eqs. exact, norms, eigerrors; diagonal modes as in Sec. 7).
+* ``hermitian`` -- a complex Hermitian source for the Hermitian case of Eq.
+  GHEP: the magnetic Laplacian with a constant potential (gauge-equivalent
+  to the Laplacian), its real-equivalent pencil and a dense Hermitian solve.
 * ``grad``     -- adjoint eigenvalue gradient with respect to per-element
   coefficients (not in the paper: first-order perturbation theory of a
   simple eigenpair of a symmetric pencil).
