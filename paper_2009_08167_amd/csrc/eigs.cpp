@@ -1072,8 +1072,6 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
     pb = slice_pairs(B);
     status = B.status;
   }
-  const int nev = split ? (int)std::min<size_t>(o->nev, pa.size() + pb.size())
-                        : std::min(A.nev, (int)pa.size());
   std::vector<int> oa, ia, ob, ib;
   int nf = 0;
   for (size_t i = 0; i < pa.size() && nf < o->nev; ++i, ++nf) {
@@ -1088,7 +1086,6 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
     ob.push_back(nf);
     ib.push_back(pb[i].col);
   }
-  (void)nev;
   if (evecs) {
     launch_copy_cols(oa, ia, A.sv.N, evecs, A.sv.B.p, nullptr, nullptr, s);
     if (!ob.empty()) {
