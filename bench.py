@@ -644,8 +644,8 @@ def main():
         trace_summary(*args.trace_summary)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the spectral slices would shard across GPUs; see DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(the spectral slices would shard across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

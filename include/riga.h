@@ -51,7 +51,7 @@ typedef enum {
   RIGA_ENOCONV = -4,       /* not all requested pairs converged; n_found holds the rest */
   RIGA_ESINGULAR = -5,     /* K - sigma M numerically singular and shift perturbation disabled */
   RIGA_EDEGENERATE = -6,   /* gradient requested for an eigenvalue that is not simple */
-  RIGA_EUNSUPPORTED = -7   /* valid request outside what this build implements */
+  RIGA_EUNSUPPORTED = -7   /* valid request outside what the library implements */
 } riga_status;
 
 enum { RIGA_FP64 = 0, RIGA_MIXED = 1 };            /* riga_eigs_opts.precision */

@@ -1,7 +1,7 @@
 """GPU parity tests: the HIP path through the C ABI against the CPU oracle on
 the same seeded inputs (workloads.py).
 
-Bars (derived in the design doc): assembled K, M entries within 1e-13 relative
+Bars (from the rounding of each computation): assembled K, M entries within 1e-13 relative
 to the matrix max; solves with backward error <= 1e-12; inertia exact;
 eigenvalues within 1e-10 relative, residuals <= 1e-9, M-orthonormality
 within 1e-10, eigenvectors of a cluster inside the oracle's cluster
