@@ -737,6 +737,14 @@ void run_slice(Slice& S) {
   sv.lo = lo;
   sv.hi = hi;
   int nev = S.nev;
+  LookAhead la;
+  la.pr = pr;
+  la.ctx = sv.ctx;
+  // an open-ended slice with a first shift inside it factorises there on
+  // the look-ahead stream while the factorisation at lo proceeds
+  const bool first_ahead =
+      lookahead_on() && !std::isfinite(hi) && !S.after_lo && std::isfinite(S.first_shift) && S.first_shift > lo;
+  if (first_ahead) la.start(S.first_shift, sv.precision, sv.s);
   int64_t nu_lo = 0;
   if (std::isfinite(hi)) {
     sv.factor(hi);
@@ -765,17 +773,31 @@ void run_slice(Slice& S) {
   // that turns out to lie past more eigenvalues than a run is sized for
   // (a poor estimate) is given up for lo
   bool inside = false;
+  if (la.active) {
+    auto a = clk::now();
+    la.join();
+    sv.st.t_fact += secs(a, clk::now());
+    sv.count_factor(la.spare());
+  }
   if (nev > 0 && std::isfinite(S.first_shift) && S.first_shift > lo && S.first_shift < hi_now) {
-    sv.factor(S.first_shift);
+    int64_t k = 0;
+    if (first_ahead) {
+      // the factorisation at lo stays current if the first shift is given up
+      k = la.spare().inertia - nu_lo;
+      if (k <= sv.per_shift) sv.ctx->cur = 1 - sv.ctx->cur;
+    } else {
+      sv.factor(S.first_shift);
+      k = sv.cur().inertia - nu_lo;
+      if (k > sv.per_shift) {
+        sv.factor(lo);
+        sv.st.n_shift++;
+      }
+    }
     sv.st.n_shift++;
-    const int64_t k = sv.cur().inertia - nu_lo;
     if (k <= sv.per_shift) {
       sigma = S.first_shift;
       known = k;
       inside = true;
-    } else {
-      sv.factor(lo);
-      sv.st.n_shift++;
     }
     if (log_on())
       std::fprintf(stderr, "[riga] first shift %.10g: count above lo=%lld (%s)\n", S.first_shift,
@@ -783,9 +805,6 @@ void run_slice(Slice& S) {
   }
   double verified = lo;  // every eigenvalue in [lo, verified) is locked
   const double* init = nullptr;
-  LookAhead la;
-  la.pr = pr;
-  la.ctx = sv.ctx;
   Solver::Ritz last;        // final Ritz data of the last run
   double last_sigma = sigma;  // its shift
   for (int shift = 0; nev > 0 && shift < 400; ++shift) {
