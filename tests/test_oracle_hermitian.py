@@ -4,7 +4,7 @@ arXiv 2009.08167) against what the mathematics fixes:
 
 * Hermitian symmetry of K (antisymmetric imaginary part), real M;
 * A = 0 gives the real oracle's K exactly;
-* the Kronecker form of the same matrices from 1D integrals (a different
+* the Kronecker form of the same matrices from 1D integrals, 2D and 3D (a different
   route from the element-by-element tensor assembly);
 * gauge invariance of the limit: the eigenvalues approach pi^2 (i^2 + j^2)
   from above at the rate of the real problem, h^(2p);
@@ -66,6 +66,26 @@ def test_kronecker_form():
     Mk = np.kron(M1, M1)
     Kk = (np.kron(M1, K1) + np.kron(K1, M1) + (A @ A) * Mk
           + 1j * (A[0] * np.kron(M1, S1) + A[1] * np.kron(S1, M1)))
+    assert np.abs(K.toarray() - Kk).max() <= 1e-12 * np.abs(Kk).max()
+    assert np.abs(M.toarray() - Mk).max() <= 1e-14 * np.abs(Mk).max()
+
+
+def test_kronecker_form_3d():
+    """3D, x fastest: each direction's factor (stiffness, or the magnetic
+    S = G - G^T times that component of A) between the other two masses."""
+    ne, p, s, A = 4, 2, 2, np.array([0.7, -1.2, 0.35])
+    K, M = hermitian.assemble_magnetic(3, ne, p, s, A)
+    K1, M1 = assembly.matrices_1d(ne, p, s)
+    G1 = _g1d(ne, p, s)
+    K1, M1, G1 = K1[1:-1, 1:-1], M1[1:-1, 1:-1], G1[1:-1, 1:-1]
+    S1 = G1 - G1.T
+
+    def k3(z, y, x):
+        return np.kron(np.kron(z, y), x)
+
+    Mk = k3(M1, M1, M1)
+    Kk = (k3(M1, M1, K1) + k3(M1, K1, M1) + k3(K1, M1, M1) + (A @ A) * Mk
+          + 1j * (A[0] * k3(M1, M1, S1) + A[1] * k3(M1, S1, M1) + A[2] * k3(S1, M1, M1)))
     assert np.abs(K.toarray() - Kk).max() <= 1e-12 * np.abs(Kk).max()
     assert np.abs(M.toarray() - Mk).max() <= 1e-14 * np.abs(Mk).max()
 
