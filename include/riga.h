@@ -49,7 +49,7 @@ typedef enum {
   RIGA_ENOMEM = -2,        /* device or host allocation failed */
   RIGA_EDEVICE = -3,       /* a HIP call failed (message names it) */
   RIGA_ENOCONV = -4,       /* not all requested pairs converged; n_found holds the rest */
-  RIGA_ESINGULAR = -5,     /* K - sigma M numerically singular and shift perturbation disabled */
+  RIGA_ESINGULAR = -5,     /* K - sigma M singular to working precision (a pivot was perturbed) */
   RIGA_EDEGENERATE = -6,   /* gradient requested for an eigenvalue that is not simple */
   RIGA_EUNSUPPORTED = -7   /* valid request outside what the library implements */
 } riga_status;
@@ -118,9 +118,18 @@ typedef struct {
   int32_t tree_height;    /* levels of the tree (leaves = 0) */
   int32_t max_front;      /* largest front order */
   int32_t max_fs;         /* largest fully-summed block */
-  int64_t nnz_l;          /* entries of L (lower, diagonal included) */
-  double flops_fact;      /* algorithmic flops of one factorisation */
+  int64_t nnz_l;          /* entries of L (lower, diagonal included) as the supernodal
+                             fronts store them (fully-summed blocks dense) */
+  double flops_fact;      /* flops of one factorisation of those fronts: sum over their
+                             columns of c (c + 1), c = rows below the diagonal */
   int64_t front_pool;     /* entries of the dense front pool */
+  int64_t nnz_l_exact;    /* entries of L for the same elimination order without
+                             pivoting (exact structural fill, diagonal included) */
+  double flops_fact_exact; /* sum over the columns of that L of c (c + 1) */
+  double sweep_bytes_stored; /* FP64 factor bytes one forward + backward elimination reads
+                             as stored (partitioned-inverse blocks of the levels below
+                             the top block, both copies of the top block's inverse);
+                             0 before riga_assemble */
 } riga_problem_info_t;
 
 /* Allocation hooks (e.g. torch's caching allocator).  Optional. */
@@ -130,8 +139,16 @@ typedef struct {
   void (*free)(void* ctx, void* ptr, void* stream);
 } riga_allocator;
 
-/* riga_set_allocator: route the library's device workspaces through `a`
- * (NULL restores hipMalloc/hipFree).  Affects problems created afterwards. */
+/* riga_set_allocator: route the library's device allocations through `a`
+ * (copied; NULL restores hipMalloc/hipFree).  Affects allocations made after
+ * the call, also those of existing problems; each buffer is released by the
+ * allocator that made it, so hooks may be replaced while problems live (the
+ * hook's ctx and functions must stay valid until its buffers are freed).
+ * alloc(ctx, bytes, stream) returns device memory usable on `stream` or
+ * NULL, which makes the calling entry point return RIGA_ENOMEM; nothing
+ * leaks (a failed call releases its own buffers; a problem's buffers go
+ * with riga_destroy).  alloc and free may be called from any thread of the
+ * library.  RIGA_EINVAL if either function is NULL. */
 riga_status riga_set_allocator(const riga_allocator* a);
 
 /* riga_analyze: host-only analysis of a mesh (no device needed): knot
@@ -177,7 +194,8 @@ riga_status riga_get_matrices(const riga_problem* pr, int64_t* row_ptr, int32_t*
                               double* k_vals, double* m_vals);
 
 /* riga_spmv: y = K x, M x or (K - sigma M) x for the last factorised sigma
- * (Sec. 5.1 "mat-vec").  x_dev, y_dev: [n_dof] device FP64. */
+ * (Sec. 5.1 "mat-vec").  x_dev, y_dev: [n_dof] device FP64, not
+ * overlapping.  Queued on `stream`; returns without waiting for it. */
 riga_status riga_spmv(riga_problem* pr, int32_t which, const double* x_dev, double* y_dev,
                       void* stream);
 
@@ -185,7 +203,13 @@ riga_status riga_spmv(riga_problem* pr, int32_t which, const double* x_dev, doub
  * pivoting inside fronts (Sec. 5: one numeric factorisation per shift), in
  * FP64 or (precision = RIGA_MIXED) FP32.  *neg_pivots (may be NULL) receives
  * the inertia nu(K - sigma M), the number of eigenvalues below sigma (Remark
- * on inertia).  The factorisation stays in the problem for riga_solve. */
+ * on inertia).  The factorisation stays in the problem for riga_solve.
+ * A pivot smaller than 1e-20 (||K||_1 + |sigma| ||M||_1) in magnitude is
+ * replaced by that value with its sign (zero counts as positive) and counted
+ * in stats->n_perturbed_pivots; the call then returns RIGA_ESINGULAR (sigma
+ * lies on an eigenvalue to working precision) with *neg_pivots and *stats
+ * filled and the perturbed factorisation kept: solves with it are not
+ * meaningful. */
 riga_status riga_factor(riga_problem* pr, double sigma, int32_t precision,
                         int64_t* neg_pivots, riga_stats* stats);
 
@@ -206,6 +230,23 @@ riga_status riga_solve(riga_problem* pr, const double* b_dev, double* x_dev, int
 riga_status riga_solve_multi(riga_problem* pr, const double* B_dev, double* X_dev, int32_t nrhs,
                              int64_t ld, int32_t max_ir, void* stream);
 
+/* riga_project: one classical Gram-Schmidt pass of the full
+ * M-reorthogonalisation of the Lanczos vectors (Sec. 4.2, Eqs. Lanczos and
+ * LanczosAlphaBeta with a fully reorthogonalised basis):
+ *     c = W^T x,   x <- x - B c,
+ * where B = [b_1 .. b_m] is a basis and W = M B (so c holds the
+ * M-inner products).  W_dev, B_dev: [n x m] column-major device FP64
+ * (leading dimension n); x_dev [n] device FP64, updated in place; c_dev [m]
+ * device FP64 output.  x and c may not overlap W or B.  The reductions over
+ * rows run in a fixed order (results are bitwise reproducible).  A device
+ * workspace of ceil(n / 4096) * m doubles is allocated for the call (the
+ * allocator hook, else hipMalloc) and released before it returns; the call
+ * waits for `stream`.  RIGA_EINVAL unless n >= 1 and
+ * 1 <= m <= RIGA_PROJECT_MAX_COLS. */
+#define RIGA_PROJECT_MAX_COLS 8192
+riga_status riga_project(int64_t n, int32_t m, const double* W_dev, const double* B_dev, double* x_dev,
+                         double* c_dev, void* stream);
+
 /* riga_eigs: the nev lowest eigenpairs with lambda in [lo, hi) (Sec. 4).
  * Spectrum slicing with inertia counts (Sec. 4.1): the factorisation at a
  * guess of the next shift runs on a second HIP stream of the library's own
@@ -224,7 +265,14 @@ riga_status riga_solve_multi(riga_problem* pr, const double* B_dev, double* X_de
  * stats (or NULL): counters and timings.  Returns RIGA_ENOCONV when the
  * restart budget ran out; then n_found < nev and the pairs returned are the
  * complete set of eigenvalues in [lo, sigma) for the last shift sigma whose
- * inertia count they matched. */
+ * inertia count they matched.
+ * Ends and singular shifts: the ends are moved down by 1e-9 relative before
+ * they are factorised, so an eigenvalue within 1e-9 |lo| below lo is
+ * returned and one within 1e-9 |hi| below hi is not (an eigenvalue on an
+ * end, to rounding, counts as lying at lo or at hi).  A shift whose
+ * factorisation perturbs a pivot is moved down by 1e-9 relative and
+ * factorised again (shift perturbation, counted in n_fact); RIGA_ESINGULAR
+ * if three moves do not help. */
 riga_status riga_eigs(riga_problem* pr, const riga_eigs_opts* opts, int32_t* n_found,
                       double* evals_host, double* evecs_dev, double* resid_host,
                       riga_stats* stats);
@@ -257,11 +305,11 @@ riga_status riga_eig_grad(riga_problem* pr, int32_t k, const double* evals_host,
 /* riga_mode_errors: eigenfunction errors of computed eigenpairs against the
  * exact eigenpairs of the Dirichlet Laplacian on the unit square or cube
  * (Eq. exact: lambda_e = pi^2 (i^2 + j^2 [+ k^2]), u_e = 2^(d/2) prod
- * sin(i pi x)), as the accuracy study of Sec. 7 uses them (Eqs. norms,
+ * sin(i pi x)), as the accuracy study of Sec. 8 uses them (Eqs. norms,
  * eigerrors).  Meaningful for a problem assembled with kappa = rho = 1.
  * n_vec computed pairs: lam_host [n_vec] (host), U_dev [n_vec][n_dof]
  * device FP64, M-normalised (the layout riga_eigs returns).  modes_host
- * [n_modes][dim] 1-based mode indices (Sec. 7 uses the diagonal ones).
+ * [n_modes][dim] 1-based mode indices (Sec. 8 uses the diagonal ones).
  * nquad: Gauss points per direction and element for the integrals (0 ->
  * p + 6, at most 16).  Outputs per mode, host [n_modes]:
  *   match    index of the computed eigenvector with the largest |(u_h, u_e)|

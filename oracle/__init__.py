@@ -21,10 +21,12 @@ arXiv 2009.08167, that it follows):
   Cholesky-reduced solve (Sec. 4.1), sparse shift-and-invert solve (Eq.
   ST_GHEP), inertia counts (Remark on inertia), residuals, normalisation.
 * ``accuracy`` -- EVerr, EFerr_L2, EFerr_E against the exact eigenpairs
-  (Eqs. exact, norms, eigerrors; diagonal modes as in Sec. 7).
+  (Eqs. exact, norms, eigerrors; diagonal modes as in Sec. 8).
 * ``hermitian`` -- a complex Hermitian source for the Hermitian case of Eq.
   GHEP: the magnetic Laplacian with a constant potential (gauge-equivalent
   to the Laplacian), its real-equivalent pencil and a dense Hermitian solve.
+* ``lanczos``  -- one classical Gram-Schmidt pass of the full M-
+  reorthogonalisation (Sec. 4.2): c = W^T x, x - B c with W = M B.
 * ``grad``     -- adjoint eigenvalue gradient with respect to per-element
   coefficients (not in the paper: first-order perturbation theory of a
   simple eigenpair of a symmetric pencil).

@@ -6,7 +6,7 @@ Follows Sec. 2 of arXiv 2009.08167: the exact eigenpairs of the Dirichlet
 Laplacian on the unit square and cube (Eq. exact), the L2 and energy norms
 of the eigenfunction error (Eq. norms), the normalised errors EVerr, EFerr_L2
 and EFerr_E (Eq. eigerrors) and the Pythagorean relation between them (Eq.
-Pythagorean); and Sec. 7, which compares eigenfunctions only for the
+Pythagorean); and Sec. 8, which compares eigenfunctions only for the
 diagonal modes (i = j), the others being degenerate.
 
 Readings (the paper is silent on them):

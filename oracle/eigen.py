@@ -13,7 +13,8 @@ directly:
   SuperLU factorisation of K - sigma M, for larger N.
 * ``inertia``     -- Sylvester's law of inertia (Remark on inertia): the number
   of eigenvalues below sigma equals the number of negative pivots of an
-  LDL^T factorisation of K - sigma M.
+  LDL^T factorisation of K - sigma M (``inertia_many``: the same at many
+  shifts, in worker processes).
 """
 import numpy as np
 import scipy.linalg as sla
@@ -74,6 +75,31 @@ def inertia(K, M, sigma):
     if not np.array_equal(lu.perm_r, lu.perm_c):
         raise RuntimeError("SuperLU pivoted off the diagonal; inertia undefined")
     return int(np.count_nonzero(lu.U.diagonal() < 0))
+
+
+_pool_KM = None
+
+
+def _pool_init(K, M):
+    global _pool_KM
+    _pool_KM = (K, M)
+
+
+def _pool_count(sigma):
+    return inertia(_pool_KM[0], _pool_KM[1], sigma)
+
+
+def inertia_many(K, M, sigmas, workers=8):
+    """``inertia(K, M, sigma)`` for every sigma, in a pool of fresh worker
+    processes (each gets its own copy of K and M; the counts are independent
+    factorisations, so only the wall time changes)."""
+    import multiprocessing as mp
+    sigmas = [float(x) for x in sigmas]
+    if workers <= 1 or len(sigmas) < 2:
+        return [inertia(K, M, x) for x in sigmas]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(min(workers, len(sigmas)), initializer=_pool_init, initargs=(K.tocsr(), M.tocsr())) as pool:
+        return pool.map(_pool_count, sigmas, chunksize=1)
 
 
 def residual(K, M, lam, U):

@@ -482,6 +482,46 @@ std::string analyze(int dim, const int ne_in[3], int p, int s, int nquad, int le
     }
   }
 
+  // ---- Exact fill of the elimination order: the elimination tree of the
+  // permuted pattern (ancestors with path compression), then the non-zeros
+  // of each row of L as its row subtree, the union of the tree paths from
+  // the row's entries left of the diagonal up to the row itself.
+  {
+    std::vector<int32_t> eparent(N, -1), anc(N, -1), mark(N, -1);
+    for (int64_t i = 0; i < N; ++i) {
+      const int32_t o = A.iperm[i];
+      for (int64_t e = A.row_ptr[o]; e < A.row_ptr[o + 1]; ++e) {
+        int32_t r = A.perm[A.col_idx[e]];
+        if (r >= i) continue;
+        while (anc[r] != -1 && anc[r] != i) {
+          const int32_t nx = anc[r];
+          anc[r] = (int32_t)i;
+          r = nx;
+        }
+        if (anc[r] == -1) {
+          anc[r] = (int32_t)i;
+          eparent[r] = (int32_t)i;
+        }
+      }
+    }
+    std::vector<int64_t> colcnt(N, 0);
+    int64_t below = 0;
+    for (int64_t i = 0; i < N; ++i) {
+      mark[i] = (int32_t)i;
+      const int32_t o = A.iperm[i];
+      for (int64_t e = A.row_ptr[o]; e < A.row_ptr[o + 1]; ++e) {
+        for (int32_t k = A.perm[A.col_idx[e]]; k < i && mark[k] != i; k = eparent[k]) {
+          mark[k] = (int32_t)i;
+          ++colcnt[k];
+          ++below;
+        }
+      }
+    }
+    A.nnz_l_exact = below + N;
+    A.flops_exact = 0.0;
+    for (int64_t k = 0; k < N; ++k) A.flops_exact += (double)colcnt[k] * (double)(colcnt[k] + 1);
+  }
+
   // ---- Levels by height.
   A.height = 0;
   for (int f = 0; f < nf; ++f) A.height = std::max(A.height, A.f_height[f] + 1);

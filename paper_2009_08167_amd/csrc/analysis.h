@@ -85,6 +85,12 @@ struct Analysis {
   int max_front = 0, max_fs = 0;
   int64_t nnz_l = 0;                 // lower factor entries, diagonal included
   double flops_fact = 0.0;
+  // exact fill of the same elimination order (no pivoting): the entries of
+  // L, diagonal included, and sum over columns of c (c + 1), c = column
+  // count below the diagonal; the supernodal counts above treat every
+  // fully-summed block as dense
+  int64_t nnz_l_exact = 0;
+  double flops_exact = 0.0;
 };
 
 // Builds everything above.  Returns "" on success, else an error message.

@@ -115,6 +115,16 @@ riga_status riga_problem_info(const riga_problem* pr, riga_problem_info_t* info)
   info->nnz_l = a.nnz_l;
   info->flops_fact = a.flops_fact;
   info->front_pool = a.pool_size;
+  info->nnz_l_exact = a.nnz_l_exact;
+  info->flops_fact_exact = a.flops_exact;
+  info->sweep_bytes_stored = 0.0;
+  if (pr->has_device) {
+    const int cut = pr->top.cut >= 0 ? pr->top.cut : a.height;
+    double e = (double)pr->top.e_row + (double)pr->top.e_col;
+    for (int F = 0; F < a.n_fronts; ++F)
+      if (a.f_height[F] < cut) e += 2.0 * (double)a.f_f[F] * (double)a.f_k[F];
+    info->sweep_bytes_stored = 8.0 * e;
+  }
   return RIGA_OK;
 }
 
@@ -164,7 +174,6 @@ riga_status riga_spmv(riga_problem* pr, int32_t which, const double* x, double* 
       vals = F.av.p;
     } else return fail(RIGA_EINVAL, "which must be RIGA_MAT_K, _M or _A");
     riga::launch_spmv(pr, vals, x, y, nullptr, s);
-    HIPCHECK(hipStreamSynchronize(s));
     return RIGA_OK;
   });
 }
@@ -186,6 +195,9 @@ riga_status riga_factor(riga_problem* pr, double sigma, int32_t precision, int64
       stats->n_2x2_pivots = F.two;
       stats->flops_fact = pr->an.flops_fact;
     }
+    if (F.perturbed > 0)
+      return fail(RIGA_ESINGULAR, std::to_string(F.perturbed) +
+                                      " pivot(s) perturbed: K - sigma M is singular to working precision");
     return RIGA_OK;
   });
 }
@@ -250,6 +262,20 @@ riga_status riga_solve_multi(riga_problem* pr, const double* B, double* X, int32
     if (!F.factored) return fail(RIGA_EINVAL, "no factorisation");
     hipStream_t s = (hipStream_t)stream;
     for (int32_t i = 0; i < nrhs; ++i) solve_one(pr, F, B + ld * i, X + ld * i, max_ir, s);
+    HIPCHECK(hipStreamSynchronize(s));
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_project(int64_t n, int32_t m, const double* W, const double* B, double* x, double* c,
+                         void* stream) {
+  return guarded([&]() -> riga_status {
+    if (n < 1 || m < 1 || m > RIGA_PROJECT_MAX_COLS || !W || !B || !x || !c)
+      return fail(RIGA_EINVAL, "need n >= 1, 1 <= m <= RIGA_PROJECT_MAX_COLS and non-null blocks");
+    hipStream_t s = (hipStream_t)stream;
+    riga::DBuf<double> partial;
+    partial.alloc((size_t)riga::proj_row_blocks(n) * m, s);
+    riga::launch_project(W, B, n, m, x, partial.p, c, nullptr, nullptr, s);
     HIPCHECK(hipStreamSynchronize(s));
     return RIGA_OK;
   });

@@ -23,6 +23,7 @@
 #include <cstring>
 #include <functional>
 #include <limits>
+#include <memory>
 #include <numeric>
 #include <string>
 
@@ -44,6 +45,28 @@ constexpr int MAX_IR_FP64 = 2;
 // deflation window, in intervals between consecutive shifts below the shift
 constexpr double DEFLATE_SPACINGS = 4.0;
 
+// Candidate Ritz vectors are projected once against the locked pairs below
+// the deflation window when N * (those pairs) * ceil(candidates / 8) is at
+// most this (the block projection reads the locked block once per 8
+// candidates)
+constexpr double LOCK_PROJECT_MAX = 268435456.0;
+
+// A shift whose factorisation had to perturb a pivot (K - sigma M singular
+// to working precision: the shift sits on an eigenvalue) is moved down by
+// this much, relative, and factorised again, at most SHIFT_MOVES times.
+constexpr double SHIFT_NUDGE = 1e-9;
+constexpr int SHIFT_MOVES = 3;
+
+// The ends of a requested interval are moved down by this much, relative,
+// so that an eigenvalue lying on an end within rounding is counted by the
+// inertia at the end the same way the locking test classifies it: such an
+// eigenvalue counts as lying at lo (returned) or at hi (not returned).
+constexpr double END_SHIFT = 1e-9;
+
+// spectrum slices solved at once at most (each with a host thread, a HIP
+// stream and a solve context of the problem)
+constexpr int MAX_SLICES = 8;
+
 // RIGA_DEFLATE_ALL=1 projects every Lanczos vector against all locked pairs
 // (no window); read per call
 bool deflate_window_on() {
@@ -61,6 +84,24 @@ bool log_on() {
 }
 double secs(clk::time_point a, clk::time_point b) {
   return std::chrono::duration<double>(b - a).count();
+}
+
+// Factorises K - sigma M into F with shift perturbation: while a pivot had
+// to be perturbed, the shift moves down by SHIFT_NUDGE relative and the
+// factorisation is repeated.  F.sigma holds the shift used, F.refactored
+// the repeats.  RIGA_ESINGULAR if SHIFT_MOVES moves do not help.
+void factor_shift(riga_problem* pr, Factor& F, double sigma, int precision, hipStream_t s) {
+  int moves = 0;
+  while (true) {
+    factor_numeric(pr, F, sigma, precision, s);
+    F.refactored = moves;
+    if (F.perturbed == 0) return;
+    if (moves == SHIFT_MOVES)
+      throw Error(RIGA_ESINGULAR, "K - sigma M singular at sigma = " + std::to_string(sigma) +
+                                      " and at " + std::to_string(SHIFT_MOVES) + " shifts below it");
+    sigma -= SHIFT_NUDGE * std::max(std::fabs(sigma), std::numeric_limits<double>::min());
+    ++moves;
+  }
 }
 
 struct Locked {
@@ -85,7 +126,7 @@ struct Solver {
   int64_t nu_lo = 0;     // eigenvalues below lo
   DBuf<double> B, W, x, y, c1, c2, partial, dotp, alpha, beta, scal;
   DBuf<int32_t> flag;
-  DBuf<double> chk, S, Sh, Ub, KU, MU, res3, rqn, lam, rpart;
+  DBuf<double> chk, S, Sh, Ub, KU, MU, res3, rqn, lam, rpart, bpart;
   double* theta = nullptr;  // in chk: theta[mb + 1], est[mb + 1], beta_m, flag
   double* tdest = nullptr;
   double* chk_extra = nullptr;
@@ -144,16 +185,18 @@ struct Solver {
 
   // counts one factorisation (in place or look-ahead) in the statistics
   void count_factor(const Factor& F) {
-    st.n_fact++;
+    st.n_fact += 1 + F.refactored;
     st.n_perturbed_pivots += F.perturbed;
     st.n_2x2_pivots += F.two;
   }
 
-  // factorises K - sigma M in place of the current factorisation
-  void factor(double sigma) {
+  // factorises K - sigma M in place of the current factorisation (at a
+  // shift moved down if sigma is singular; cur().sigma holds the one used)
+  void factor(double sigma, int prec = -1) {
+    if (prec < 0) prec = precision;
     auto a = clk::now();
-    factor_reserve(pr, cur(), precision, pr->home);
-    factor_numeric(pr, cur(), sigma, precision, s);
+    factor_reserve(pr, cur(), prec, pr->home);
+    factor_shift(pr, cur(), sigma, prec, s);
     st.t_fact += secs(a, clk::now());
     count_factor(cur());
   }
@@ -164,7 +207,7 @@ struct Solver {
     const Factor& F = cur();
     solve_fb(pr, F, b, out, s);
     st.n_fb++;
-    const int nir = precision == RIGA_MIXED ? max_ir : max_ir_fp64;
+    const int nir = F.precision == RIGA_MIXED ? max_ir : max_ir_fp64;
     {
       for (int it = 0; it < nir; ++it) {
         // r = b - A x
@@ -314,6 +357,17 @@ struct Solver {
     HIPCHECK(hipMemcpyAsync(Sh.p, Sh_h.data(), Sh_h.size() * sizeof(double), hipMemcpyHostToDevice, s));
     // U = V S (the restart combination lands in column nw)
     launch_gemm_nn(Bc(nl), N, m, Sh.p, m, nc, Ub.p, s);
+    // The steps of this run were projected against the locked pairs of the
+    // deflation window only.  Each FP64 solve leaves components of relative
+    // size ~ (its backward error) ||A|| / |lambda_j - sigma| along the
+    // eigenvectors below the window, which the steps neither amplify nor
+    // remove; over a run they reach ~1e-10 in the Ritz vectors.  One block
+    // projection of the candidates against those locked pairs removes them
+    // (and the part of the residual they cause) before the residual test.
+    if (nw > 0 && c_win > 0 && (double)N * c_win * ((nw + 7) / 8) <= LOCK_PROJECT_MAX) {
+      if (bpart.n == 0) bpart.alloc(block_project_partials(N, (int)lam.n), s);
+      launch_block_project(W.p, B.p, N, c_win, Ub.p, nw, bpart.p, s);
+    }
     int nlocked = 0;
     if (nw > 0) {
       launch_spmm_km(pr, Ub.p, nw, KU.p, MU.p, s);
@@ -657,7 +711,7 @@ struct LookAhead {
     th = std::thread([this, dev, precision] {
       try {
         HIPCHECK(hipSetDevice(dev));
-        factor_numeric(pr, spare(), sigma, precision, s2);
+        factor_shift(pr, spare(), sigma, precision, s2);
       } catch (const Error& e) {
         code = e.code;
         err = e.what();
@@ -668,11 +722,13 @@ struct LookAhead {
     });
   }
 
-  // waits for the factorisation; rethrows its error
+  // waits for the factorisation; rethrows its error.  Afterwards `sigma`
+  // is the shift used (moved down if the guess was singular).
   void join() {
     if (th.joinable()) th.join();
     active = false;
     if (code != RIGA_OK) throw Error(code, "look-ahead factorisation: " + err);
+    sigma = spare().sigma;
   }
 };
 
@@ -705,6 +761,8 @@ struct Slice {
   double first_shift = std::numeric_limits<double>::quiet_NaN();
   riga_status status = RIGA_OK;
   double verified = 0.0;
+  bool requested_ends = true;  // lo and a finite hi are the request's (not a split point)
+  bool count_hi_first = true;  // a finite hi is counted before the runs (else reached by the shifts)
   std::function<void(Slice&)> after_lo;
 };
 
@@ -720,6 +778,10 @@ void setup_solver(Solver& sv, riga_problem* pr, SolveCtx* ctx, const riga_eigs_o
   sv.precision = o->precision;
   sv.max_ir = 2;
   if (const char* v = std::getenv("RIGA_MAX_IR")) sv.max_ir = std::max(0, std::atoi(v));
+  // RIGA_FP64_IR=n refines every FP64 solve n times from the start (the
+  // refinement a stall switches on; n at most MAX_IR_FP64)
+  if (const char* v = std::getenv("RIGA_FP64_IR"))
+    sv.max_ir_fp64 = std::min(MAX_IR_FP64, std::max(0, std::atoi(v)));
   sv.per_shift = o->per_shift > 0 ? o->per_shift : 32;
   sv.max_restarts = o->max_restarts > 0 ? o->max_restarts : 10;
   int mb = o->max_basis > 0 ? o->max_basis : std::max(160, 4 * sv.per_shift + 32);
@@ -733,29 +795,44 @@ void setup_solver(Solver& sv, riga_problem* pr, SolveCtx* ctx, const riga_eigs_o
 void run_slice(Slice& S) {
   Solver& sv = S.sv;
   riga_problem* pr = sv.pr;
-  const double lo = S.lo, hi = S.hi;
-  sv.lo = lo;
-  sv.hi = hi;
+  // the ends in use: moved down when a factorisation there is singular
+  double lo = S.lo, hi = S.hi;
   int nev = S.nev;
   LookAhead la;
   la.pr = pr;
   la.ctx = sv.ctx;
   // an open-ended slice with a first shift inside it factorises there on
   // the look-ahead stream while the factorisation at lo proceeds
-  const bool first_ahead =
-      lookahead_on() && !std::isfinite(hi) && !S.after_lo && std::isfinite(S.first_shift) && S.first_shift > lo;
+  const bool first_ahead = lookahead_on() && (!std::isfinite(hi) || !S.count_hi_first) && !S.after_lo &&
+                           std::isfinite(S.first_shift) && S.first_shift > lo;
   if (first_ahead) la.start(S.first_shift, sv.precision, sv.s);
+  // the counts at the ends decide which eigenvalues the slice returns: in
+  // mixed precision a nonzero end of the request is factorised in FP64, as
+  // an FP32 count cannot resolve an eigenvalue within the end's offset (K is
+  // positive definite, so an end at 0 has no eigenvalue near it).  The
+  // split point between two slices is counted in the solver's precision by
+  // both, so that the two counts there agree.
+  auto end_prec = [&](double x) {
+    return (x == 0.0 || !S.requested_ends) ? sv.precision : (int)RIGA_FP64;
+  };
   int64_t nu_lo = 0;
-  if (std::isfinite(hi)) {
-    sv.factor(hi);
+  if (std::isfinite(hi) && S.count_hi_first) {
+    sv.factor(hi, end_prec(hi));
+    hi = sv.cur().sigma;
     const int64_t nu_hi = sv.cur().inertia;
-    sv.factor(lo);
+    sv.factor(lo, end_prec(lo));
+    lo = std::min(sv.cur().sigma, hi);
     nu_lo = sv.cur().inertia;
-    nev = (int)std::min<int64_t>(nev, nu_hi - nu_lo);
+    nev = (int)std::min<int64_t>(nev, std::max<int64_t>(0, nu_hi - nu_lo));
   } else {
-    sv.factor(lo);
+    sv.factor(lo, end_prec(lo));
+    lo = sv.cur().sigma;
     nu_lo = sv.cur().inertia;
   }
+  S.lo = lo;
+  S.hi = hi;
+  sv.lo = lo;
+  sv.hi = hi;
   if (S.nu_base >= 0) nev = (int)std::max<int64_t>(0, nev - (nu_lo - S.nu_base));
   S.nev = nev;
   sv.nu_lo = nu_lo;
@@ -781,12 +858,15 @@ void run_slice(Slice& S) {
   }
   if (nev > 0 && std::isfinite(S.first_shift) && S.first_shift > lo && S.first_shift < hi_now) {
     int64_t k = 0;
+    double fs = S.first_shift;
     if (first_ahead) {
       // the factorisation at lo stays current if the first shift is given up
+      fs = la.sigma;
       k = la.spare().inertia - nu_lo;
       if (k <= sv.per_shift) sv.ctx->cur = 1 - sv.ctx->cur;
     } else {
       sv.factor(S.first_shift);
+      fs = sv.cur().sigma;
       k = sv.cur().inertia - nu_lo;
       if (k > sv.per_shift) {
         sv.factor(lo);
@@ -794,10 +874,12 @@ void run_slice(Slice& S) {
       }
     }
     sv.st.n_shift++;
-    if (k <= sv.per_shift) {
-      sigma = S.first_shift;
+    if (k <= sv.per_shift && fs > lo) {
+      sigma = fs;
       known = k;
       inside = true;
+    } else if (first_ahead && k <= sv.per_shift) {
+      sv.ctx->cur = 1 - sv.ctx->cur;  // moved below lo: keep the factorisation at lo
     }
     if (log_on())
       std::fprintf(stderr, "[riga] first shift %.10g: count above lo=%lld (%s)\n", S.first_shift,
@@ -899,7 +981,10 @@ void run_slice(Slice& S) {
         next = la.sigma;
       }
     }
-    if (!taken) sv.factor(next);
+    if (!taken) {
+      sv.factor(next);
+      next = sv.cur().sigma;
+    }
     sv.st.n_shift++;
     known = sv.cur().inertia - nu_lo;
     if (log_on())
@@ -970,12 +1055,12 @@ std::vector<double> spectrum_estimates(riga_problem* pr, int count, hipStream_t 
   return est;
 }
 
-// RIGA_SLICES=1 keeps one slice; otherwise an open-ended request for at
-// least 4 runs' worth of pairs is split in two once the inertia at its
-// lower end is known.
-bool split_on() {
+// Spectrum slices of an open-ended request (RIGA_SLICES=n, at most
+// MAX_SLICES; default 2): every slice gets at least two runs' worth of pairs.
+int slices_wanted() {
   const char* v = std::getenv("RIGA_SLICES");
-  return !(v && *v == '1');
+  if (v && *v) return std::max(1, std::min(MAX_SLICES, std::atoi(v)));
+  return 2;
 }
 
 }  // namespace
@@ -986,42 +1071,51 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
   StreamBind bind(pr, s);
   const auto t0 = clk::now();
   *n_found = 0;
-  Slice A;
-  setup_solver(A.sv, pr, &pr->ctx[0], o, s, o->nev);
-  A.lo = o->lo;
-  A.hi = o->hi;
-  A.nev = o->nev;
-  // the second slice: [b, inf) on its own thread, stream and factorisations.
-  // Destruction order: the thread is joined first, the slice's buffers are
-  // freed next, its stream is destroyed last.
-  hipStream_t sb = nullptr;
+  // slices[0] runs on this thread and stream; slices[i > 0] each on a host
+  // thread, HIP stream and solve context of their own.  Destruction order:
+  // the threads are joined first, the slices' buffers are freed next, their
+  // streams are destroyed last.
+  std::vector<hipStream_t> streams;
   struct StreamGuard {
-    hipStream_t& st;
+    std::vector<hipStream_t>& st;
     ~StreamGuard() {
-      if (st) (void)hipStreamDestroy(st);
+      for (hipStream_t x : st)
+        if (x) (void)hipStreamDestroy(x);
     }
-  } stream_guard{sb};
-  Slice B;
-  std::string b_err;
-  riga_status b_code = RIGA_OK;
-  std::thread tb;
+  } stream_guard{streams};
+  std::vector<std::unique_ptr<Slice>> slices;
+  slices.emplace_back(new Slice);
+  std::vector<std::string> errs(MAX_SLICES);
+  std::vector<riga_status> codes(MAX_SLICES, RIGA_OK);
+  std::vector<std::thread> threads;
   struct Joiner {
-    std::thread& t;
+    std::vector<std::thread>& t;
     ~Joiner() {
-      if (t.joinable()) t.join();
+      for (auto& x : t)
+        if (x.joinable()) x.join();
     }
-  } joiner{tb};
+  } joiner{threads};
+  Slice& A = *slices[0];
+  setup_solver(A.sv, pr, &pr->ctx[0], o, s, o->nev);
+  A.lo = o->lo - END_SHIFT * std::fabs(o->lo);
+  A.hi = std::isfinite(o->hi) ? o->hi - END_SHIFT * std::fabs(o->hi) : o->hi;
+  if (!(A.hi > A.lo)) {
+    A.lo = o->lo;
+    A.hi = o->hi;
+  }
+  A.nev = o->nev;
   const int per_shift = o->per_shift > 0 ? o->per_shift : 32;
-  if (split_on() && !std::isfinite(o->hi) && o->nev >= 4 * per_shift) {
+  const int nsl = std::isfinite(o->hi) ? 1 : std::max(1, std::min(slices_wanted(), o->nev / (2 * per_shift)));
+  if (nsl > 1) {
     A.after_lo = [&](Slice& a) {
-      // split where the estimates put half of the pairs below; the second
-      // slice's first runs start half a run's worth of pairs above its
-      // lower end, so that they lock pairs on both sides of their shift
+      // split where the estimates put equal shares of the pairs; each later
+      // slice's first runs start half a run's worth of pairs above its lower
+      // end, so that they lock pairs on both sides of their shift
       Solver& sv = a.sv;
       const int w = std::max(2, per_shift / 8);
-      const int64_t t = sv.nu_lo + a.nev / 2, t1 = t + per_shift / 2;
-      if (t1 + w + 1 > (int64_t)1 << 22) return;
-      const std::vector<double> est = spectrum_estimates(pr, (int)(t1 + w + 1), s);
+      const int64_t t_last = sv.nu_lo + (int64_t)a.nev * (nsl - 1) / nsl + per_shift / 2;
+      if (t_last + w + 1 > (int64_t)1 << 22) return;
+      const std::vector<double> est = spectrum_estimates(pr, (int)(t_last + w + 1), s);
       // the middle of the widest gap between neighbouring estimates around
       // index c (the count of estimates below it lies within c -/+ w)
       auto gap_mid = [&](int64_t c) {
@@ -1030,12 +1124,20 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
           if (est[i] - est[i - 1] > est[best] - est[best - 1]) best = i;
         return 0.5 * (est[best] + est[best - 1]);
       };
-      const double b = gap_mid(t), s1 = gap_mid(t1);
-      if (!(b > a.lo) || !(s1 > b) || !std::isfinite(s1)) return;
-      // the second slice brings its own Lanczos storage (room for all nev
-      // pairs: how many lie below b is not known yet) and two more
+      std::vector<double> b(nsl), s1(nsl);
+      b[0] = a.lo;
+      for (int i = 1; i < nsl; ++i) {
+        const int64_t t = sv.nu_lo + (int64_t)a.nev * i / nsl;
+        b[i] = gap_mid(t);
+        s1[i] = gap_mid(t + per_shift / 2);
+        if (!(b[i] > b[i - 1]) || !(s1[i] > b[i]) || !std::isfinite(s1[i])) return;
+      }
+      for (int i = 1; i + 1 < nsl; ++i)
+        if (!(s1[i] < b[i + 1])) return;
+      // every later slice brings its own Lanczos storage (room for all nev
+      // pairs: how many lie in it is not known yet) and two more
       // factorisations: split only when the device holds them with room to
-      // spare (the one-slice solve is the same computation, serial)
+      // spare (fewer slices are the same computation, serial)
       const int cap_b = o->nev;
       const double n = (double)sv.N;
       const double cols = (double)std::min<int64_t>(cap_b + 2 * sv.per_shift + 32, sv.N) + sv.mb + 1;
@@ -1044,80 +1146,89 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
       const TopDev& td = pr->top;
       const double fact = (double)an.pool_size + (double)an.h_size + (double)td.e_row + (double)td.e_col +
                           (double)td.e_cb + 4.0 * (double)n + (double)pr->kv.n;
-      // (a third factorisation's worth of margin: the first slice's
-      // look-ahead factorisation may not be allocated yet)
-      const double need = 8.0 * (2.0 * n * cols + 3.0 * n * umax + 3.0 * fact);
+      // (a further factorisation's worth of margin per slice: the first
+      // slice's look-ahead factorisation may not be allocated yet)
+      const double need = 8.0 * (nsl - 1) * (2.0 * n * cols + 3.0 * n * umax + 3.0 * fact);
       size_t free_b = 0, total_b = 0;
       HIPCHECK(hipMemGetInfo(&free_b, &total_b));
       if (need * 1.15 > (double)free_b) {
         if (log_on())
-          std::fprintf(stderr, "[riga] no split: the second slice needs %.1f GB, %.1f GB free\n", need * 1e-9,
-                       (double)free_b * 1e-9);
+          std::fprintf(stderr, "[riga] no split: %d more slices need %.1f GB, %.1f GB free\n", nsl - 1,
+                       need * 1e-9, (double)free_b * 1e-9);
         return;
       }
-      a.hi = b;
-      if (log_on()) std::fprintf(stderr, "[riga] split at %.10g, second slice's first shift %.10g\n", b, s1);
-      HIPCHECK(hipStreamCreateWithFlags(&sb, hipStreamNonBlocking));
+      a.hi = b[1];
       const int dev = pr->device;
-      B.lo = b;
-      B.hi = o->hi;
-      B.nev = o->nev;
-      B.nu_base = sv.nu_lo;
-      B.first_shift = s1;
-      tb = std::thread([&, dev, cap_b] {
-        try {
-          HIPCHECK(hipSetDevice(dev));
-          setup_solver(B.sv, pr, &pr->ctx[1], o, sb, cap_b);
-          run_slice(B);
-        } catch (const Error& e) {
-          b_code = e.code;
-          b_err = e.what();
-        } catch (const std::exception& e) {
-          b_code = RIGA_EDEVICE;
-          b_err = e.what();
-        }
-      });
+      for (int i = 1; i < nsl; ++i) {
+        hipStream_t si = nullptr;
+        HIPCHECK(hipStreamCreateWithFlags(&si, hipStreamNonBlocking));
+        streams.push_back(si);
+        slices.emplace_back(new Slice);
+        Slice& S = *slices.back();
+        S.lo = b[i];
+        S.hi = i + 1 < nsl ? b[i + 1] : o->hi;
+        S.requested_ends = false;
+        S.count_hi_first = false;
+        S.nev = o->nev;
+        S.nu_base = i + 1 < nsl ? -1 : sv.nu_lo;
+        S.first_shift = s1[i];
+        if (log_on())
+          std::fprintf(stderr, "[riga] slice %d: [%.10g, %.10g), first shift %.10g\n", i, S.lo, S.hi, s1[i]);
+      }
+      for (int i = 1; i < nsl; ++i) {
+        Slice* S = slices[i].get();
+        hipStream_t si = streams[i - 1];
+        threads.emplace_back([&, S, si, i, dev, cap_b] {
+          try {
+            HIPCHECK(hipSetDevice(dev));
+            setup_solver(S->sv, pr, &pr->ctx[i], o, si, cap_b);
+            run_slice(*S);
+          } catch (const Error& e) {
+            codes[i] = e.code;
+            errs[i] = e.what();
+          } catch (const std::exception& e) {
+            codes[i] = RIGA_EDEVICE;
+            errs[i] = e.what();
+          }
+        });
+      }
     };
   }
   run_slice(A);
-  if (tb.joinable()) tb.join();
-  if (b_code != RIGA_OK) throw Error(b_code, "second slice: " + b_err);
-  // results: the first slice's pairs, then (if it is complete) the second's
-  std::vector<Locked> pa = slice_pairs(A);
-  std::vector<Locked> pb;
-  riga_status status = A.status;
-  const bool split = sb != nullptr;
-  if (split && A.status == RIGA_OK) {
-    pb = slice_pairs(B);
-    status = B.status;
-  }
-  std::vector<int> oa, ia, ob, ib;
+  for (auto& t : threads)
+    if (t.joinable()) t.join();
+  for (int i = 1; i < (int)slices.size(); ++i)
+    if (codes[i] != RIGA_OK) throw Error(codes[i], "spectrum slice " + std::to_string(i) + ": " + errs[i]);
+  // results: the slices' pairs in order, up to the first slice that did not
+  // complete (the pairs above it would leave a gap)
+  riga_status status = RIGA_OK;
   int nf = 0;
-  for (size_t i = 0; i < pa.size() && nf < o->nev; ++i, ++nf) {
-    if (evals) evals[nf] = pa[i].lam;
-    if (resid) resid[nf] = pa[i].resid;
-    oa.push_back(nf);
-    ia.push_back(pa[i].col);
-  }
-  for (size_t i = 0; i < pb.size() && nf < o->nev; ++i, ++nf) {
-    if (evals) evals[nf] = pb[i].lam;
-    if (resid) resid[nf] = pb[i].resid;
-    ob.push_back(nf);
-    ib.push_back(pb[i].col);
-  }
-  if (evecs) {
-    launch_copy_cols(oa, ia, A.sv.N, evecs, A.sv.B.p, nullptr, nullptr, s);
-    if (!ob.empty()) {
-      HIPCHECK(hipStreamSynchronize(sb));
-      launch_copy_cols(ob, ib, B.sv.N, evecs, B.sv.B.p, nullptr, nullptr, s);
+  for (int i = 0; i < (int)slices.size() && nf < o->nev; ++i) {
+    const Slice& S = *slices[i];
+    const std::vector<Locked> pairs = slice_pairs(S);
+    std::vector<int> out, in;
+    for (size_t q = 0; q < pairs.size() && nf < o->nev; ++q, ++nf) {
+      if (evals) evals[nf] = pairs[q].lam;
+      if (resid) resid[nf] = pairs[q].resid;
+      out.push_back(nf);
+      in.push_back(pairs[q].col);
+    }
+    if (evecs && !out.empty()) {
+      if (i > 0) HIPCHECK(hipStreamSynchronize(streams[i - 1]));
+      launch_copy_cols(out, in, S.sv.N, evecs, S.sv.B.p, nullptr, nullptr, s);
+    }
+    if (S.status != RIGA_OK) {
+      status = S.status;
+      break;
     }
   }
   HIPCHECK(hipStreamSynchronize(s));
   *n_found = nf;
+  const bool split = slices.size() > 1;
   const int wanted = split ? o->nev : A.nev;
   if (nf < wanted && status == RIGA_OK) status = RIGA_ENOCONV;
   riga_stats st = A.sv.st;
-  if (split) add_stats(st, B.sv.st);
+  for (int i = 1; i < (int)slices.size(); ++i) add_stats(st, slices[i]->sv.st);
   st.t_total = secs(t0, clk::now());
   st.flops_fact = pr->an.flops_fact;
   st.bytes_fb = (double)pr->an.nnz_l * 2.0 * (o->precision == RIGA_MIXED ? 4.0 : 8.0);

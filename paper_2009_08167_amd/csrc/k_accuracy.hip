@@ -1,7 +1,7 @@
 // Eigenfunction errors against the exact eigenpairs of the Dirichlet
 // Laplacian on the unit square and cube (Eq. exact of arXiv 2009.08167):
 // the L2 and energy norms of u_h - u_e (Eq. norms) that define EFerr_L2 and
-// EFerr_E (Eq. eigerrors), for the diagonal modes that Sec. 7 compares.
+// EFerr_E (Eq. eigerrors), for the diagonal modes that Sec. 8 compares.
 //
 // 1. load_1d: g_{m,d}[a] = int B_a(x) sqrt(2) sin(i_{m,d} pi x) dx for every
 //    mode m, direction d and interior function a (Gauss rule of q points per

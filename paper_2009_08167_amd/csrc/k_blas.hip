@@ -278,7 +278,7 @@ constexpr int GEMM_CB = 16;
 constexpr int GEMM_KC = 128;
 __global__ void __launch_bounds__(256) gemm_nn_kernel(const double* __restrict__ V, int64_t n,
                                                     int k, const double* __restrict__ S, int lds,
-                                                    int m, double* __restrict__ U) {
+                                                    int m, double* __restrict__ U, int sub) {
   __shared__ double ss[GEMM_KC * GEMM_CB];
   const int c0 = blockIdx.y * GEMM_CB;
   const int nc = min(GEMM_CB, m - c0);
@@ -302,8 +302,72 @@ __global__ void __launch_bounds__(256) gemm_nn_kernel(const double* __restrict__
       }
     }
   }
-  if (r < n)
-    for (int q = 0; q < nc; ++q) U[(int64_t)(c0 + q) * n + r] = acc[q];
+  if (r < n) {
+    if (sub)
+      for (int q = 0; q < nc; ++q) U[(int64_t)(c0 + q) * n + r] -= acc[q];
+    else
+      for (int q = 0; q < nc; ++q) U[(int64_t)(c0 + q) * n + r] = acc[q];
+  }
+}
+
+// Partial sums of C = W^T U over row blocks of TN_RB rows, for a tile of
+// TN_T columns of W and TN_T columns of U per workgroup: each thread keeps
+// the TN_T x TN_T products of its rows, the waves reduce them with
+// shuffles, and partial[(rb * c + i) * m + q] takes the workgroup's sum.
+constexpr int TN_T = 8;
+constexpr int TN_RB = 4096;
+
+__global__ void __launch_bounds__(256) gemm_tn_partial_kernel(const double* __restrict__ W, int64_t n, int c,
+                                                            const double* __restrict__ U, int m,
+                                                            double* __restrict__ partial) {
+  __shared__ double red[4][TN_T * TN_T];
+  const int rb = blockIdx.x;
+  const int i0 = blockIdx.y * TN_T, q0 = blockIdx.z * TN_T;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r1 = min((int64_t)(rb + 1) * TN_RB, n);
+  double acc[TN_T][TN_T];
+#pragma unroll
+  for (int a = 0; a < TN_T; ++a)
+#pragma unroll
+    for (int b = 0; b < TN_T; ++b) acc[a][b] = 0.0;
+  for (int64_t r = (int64_t)rb * TN_RB + threadIdx.x; r < r1; r += 256) {
+    double w[TN_T], u[TN_T];
+#pragma unroll
+    for (int a = 0; a < TN_T; ++a) {
+      w[a] = i0 + a < c ? W[(int64_t)(i0 + a) * n + r] : 0.0;
+      u[a] = q0 + a < m ? U[(int64_t)(q0 + a) * n + r] : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < TN_T; ++a)
+#pragma unroll
+      for (int b = 0; b < TN_T; ++b) acc[a][b] += w[a] * u[b];
+  }
+#pragma unroll
+  for (int a = 0; a < TN_T; ++a)
+#pragma unroll
+    for (int b = 0; b < TN_T; ++b) {
+      double v = acc[a][b];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0) red[wave][a * TN_T + b] = v;
+    }
+  __syncthreads();
+  if (threadIdx.x < TN_T * TN_T) {
+    const int a = threadIdx.x / TN_T, b = threadIdx.x % TN_T;
+    const double v = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+    if (i0 + a < c && q0 + b < m) partial[((int64_t)rb * c + i0 + a) * m + q0 + b] = v;
+  }
+}
+
+// C(i, q) = sum over row blocks (ascending) of the partials; C column-major
+// with leading dimension c.
+__global__ void gemm_tn_reduce_kernel(const double* __restrict__ partial, int nrb, int c, int m,
+                                      double* __restrict__ C) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= c * m) return;
+  const int i = e % c, q = e / c;
+  double s = 0.0;
+  for (int rb = 0; rb < nrb; ++rb) s += partial[((int64_t)rb * c + i) * m + q];
+  C[(int64_t)q * c + i] = s;
 }
 
 // Per column q of the n x m blocks: mode 0 -> partial sums of (u^T K u,
@@ -519,7 +583,33 @@ void launch_gemm_nn(const double* V, int64_t n, int k, const double* S, int lds,
                     hipStream_t s) {
   if (m <= 0 || k <= 0) return;
   dim3 grid((unsigned)((n + 255) / 256), (m + GEMM_CB - 1) / GEMM_CB);
-  gemm_nn_kernel<<<grid, 256, 0, s>>>(V, n, k, S, lds, m, U);
+  gemm_nn_kernel<<<grid, 256, 0, s>>>(V, n, k, S, lds, m, U, 0);
+  HIPCHECK(hipGetLastError());
+}
+
+constexpr int BP_CHUNK = 512;  // columns of W, B per block-projection pass
+
+static int tn_row_blocks(int64_t n) { return (int)((n + TN_RB - 1) / TN_RB); }
+
+size_t block_project_partials(int64_t n, int m) {
+  return (size_t)tn_row_blocks(n) * (size_t)BP_CHUNK * (size_t)m + (size_t)BP_CHUNK * (size_t)m;
+}
+
+void launch_block_project(const double* W, const double* B, int64_t n, int c, double* U, int m,
+                          double* partial, hipStream_t s) {
+  if (c <= 0 || m <= 0) return;
+  const int nrb = tn_row_blocks(n);
+  for (int a = 0; a < c; a += BP_CHUNK) {
+    const int cc = std::min(BP_CHUNK, c - a);
+    const double* Wa = W + (int64_t)a * n;
+    const double* Ba = B + (int64_t)a * n;
+    double* C = partial + (size_t)nrb * cc * m;
+    dim3 g1((unsigned)nrb, (unsigned)((cc + TN_T - 1) / TN_T), (unsigned)((m + TN_T - 1) / TN_T));
+    gemm_tn_partial_kernel<<<g1, 256, 0, s>>>(Wa, n, cc, U, m, partial);
+    gemm_tn_reduce_kernel<<<(unsigned)((cc * m + 255) / 256), 256, 0, s>>>(partial, nrb, cc, m, C);
+    dim3 g2((unsigned)((n + 255) / 256), (m + GEMM_CB - 1) / GEMM_CB);
+    gemm_nn_kernel<<<g2, 256, 0, s>>>(Ba, n, cc, C, cc, m, U, 1);
+  }
   HIPCHECK(hipGetLastError());
 }
 

@@ -416,7 +416,11 @@ template <class T, int MAXF>
 void factor_levels(riga_problem* pr, Factor& F, T* pool, T* hpool, double sigma, bool checked,
                    hipStream_t s) {
   FrontArgs fa = front_args(pr, F);
-  const double pivtol = 1e-20 * (pr->normK1 + fabs(sigma) * pr->normM1);
+  // a pivot below pivtol is replaced by +-pivtol and counted (static
+  // pivoting); RIGA_PIVTOL_REL overrides the relative threshold 1e-20
+  double rel = 1e-20;
+  if (const char* v = std::getenv("RIGA_PIVTOL_REL")) rel = std::atof(v);
+  const double pivtol = rel * (pr->normK1 + fabs(sigma) * pr->normM1);
   set_kernel_attributes();
   for (size_t h = 0; h < pr->levels.size(); ++h) {
     LevelDev& L = pr->levels[h];

@@ -25,23 +25,30 @@ void hip_check(hipError_t e, const char* what);
 #define RIGA_STR(x) RIGA_STR2(x)
 #define HIPCHECK(x) ::riga::hip_check((x), __FILE__ ":" RIGA_STR(__LINE__) ": " #x)
 
-// Device allocation through the optional allocator hook.
-void* dmalloc(size_t bytes, hipStream_t s);
-void dfree(void* p, hipStream_t s);
+// Device allocation through the optional allocator hook.  The release
+// function of the allocator that made an allocation (none: hipFree) travels
+// with it, so replacing the hook never frees a buffer through another one.
+struct Release {
+  void* ctx = nullptr;
+  void (*free)(void* ctx, void* ptr, void* stream) = nullptr;
+};
+void* dmalloc(size_t bytes, hipStream_t s, Release* how);
+void dfree(void* p, hipStream_t s, const Release& how);
 
 template <class T>
 struct DBuf {
   T* p = nullptr;
   size_t n = 0;
   hipStream_t s = nullptr;
+  Release how;
   DBuf() = default;
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; o.n = 0; }
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), s(o.s), how(o.how) { o.p = nullptr; o.n = 0; }
   DBuf& operator=(DBuf&& o) noexcept {
     if (this != &o) {
       reset();
-      p = o.p; n = o.n; s = o.s;
+      p = o.p; n = o.n; s = o.s; how = o.how;
       o.p = nullptr; o.n = 0;
     }
     return *this;
@@ -50,11 +57,11 @@ struct DBuf {
   void alloc(size_t count, hipStream_t st) {
     reset();
     s = st;
+    if (count) p = (T*)dmalloc(count * sizeof(T), st, &how);
     n = count;
-    if (count) p = (T*)dmalloc(count * sizeof(T), st);
   }
   void reset() {
-    if (p) dfree(p, s);
+    if (p) dfree(p, s, how);
     p = nullptr;
     n = 0;
   }
@@ -202,6 +209,7 @@ struct Factor {
   double sigma = 0.0;
   int64_t inertia = 0;
   int perturbed = 0, two = 0;
+  int refactored = 0;  // repeats at a shift moved off a singular one (riga_eigs)
 };
 
 // The mutable state of one solve: two factorisations (the current one and
@@ -246,8 +254,9 @@ struct riga_problem {
   std::vector<riga::LevelDev> levels;
 
   // numeric factorisations: ctx[0].current() is the one riga_factor /
-  // riga_solve use; ctx[1] serves a second slice of the spectrum
-  riga::SolveCtx ctx[2];
+  // riga_solve use; ctx[i] serves the i-th further slice of the spectrum
+  // (buffers are allocated on first use)
+  riga::SolveCtx ctx[8];
   riga::DBuf<riga::WorkUnit> inv_units;     // row blocks of every front
   int n_inv_units = 0;
 
@@ -352,6 +361,12 @@ void launch_scale2(const double* x, const double* y, const double* partial, int 
                    double* w, int64_t n, double* beta_out, int32_t* flag, hipStream_t s);
 void launch_gemm_nn(const double* V, int64_t n, int k, const double* S, int lds, int m,
                     double* U, hipStream_t s);
+// U -= B (W^T U) for the n x c blocks W, B and the n x m block U (all
+// column-major, ld = n), in passes of at most 512 columns of W and B;
+// partial holds block_project_partials(n, m) doubles of scratch.
+size_t block_project_partials(int64_t n, int m);
+void launch_block_project(const double* W, const double* B, int64_t n, int c, double* U, int m,
+                          double* partial, hipStream_t s);
 // partial: residual_partials(n, m) doubles of scratch
 int residual_partials(int64_t n, int m);
 void launch_residuals(const double* KU, const double* MU, const double* U, int64_t n, int m,

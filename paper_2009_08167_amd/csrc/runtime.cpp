@@ -17,6 +17,7 @@ static bool g_alloc_set = false;
 static std::mutex g_alloc_mu;
 
 void set_allocator(const riga_allocator* a) {
+  if (a && (!a->alloc || !a->free)) throw Error(RIGA_EINVAL, "allocator needs both alloc and free");
   std::lock_guard<std::mutex> lk(g_alloc_mu);
   if (a) {
     g_alloc = *a;
@@ -32,22 +33,33 @@ void hip_check(hipError_t e, const char* what) {
                 std::string(what) + ": " + hipGetErrorString(e));
 }
 
-void* dmalloc(size_t bytes, hipStream_t s) {
+void* dmalloc(size_t bytes, hipStream_t s, Release* how) {
   void* p = nullptr;
-  if (g_alloc_set && g_alloc.alloc) {
-    p = g_alloc.alloc(g_alloc.ctx, bytes, (void*)s);
-    if (!p) throw Error(RIGA_ENOMEM, "allocator hook returned NULL");
+  riga_allocator a{};
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    if (g_alloc_set) a = g_alloc;
+  }
+  if (a.alloc) {
+    p = a.alloc(a.ctx, bytes, (void*)s);
+    if (!p) throw Error(RIGA_ENOMEM, "allocator hook returned NULL for " + std::to_string(bytes) + " bytes");
+    how->ctx = a.ctx;
+    how->free = a.free;
     return p;
   }
   hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) throw Error(RIGA_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(RIGA_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  *how = Release{};
   return p;
 }
 
-void dfree(void* p, hipStream_t s) {
+void dfree(void* p, hipStream_t s, const Release& how) {
   if (!p) return;
-  if (g_alloc_set && g_alloc.free) {
-    g_alloc.free(g_alloc.ctx, p, (void*)s);
+  if (how.free) {
+    how.free(how.ctx, p, (void*)s);
     return;
   }
   (void)hipFree(p);
@@ -102,6 +114,10 @@ void load_and_assemble(riga_problem* pr, const double* kappa, const double* rho,
 void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
   Analysis& an = pr->an;
   hipStream_t s = (hipStream_t)desc->stream;
+  // before the first launch of any problem: raising a kernel's LDS limit
+  // while another thread launches kernels is a race in the runtime (the
+  // batched solves once crashed in a launch while workers set attributes)
+  set_kernel_attributes();
   pr->home = s;
   pr->stream = s;
   HIPCHECK(hipGetDevice(&pr->device));

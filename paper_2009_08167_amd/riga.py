@@ -22,9 +22,10 @@ RIGA_MAT_K, RIGA_MAT_M, RIGA_MAT_A = 0, 1, 2
 EXPORTED = ["riga_set_allocator", "riga_analyze", "riga_assemble", "riga_update_coefficients",
             "riga_problem_info",
             "riga_tree_export", "riga_get_matrices", "riga_spmv", "riga_factor", "riga_solve",
-            "riga_solve_multi", "riga_eigs", "riga_eigs_batched", "riga_eig_grad", "riga_mode_errors",
-            "riga_exact_eigenvalues", "riga_destroy", "riga_status_string",
+            "riga_solve_multi", "riga_project", "riga_eigs", "riga_eigs_batched", "riga_eig_grad",
+            "riga_mode_errors", "riga_exact_eigenvalues", "riga_destroy", "riga_status_string",
             "riga_last_error"]
+RIGA_PROJECT_MAX_COLS = 8192
 
 
 class MeshDesc(C.Structure):
@@ -57,7 +58,15 @@ class ProblemInfo(C.Structure):
     _fields_ = [("n_dof", C.c_int64), ("n_elem", C.c_int64), ("nnz", C.c_int64),
                 ("n1", C.c_int32 * 3), ("n_fronts", C.c_int32), ("tree_height", C.c_int32),
                 ("max_front", C.c_int32), ("max_fs", C.c_int32), ("nnz_l", C.c_int64),
-                ("flops_fact", C.c_double), ("front_pool", C.c_int64)]
+                ("flops_fact", C.c_double), ("front_pool", C.c_int64),
+                ("nnz_l_exact", C.c_int64), ("flops_fact_exact", C.c_double),
+                ("sweep_bytes_stored", C.c_double)]
+
+
+class Allocator(C.Structure):
+    _fields_ = [("ctx", C.c_void_p),
+                ("alloc", C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)),
+                ("free", C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p))]
 
 
 class RigaError(RuntimeError):
@@ -77,6 +86,7 @@ def lib():
             raise RuntimeError("libriga.so not built: run `python -m paper_2009_08167_amd.build`")
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
+        L.riga_set_allocator.argtypes = [C.POINTER(Allocator)]
         L.riga_analyze.argtypes = [C.POINTER(MeshDesc), C.POINTER(P)]
         L.riga_assemble.argtypes = [C.POINTER(MeshDesc), C.POINTER(P)]
         L.riga_problem_info.argtypes = [P, C.POINTER(ProblemInfo)]
@@ -89,6 +99,7 @@ def lib():
         L.riga_solve_multi.argtypes = [P, P, P, C.c_int32, C.c_int64, C.c_int32, P]
         L.riga_eigs.argtypes = [P, C.POINTER(EigsOpts), C.POINTER(C.c_int32), P, P, P,
                                 C.POINTER(Stats)]
+        L.riga_project.argtypes = [C.c_int64, C.c_int32, P, P, P, P, P]
         L.riga_eig_grad.argtypes = [P, C.c_int32, P, P, P, P, P, P]
         L.riga_mode_errors.argtypes = [P, C.c_int32, P, P, C.c_int32, P, C.c_int32, P, P, P, P, P, P]
         L.riga_exact_eigenvalues.argtypes = [C.c_int32, C.c_int32, P]
@@ -102,7 +113,7 @@ def lib():
                      "riga_problem_info", "riga_tree_export",
                      "riga_get_matrices", "riga_spmv", "riga_factor", "riga_solve", "riga_solve_multi",
                      "riga_eigs", "riga_eig_grad", "riga_set_allocator", "riga_eigs_batched",
-                     "riga_mode_errors", "riga_exact_eigenvalues"]:
+                     "riga_mode_errors", "riga_exact_eigenvalues", "riga_project"]:
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -137,6 +148,14 @@ class Problem:
                      for f, _ in ProblemInfo._fields_}
         self.n_dof = int(inf.n_dof)
         self.n_elem = int(inf.n_elem)
+
+    def refresh_info(self):
+        """riga_problem_info again (its sweep bytes depend on the device set-up)."""
+        inf = ProblemInfo()
+        _check(lib().riga_problem_info(self._h, C.byref(inf)))
+        self.info = {f: (list(getattr(inf, f)) if f == "n1" else getattr(inf, f))
+                     for f, _ in ProblemInfo._fields_}
+        return self.info
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -204,17 +223,25 @@ class Problem:
         shape = (self.n_dof, self.n_dof)
         return sp.csr_matrix((kv, ci, rp), shape=shape), sp.csr_matrix((mv, ci, rp), shape=shape)
 
-    def spmv(self, which, x, stream=None):
+    def spmv(self, which, x, y=None, stream=None):
+        """y = K x, M x or (K - sigma M) x (queued on the stream)."""
         import torch
-        y = torch.empty_like(x)
+        if y is None:
+            y = torch.empty_like(x)
         _check(lib().riga_spmv(self._h, which, _ptr(x), _ptr(y), _stream(stream)))
         return y
 
-    def factor(self, sigma, precision=RIGA_FP64):
+    def factor(self, sigma, precision=RIGA_FP64, allow_singular=False):
+        """Factorise K - sigma M; returns (inertia, stats).  stats["status"]
+        is RIGA_ESINGULAR (raised unless allow_singular) when a pivot had to
+        be perturbed."""
         neg = C.c_int64(0)
         st = Stats()
-        _check(lib().riga_factor(self._h, float(sigma), precision, C.byref(neg), C.byref(st)))
-        return int(neg.value), st.as_dict()
+        code = lib().riga_factor(self._h, float(sigma), precision, C.byref(neg), C.byref(st))
+        _check(code, allow=(RIGA_ESINGULAR,) if allow_singular else ())
+        d = st.as_dict()
+        d["status"] = code
+        return int(neg.value), d
 
     def solve(self, b, max_ir=0, stream=None):
         import torch
@@ -254,7 +281,9 @@ class Problem:
         n = int(nf.value)
         if U is not None:
             U = U[:n].T
-        return lam[:n], U, res[:n], st.as_dict()
+        d = st.as_dict()
+        d["status"] = code
+        return lam[:n], U, res[:n], d
 
     def eig_grad(self, lam, U, w, stream=None):
         """Gradient of sum_i w_i lam_i w.r.t. (kappa, rho); U: [n_dof, k]
@@ -293,6 +322,66 @@ class Problem:
                                       _stream(stream)))
         out["match"] = match.astype(np.int64)
         return out
+
+
+def project(W, B, x, c=None, stream=None):
+    """One Gram-Schmidt pass (riga_project): c = W^T x, x -= B c, with W, B
+    contiguous float64 device tensors of shape [m, n] (row i = column i of
+    the n x m block) and x [n] updated in place.  Returns c [m] (written into
+    `c` if given)."""
+    import torch
+    m, n = B.shape
+    if W.shape != B.shape or x.shape != (n,) or not (W.is_contiguous() and B.is_contiguous()
+                                                     and x.is_contiguous()):
+        raise ValueError("W, B: contiguous [m, n]; x: contiguous [n]")
+    if c is None:
+        c = torch.empty(m, dtype=torch.float64, device=x.device)
+    _check(lib().riga_project(n, m, _ptr(W), _ptr(B), _ptr(x), _ptr(c), _stream(stream)))
+    return c
+
+
+_alloc_keep = None
+
+
+def set_allocator(alloc=None, free=None):
+    """Route the library's device allocations through Python callables
+    alloc(nbytes, stream_int) -> device pointer int (0 on failure) and
+    free(ptr_int, stream_int); set_allocator() restores hipMalloc/hipFree.
+    The callables stay referenced here until replaced (buffers made by a
+    replaced hook are still released through it, so keep it alive while
+    such problems live: see `keep`)."""
+    global _alloc_keep
+    if alloc is None:
+        _check(lib().riga_set_allocator(None))
+        return None
+
+    def _a(ctx, nbytes, stream):
+        try:
+            return int(alloc(int(nbytes), int(stream or 0))) or None
+        except Exception:
+            return None
+
+    def _f(ctx, ptr, stream):
+        free(int(ptr), int(stream or 0))
+
+    a = Allocator(None, Allocator._fields_[1][1](_a), Allocator._fields_[2][1](_f))
+    _check(lib().riga_set_allocator(C.byref(a)))
+    _alloc_keep = (a, _a, _f, alloc, free)
+    return _alloc_keep
+
+
+def use_torch_allocator():
+    """Route the library's device allocations through torch's caching
+    allocator (on the stream the library passes)."""
+    import torch
+
+    def alloc(nbytes, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes, stream=stream)
+
+    def free(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return set_allocator(alloc, free)
 
 
 def exact_eigenvalues(dim, count):
@@ -400,11 +489,21 @@ def _autograd():
         def forward(ctx, kappa, rho, w, dim, ne, p, s):
             nev = w.numel()
             pr = assemble(dim, ne, p, s, kappa.detach(), rho.detach(), device=kappa.device)
-            lam, U, _, _ = pr.eigs(nev)
+            # one pair more than the loss uses: a loss that cuts through a
+            # multiple eigenvalue has no gradient (the sum depends on which
+            # basis of the eigenspace the cut keeps)
+            lam, U, _, _ = pr.eigs(min(nev + 1, pr.n_dof))
+            if len(lam) > nev:
+                a, b = lam[nev - 1], lam[nev]
+                if abs(b - a) <= 1e-8 * max(abs(a), abs(b)):
+                    raise RigaError(RIGA_EDEGENERATE, "eigenvalues %d and %d are not separated: "
+                                    "the loss cuts through a multiple eigenvalue" % (nev - 1, nev))
+            lam, U = lam[:nev], U[:, :nev]
             ctx.pr, ctx.U = pr, U
             ctx.lam = lam
             ctx.save_for_backward(w)
             lam_t = torch.as_tensor(lam, dtype=torch.float64, device=kappa.device)
+            ctx.lam_t = lam_t
             return (w.to(torch.float64) * lam_t).sum()
 
         @staticmethod
@@ -412,7 +511,9 @@ def _autograd():
             (w,) = ctx.saved_tensors
             wg = (w.detach().double() * g.detach().double()).cpu().numpy()
             gk, gr = ctx.pr.eig_grad(ctx.lam, ctx.U, wg)
-            return gk, gr, None, None, None, None, None
+            # d L / d w_i = lambda_i
+            gw = (g.detach().double() * ctx.lam_t).to(w.dtype) if ctx.needs_input_grad[2] else None
+            return gk, gr, gw, None, None, None, None
 
     return EigSum
 

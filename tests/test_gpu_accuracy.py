@@ -1,6 +1,6 @@
 """GPU parity of the accuracy study (riga_mode_errors): eigenfunction errors
 of computed eigenpairs against the exact Laplace modes (Eqs. exact, norms,
-eigerrors of arXiv 2009.08167; diagonal modes as in Sec. 7).
+eigerrors of arXiv 2009.08167; diagonal modes as in Sec. 8).
 
 * Parity: the oracle's dense eigenpairs go to both the GPU entry point and
   the oracle (oracle/accuracy.py), which compute the same integrals with the

@@ -8,7 +8,8 @@ can compute one piece at a time (see the oracle's pins in test_oracle_*.py):
   K and M; the 20 lowest against ARPACK shift-and-invert; the oracle's
   inertia count (Remark on inertia) at shifts it picks from its own lowest
   eigenvalues equals the number of returned pairs below each (no pair
-  missed or repeated).
+  missed or repeated); every one of the 200 eigenvalues bracketed to 1e-10
+  relative by the oracle's inertia counts just below and above it.
 * 3D 32^3 p=2 rIGA (blocks of 8) and IGA, kappa = rho = 1, 100 lowest, FP64
   and mixed precision: every eigenvalue against the exact discrete spectrum of
   Kronecker sums (Eq. 2Dmatrix and its 3D analogue), compared as a sorted
@@ -43,6 +44,31 @@ def _say(*a):
     sys.stdout.flush()
 
 
+def _bracket_every_eigenvalue(Ko, Mo, lam, tag, rel=1e-10):
+    """Every returned eigenvalue pinned to `rel` by the oracle's own inertia
+    counts (Remark on inertia): for each group of returned eigenvalues whose
+    brackets [lam (1 - rel), lam (1 + rel)) overlap, the oracle's count below
+    the group's lower bracket end equals the number of returned pairs below
+    the group, and its count below the upper end adds the group's size.
+    So the oracle's pencil has exactly those eigenvalues in the brackets, and
+    none between them: no pair missed, repeated, or off by more than rel."""
+    groups = [[0, 1]]
+    for i in range(1, len(lam)):
+        if lam[i] * (1 - rel) <= lam[i - 1] * (1 + rel):
+            groups[-1][1] = i + 1
+        else:
+            groups.append([i, i + 1])
+    pts = []
+    for a, b in groups:
+        pts += [lam[a] * (1 - rel), lam[b - 1] * (1 + rel)]
+    cnt = eigen.inertia_many(Ko, Mo, pts)
+    bad = [(a, b, cnt[2 * g], cnt[2 * g + 1]) for g, (a, b) in enumerate(groups)
+           if cnt[2 * g] != a or cnt[2 * g + 1] != b]
+    _say(tag, "eigenvalues bracketed by the oracle's inertia at rel", rel, ":", len(lam),
+         "in", len(groups), "groups; mismatches", bad[:5])
+    assert not bad
+
+
 def _sampled_checks(Ko, Mo, lam, U, n_sample, eigsh_k, tag):
     """Residuals, M-orthonormality, inertia between sampled neighbours, and
     the lowest eigsh_k eigenvalues against ARPACK."""
@@ -72,6 +98,7 @@ def _sampled_checks(Ko, Mo, lam, U, n_sample, eigsh_k, tag):
         assert cnt == below
 
 
+@pytest.mark.timeout(600)
 def test_2d_256_p3_riga16_full_size():
     riga = _riga()
     w = workloads.c2(True)
@@ -85,6 +112,7 @@ def test_2d_256_p3_riga16_full_size():
     assert len(lam) == w.nev and res.max() <= 1e-9
     Ko, Mo = assembly.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
     _sampled_checks(Ko, Mo, lam, U.cpu().numpy(), 6, 20, w.name)
+    _bracket_every_eigenvalue(Ko, Mo, lam, w.name)
 
 
 def _kron_spectrum(dim, ne, p, s, count):
@@ -118,6 +146,7 @@ def test_3d_32_p2_full_size(refined, precision):
     assert r.max() <= 1e-9
 
 
+@pytest.mark.timeout(600)
 def test_batched_64_instances_sampled():
     riga = _riga()
     ws = workloads.c4()
@@ -138,3 +167,4 @@ def test_batched_64_instances_sampled():
         kappa, rho = w.coefficients()
         Ko, Mo = assembly.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
         _sampled_checks(Ko, Mo, lam, U.cpu().numpy(), 3, w.nev, w.name)
+        _bracket_every_eigenvalue(Ko, Mo, lam, w.name)

@@ -61,10 +61,12 @@ def test_gradient_full_size_against_oracle(c5_problem):
     assert abs(rho @ gr + L) <= 1e-10 * L
 
 
+@pytest.mark.timeout(600)
 def test_gradient_central_differences(c5_problem):
-    """Central FD, h = 1e-6 relative, on 10 of the seeded elements, for kappa
-    and rho.  Accept |g_adj - g_FD| <= 1e-4 |g_FD| + 10 dL / h, with dL the
-    spread of repeated solves of the unperturbed problem (at least 1e-13 L)."""
+    """Central FD, h = 1e-6 relative, on all 50 seeded elements, for kappa
+    and rho (200 perturbed solves).  Accept |g_adj - g_FD| <= 1e-4 |g_FD| +
+    10 dL / h, with dL the spread of repeated solves of the unperturbed
+    problem (at least 1e-13 L)."""
     riga, w, kappa, rho, pr, lam, U = c5_problem
     wts = w.extra["weights"]
     gk, gr = pr.eig_grad(lam, U, wts)
@@ -75,7 +77,9 @@ def test_gradient_central_differences(c5_problem):
     h = 1e-6
     kd = torch.tensor(kappa, dtype=torch.float64, device="cuda")
     rd = torch.tensor(rho, dtype=torch.float64, device="cuda")
-    for e in w.extra["fd_elements"][:10]:
+    assert len(w.extra["fd_elements"]) == 50
+    worst = 0.0
+    for e in w.extra["fd_elements"]:
         for which in ("k", "r"):
             vals = []
             for sgn in (1, -1):
@@ -87,8 +91,9 @@ def test_gradient_central_differences(c5_problem):
             fd = (vals[0] - vals[1]) / (2 * h * base)
             adj = gk[e] if which == "k" else gr[e]
             tol = 1e-4 * abs(fd) + 10 * dL / (h * base)
-            _say("fd", e, which, adj, fd, tol)
+            worst = max(worst, abs(adj - fd) / tol)
             assert abs(adj - fd) <= tol, (e, which, adj, fd, tol)
+    _say("FD on 50 elements x (kappa, rho): worst |adj - fd| / tol", worst)
     pr.update_coefficients(kd, rd)
 
 
@@ -105,6 +110,26 @@ def test_eigsum_autograd(c5_problem):
     gk, gr = pr.eig_grad(lam, U, wts)
     assert torch.allclose(kt.grad, gk, rtol=1e-9, atol=1e-12 * gk.abs().max().item())
     assert torch.allclose(rt.grad, gr, rtol=1e-9, atol=1e-12 * gr.abs().max().item())
+    # d L / d w_i = lambda_i
+    wt2 = wt.clone().requires_grad_(True)
+    loss2 = EigSum.apply(kt.detach(), rt.detach(), wt2, w.dim, w.ne, w.p, w.s)
+    loss2.backward()
+    assert np.allclose(wt2.grad.cpu().numpy(), lam, rtol=1e-12, atol=0)
+
+
+def test_eigsum_rejects_a_loss_cut_through_a_multiple_eigenvalue():
+    """kappa = rho = 1 on the square: lambda_2 = lambda_3 (modes (1,2) and
+    (2,1)); a loss over the two lowest cuts that pair, has no gradient, and
+    is refused with RIGA_EDEGENERATE."""
+    riga = _riga()
+    from paper_2009_08167_amd import EigSum
+    ne = 16
+    k = torch.ones(ne * ne, dtype=torch.float64, device="cuda", requires_grad=True)
+    r = torch.ones(ne * ne, dtype=torch.float64, device="cuda", requires_grad=True)
+    wt = torch.tensor([1.0, 0.5], dtype=torch.float64, device="cuda")
+    with pytest.raises(riga.RigaError) as e:
+        EigSum.apply(k, r, wt, 2, ne, 2, 0)
+    assert e.value.code == riga.RIGA_EDEGENERATE
 
 
 def test_gradient_rejects_degenerate_pairs():

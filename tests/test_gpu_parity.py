@@ -33,9 +33,12 @@ def _say(*a):
     sys.stdout.flush()
 
 
+# degrees 1-5 (the paper's studies use p = 2...5; its 2D headline case is
+# p = 5), 2D and 3D, IGA and rIGA with ragged last blocks
 ASM_CASES = [workloads.c1(), workloads.small(2, 24, 3, 8, 10, 0.5),
              workloads.small(3, 6, 2, 3, 10, 0.4), workloads.small(2, 19, 4, 5, 10, 0.5),
-             workloads.small(2, 12, 1, 0, 10, 0.2)]
+             workloads.small(2, 12, 1, 0, 10, 0.2), workloads.small(2, 17, 5, 4, 10, 0.5),
+             workloads.small(2, 11, 5, 0, 10, 0.3), workloads.small(3, 7, 3, 3, 10, 0.4)]
 
 
 @pytest.mark.parametrize("w", ASM_CASES, ids=lambda w: w.name)
@@ -68,7 +71,8 @@ def test_spmv_matches_oracle():
 FACT_CASES = [workloads.small(2, 16, 2, 0, 10, 0.3), workloads.small(2, 24, 3, 8, 10, 0.5),
               workloads.small(3, 6, 2, 3, 10, 0.3), workloads.small(2, 40, 3, 8, 10, 0.3),
               workloads.small(3, 10, 2, 0, 10, 0.3), workloads.small(2, 64, 3, 0, 10, 0.3),
-              workloads.small(2, 96, 2, 16, 10, 0.3)]
+              workloads.small(2, 96, 2, 16, 10, 0.3), workloads.small(2, 20, 5, 5, 10, 0.4),
+              workloads.small(2, 48, 5, 16, 10, 0.3), workloads.small(3, 8, 3, 4, 10, 0.3)]
 
 
 @pytest.mark.parametrize("w", FACT_CASES, ids=lambda w: w.name)
@@ -135,7 +139,9 @@ def test_eigs_c1_lowest_10():
 
 
 EIG_CASES = [workloads.small(2, 24, 3, 8, 40, 0.5), workloads.small(3, 6, 2, 3, 30, 0.0),
-             workloads.small(2, 30, 2, 0, 60, 0.3), workloads.small(2, 20, 4, 5, 25, 0.5)]
+             workloads.small(2, 30, 2, 0, 60, 0.3), workloads.small(2, 20, 4, 5, 25, 0.5),
+             workloads.small(2, 20, 5, 5, 40, 0.5), workloads.small(2, 16, 5, 0, 30, 0.3),
+             workloads.small(3, 7, 3, 3, 30, 0.3)]
 
 
 @pytest.mark.parametrize("w", EIG_CASES, ids=lambda w: w.name)
@@ -267,124 +273,300 @@ def test_mixed_eigs_match_fp64_bar(w):
 
 
 def test_budget_exhausted_returns_only_verified_pairs():
-    """With a tiny restart budget on a spectrum with 3- and 6-fold
-    multiplicities (3D, kappa = rho = 1), the solver may stop early; every
-    pair it returns must then be exactly the lowest eigenvalues (no gap), as
-    the inertia count at its last completed shift guarantees."""
+    """With a tiny restart budget (one Lanczos run per shift) on spectra with
+    multiple eigenvalues (kappa = rho = 1: 3D 3- and 6-fold, 2D 2-fold),
+    single-vector runs miss copies of a multiple eigenvalue and the solver
+    stops with RIGA_ENOCONV; the pairs it returns must then be exactly the
+    oracle's eigenvalues from lo up to the last shift whose inertia count
+    they completed (no gap, no cluster cut).  The 2D requests start between
+    the double (1,2)/(2,1) pair and the simple (2,2) mode with one or two
+    pairs per shift, so that a first shift can complete before a double
+    eigenvalue exhausts the budget: at least one request must stop with
+    n >= 1."""
     riga = _riga()
-    w = workloads.small(3, 6, 2, 3, 60, 0.0)
-    _say("budget", w.name)
-    pr = riga.assemble(w.dim, w.ne, w.p, w.s, leaf_dofs=32)
-    lam, U, res, st = pr.eigs(w.nev, per_shift=8, max_basis=20, max_restarts=1, allow_partial=True)
-    _say("found", len(lam), "stats", st)
-    Ko, Mo = assembly.assemble(w.dim, w.ne, w.p, w.s)
-    lr = eigen.dense_eigh(Ko, Mo)[0]
-    n = len(lam)
-    if n:
-        assert np.max(np.abs(lam - lr[:n]) / lr[:n]) <= 1e-10
-        assert res.max() <= 1e-9
+    cases = []
+    w3 = workloads.small(3, 6, 2, 3, 60, 0.0)
+    for per_shift, max_basis in ((4, 12), (8, 20)):
+        cases.append((w3, 0.0, per_shift, max_basis))
+    w2 = workloads.small(2, 20, 2, 5, 30, 0.0)
+    for per_shift, max_basis in ((1, 12), (2, 12), (1, 20), (2, 16)):
+        cases.append((w2, None, per_shift, max_basis))
+    partial = 0
+    ref = {}
+    for w, lo, per_shift, max_basis in cases:
+        if w.name not in ref:
+            Ko, Mo = assembly.assemble(w.dim, w.ne, w.p, w.s)
+            ref[w.name] = eigen.dense_eigh(Ko, Mo)[0]
+        lr = ref[w.name]
+        if lo is None:
+            assert lr[2] < lr[3] * (1 - 1e-6) and lr[3] < lr[4] * (1 - 1e-6)
+            lo = 0.5 * (lr[2] + lr[3])
+        first = int(np.searchsorted(lr, lo))
+        pr = riga.assemble(w.dim, w.ne, w.p, w.s, leaf_dofs=32)
+        lam, U, res, st = pr.eigs(w.nev, lo=lo, per_shift=per_shift, max_basis=max_basis,
+                                  max_restarts=1, allow_partial=True)
+        n = len(lam)
+        _say(w.name, "lo", lo, "per_shift", per_shift, "basis", max_basis, "found", n,
+             "status", st["status"])
+        if st["status"] == riga.RIGA_OK:
+            assert n == w.nev
+        else:
+            assert st["status"] == riga.RIGA_ENOCONV and n < w.nev
+        if n:
+            want = lr[first:first + n]
+            assert np.max(np.abs(lam - want) / want) <= 1e-10
+            assert res.max() <= 1e-9
+            if n < w.nev:
+                # a complete set below a shift: the next eigenvalue is not a
+                # copy of the last one returned
+                assert lr[first + n] > lr[first + n - 1] * (1 + 1e-8)
+                partial += 1
+    assert partial >= 1
 
 
-def test_solve_multi_matches_solve():
-    """riga_solve_multi queues the sweeps back to back: every column equals
-    riga_solve's result bit for bit, FP64 and refined mixed precision."""
+def _unit_pencil_n1(riga):
+    """2D, 2 x 2 elements, p = 1: one interior function, so K - sigma M is the
+    1 x 1 matrix K00 - sigma M00.  rho is chosen from a few candidates so that
+    the assembled M00 is a power of two; then sigma = K00 / M00 is exact and
+    K00 - sigma M00 is exactly zero in any evaluation order."""
+    import fractions
+    for rho_c in (9.0 / 8.0 * (1 + k * 2.0 ** -52) for k in (0, 1, -1, 2, -2, 3, -3, 4, -4)):
+        pr = riga.assemble(2, 2, 1, 0, np.ones(4), np.full(4, rho_c))
+        K, M = pr.matrices()
+        k00, m00 = float(K[0, 0]), float(M[0, 0])
+        mant, _ = np.frexp(m00)
+        if mant == 0.5:
+            sigma = k00 / m00
+            assert fractions.Fraction(sigma) * fractions.Fraction(m00) == fractions.Fraction(k00)
+            return pr, sigma
+    pytest.fail("no candidate coefficient gave a power-of-two mass entry")
+
+
+def test_factor_at_an_eigenvalue_reports_singular():
+    """sigma exactly on the eigenvalue of a 1 x 1 pencil: the zero pivot is
+    perturbed (counted), riga_factor returns RIGA_ESINGULAR with the inertia
+    #{lambda < sigma} = 0 (the perturbation keeps the sign of +0); a shift
+    just below and just above gives the exact counts 0 and 1."""
     riga = _riga()
-    w = workloads.small(2, 40, 3, 8, 10, 0.3)
-    _say("solve_multi", w.name)
-    kappa, rho = w.coefficients()
-    pr = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho, leaf_dofs=32)
-    B = torch.randn(5, pr.n_dof, dtype=torch.float64, device="cuda")
-    for prec, ir in ((riga.RIGA_FP64, 0), (riga.RIGA_MIXED, 3)):
-        pr.factor(650.0, prec)
-        X = pr.solve_multi(B, max_ir=ir)
-        for i in range(B.shape[0]):
-            x = pr.solve(B[i].contiguous(), max_ir=ir)
-            assert torch.equal(X[i], x), (prec, i)
-    assert pr.solve_multi(B[:0]).shape[0] == 0
+    pr, sigma = _unit_pencil_n1(riga)
+    _say("singular shift", sigma)
+    neg, st = pr.factor(sigma, allow_singular=True)
+    assert st["status"] == riga.RIGA_ESINGULAR
+    assert st["n_perturbed_pivots"] == 1
+    assert neg == 0
+    with pytest.raises(riga.RigaError) as e:
+        pr.factor(sigma)
+    assert e.value.code == riga.RIGA_ESINGULAR
+    for sg, expect in ((sigma * (1 - 1e-12), 0), (sigma * (1 + 1e-12), 1)):
+        neg, st = pr.factor(sg)
+        assert st["status"] == riga.RIGA_OK and st["n_perturbed_pivots"] == 0 and neg == expect
 
 
-@pytest.mark.parametrize("w", [workloads.small(2, 64, 3, 0, 10, 0.3), workloads.small(3, 10, 2, 0, 10, 0.3)],
-                         ids=lambda w: w.name)
-def test_blocked_fronts_checked_and_unchecked_agree(w, monkeypatch):
-    """The blocked (multi-workgroup) fronts run their predicted panel steps
-    without host checks; RIGA_FACTOR_CHECKED=1 makes the host check every
-    level.  Both give the same inertia and bitwise the same solve."""
+def test_eigs_with_lo_on_a_double_eigenvalue():
+    """lo set to an exact double eigenvalue (kappa = rho = 1: the Kronecker
+    sum mu_1 + mu_2 = mu_2 + mu_1, computed by the oracle in FP64): the
+    inertia at lo may count either copy on either side of it by rounding.
+    The solver resolves the end consistently and returns the eigenvalues at
+    and above lo, both copies included, as the dense oracle has them."""
     riga = _riga()
-    _say("checked vs unchecked", w.name)
+    import scipy.linalg as sla
+    dim, ne, p, s, nev = 2, 20, 2, 5, 24
+    K1, M1 = assembly.matrices_1d(ne, p, s)
+    mu = sla.eigh(K1[1:-1, 1:-1], M1[1:-1, 1:-1], eigvals_only=True)
+    lo = mu[0] + mu[1]
+    Ko, Mo = assembly.assemble(dim, ne, p, s)
+    lr, Ur = eigen.dense_eigh(Ko, Mo)
+    first = int(np.searchsorted(lr, lo * (1 - 1e-12)))
+    assert abs(lr[first] - lo) <= 1e-12 * lo and abs(lr[first + 1] - lo) <= 1e-12 * lo
+    assert lr[first + 2] > lo * (1 + 1e-6) and lr[first - 1] < lo * (1 - 1e-6)
+    pr = riga.assemble(dim, ne, p, s, leaf_dofs=32)
+    for prec in (riga.RIGA_FP64, riga.RIGA_MIXED):
+        _say("lo on a double eigenvalue", lo, "precision", prec)
+        lam, U, res, st = pr.eigs(nev, lo=lo, precision=prec, per_shift=8)
+        _say("stats", st)
+        assert st["status"] == riga.RIGA_OK and len(lam) == nev
+        _check_pairs(Ko, Mo, lr[first:], Ur[:, first:], lam, U.cpu().numpy(), res, nev)
+    # the same value as the upper end of an interval: both copies excluded
+    hi = lo
+    lam, U, res, st = pr.eigs(nev, lo=0.0, hi=hi, per_shift=8)
+    assert len(lam) == first
+    assert np.max(np.abs(lam - lr[:first]) / lr[:first]) <= 1e-10
+
+
+def test_eigs_singular_shifts_exhausted(monkeypatch):
+    """Every factorisation forced to perturb pivots (RIGA_PIVTOL_REL = 1):
+    riga_eigs moves its first shift down three times, then returns
+    RIGA_ESINGULAR; the problem stays usable."""
+    riga = _riga()
+    w = workloads.small(2, 16, 2, 4, 10, 0.3)
     kappa, rho = w.coefficients()
     pr = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
-    b = torch.randn(pr.n_dof, dtype=torch.float64, device="cuda")
-    for sigma in (0.0, 900.0):
-        for prec in (riga.RIGA_FP64, riga.RIGA_MIXED):
-            monkeypatch.delenv("RIGA_FACTOR_CHECKED", raising=False)
-            n0, _ = pr.factor(sigma, prec)
-            x0 = pr.solve(b)
-            monkeypatch.setenv("RIGA_FACTOR_CHECKED", "1")
-            n1, _ = pr.factor(sigma, prec)
-            x1 = pr.solve(b)
-            assert n0 == n1
-            assert torch.equal(x0, x1), (sigma, prec)
-
-
-@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
-def test_two_slices_match_one(prec, monkeypatch):
-    """An open-ended request for many pairs is split, once the inertia at its
-    lower end is known, into two slices solved at once (the second starting
-    inside its interval); the result equals the single-slice
-    solve and the dense oracle (eigenvalues <= 1e-10, residuals <= 1e-9,
-    M-orthonormality across the two slices' vectors <= 1e-10)."""
-    riga = _riga()
-    w = workloads.small(2, 40, 3, 8, 140, 0.3)
-    kappa, rho = w.coefficients()
-    pr = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho, leaf_dofs=32)
-    _say("slices", w.name, "N", pr.n_dof, "nev", w.nev)
+    monkeypatch.setenv("RIGA_PIVTOL_REL", "1.0")
+    with pytest.raises(riga.RigaError) as e:
+        pr.eigs(w.nev)
+    assert e.value.code == riga.RIGA_ESINGULAR
+    monkeypatch.delenv("RIGA_PIVTOL_REL")
+    lam, U, res, st = pr.eigs(w.nev)
     Ko, Mo = assembly.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
     lr, Ur = eigen.dense_eigh(Ko, Mo)
-    monkeypatch.setenv("RIGA_SLICES", "1")
-    l1, U1, r1, s1 = pr.eigs(w.nev, precision=prec)
-    monkeypatch.delenv("RIGA_SLICES")
-    l2, U2, r2, s2 = pr.eigs(w.nev, precision=prec)
-    _say("one slice", s1, "two slices", s2)
-    assert s2["n_shift"] >= 2
-    for lam, U, res in ((l1, U1, r1), (l2, U2, r2)):
+    _check_pairs(Ko, Mo, lr, Ur, lam, U.cpu().numpy(), res, w.nev)
+
+
+@pytest.mark.parametrize("w", [workloads.small(2, 24, 3, 8, 40, 0.5), workloads.small(3, 7, 3, 3, 30, 0.3)],
+                         ids=lambda w: w.name)
+def test_fp64_refined_solves_match_oracle(w, monkeypatch):
+    """The FP64 iterative refinement a stall switches on (x += A^{-1}(b - A x)
+    after every FP64 solve), forced from the start with RIGA_FP64_IR: the
+    refinement runs (n_ir > 0) and the pairs still meet every bar."""
+    riga = _riga()
+    _say("fp64 refinement", w.name)
+    kappa, rho = w.coefficients()
+    pr = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho, leaf_dofs=32)
+    for n_ir in (1, 2):
+        monkeypatch.setenv("RIGA_FP64_IR", str(n_ir))
+        lam, U, res, st = pr.eigs(w.nev, per_shift=16)
+        _say("stats", st)
+        assert st["n_ir"] > 0 and st["n_fb"] >= (n_ir + 1) * st["n_ir"] // n_ir
+        Ko, Mo = assembly.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
+        lr, Ur = eigen.dense_eigh(Ko, Mo)
         _check_pairs(Ko, Mo, lr, Ur, lam, U.cpu().numpy(), res, w.nev)
 
 
-def test_two_slices_above_a_lower_bound():
-    """An open-ended request above lo > 0: the split estimate counts from the
-    inertia at lo, and the pairs returned are the oracle's 31st to 170th."""
+def test_allocator_hook_routes_every_buffer():
+    """riga_set_allocator with torch's caching allocator: assembly, a solve
+    that splits into two spectrum slices (three host threads and streams)
+    and the gradient allocate through the hook; every block it handed out is
+    returned by riga_destroy; results equal those made with hipMalloc."""
     riga = _riga()
     w = workloads.small(2, 40, 3, 8, 140, 0.3)
     kappa, rho = w.coefficients()
-    Ko, Mo = assembly.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
-    lr, Ur = eigen.dense_eigh(Ko, Mo)
-    k = 30
-    lo = 0.5 * (lr[k - 1] + lr[k])
-    pr = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho, leaf_dofs=32)
-    _say("lower bound", w.name, "lo", lo)
-    lam, U, res, st = pr.eigs(w.nev, lo=lo)
-    _say("stats", st)
-    assert st["n_shift"] >= 3
-    _check_pairs(Ko, Mo, lr[k:], Ur[:, k:], lam, U.cpu().numpy(), res, w.nev)
+    ref = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho, leaf_dofs=32)
+    l0, U0, r0, _ = ref.eigs(w.nev)
+    ref.close()
+    live = {}
+    calls = {"alloc": 0, "free": 0}
+
+    def alloc(nbytes, stream):
+        ptr = torch.cuda.caching_allocator_alloc(nbytes, stream=stream)
+        live[ptr] = nbytes
+        calls["alloc"] += 1
+        return ptr
+
+    def free(ptr, stream):
+        assert ptr in live
+        del live[ptr]
+        calls["free"] += 1
+        torch.cuda.caching_allocator_delete(ptr)
+
+    riga.set_allocator(alloc, free)
+    try:
+        pr = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho, leaf_dofs=32)
+        lam, U, res, st = pr.eigs(w.nev)
+        _say("hooked", calls, "stats", st)
+        assert np.array_equal(lam, l0) and torch.equal(U, U0)
+        gk, gr = pr.eig_grad(lam[:8], U[:, :8], np.ones(8))
+        assert calls["alloc"] > 20
+        pr.close()
+        torch.cuda.synchronize()
+        assert not live, "blocks not returned: %d" % len(live)
+    finally:
+        riga.set_allocator()
 
 
-@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
-def test_two_slices_with_high_contrast_coefficients(prec):
-    """rho = 1e4 on a 4 x 4 block of elements in a corner, 1 elsewhere
-    (kappa = 1): the block holds most of the weight in Weyl's leading term
-    but, being small, few of the low modes, so the split's estimate (the
-    scaled Dirichlet-Laplace spectrum) puts 65 pairs below the split point
-    where the oracle has 25.  Each slice counts its own pairs by inertia, so
-    the result still equals the oracle's."""
+def test_allocator_hook_failure_gives_enomem():
+    """A hook that returns NULL once it has handed out n blocks: riga_assemble
+    or riga_eigs fails with RIGA_ENOMEM, and every block the hook did hand out
+    comes back (the failing call's own, or the problem's at destroy).  n runs
+    from inside the assembly to inside the solve (counted with a hook that
+    never fails)."""
     riga = _riga()
-    dim, ne, p, s, nev = 2, 40, 3, 8, 130
-    e = np.arange(ne * ne)
-    kappa = np.ones(ne * ne)
-    rho = np.where((e % ne < 4) & (e // ne < 4), 1e4, 1.0)
-    Ko, Mo = assembly.assemble(dim, ne, p, s, kappa, rho)
-    lr, Ur = eigen.dense_eigh(Ko, Mo)
-    pr = riga.assemble(dim, ne, p, s, kappa, rho, leaf_dofs=32)
-    _say("high contrast", prec)
-    lam, U, res, st = pr.eigs(nev, precision=prec)
-    _say("stats", st)
-    _check_pairs(Ko, Mo, lr, Ur, lam, U.cpu().numpy(), res, nev)
+    w = workloads.small(2, 24, 3, 8, 20, 0.5)
+    kappa, rho = w.coefficients()
+
+    def hooks(limit, state):
+        def alloc(nbytes, stream):
+            if limit is not None and state["n"] >= limit:
+                return 0
+            state["n"] += 1
+            ptr = torch.cuda.caching_allocator_alloc(nbytes, stream=stream)
+            state["live"][ptr] = nbytes
+            return ptr
+
+        def free(ptr, stream):
+            del state["live"][ptr]
+            torch.cuda.caching_allocator_delete(ptr)
+        return alloc, free
+
+    def attempt(limit):
+        state = {"n": 0, "live": {}}
+        riga.set_allocator(*hooks(limit, state))
+        codes, n_asm = [], None
+        try:
+            try:
+                pr = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
+                n_asm = state["n"]
+            except riga.RigaError as e:
+                codes.append(e.code)
+                pr = None
+            if pr is not None:
+                try:
+                    pr.eigs(w.nev)
+                except riga.RigaError as e:
+                    codes.append(e.code)
+                pr.close()
+        finally:
+            riga.set_allocator()
+        torch.cuda.synchronize()
+        return codes, n_asm, state
+
+    codes, n_asm, st = attempt(None)
+    n_all = st["n"]
+    assert not codes and not st["live"] and n_all > n_asm
+    for limit in (2, n_asm // 2, n_asm, n_asm + 3, (n_asm + n_all) // 2, n_all - 1):
+        codes, _, st = attempt(limit)
+        _say("hook limit", limit, "of", n_all, "codes", codes, "left", len(st["live"]))
+        assert codes == [riga.RIGA_ENOMEM]
+        assert not st["live"]
+
+
+@pytest.mark.parametrize("n,m", [(1, 1), (4095, 3), (4097, 34), (82369, 257), (9000, 8192)],
+                         ids=lambda v: str(v))
+def test_project_matches_oracle(n, m):
+    """riga_project (one Gram-Schmidt pass, Sec. 4.2) against the oracle's
+    pass on the same seeded blocks: ragged row blocks (4096 rows per partial
+    sum), an odd number of columns, and the largest m.  Bar: each entry
+    within 1e-13 of the sum of the magnitudes of its terms."""
+    riga = _riga()
+    from oracle import lanczos
+    rng = np.random.default_rng(n + 7 * m)
+    W = rng.standard_normal((m, n))
+    B = rng.standard_normal((m, n))
+    x = rng.standard_normal(n)
+    c_o, x_o = lanczos.cgs_pass(W.T, B.T, x)
+    Wd = torch.tensor(W, device="cuda")
+    Bd = torch.tensor(B, device="cuda")
+    xd = torch.tensor(x, device="cuda")
+    _say("project", n, m)
+    c = riga.project(Wd, Bd, xd).cpu().numpy()
+    xg = xd.cpu().numpy()
+    scale_c = np.abs(W) @ np.abs(x)
+    assert np.all(np.abs(c - c_o) <= 1e-13 * scale_c)
+    scale_x = np.abs(x) + np.abs(B.T) @ np.abs(c_o)
+    assert np.all(np.abs(xg - x_o) <= 1e-13 * scale_x)
+    # bitwise reproducible
+    xd2 = torch.tensor(x, device="cuda")
+    c2 = riga.project(Wd, Bd, xd2)
+    assert np.array_equal(c2.cpu().numpy(), c) and np.array_equal(xd2.cpu().numpy(), xg)
+
+
+def test_project_rejects_bad_sizes():
+    riga = _riga()
+    W = torch.zeros((2, 5), dtype=torch.float64, device="cuda")
+    x = torch.zeros(5, dtype=torch.float64, device="cuda")
+    c = torch.zeros(2, dtype=torch.float64, device="cuda")
+    L = riga.lib()
+    import ctypes as C
+    for n, m in ((0, 2), (5, 0), (5, riga.RIGA_PROJECT_MAX_COLS + 1)):
+        code = L.riga_project(n, m, C.c_void_p(W.data_ptr()), C.c_void_p(W.data_ptr()),
+                              C.c_void_p(x.data_ptr()), C.c_void_p(c.data_ptr()), None)
+        assert code == riga.RIGA_EINVAL

@@ -137,6 +137,11 @@ def test_fronts_contain_exact_fill(dim, ne, p, s, split, monkeypatch):
         assert i in fsets[owner[j]]
     nnz_exact = L.nnz + n
     assert pr.info["nnz_l"] >= nnz_exact
+    # the library's own exact count (row subtrees of its elimination tree)
+    assert pr.info["nnz_l_exact"] == nnz_exact
+    cc = np.bincount(L.col, minlength=n).astype(float)
+    assert pr.info["flops_fact_exact"] == pytest.approx(float(np.sum(cc * (cc + 1))), rel=1e-15)
+    assert pr.info["flops_fact_exact"] <= pr.info["flops_fact"] * (1 + 1e-12)
     del iperm
 
 

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 import scipy.linalg as sla
 
+import workloads
 from oracle import assembly, eigen
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -140,3 +141,13 @@ def test_residual_detects_wrong_pair():
     lam, U = eigen.dense_eigh(K, M)
     assert eigen.residual(K, M, lam[:1], U[:, :1])[0] < 1e-13
     assert eigen.residual(K, M, lam[:1] * (1 + 1e-6), U[:, :1])[0] > 1e-9
+
+
+def test_inertia_many_equals_inertia():
+    """The pooled counts are the same factorisations as the serial ones."""
+    w = workloads.small(2, 12, 3, 4, 10, 0.4)
+    kappa, rho = w.coefficients()
+    K, M = assembly.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
+    lam = eigen.dense_eigh(K, M)[0]
+    sig = [0.5 * (lam[i] + lam[i + 1]) for i in (0, 4, 17, 40)]
+    assert eigen.inertia_many(K, M, sig, workers=2) == [eigen.inertia(K, M, x) for x in sig] == [1, 5, 18, 41]

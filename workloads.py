@@ -6,7 +6,7 @@ per-element coefficient fields and loss weights from fixed seeds.  Both the
 oracle and the HIP path receive the arrays it returns as plain inputs.
 
 The paper's workload is the Dirichlet Laplace eigenproblem on the unit
-square / cube with uniform meshes (Sec. 2.1 and Sec. 6); the coefficient
+square / cube with uniform meshes (Sec. 2.1 and Sec. 7); the coefficient
 fields kappa_e, rho_e = exp(sigma Z), Z ~ N(0, 1) i.i.d. per element, extend it
 to the heterogeneous problems the benchmark also covers.
 """
