@@ -247,6 +247,19 @@ riga_status riga_solve_multi(riga_problem* pr, const double* B_dev, double* X_de
 riga_status riga_project(int64_t n, int32_t m, const double* W_dev, const double* B_dev, double* x_dev,
                          double* c_dev, void* stream);
 
+/* riga_project_noalloc: riga_project for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments and results (bitwise),
+ * but the workspace is a fixed scratch array of 2^20 doubles (8 MiB) per
+ * GPU, held by the library until the process ends: RIGA_EINVAL when
+ * ceil(n / 4096) * m exceeds it (or as riga_project).  Allocates nothing
+ * and does not wait: the work is queued on `stream` and the call returns.
+ * Every call on a GPU uses that GPU's one scratch array, so calls that
+ * overlap on one GPU (other streams, other threads) race; nothing in the
+ * scratch needs to start at zero. */
+riga_status riga_project_noalloc(int64_t n, int32_t m, const double* W_dev, const double* B_dev,
+                                 double* x_dev, double* c_dev, void* stream);
+
 /* riga_eigs: the nev lowest eigenpairs with lambda in [lo, hi) (Sec. 4).
  * Spectrum slicing with inertia counts (Sec. 4.1): the factorisation at a
  * guess of the next shift runs on a second HIP stream of the library's own

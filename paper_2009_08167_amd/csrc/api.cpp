@@ -281,6 +281,22 @@ riga_status riga_project(int64_t n, int32_t m, const double* W, const double* B,
   });
 }
 
+riga_status riga_project_noalloc(int64_t n, int32_t m, const double* W, const double* B, double* x,
+                                 double* c, void* stream) {
+  return guarded([&]() -> riga_status {
+    if (n < 1 || m < 1 || m > RIGA_PROJECT_MAX_COLS || !W || !B || !x || !c)
+      return fail(RIGA_EINVAL, "need n >= 1, 1 <= m <= RIGA_PROJECT_MAX_COLS and non-null blocks");
+    const size_t need = (size_t)riga::proj_row_blocks(n) * (size_t)m;
+    if (need > riga::NOALLOC_SCRATCH_DOUBLES)
+      return fail(RIGA_EINVAL, "ceil(n / 4096) * m = " + std::to_string(need) +
+                                   " exceeds the fixed scratch of " +
+                                   std::to_string(riga::NOALLOC_SCRATCH_DOUBLES) + " doubles");
+    double* partial = riga::noalloc_scratch();
+    riga::launch_project(W, B, n, m, x, partial, c, nullptr, nullptr, (hipStream_t)stream);
+    return RIGA_OK;
+  });
+}
+
 riga_status riga_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found, double* evals,
                       double* evecs, double* resid, riga_stats* stats) {
   return guarded([&]() -> riga_status {

@@ -346,6 +346,11 @@ struct StreamBind {
 void set_kernel_attributes();
 void solve_fb(riga_problem* pr, const Factor& F, const double* b, double* x, hipStream_t s);
 
+// Fixed per-device scratch of the entry points that allocate nothing
+// (8 MiB; scratch.hip): its device address on the current device.
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = (size_t)1 << 20;
+double* noalloc_scratch();
+
 // BLAS-like helpers on column-major N x m blocks (ld = N).
 int gemv_row_blocks(int64_t n);
 // One Gram-Schmidt pass: c = W^T x, then x -= B c (W, B: n x m column-major,

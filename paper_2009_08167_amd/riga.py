@@ -22,7 +22,7 @@ RIGA_MAT_K, RIGA_MAT_M, RIGA_MAT_A = 0, 1, 2
 EXPORTED = ["riga_set_allocator", "riga_analyze", "riga_assemble", "riga_update_coefficients",
             "riga_problem_info",
             "riga_tree_export", "riga_get_matrices", "riga_spmv", "riga_factor", "riga_solve",
-            "riga_solve_multi", "riga_project", "riga_eigs", "riga_eigs_batched", "riga_eig_grad",
+            "riga_solve_multi", "riga_project", "riga_project_noalloc", "riga_eigs", "riga_eigs_batched", "riga_eig_grad",
             "riga_mode_errors", "riga_exact_eigenvalues", "riga_destroy", "riga_status_string",
             "riga_last_error"]
 RIGA_PROJECT_MAX_COLS = 8192
@@ -100,6 +100,7 @@ def lib():
         L.riga_eigs.argtypes = [P, C.POINTER(EigsOpts), C.POINTER(C.c_int32), P, P, P,
                                 C.POINTER(Stats)]
         L.riga_project.argtypes = [C.c_int64, C.c_int32, P, P, P, P, P]
+        L.riga_project_noalloc.argtypes = [C.c_int64, C.c_int32, P, P, P, P, P]
         L.riga_eig_grad.argtypes = [P, C.c_int32, P, P, P, P, P, P]
         L.riga_mode_errors.argtypes = [P, C.c_int32, P, P, C.c_int32, P, C.c_int32, P, P, P, P, P, P]
         L.riga_exact_eigenvalues.argtypes = [C.c_int32, C.c_int32, P]
@@ -113,7 +114,8 @@ def lib():
                      "riga_problem_info", "riga_tree_export",
                      "riga_get_matrices", "riga_spmv", "riga_factor", "riga_solve", "riga_solve_multi",
                      "riga_eigs", "riga_eig_grad", "riga_set_allocator", "riga_eigs_batched",
-                     "riga_mode_errors", "riga_exact_eigenvalues", "riga_project"]:
+                     "riga_mode_errors", "riga_exact_eigenvalues", "riga_project",
+                     "riga_project_noalloc"]:
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -324,11 +326,11 @@ class Problem:
         return out
 
 
-def project(W, B, x, c=None, stream=None):
-    """One Gram-Schmidt pass (riga_project): c = W^T x, x -= B c, with W, B
-    contiguous float64 device tensors of shape [m, n] (row i = column i of
-    the n x m block) and x [n] updated in place.  Returns c [m] (written into
-    `c` if given)."""
+def project(W, B, x, c=None, noalloc=False, stream=None):
+    """One Gram-Schmidt pass (riga_project, or riga_project_noalloc with
+    noalloc=True): c = W^T x, x -= B c, with W, B contiguous float64 device
+    tensors of shape [m, n] (row i = column i of the n x m block) and x [n]
+    updated in place.  Returns c [m] (written into `c` if given)."""
     import torch
     m, n = B.shape
     if W.shape != B.shape or x.shape != (n,) or not (W.is_contiguous() and B.is_contiguous()
@@ -336,7 +338,8 @@ def project(W, B, x, c=None, stream=None):
         raise ValueError("W, B: contiguous [m, n]; x: contiguous [n]")
     if c is None:
         c = torch.empty(m, dtype=torch.float64, device=x.device)
-    _check(lib().riga_project(n, m, _ptr(W), _ptr(B), _ptr(x), _ptr(c), _stream(stream)))
+    fn = lib().riga_project_noalloc if noalloc else lib().riga_project
+    _check(fn(n, m, _ptr(W), _ptr(B), _ptr(x), _ptr(c), _stream(stream)))
     return c
 
 
