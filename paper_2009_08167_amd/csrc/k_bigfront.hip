@@ -28,6 +28,7 @@
 #include <cmath>
 #include <vector>
 
+#include "mfma_tile.h"
 #include "problem.h"
 
 namespace riga {
@@ -37,7 +38,6 @@ constexpr int BF_NB = 64;        // widest panel
 constexpr int BF_LDS = 18432;    // doubles of the panel kernel's LDS panel
 constexpr int BF_TILE = 64;      // trailing-update tile
 constexpr double BF_ALPHA = 0.6403882032022076;  // (1 + sqrt(17)) / 8
-typedef double v4d __attribute__((ext_vector_type(4)));
 
 struct BigState {
   int32_t next;   // first column of the next panel
@@ -441,17 +441,19 @@ __global__ void __launch_bounds__(256) big_trailing_kernel(BigArgs a, T* pool) {
       Wb[t * (BF_TILE + 1) + ii] = wv;
     }
     __syncthreads();
-    // wave w: column block w (16 columns), all four row blocks
-    v4d acc[4];
+    // wave w: column block w (16 columns), all four row blocks, on the
+    // matrix cores in the factor's precision (FP64, or FP32 for the mixed
+    // precision fronts)
+    Tile16<T> acc[4];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) acc[rt] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int rt = 0; rt < 4; ++rt) acc[rt].zero();
     for (int t0 = 0; t0 < kpad; t0 += 4) {
       const int kr = t0 + (lane >> 4);
       const double bv = Wb[kr * (BF_TILE + 1) + wave * 16 + (lane & 15)];
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt) {
         const double av = La[kr * (BF_TILE + 1) + rt * 16 + (lane & 15)];
-        acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[rt], 0, 0, 0);
+        acc[rt].step(av, bv);
       }
     }
     __syncthreads();
@@ -462,8 +464,8 @@ __global__ void __launch_bounds__(256) big_trailing_kernel(BigArgs a, T* pool) {
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int ii = rt * 16 + (lane >> 4) + 4 * r;
-        Ct[ii * (BF_TILE + 1) + wave * 16 + (lane & 15)] = acc[rt][r];
+        const int ii = rt * 16 + Tile16<T>::row(lane, r);
+        Ct[ii * (BF_TILE + 1) + wave * 16 + (lane & 15)] = acc[rt].get(r);
       }
     __syncthreads();
     for (int e = tid; e < BF_TILE * BF_TILE; e += 256) {

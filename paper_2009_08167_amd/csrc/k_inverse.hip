@@ -21,12 +21,14 @@
 // row of L21), so a workgroup takes a block of up to 64 rows and walks the
 // columns from the right in 64-wide panels:
 //     Hp = R(:, panel) - H(:, right of panel) * L11(right of panel, panel)
-//     (a GEMM on the FP64 MFMA units, operands staged in LDS), then the
+//     (a GEMM on the matrix cores in the factor's precision, operands
+//     staged in LDS), then the
 //     unit-triangular solve with the panel's diagonal block of L11.
 // The columns to the right were written by the same workgroup earlier; the
 // workgroup barrier orders those global writes before the reads.
 #include <hip/hip_runtime.h>
 
+#include "mfma_tile.h"
 #include "problem.h"
 
 namespace riga {
@@ -34,7 +36,6 @@ namespace {
 
 constexpr int IB = 64;       // panel width and row block
 constexpr int LDP = IB + 1;  // padded LDS leading dimension
-typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double lane_bcast(double v, int l) {
   const long long bits = __double_as_longlong(v);
@@ -100,9 +101,9 @@ __global__ void __launch_bounds__(256) front_inverse_kernel(const FrontDesc* __r
     }
     // Hp -= H(:, j1:k) * L11(j1:k, panel), 64-deep chunks on the MFMA units
     if (j1 < k) {
-      v4d acc[4];
+      Tile16<T> acc[4];
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt) acc[rt] = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int rt = 0; rt < 4; ++rt) acc[rt].zero();
       for (int m0 = j1; m0 < k; m0 += IB) {
         const int mw = min(IB, k - m0);
         double ar[IB * IB / 256], br[IB * IB / 256];
@@ -137,20 +138,20 @@ __global__ void __launch_bounds__(256) front_inverse_kernel(const FrontDesc* __r
           for (int rt = 0; rt < 4; ++rt)
             if (rt < nrt) {
               const double av = Ac[kr * LDP + rt * 16 + (lane & 15)];
-              acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[rt], 0, 0, 0);
+              acc[rt].step(av, bv);
             }
         }
         __syncthreads();
       }
-      // lane holds the product at row (lane >> 4) + 4 r of the row tile,
-      // column lane & 15 of this wave's column tile
+      // lane holds the product at row Tile16::row(lane, r) of the row
+      // tile, column lane & 15 of this wave's column tile
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt)
         if (rt < nrt) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int ii = rt * 16 + (lane >> 4) + 4 * r;
-            Hp[ii * LDP + wave * 16 + (lane & 15)] -= acc[rt][r];
+            const int ii = rt * 16 + Tile16<T>::row(lane, r);
+            Hp[ii * LDP + wave * 16 + (lane & 15)] -= acc[rt].get(r);
           }
         }
     }

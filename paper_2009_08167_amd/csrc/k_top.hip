@@ -37,6 +37,7 @@
 #include <cstdlib>
 #include <map>
 
+#include "mfma_tile.h"
 #include "problem.h"
 
 namespace riga {
@@ -57,7 +58,6 @@ constexpr int TOP_MAX_ANC = 64;       // fronts in one ancestor chain
 
 constexpr int TB = 64;        // construction tile
 constexpr int TLD = TB + 1;   // padded LDS leading dimension
-typedef double v4d __attribute__((ext_vector_type(4)));
 
 struct Sizes {
   int64_t e_row = 0, e_col = 0, e_cb = 0;
@@ -158,9 +158,9 @@ __global__ void __launch_bounds__(256) top_inverse_kernel(
   const int kP = p.kP, fP = p.fP, kF = p.kF;
   const bool self = p.inv_off < 0;  // F = P: R_FS is the identity, R_CB zero
   const T* Hp = H + p.h_off;
-  v4d acc[4];
+  Tile16<T> acc[4];
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt) acc[rt] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int rt = 0; rt < 4; ++rt) acc[rt].zero();
   // A(r, u): strictly lower L11^{-1} (the 2x2 slots hold D) on the top rows,
   // L21 L11^{-1} below; rows of the top part need u < r only
   const int kmax = (r0 + TB <= kP) ? r0 + TB : kP;
@@ -219,20 +219,20 @@ __global__ void __launch_bounds__(256) top_inverse_kernel(
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt) {
         const double av = At[kr * TLD + rt * 16 + (lane & 15)];
-        acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[rt], 0, 0, 0);
+        acc[rt].step(av, bv);
       }
     }
     __syncthreads();
   }
-  // lane holds rows (lane >> 4) + 4 i of each 16-row tile, column lane & 15
-  // of this wave's 16 columns
+  // lane holds rows Tile16::row(lane, i) of each 16-row tile, column
+  // lane & 15 of this wave's 16 columns
   const int col = c0 + wave * 16 + (lane & 15);
   if (col >= kF) return;
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int r = r0 + rt * 16 + (lane >> 4) + 4 * i;
+      const int r = r0 + rt * 16 + Tile16<T>::row(lane, i);
       if (r >= fP) continue;
       if (r < kP) {
         double base;
@@ -242,7 +242,7 @@ __global__ void __launch_bounds__(256) top_inverse_kernel(
           const int q = inv[p.inv_off + piv_perm[p.startP + r]];
           base = q >= 0 ? cb[p.cb_in + (int64_t)q * kF + col] : 0.0;
         }
-        const double out = base + acc[rt][i];
+        const double out = base + acc[rt].get(i);
         tcol[p.xcol + (int64_t)p.ldF * col + r] = (T)out;
         if (!self || col <= r) trow[roff[p.tstartP + r] + p.colbase + col] = (T)out;
       } else if (p.cb_out >= 0) {
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(256) top_inverse_kernel(
           const int q = inv[p.inv_off + r];
           base = q >= 0 ? cb[p.cb_in + (int64_t)q * kF + col] : 0.0;
         }
-        cb[p.cb_out + (int64_t)(r - kP) * kF + col] = base - acc[rt][i];
+        cb[p.cb_out + (int64_t)(r - kP) * kF + col] = base - acc[rt].get(i);
       }
     }
   }
