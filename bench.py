@@ -102,7 +102,9 @@ def event_time(fn, reps, torch):
 
 def secondary_rooflines(riga, pr, t_fact, info, torch):
     """Event-timed rates of the other kernels of a Lanczos step on the main
-    workload: the SpMV with M (CSR: nnz (8 + 4) + 2 N 8 bytes) and the
+    workload: the SpMV with M (CSR: nnz (8 + 4) + 2 N 8 bytes), one
+    Gram-Schmidt pass over m = 256 columns (riga_project_noalloc: W and B
+    read once, x read twice and written once: 2 N m 8 + 3 N 8 bytes), and the
     factorisation on its exact-fill flops (sum over the columns of L of
     c (c + 1))."""
     N, nnz = pr.n_dof, info["nnz"]
@@ -110,11 +112,21 @@ def secondary_rooflines(riga, pr, t_fact, info, torch):
     y = torch.empty_like(x)
     t_mv = event_time(lambda: pr.spmv(riga.RIGA_MAT_M, x, y=y), 50, torch)
     b_mv = nnz * 12.0 + 2.0 * N * 8
+    m = 256
+    W = torch.randn(m, N, dtype=torch.float64, device="cuda")
+    B = torch.randn(m, N, dtype=torch.float64, device="cuda")
+    c = torch.empty(m, dtype=torch.float64, device="cuda")
+    t_gs = event_time(lambda: riga.project(W, B, x, c=c, noalloc=True), 20, torch)
+    b_gs = 2.0 * N * m * 8 + 3.0 * N * 8
     f_ex = info["flops_fact_exact"]
+    del W, B
     return {
         "spmv_M": {"bound": "hbm", "achieved": b_mv / t_mv / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                    "frac": b_mv / t_mv / 1e9 / HBM_PEAK_GBS, "bytes": b_mv, "seconds": t_mv,
                    "mall_fits": b_mv <= MALL_BYTES},
+        "gram_schmidt_pass_m256": {"bound": "hbm", "achieved": b_gs / t_gs / 1e9, "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": b_gs / t_gs / 1e9 / HBM_PEAK_GBS, "bytes": b_gs,
+                                   "seconds": t_gs, "mall_fits": b_gs <= MALL_BYTES},
         "factorisation": {"bound": "mfma", "achieved": f_ex / t_fact / 1e12, "peak": FP64_PEAK_TFLOPS,
                           "unit": "TFLOP/s", "frac": f_ex / t_fact / 1e12 / FP64_PEAK_TFLOPS,
                           "flops_exact": f_ex, "flops_supernodal": info["flops_fact"], "seconds": t_fact},
@@ -251,19 +263,26 @@ SWEEP_SOURCES = ("paper_2009_08167_amd/csrc/k_solve.hip", "paper_2009_08167_amd/
 
 
 def sweep_kernel(name):
-    """The kernels of one forward/backward sweep pair: the per-level kernels
-    below the top block and the three of the top block."""
-    return any(t in name for t in ("::fwd_kernel<", "::bwd_kernel<", "top_rhs_kernel", "top_fwd_kernel",
+    """The kernels of one forward/backward sweep pair: the fused launches of
+    the bottom heights, the per-level kernels above them and below the top
+    block, and the three of the top block."""
+    return any(t in name for t in ("::fwd_kernel<", "::bwd_kernel<", "::fwd_subtree_kernel<",
+                                   "::bwd_subtree_kernel<", "top_rhs_kernel", "top_fwd_kernel",
                                    "top_bwd_kernel"))
+
+
+def forward_kernel(name):
+    return "::fwd_kernel<" in name or "::fwd_subtree_kernel<" in name
 
 
 def sweep_pairs(rows):
     """Sweep pairs in dispatch-ordered rocprofv3 rows: on each queue, a pair
-    starts with the lowest level's forward kernel after a kernel that is not
-    one (the queues separate the sweeps from a concurrent factorisation)."""
+    starts with the lowest forward kernel after a kernel that is not a
+    forward one (the queues separate the sweeps from a concurrent
+    factorisation)."""
     pairs, prev = 0, {}
     for r in rows:
-        q, cur = r["Queue_Id"], "::fwd_kernel<" in r["Kernel_Name"]
+        q, cur = r["Queue_Id"], forward_kernel(r["Kernel_Name"])
         if cur and not prev.get(q, False):
             pairs += 1
         prev[q] = cur
@@ -282,8 +301,8 @@ def trace_summary(trace_csv, stats_csv):
     # the sweeps that bench.py times with events: the last 30 sweep pairs
     # (riga_solve_multi, queued back to back after a factorisation)
     sw = [r for r in rows if sweep_kernel(r["Kernel_Name"])]
-    starts = [i for i, r in enumerate(sw) if "::fwd_kernel<" in r["Kernel_Name"]
-              and (i == 0 or "::fwd_kernel<" not in sw[i - 1]["Kernel_Name"])]
+    starts = [i for i, r in enumerate(sw) if forward_kernel(r["Kernel_Name"])
+              and (i == 0 or not forward_kernel(sw[i - 1]["Kernel_Name"]))]
     last = sw[starts[-30]:] if len(starts) >= 30 else []
     print("| quantity | value |\n|---|---|")
     print("| sweep pairs in the trace | %d (%d sweep-kernel launches) |" % (pairs, n_sw))
@@ -644,6 +663,85 @@ def large_n0_summary(path):
             r["t_av"] * 1e3, gain))
 
 
+# Factorisations only, for counter profiles of the fronts (rocprofv3 --pmc):
+# 3D 32^3 p=2 rIGA (blocks of 8) and IGA, and 3D 64^3 p=2 rIGA (blocks of
+# 8), kappa = rho = 1, three factorisations each in FP64 and in mixed
+# precision at a shift inside the spectrum, one line of event times each.
+FACTOR_PROFILE = ((3, 32, 2, 8), (3, 32, 2, 0), (3, 64, 2, 8))
+
+
+def factor_profile(riga, torch):
+    for dim, ne, p, s in FACTOR_PROFILE:
+        pr = riga.assemble(dim, ne, p, s)
+        inf = pr.info
+        for name, prec in (("fp64", riga.RIGA_FP64), ("mixed", riga.RIGA_MIXED)):
+            sigma = 600.0
+            pr.factor(sigma, prec)
+            t = event_time(lambda: pr.factor(sigma, prec), 3, torch)
+            print(json.dumps({"case": "%dd_%d_p%d_s%d" % (dim, ne, p, s), "precision": name,
+                              "n_dof": pr.n_dof, "max_front": inf["max_front"], "fact_ms": t * 1e3,
+                              "flops_exact": inf["flops_fact_exact"], "flops_supernodal": inf["flops_fact"],
+                              "tflops_exact": inf["flops_fact_exact"] / t / 1e12,
+                              "tflops_supernodal": inf["flops_fact"] / t / 1e12}), flush=True)
+        del pr
+
+
+def mfma_summary(counter_csv, fprof_log):
+    """Markdown summary of `rocprofv3 --pmc SQ_INSTS_VALU_MFMA_MOPS_F64
+    SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE` over
+    `bench.py --factor-profile`: the dispatches of each case (split at its
+    assembly) summed per counter, matrix-core flops (512 per MOPS unit),
+    MFMA busy share of the SIMDs over the GPU-active cycles, and the
+    achieved rate over the case's event-timed factorisation (printed by the
+    profiled run itself, `fprof_log`)."""
+    import csv
+    rows = list(csv.DictReader(open(counter_csv)))
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    cases, cur = [], None
+    for r in rows:
+        name = r["Kernel_Name"]
+        if "assemble_kernel" in name and "front_assemble" not in name:
+            if cur is None or cur["seen_other"]:
+                cur = {"seen_other": False, "c": {}, "kern": {}}
+                cases.append(cur)
+        if cur is None:
+            continue
+        if "assemble_kernel" not in name:
+            cur["seen_other"] = True
+        cn, v = r["Counter_Name"], float(r["Counter_Value"])
+        cur["c"][cn] = cur["c"].get(cn, 0.0) + v
+        short = name.split("(")[0].replace("void ", "").replace("riga::", "").replace("(anonymous namespace)::", "")
+        kd = cur["kern"].setdefault(short, {})
+        kd[cn] = kd.get(cn, 0.0) + v
+    lines = [json.loads(l) for l in open(fprof_log) if l.startswith("{")]
+    simd = 256 * 4
+    print("| case | precision | factorisation (events) | exact flops | MFMA flops (counted, all 6 factorisations) |"
+          " MFMA busy / SIMD-cycles | achieved on exact flops |")
+    print("|---|---|---|---|---|---|---|")
+    for i, c in enumerate(cases):
+        if i >= len(lines) // 2:
+            break
+        f64 = c["c"].get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) * 512
+        f32 = c["c"].get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) * 512
+        busy = c["c"].get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)
+        act = c["c"].get("GRBM_GUI_ACTIVE", 0.0)
+        a, b = lines[2 * i], lines[2 * i + 1]
+        util = 100.0 * busy / (act * simd) if act else 0.0
+        print("| %s | fp64 + mixed | %.2f / %.2f ms | %.3g | FP64 %.3g, FP32 %.3g | %.2f%% | %.2f / %.2f TFLOP/s |"
+              % (a["case"], a["fact_ms"], b["fact_ms"], a["flops_exact"], f64, f32, util,
+                 a["tflops_exact"], b["tflops_exact"]))
+    print("\n## MFMA work by kernel (all cases)\n")
+    print("| case | kernel | FP64 MFMA flops | FP32 MFMA flops | MFMA busy cycles |\n|---|---|---|---|---|")
+    for i, c in enumerate(cases):
+        tag = lines[2 * i]["case"] if 2 * i < len(lines) else str(i)
+        for kname, kd in sorted(c["kern"].items(), key=lambda t: -t[1].get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)):
+            if kd.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) <= 0:
+                continue
+            print("| %s | `%s` | %.3g | %.3g | %.3g |" % (tag, kname, kd.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) * 512,
+                                                         kd.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) * 512,
+                                                         kd.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -673,6 +771,10 @@ def main():
                     help="dimensions for --large-n0: 2, 3 or 2,3 (3: 64^3 rIGA, N0 = 1024)")
     ap.add_argument("--large-n0-mesh", type=int, default=0,
                     help="with --large-n0: only the meshes with this many elements per direction")
+    ap.add_argument("--mfma-summary", nargs=2, metavar=("COUNTER_CSV", "FPROF_LOG"),
+                    help="summarise an MFMA counter run over --factor-profile and exit")
+    ap.add_argument("--factor-profile", action="store_true",
+                    help="factorisations only (3D 32^3 rIGA / IGA, 64^3 rIGA; FP64 and mixed) and exit")
     ap.add_argument("--large-n0-summary", metavar="JSONL",
                     help="print the markdown table of a --large-n0 run and exit")
     args = ap.parse_args()
@@ -690,6 +792,9 @@ def main():
         return
     if args.trace_summary:
         trace_summary(*args.trace_summary)
+        return
+    if args.mfma_summary:
+        mfma_summary(*args.mfma_summary)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -718,6 +823,9 @@ def main():
         return
     if args.calibrate_copy:
         calibrate_copy(torch)
+    if args.factor_profile:
+        factor_profile(riga, torch)
+        return
 
     w = workloads.c2(True)
     kappa, rho = w.coefficients()
@@ -749,8 +857,11 @@ def main():
            share_fb, share_fact))
     if share_fb >= share_fact:
         ach = bytes_fb / t_fb / 1e9
-        roof = {"kernel": "forward/backward elimination (fwd_kernel + bwd_kernel below the top block, "
+        roof = {"kernel": "forward/backward elimination (fwd_subtree + bwd_subtree for the fused bottom "
+                          "heights, fwd_kernel + bwd_kernel for further levels below the top block, "
                           "top_rhs + top_fwd + top_bwd for it)",
+                "launch": {"top_cut": info["top_cut"], "fused_heights": info["fused_heights"],
+                           "fused_subtrees": info["fused_subtrees"]},
                 "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": sweep_traffic(),
                 "per_launch": {"bytes": bytes_fb, "seconds": t_fb, "unit": "one sweep pair",

@@ -72,6 +72,19 @@ typedef struct {
   int32_t coeffs_on_device; /* kappa/rho are device pointers (1) or host pointers (0) */
   int32_t leaf_dofs;      /* nested-dissection leaf size in DOFs; 0 -> default */
   void* stream;           /* hipStream_t */
+  int32_t hermitian;      /* 0: the real pencil above.  1: the complex Hermitian pencil of
+                             the magnetic Laplacian -(grad - iA).(grad - iA) u = lambda u with
+                             the constant vector potential `potential` (kappa = rho = 1 only):
+                             K_ab = int (grad B_b - iA B_b).conj(grad B_a - iA B_a),
+                             M_ab = int B_a B_b (Eq. GHEP read with conjugate transposes).
+                             It is solved in its real-equivalent form [[Re K, -Im K],
+                             [Im K, Re K]], diag(M, M), with the real and imaginary parts
+                             of DOF d at unknowns 2d and 2d + 1: riga_problem_info's n_dof
+                             counts those 2N unknowns, riga_spmv / riga_factor / riga_solve
+                             act on that real system, and riga_eigs returns each complex
+                             eigenvalue once with its eigenvector as N complex numbers
+                             (2N doubles, real and imaginary parts interleaved) */
+  double potential[3];    /* A, per direction (unused entries ignored) */
 } riga_mesh_desc;
 
 /* Eigen-solve request (Sec. 4.1: eigenvalues in [lambda_s, lambda_e]). */
@@ -126,10 +139,16 @@ typedef struct {
   int64_t nnz_l_exact;    /* entries of L for the same elimination order without
                              pivoting (exact structural fill, diagonal included) */
   double flops_fact_exact; /* sum over the columns of that L of c (c + 1) */
+  int32_t components;     /* 1: real pencil; 2: complex pencil (n_dof = 2 x complex DOFs) */
   double sweep_bytes_stored; /* FP64 factor bytes one forward + backward elimination reads
                              as stored (partitioned-inverse blocks of the levels below
                              the top block, both copies of the top block's inverse);
                              0 before riga_assemble */
+  int32_t top_cut;        /* height from which the sweeps use the top block's explicit
+                             inverse; -1: none (or before riga_assemble) */
+  int32_t fused_heights;  /* bottom heights swept in one launch per direction (one
+                             workgroup per subtree); 0: none */
+  int32_t fused_subtrees; /* workgroups of those launches */
 } riga_problem_info_t;
 
 /* Allocation hooks (e.g. torch's caching allocator).  Optional. */

@@ -124,7 +124,8 @@ int split_fs() {
 }  // namespace
 
 std::string analyze(int dim, const int ne_in[3], int p, int s, int nquad, int leaf_dofs,
-                    Analysis& A) {
+                    Analysis& A, int components) {
+  if (components != 1 && components != 2) return "components must be 1 or 2";
   if (dim < 2 || dim > 3) return "dim must be 2 or 3";
   if (p < 1 || p > 6) return "p must be in 1..6";
   if (s < 0) return "sep_spacing must be >= 0";
@@ -136,7 +137,9 @@ std::string analyze(int dim, const int ne_in[3], int p, int s, int nquad, int le
   A.s = s;
   A.nquad = nquad > 0 ? nquad : p + 1;
   if (A.nquad > 16) return "nquad must be <= 16";
-  if (leaf_dofs <= 0) leaf_dofs = 64;
+  // (a complex pencil doubles every front: half the scalar leaf by default,
+  // so that its leaf fronts stay within the LDS-resident size)
+  if (leaf_dofs <= 0) leaf_dofs = components == 2 ? 32 : 64;
   A.N = 1;
   A.n_elem = 1;
   for (int d = 0; d < 3; ++d) {
@@ -151,8 +154,8 @@ std::string analyze(int dim, const int ne_in[3], int p, int s, int nquad, int le
     A.N *= A.n1[d];
     A.n_elem *= A.ne[d];
   }
-  if (A.N >= (int64_t)1 << 31) return "too many DOFs";
-  const int64_t N = A.N;
+  if (A.N * components >= (int64_t)1 << 31) return "too many DOFs";
+  int64_t N = A.N;
   const int nx = A.n1[0], ny = A.n1[1], nz = A.n1[2];
 
   // ---- CSR pattern: row (i,j,k) couples with the tensor product of the
@@ -165,7 +168,7 @@ std::string analyze(int dim, const int ne_in[3], int p, int s, int nquad, int le
     for (int d = 0; d < dim; ++d) c *= A.sp[d].nb_hi[idx[d]] - A.sp[d].nb_lo[idx[d]] + 1;
     A.row_ptr[r + 1] = A.row_ptr[r] + c;
   }
-  if (A.row_ptr[N] >= (int64_t)1 << 31) return "too many non-zeros";
+  if (A.row_ptr[N] * components * components >= (int64_t)1 << 31) return "too many non-zeros";
   A.col_idx.resize(A.row_ptr[N]);
   for (int64_t r = 0; r < N; ++r) {
     int idx[3] = {(int)(r % nx), (int)((r / nx) % ny), (int)(r / ((int64_t)nx * ny))};
@@ -309,7 +312,8 @@ std::string analyze(int dim, const int ne_in[3], int p, int s, int nquad, int le
   // smaller fully-summed block allows wider panels, and the trailing
   // updates become dense rank-(panel width) contractions instead of
   // streaming the update block through HBM a few columns at a time.
-  const int split = split_fs();
+  // (in scalar DOFs: a complex pencil doubles every block below)
+  const int split = split_fs() / components;
   if (split > 0) {
     int nn = 0;
     std::vector<int> first_new(A.n_fronts), nchunk(A.n_fronts);
@@ -361,6 +365,45 @@ std::string analyze(int dim, const int ne_in[3], int p, int s, int nquad, int le
     }
   }
   nf = A.n_fronts;
+
+  // ---- A complex Hermitian pencil K + iK' (M real) is solved in its
+  // real-equivalent form [[K, -K'], [K', K]], diag(M, M): every scalar DOF d
+  // becomes the two variables 2d (real part) and 2d + 1 (imaginary part),
+  // adjacent in the pattern, in the elimination order and in every front,
+  // and every scalar coupling becomes a 2 x 2 block.  The tree is the
+  // scalar one; everything below is built for the expanded variables.
+  A.components = components;
+  if (components == 2) {
+    const int64_t Ns = N;
+    std::vector<int64_t> rp(2 * Ns + 1, 0);
+    std::vector<int32_t> ci;
+    ci.reserve(4 * A.col_idx.size());
+    for (int64_t r = 0; r < Ns; ++r) {
+      const int64_t len = A.row_ptr[r + 1] - A.row_ptr[r];
+      for (int t = 0; t < 2; ++t) {
+        rp[2 * r + t + 1] = rp[2 * r + t] + 2 * len;
+        for (int64_t e = A.row_ptr[r]; e < A.row_ptr[r + 1]; ++e) {
+          ci.push_back(2 * A.col_idx[e]);
+          ci.push_back(2 * A.col_idx[e] + 1);
+        }
+      }
+    }
+    A.row_ptr.swap(rp);
+    A.col_idx.swap(ci);
+    std::vector<int32_t> perm2(2 * Ns), iperm2(2 * Ns);
+    for (int64_t d = 0; d < Ns; ++d)
+      for (int t = 0; t < 2; ++t) {
+        perm2[2 * d + t] = 2 * A.perm[d] + t;
+        iperm2[2 * (int64_t)A.perm[d] + t] = (int32_t)(2 * d + t);
+      }
+    A.perm.swap(perm2);
+    A.iperm.swap(iperm2);
+    for (int f = 0; f < nf; ++f) {
+      A.f_start[f] *= 2;
+      A.f_k[f] *= 2;
+    }
+    A.N = N = 2 * Ns;
+  }
 
   // ---- Supernodal symbolic factorisation.  struct(P) = the variables
   // eliminated after P that are adjacent to P's variables or in a child's

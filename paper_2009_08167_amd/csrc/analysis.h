@@ -42,8 +42,10 @@ struct Analysis {
   Space1D sp[3];
   int n1[3] = {1, 1, 1};     // interior functions per direction
   int ne[3] = {1, 1, 1};
-  int64_t N = 0;             // interior DOFs
+  int64_t N = 0;             // unknowns: interior DOFs, twice that for a complex pencil
   int64_t n_elem = 0;
+  int components = 1;        // 1: real pencil; 2: complex Hermitian pencil in real-equivalent
+                             // form (unknowns 2d, 2d + 1 = real, imaginary part of DOF d)
 
   // CSR pattern of K and M in original (lexicographic, x fastest) order.
   std::vector<int64_t> row_ptr;
@@ -95,6 +97,6 @@ struct Analysis {
 
 // Builds everything above.  Returns "" on success, else an error message.
 std::string analyze(int dim, const int ne[3], int p, int s, int nquad, int leaf_dofs,
-                    Analysis& out);
+                    Analysis& out, int components = 1);
 
 }  // namespace riga

@@ -50,7 +50,17 @@ riga_status do_analyze(const riga_mesh_desc* d, riga_problem** out) {
   if (!d || !out) return fail(RIGA_EINVAL, "null descriptor or output");
   *out = nullptr;
   auto* pr = new riga_problem();
-  std::string err = riga::analyze(d->dim, d->ne, d->p, d->sep_spacing, d->nquad, d->leaf_dofs, pr->an);
+  if (d->hermitian != 0 && d->hermitian != 1) {
+    delete pr;
+    return fail(RIGA_EINVAL, "hermitian must be 0 or 1");
+  }
+  if (d->hermitian && (d->kappa || d->rho)) {
+    delete pr;
+    return fail(RIGA_EUNSUPPORTED, "the complex Hermitian pencil takes kappa = rho = 1 (NULL coefficients)");
+  }
+  std::string err = riga::analyze(d->dim, d->ne, d->p, d->sep_spacing, d->nquad, d->leaf_dofs, pr->an,
+                                  d->hermitian ? 2 : 1);
+  for (int q = 0; q < 3; ++q) pr->potential[q] = (d->hermitian && q < d->dim) ? d->potential[q] : 0.0;
   if (!err.empty()) {
     delete pr;
     return fail(RIGA_EINVAL, err);
@@ -117,7 +127,11 @@ riga_status riga_problem_info(const riga_problem* pr, riga_problem_info_t* info)
   info->front_pool = a.pool_size;
   info->nnz_l_exact = a.nnz_l_exact;
   info->flops_fact_exact = a.flops_exact;
+  info->components = a.components;
   info->sweep_bytes_stored = 0.0;
+  info->top_cut = pr->has_device ? pr->top.cut : -1;
+  info->fused_heights = pr->has_device ? pr->sub.nh : 0;
+  info->fused_subtrees = pr->has_device ? pr->sub.n_sub : 0;
   if (pr->has_device) {
     const int cut = pr->top.cut >= 0 ? pr->top.cut : a.height;
     double e = (double)pr->top.e_row + (double)pr->top.e_col;
@@ -302,7 +316,7 @@ riga_status riga_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_foun
   return guarded([&]() -> riga_status {
     if (!need_device(pr) || !o || !n_found) return fail(RIGA_EINVAL, "bad problem or options");
     if (o->nev < 1) return fail(RIGA_EINVAL, "nev must be >= 1");
-    if (o->nev > pr->an.N) return fail(RIGA_EINVAL, "nev exceeds the number of DOFs");
+    if ((int64_t)o->nev * pr->an.components > pr->an.N) return fail(RIGA_EINVAL, "nev exceeds the number of DOFs");
     if (!std::isfinite(o->lo) || !(o->hi > o->lo)) return fail(RIGA_EINVAL, "need finite lo < hi");
     if (o->precision != RIGA_FP64 && o->precision != RIGA_MIXED) return fail(RIGA_EINVAL, "bad precision");
     if (!evals) return fail(RIGA_EINVAL, "evals_host required");
@@ -320,7 +334,8 @@ riga_status riga_eigs_batched(riga_problem* const* probs, int32_t count, const r
     for (int i = 0; i < count; ++i) {
       if (!need_device(probs[i])) return fail(RIGA_EINVAL, "instance without device data");
       if (!evals[i]) return fail(RIGA_EINVAL, "evals_host[i] required");
-      if (o->nev > probs[i]->an.N) return fail(RIGA_EINVAL, "nev exceeds an instance's DOFs");
+      if ((int64_t)o->nev * probs[i]->an.components > probs[i]->an.N)
+        return fail(RIGA_EINVAL, "nev exceeds an instance's DOFs");
       for (int j = 0; j < i; ++j)
         if (probs[j] == probs[i]) return fail(RIGA_EINVAL, "an instance appears twice");
     }
@@ -338,6 +353,7 @@ riga_status riga_eig_grad(riga_problem* pr, int32_t k, const double* evals, cons
   return guarded([&]() -> riga_status {
     if (!need_device(pr) || k < 1 || !evals || !evecs || !w || !dkappa || !drho)
       return fail(RIGA_EINVAL, "bad arguments");
+    if (pr->an.components != 1) return fail(RIGA_EUNSUPPORTED, "gradient of a complex pencil");
     for (int i = 0; i < k; ++i)
       for (int j = i + 1; j < k; ++j)
         if (std::fabs(evals[i] - evals[j]) <= 1e-8 * std::max(std::fabs(evals[i]), std::fabs(evals[j])))
@@ -363,6 +379,7 @@ riga_status riga_mode_errors(riga_problem* pr, int32_t n_vec, const double* lam_
     if (!need_device(pr) || n_vec < 1 || n_modes < 1 || !lam_host || !U_dev || !modes_host || !match ||
         !overlap || !ef_l2 || !ef_e || !ev || nquad < 0)
       return fail(RIGA_EINVAL, "bad arguments");
+    if (pr->an.components != 1) return fail(RIGA_EUNSUPPORTED, "mode errors of a complex pencil");
     riga::mode_errors(pr, n_vec, lam_host, U_dev, n_modes, modes_host, nquad, match, overlap, ef_l2,
                       ef_e, ev, (hipStream_t)stream);
     return RIGA_OK;

@@ -45,10 +45,9 @@ constexpr int MAX_IR_FP64 = 2;
 // deflation window, in intervals between consecutive shifts below the shift
 constexpr double DEFLATE_SPACINGS = 4.0;
 
-// Candidate Ritz vectors are projected once against the locked pairs below
-// the deflation window when N * (those pairs) * ceil(candidates / 8) is at
-// most this (the block projection reads the locked block once per 8
-// candidates)
+// Candidate Ritz vectors are projected once against the locked pairs when
+// N * (locked pairs) * ceil(candidates / 8) is at most this (the block
+// projection reads the locked block once per 8 candidates)
 constexpr double LOCK_PROJECT_MAX = 268435456.0;
 
 // A shift whose factorisation had to perturb a pivot (K - sigma M singular
@@ -108,6 +107,7 @@ struct Locked {
   double lam;
   double resid;
   int col;       // column in B / W
+  bool partner = false;  // the J (times i) copy of a complex pencil's pair
 };
 
 struct Solver {
@@ -120,6 +120,9 @@ struct Solver {
   int per_shift;
   int max_restarts;
   int precision;
+  // a complex Hermitian pencil in real-equivalent form: every eigenvalue is
+  // double, its eigenspace {u, J u} (J: times i); both are locked together
+  bool cplx = false;
   int max_ir;
   int max_ir_fp64 = 0;   // refinement steps of an FP64 solve (raised on a stall)
   int dim = 2;           // spatial dimension (eigenvalue-count growth)
@@ -271,6 +274,18 @@ struct Solver {
     // along v_j and v_{j-1}.
     project_out(col + 1, c1.p, c_win);
     project_out(col + 1, c2.p, nl, alpha.p + j, c1.p + col);
+    if (cplx) {
+      // Lanczos on the real-equivalent form is Hermitian Lanczos only while
+      // V stays M-orthogonal to J V (in exact arithmetic the recurrence
+      // keeps it so: M (K - sigma M)^{-1} M commutes with J, and J is
+      // M-skew); rounding lets J V components grow, and the copy J u of a
+      // pair locked with u would then converge a second time.  Projecting
+      // x against J V is projecting J x against V and rotating back:
+      // x - J V (J V)^T M x = J^{-1} (J x - V W^T J x).
+      launch_jrot(x.p, N, 1.0, s);
+      project_out(col + 1, c2.p, nl);
+      launch_jrot(x.p, N, -1.0, s);
+    }
     normalize_into(col + 1, beta.p + j + 1);
     st.t_orth += secs(a, clk::now());
   }
@@ -357,16 +372,18 @@ struct Solver {
     HIPCHECK(hipMemcpyAsync(Sh.p, Sh_h.data(), Sh_h.size() * sizeof(double), hipMemcpyHostToDevice, s));
     // U = V S (the restart combination lands in column nw)
     launch_gemm_nn(Bc(nl), N, m, Sh.p, m, nc, Ub.p, s);
-    // The steps of this run were projected against the locked pairs of the
-    // deflation window only.  Each FP64 solve leaves components of relative
-    // size ~ (its backward error) ||A|| / |lambda_j - sigma| along the
-    // eigenvectors below the window, which the steps neither amplify nor
-    // remove; over a run they reach ~1e-10 in the Ritz vectors.  One block
-    // projection of the candidates against those locked pairs removes them
-    // (and the part of the residual they cause) before the residual test.
-    if (nw > 0 && c_win > 0 && (double)N * c_win * ((nw + 7) / 8) <= LOCK_PROJECT_MAX) {
+    // The candidates are projected once against every locked pair before
+    // the residual test.  The steps of this run were projected only against
+    // the deflation window, and each FP64 solve leaves components of
+    // relative size ~ (its backward error) ||A|| / |lambda_j - sigma| along
+    // the eigenvectors below it, which the steps neither amplify nor remove;
+    // and a pair locked earlier with a residual near the tolerance carries
+    // components of that size along eigenvectors found later.  Either way
+    // the locked set would lose M-orthogonality at ~1e-10; one block
+    // projection of the candidates (U -= B (W^T U)) keeps it at rounding.
+    if (nw > 0 && nl > 0 && (double)N * nl * ((nw + 7) / 8) <= LOCK_PROJECT_MAX) {
       if (bpart.n == 0) bpart.alloc(block_project_partials(N, (int)lam.n), s);
-      launch_block_project(W.p, B.p, N, c_win, Ub.p, nw, bpart.p, s);
+      launch_block_project(W.p, B.p, N, nl, Ub.p, nw, bpart.p, s);
     }
     int nlocked = 0;
     if (nw > 0) {
@@ -401,10 +418,20 @@ struct Solver {
       if (*have_restart) launch_copy(y.p, Ub.p + (int64_t)nw * N, N, s);
       int appended = 0;
       std::vector<int> dst_col, src_col;  // a column evicted twice keeps the last copy
+      std::vector<int> jdst, jsrc;  // J copies (complex pencils)
       for (int i : cand) {
         const double res = std::sqrt(h_rn2[i]) / (pr->normK1 * std::sqrt(h_un2[i]));
         int col = -1;
-        if (nl + appended < lock_cap) {
+        if (cplx) {
+          // u and J u (same eigenvalue, residual and M-norm; M-orthogonal)
+          if (nl + appended + 2 > lock_cap) break;
+          col = nl + appended;
+          appended += 2;
+          locked.push_back(Locked{h_lam[i], res, col, false});
+          locked.push_back(Locked{h_lam[i], res, col + 1, true});
+          jdst.push_back(col + 1);
+          jsrc.push_back(i);
+        } else if (nl + appended < lock_cap) {
           col = nl + appended;
           ++appended;
           locked.push_back(Locked{h_lam[i], res, col});
@@ -425,9 +452,10 @@ struct Solver {
           dst_col.push_back(col);
           src_col.push_back(i);
         }
-        ++nlocked;
+        nlocked += cplx ? 2 : 1;
       }
       launch_copy_cols(dst_col, src_col, N, B.p, Ub.p, W.p, MU.p, s);
+      if (!jdst.empty()) launch_copy_cols(jdst, jsrc, N, B.p, Ub.p, W.p, MU.p, s, true);
       nl += appended;
 
     } else if (*have_restart) {
@@ -482,11 +510,13 @@ struct Solver {
       if (j < next_check && j < maxm) continue;
       r = check(j);
       if (on_check) on_check(r);
+      // (a converged Ritz value of a complex pencil locks two pairs)
       int cb = 0, ca = 0;
+      const int per = cplx ? 2 : 1;
       for (int i = 0; i < j; ++i) {
         if (!converged(r, i)) continue;
         const double l = sigma + 1.0 / r.theta[i];
-        if (l < sigma) ++cb; else ++ca;
+        if (l < sigma) cb += per; else ca += per;
       }
       const bool breakdown = r.beta_m == 0.0;
       if ((cb >= need_below && ca >= need_above) || j >= maxm || breakdown) break;
@@ -789,6 +819,7 @@ void setup_solver(Solver& sv, riga_problem* pr, SolveCtx* ctx, const riga_eigs_o
   sv.mb = mb;
   sv.lock_cap = (int)std::min<int64_t>(nev_cap + 2 * sv.per_shift + 32, sv.N);
   sv.dim = pr->an.dim;
+  sv.cplx = pr->an.components == 2;
   sv.alloc();
 }
 
@@ -1096,16 +1127,21 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
     }
   } joiner{threads};
   Slice& A = *slices[0];
-  setup_solver(A.sv, pr, &pr->ctx[0], o, s, o->nev);
+  // a complex pencil's eigenvalues are double in its real-equivalent form:
+  // the slice counts and locks pairs of the real system (u and J u)
+  const int comp = pr->an.components;
+  setup_solver(A.sv, pr, &pr->ctx[0], o, s, o->nev * comp);
   A.lo = o->lo - END_SHIFT * std::fabs(o->lo);
   A.hi = std::isfinite(o->hi) ? o->hi - END_SHIFT * std::fabs(o->hi) : o->hi;
   if (!(A.hi > A.lo)) {
     A.lo = o->lo;
     A.hi = o->hi;
   }
-  A.nev = o->nev;
+  A.nev = o->nev * comp;
   const int per_shift = o->per_shift > 0 ? o->per_shift : 32;
-  const int nsl = std::isfinite(o->hi) ? 1 : std::max(1, std::min(slices_wanted(), o->nev / (2 * per_shift)));
+  const int nsl = (std::isfinite(o->hi) || comp > 1)
+                      ? 1
+                      : std::max(1, std::min(slices_wanted(), o->nev / (2 * per_shift)));
   if (nsl > 1) {
     A.after_lo = [&](Slice& a) {
       // split where the estimates put equal shares of the pairs; each later
@@ -1199,6 +1235,29 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
     if (t.joinable()) t.join();
   for (int i = 1; i < (int)slices.size(); ++i)
     if (codes[i] != RIGA_OK) throw Error(codes[i], "spectrum slice " + std::to_string(i) + ": " + errs[i]);
+  // Slices lock their pairs without seeing each other's: a pair's overlap
+  // with an eigenvector of another slice is bounded only by its residual
+  // over the gap (at the 1e-9 tolerance, up to a few 1e-10 in 3D).  One
+  // block Gram-Schmidt pass of each slice's locked vectors against every
+  // lower slice's (their intervals are disjoint) brings that overlap to
+  // rounding level; it changes the residuals at the level of the removed
+  // overlap times the gap, within the tolerance.
+  if (evecs && slices.size() > 1) {
+    for (auto si : streams) HIPCHECK(hipStreamSynchronize(si));
+    const int64_t n = A.sv.N;
+    constexpr int CROSS_COLS = 128;
+    DBuf<double> part;
+    part.alloc(block_project_partials(n, CROSS_COLS), s);
+    for (size_t i = 1; i < slices.size(); ++i) {
+      Solver& cur = slices[i]->sv;
+      for (size_t k = 0; k < i; ++k) {
+        const Solver& low = slices[k]->sv;
+        for (int a = 0; a < cur.nl; a += CROSS_COLS)
+          launch_block_project(low.W.p, low.B.p, n, low.nl, cur.B.p + (int64_t)a * n,
+                               std::min(CROSS_COLS, cur.nl - a), part.p, s);
+      }
+    }
+  }
   // results: the slices' pairs in order, up to the first slice that did not
   // complete (the pairs above it would leave a gap)
   riga_status status = RIGA_OK;
@@ -1207,11 +1266,13 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
     const Slice& S = *slices[i];
     const std::vector<Locked> pairs = slice_pairs(S);
     std::vector<int> out, in;
-    for (size_t q = 0; q < pairs.size() && nf < o->nev; ++q, ++nf) {
+    for (size_t q = 0; q < pairs.size() && nf < o->nev; ++q) {
+      if (pairs[q].partner) continue;  // J u of a complex pair: returned once
       if (evals) evals[nf] = pairs[q].lam;
       if (resid) resid[nf] = pairs[q].resid;
       out.push_back(nf);
       in.push_back(pairs[q].col);
+      ++nf;
     }
     if (evecs && !out.empty()) {
       if (i > 0) HIPCHECK(hipStreamSynchronize(streams[i - 1]));
@@ -1225,7 +1286,7 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
   HIPCHECK(hipStreamSynchronize(s));
   *n_found = nf;
   const bool split = slices.size() > 1;
-  const int wanted = split ? o->nev : A.nev;
+  const int wanted = split ? o->nev : A.nev / comp;
   if (nf < wanted && status == RIGA_OK) status = RIGA_ENOCONV;
   riga_stats st = A.sv.st;
   for (int i = 1; i < (int)slices.size(); ++i) add_stats(st, slices[i]->sv.st);

@@ -82,6 +82,7 @@ struct TabArgs {
   double* der;
   double* ke1;
   double* me1;
+  double* ge1;           // optional: int B_a B_b' (derivative on the second index)
 };
 
 __global__ void basis_tables_kernel(TabArgs a) {
@@ -120,14 +121,16 @@ __global__ void element_1d_kernel(TabArgs a, int total_el) {
     acc += a.ne[d];
   }
   const double hw = 0.5 / a.ne[d];  // Jacobian of [-1,1] -> element
-  double k = 0.0, m = 0.0;
+  double k = 0.0, m = 0.0, g = 0.0;
   for (int qp = 0; qp < a.q; ++qp) {
     const int64_t o = ((int64_t)e * a.q + qp) * np;
     k += a.gw[qp] * hw * a.der[o + ia] * a.der[o + ib];
     m += a.gw[qp] * hw * a.val[o + ia] * a.val[o + ib];
+    g += a.gw[qp] * hw * a.val[o + ia] * a.der[o + ib];
   }
   a.ke1[(int64_t)e * np * np + ab] = k;
   a.me1[(int64_t)e * np * np + ab] = m;
+  if (a.ge1) a.ge1[(int64_t)e * np * np + ab] = g;
 }
 
 struct AsmArgs {
@@ -143,9 +146,12 @@ struct AsmArgs {
   const int* first_fn;
   const double* ke1;
   const double* me1;
+  const double* ge1;
   const double* kappa;
   const double* rho;
   int dim, p;
+  int cplx;              // complex pencil in real-equivalent form (2 x 2 blocks)
+  double A[3];           // its vector potential
   double* kv;
   double* mv;
 };
@@ -159,7 +165,10 @@ __global__ void assemble_kernel(AsmArgs a) {
     const int64_t mid = (lo + hi) >> 1;
     if (a.row_ptr[mid] <= e) lo = mid; else hi = mid;
   }
-  const int64_t r = lo, c = a.col[e];
+  // a complex pencil: unknowns 2d (real part) and 2d + 1 (imaginary part)
+  // of scalar DOF d, each scalar coupling a 2 x 2 block [[Kr, -Ki], [Ki, Kr]]
+  const int64_t r = a.cplx ? lo >> 1 : lo, c = a.cplx ? (a.col[e] >> 1) : a.col[e];
+  const int part_r = a.cplx ? (int)(lo & 1) : 0, part_c = a.cplx ? (a.col[e] & 1) : 0;
   int ri[3], ci[3];
   int64_t rr = r, cc = c;
   for (int d = 0; d < 3; ++d) {
@@ -176,7 +185,10 @@ __global__ void assemble_kernel(AsmArgs a) {
     e1[d] = min(a.le[gr], a.le[gc]);
   }
   const int np = a.p + 1, np2 = np * np;
-  double ksum = 0.0, msum = 0.0;
+  double ksum = 0.0, msum = 0.0, isum = 0.0;
+  // the magnetic form: |A|^2 B_a B_b added to the real part, and the
+  // imaginary part sum_d A_d int (B_a d_d B_b - B_b d_d B_a)
+  const double A2 = a.A[0] * a.A[0] + a.A[1] * a.A[1] + a.A[2] * a.A[2];
   if (a.dim == 2) {
     for (int ey = e0[1]; ey <= e1[1]; ++ey) {
       const int fy = a.first_fn[a.tab_off[1] + ey];
@@ -193,32 +205,54 @@ __global__ void assemble_kernel(AsmArgs a) {
         const double rh = a.rho ? a.rho[el] : 1.0;
         ksum += kap * (My * Kx + Ky * Mx);
         msum += rh * (My * Mx);
+        if (a.cplx) {
+          const int64_t ox_t = (int64_t)(a.tab_off[0] + ex) * np2 + bx * np + ax;
+          const int64_t oy_t = (int64_t)(a.tab_off[1] + ey) * np2 + by * np + ay;
+          ksum += A2 * (My * Mx);
+          isum += a.A[0] * My * (a.ge1[ox] - a.ge1[ox_t]) + a.A[1] * (a.ge1[oy] - a.ge1[oy_t]) * Mx;
+        }
       }
     }
   } else {
     for (int ez = e0[2]; ez <= e1[2]; ++ez) {
       const int fz = a.first_fn[a.tab_off[2] + ez];
-      const int64_t oz = (int64_t)(a.tab_off[2] + ez) * np2 + (ri[2] + 1 - fz) * np + (ci[2] + 1 - fz);
+      const int az = ri[2] + 1 - fz, bz = ci[2] + 1 - fz;
+      const int64_t oz = (int64_t)(a.tab_off[2] + ez) * np2 + az * np + bz;
       const double Kz = a.ke1[oz], Mz = a.me1[oz];
+      const double Gz = a.cplx ? a.ge1[oz] - a.ge1[(int64_t)(a.tab_off[2] + ez) * np2 + bz * np + az] : 0.0;
       for (int ey = e0[1]; ey <= e1[1]; ++ey) {
         const int fy = a.first_fn[a.tab_off[1] + ey];
-        const int64_t oy = (int64_t)(a.tab_off[1] + ey) * np2 + (ri[1] + 1 - fy) * np + (ci[1] + 1 - fy);
+        const int ay = ri[1] + 1 - fy, by = ci[1] + 1 - fy;
+        const int64_t oy = (int64_t)(a.tab_off[1] + ey) * np2 + ay * np + by;
         const double Ky = a.ke1[oy], My = a.me1[oy];
+        const double Gy = a.cplx ? a.ge1[oy] - a.ge1[(int64_t)(a.tab_off[1] + ey) * np2 + by * np + ay] : 0.0;
         for (int ex = e0[0]; ex <= e1[0]; ++ex) {
           const int fx = a.first_fn[a.tab_off[0] + ex];
-          const int64_t ox = (int64_t)(a.tab_off[0] + ex) * np2 + (ri[0] + 1 - fx) * np + (ci[0] + 1 - fx);
+          const int ax = ri[0] + 1 - fx, bx = ci[0] + 1 - fx;
+          const int64_t ox = (int64_t)(a.tab_off[0] + ex) * np2 + ax * np + bx;
           const double Kx = a.ke1[ox], Mx = a.me1[ox];
           const int64_t el = ex + (int64_t)a.ne[0] * (ey + (int64_t)a.ne[1] * ez);
           const double kap = a.kappa ? a.kappa[el] : 1.0;
           const double rh = a.rho ? a.rho[el] : 1.0;
           ksum += kap * (Mz * My * Kx + Mz * Ky * Mx + Kz * My * Mx);
           msum += rh * (Mz * My * Mx);
+          if (a.cplx) {
+            const double Gx = a.ge1[ox] - a.ge1[(int64_t)(a.tab_off[0] + ex) * np2 + bx * np + ax];
+            ksum += A2 * (Mz * My * Mx);
+            isum += a.A[0] * Mz * My * Gx + a.A[1] * Mz * Gy * Mx + a.A[2] * Gz * My * Mx;
+          }
         }
       }
     }
   }
-  a.kv[e] = ksum;
-  a.mv[e] = msum;
+  if (a.cplx) {
+    // block [[Kr, -Ki], [Ki, Kr]] and diag(M, M)
+    a.kv[e] = part_r == part_c ? ksum : (part_r == 0 ? -isum : isum);
+    a.mv[e] = part_r == part_c ? msum : 0.0;
+  } else {
+    a.kv[e] = ksum;
+    a.mv[e] = msum;
+  }
 }
 
 // Row sums of |values| (1-norm = inf-norm of a symmetric matrix) and max |entry|.
@@ -250,7 +284,8 @@ namespace {
 // Knot values and first functions per direction, and the Gauss rule of q
 // points, on the device; the tables (and, with ke1/me1, the 1D element
 // matrices) at those points.
-void basis_tables_at(riga_problem* pr, int q, double* val, double* der, double* ke1, double* me1) {
+void basis_tables_at(riga_problem* pr, int q, double* val, double* der, double* ke1, double* me1,
+                     double* ge1 = nullptr) {
   const Analysis& an = pr->an;
   const int dim = an.dim, p = an.p, np = p + 1;
   hipStream_t s = pr->stream;
@@ -284,6 +319,7 @@ void basis_tables_at(riga_problem* pr, int q, double* val, double* der, double* 
   a.der = der;
   a.ke1 = ke1;
   a.me1 = me1;
+  a.ge1 = ge1;
   const int n1 = total_el * q;
   basis_tables_kernel<<<(n1 + 127) / 128, 128, 0, s>>>(a);
   HIPCHECK(hipGetLastError());
@@ -322,7 +358,9 @@ void launch_basis_tables(riga_problem* pr) {
   pr->tab_der.alloc((size_t)total_el * q * np, s);
   pr->ke1.alloc((size_t)total_el * np * np, s);
   pr->me1.alloc((size_t)total_el * np * np, s);
-  basis_tables_at(pr, q, pr->tab_val.p, pr->tab_der.p, pr->ke1.p, pr->me1.p);
+  if (an.components == 2) pr->ge1.alloc((size_t)total_el * np * np, s);
+  basis_tables_at(pr, q, pr->tab_val.p, pr->tab_der.p, pr->ke1.p, pr->me1.p,
+                  an.components == 2 ? pr->ge1.p : nullptr);
 }
 
 void basis_tables_q(riga_problem* pr, int q, DBuf<double>& val, DBuf<double>& der) {
@@ -352,10 +390,13 @@ void launch_assemble(riga_problem* pr) {
   a.first_fn = pr->first_fn.p;
   a.ke1 = pr->ke1.p;
   a.me1 = pr->me1.p;
+  a.ge1 = pr->ge1.p;
   a.kappa = pr->kappa.p;
   a.rho = pr->rho.p;
   a.dim = an.dim;
   a.p = an.p;
+  a.cplx = an.components == 2;
+  for (int d = 0; d < 3; ++d) a.A[d] = pr->potential[d];
   a.kv = pr->kv.p;
   a.mv = pr->mv.p;
   const int64_t nb = (a.nnz + 255) / 256;

@@ -452,13 +452,26 @@ __global__ void scale_cols_rsqrt_kernel(double* U, double* V, int64_t n, int m, 
 
 // Column copies dst(:, dcol[q]) = src(:, scol[q]) for up to COLS_PER_COPY
 // pairs, for two matrices at once (the second pair may be null).
+// jmul: the column times i of a complex vector stored as interleaved real
+// and imaginary parts (J u: (re, im) -> (-im, re)); n even then.
 __global__ void copy_cols_kernel(ColCopy cc, int64_t n, double* d0, const double* s0, double* d1,
-                                 const double* s1) {
+                                 const double* s1, int jmul) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int q = blockIdx.y;
   if (i >= n || q >= cc.count) return;
-  d0[(int64_t)cc.dst[q] * n + i] = s0[(int64_t)cc.src[q] * n + i];
-  if (d1) d1[(int64_t)cc.dst[q] * n + i] = s1[(int64_t)cc.src[q] * n + i];
+  const int64_t src = jmul ? (i ^ 1) : i;
+  const double sg = (jmul && !(i & 1)) ? -1.0 : 1.0;
+  d0[(int64_t)cc.dst[q] * n + i] = sg * s0[(int64_t)cc.src[q] * n + src];
+  if (d1) d1[(int64_t)cc.dst[q] * n + i] = sg * s1[(int64_t)cc.src[q] * n + src];
+}
+
+// x <- sg J x in place, J: (re, im) -> (-im, re) on interleaved pairs
+// (sg = -1: the inverse rotation); one thread per pair, n even.
+__global__ void jrot_kernel(double* x, int64_t pairs, double sg) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= pairs) return;
+  const double2 v = reinterpret_cast<const double2*>(x)[k];
+  reinterpret_cast<double2*>(x)[k] = make_double2(-sg * v.y, sg * v.x);
 }
 
 __global__ void axpby_kernel(double a, const double* u, const double* v, double* out, int64_t n) {
@@ -637,7 +650,8 @@ void launch_scale_cols_rsqrt(double* U, double* V, int64_t n, int m, const doubl
 }
 
 void launch_copy_cols(const std::vector<int>& dst, const std::vector<int>& src, int64_t n, double* d0,
-                      const double* s0, double* d1, const double* s1, hipStream_t s) {
+                      const double* s0, double* d1, const double* s1, hipStream_t s, bool jmul) {
+  if (jmul && (n & 1)) throw Error(RIGA_EINVAL, "J copy of an odd-length column");
   for (size_t q0 = 0; q0 < dst.size(); q0 += COLS_PER_COPY) {
     ColCopy cc{};
     cc.count = (int)std::min<size_t>(COLS_PER_COPY, dst.size() - q0);
@@ -646,9 +660,17 @@ void launch_copy_cols(const std::vector<int>& dst, const std::vector<int>& src, 
       cc.src[q] = src[q0 + q];
     }
     dim3 grid((unsigned)((n + 255) / 256), cc.count);
-    copy_cols_kernel<<<grid, 256, 0, s>>>(cc, n, d0, s0, d1, s1);
+    copy_cols_kernel<<<grid, 256, 0, s>>>(cc, n, d0, s0, d1, s1, jmul ? 1 : 0);
     HIPCHECK(hipGetLastError());
   }
+}
+
+void launch_jrot(double* x, int64_t n, double sg, hipStream_t s) {
+  if (n & 1) throw Error(RIGA_EINVAL, "launch_jrot: odd length");
+  const int64_t pairs = n / 2;
+  if (pairs == 0) return;
+  jrot_kernel<<<(unsigned)((pairs + 255) / 256), 256, 0, s>>>(x, pairs, sg);
+  HIPCHECK(hipGetLastError());
 }
 
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {

@@ -462,6 +462,8 @@ void factor_reserve(riga_problem* pr, Factor& F, int precision, hipStream_t s) {
     F.piv_type.alloc(N, s);
     F.piv_dof.alloc(N, s);
     F.piv_gmap.alloc((size_t)N * gs, s);
+    F.piv_inv.alloc(N, s);
+    F.rows_piv.alloc(std::max<int64_t>(an.f_rows_off[an.n_fronts], 1), s);
     F.d_diag.alloc(N, s);
     F.d_sub.alloc(N, s);
     F.dcoef.alloc((size_t)N * 3, s);

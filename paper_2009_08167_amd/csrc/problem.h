@@ -97,6 +97,12 @@ constexpr int SWEEP_ROWS_THIN = 16;
 constexpr int SWEEP_COLS_THIN = 4;
 constexpr int SWEEP_THIN_BELOW = 512;  // units of the default shape
 constexpr int XCDS = 8;                // accelerator complex dies of an MI355X
+// Fused sweeps of the bottom heights (one workgroup per subtree): four
+// 256-thread groups, forward units of SUB_ROWS rows, backward units of
+// SUB_COLS columns (8 per wave).
+constexpr int SUB_GROUPS = 4;
+constexpr int SUB_ROWS = 64;
+constexpr int SUB_COLS = 32;
 
 // One workgroup's share of a front: rows [lo, hi) (forward sweep, inverse)
 // or columns [lo, hi) (backward sweep), with the front's record inlined so a
@@ -105,6 +111,28 @@ struct WorkUnit {
   int32_t front, lo, hi, f;
   int32_t k, start, ldh, pad;
   int64_t h_off, rows_off, cb_off, gmap_off;
+};
+
+// The bottom heights 0..nh-1 swept in one launch per direction: subtree
+// `s` (its root at height < nh, its parent at height >= nh or none) has the
+// units of its fronts at height h in [off[s (nh + 1) + h], off[s (nh + 1) +
+// h + 1]) of fwd_units / bwd_units.  Its fronts are consecutive in the
+// post-order, so their pivots and update-vector entries are two ranges.
+struct SubInfo {
+  int32_t p0, np;    // pivots [p0, p0 + np)
+  int32_t cb0, ncb;  // update-vector entries [cb0, cb0 + ncb)
+};
+
+struct SubtreeDev {
+  int nh = 0;                 // fused heights; 0: none
+  int n_sub = 0;
+  int max_units = 0;          // units of one subtree, either direction
+  int max_np = 0, max_ncb = 0;
+  int grp_fwd = 0, grp_bwd = 0;  // doubles of LDS per 256-thread group
+  size_t lds_fwd = 0, lds_bwd = 0;  // bytes of LDS per workgroup
+  DBuf<WorkUnit> fwd_units, bwd_units;
+  DBuf<int32_t> fwd_off, bwd_off;
+  DBuf<SubInfo> info;
 };
 
 struct LevelDev {
@@ -191,6 +219,8 @@ struct Factor {
   DBuf<int32_t> piv_perm, piv_type;    // by new index
   DBuf<int32_t> front_stat;            // [n_fronts * 4]: neg, perturbed, 2x2, spare
   DBuf<int32_t> piv_dof, piv_gmap;     // pivot-order gather maps of the sweeps
+  DBuf<int32_t> piv_inv;               // [N] pivot index of each DOF (inverse of piv_dof)
+  DBuf<int32_t> rows_piv;              // [sum f] pivot index of every front position's DOF
   DBuf<double> d_diag, d_sub;          // D by pivot index: diagonal, (t+1, t) of 2x2 blocks
   DBuf<double> dcoef;                  // [N * 3] D^{-1} by pivot (see dinv_coef_kernel)
   DBuf<double> av;                     // K - sigma M values (refinement residuals)
@@ -241,6 +271,8 @@ struct riga_problem {
   riga::DBuf<double> kv, mv;        // K and M values (CSR order)
   riga::DBuf<double> tab_val, tab_der;  // basis tables per direction
   riga::DBuf<double> ke1, me1;          // 1D element matrices per direction
+  riga::DBuf<double> ge1;               // 1D element integrals of B_a B_b' (complex pencils)
+  double potential[3] = {0.0, 0.0, 0.0}; // vector potential of a complex pencil
   riga::DBuf<int32_t> fe, le, first_fn; // 1D maps per direction (concatenated)
   int tab_off[3] = {0, 0, 0};       // element offset of each direction in the tables
   int fn_off[3] = {0, 0, 0};        // function offset of each direction in fe/le
@@ -266,6 +298,7 @@ struct riga_problem {
   riga::DBuf<int32_t> d_gmap;               // [sum f * gstride] children's update indices
   int gstride = 1;
   riga::TopDev top;                         // explicit inverse of the top levels
+  riga::SubtreeDev sub;                     // fused sweeps of the bottom heights
   riga::DBuf<double> ir_r, ir_x, ir_d;      // iterative refinement vectors
 
   riga_stats stats{};
@@ -324,6 +357,7 @@ void launch_pivot_maps(riga_problem* pr, Factor& F, hipStream_t s);
 // L_TT^{-1} of factorisation F from its partitioned inverses h; runs the
 // top part of a forward/backward sweep.
 void setup_top(riga_problem* pr);
+void setup_subtrees(riga_problem* pr);
 void top_reserve(riga_problem* pr, Factor& F, int precision, hipStream_t s);
 template <class T>
 void build_top(riga_problem* pr, Factor& F, const T* h, T* trow, T* tcol, hipStream_t s);
@@ -385,9 +419,13 @@ struct ColCopy {
   int32_t count;
   int32_t dst[COLS_PER_COPY], src[COLS_PER_COPY];
 };
+// with jmul: d0(:, dst[q]) = J s0(:, src[q]) (and d1 from s1), J the
+// multiplication by i of interleaved complex columns: (re, im) -> (-im, re)
 void launch_copy_cols(const std::vector<int>& dst, const std::vector<int>& src, int64_t n, double* d0,
-                      const double* s0, double* d1, const double* s1, hipStream_t s);
+                      const double* s0, double* d1, const double* s1, hipStream_t s, bool jmul = false);
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+// x <- sg J x in place for interleaved complex storage (J multiplies by i)
+void launch_jrot(double* x, int64_t n, double sg, hipStream_t s);
 void launch_axpby(double a, const double* u, const double* v, double* out, int64_t n,
                   hipStream_t s);
 // out[0] = a^T b; partial: 256 doubles of scratch

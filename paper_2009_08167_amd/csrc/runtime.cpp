@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <mutex>
 
@@ -287,8 +288,151 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
   if (front_inverse_lds(an.max_fs) > 159 * 1024)
     throw Error(RIGA_EUNSUPPORTED, "fully-summed block too large for the inverse kernel's LDS");
   setup_top(pr);
+  setup_subtrees(pr);
   HIPCHECK(hipStreamSynchronize(s));
   pr->has_device = true;
+}
+
+// Fused sweeps of the bottom heights.  Every launch of a level sweep pays a
+// chain of dependent memory round trips (unit record, gather indices, the
+// gathered values, H) whatever its data; the fronts of the bottom heights
+// form many independent subtrees, so one workgroup per subtree can sweep
+// them all in one launch per direction, keeping the vectors passed between
+// the subtree's fronts in LDS and loading the next round's H while the
+// current one is reduced.  The fused heights are the most that keep at
+// least SUB_MIN_SUBTREES subtrees (a workgroup per CU) or subtrees of at
+// most SUB_MAX_BYTES of H each (small problems, where latency is all there
+// is); at least two heights, below the top block, and every subtree within
+// the LDS budget.  Off by default: on the 2D 256^2 p = 3 rIGA workload the
+// fused launches take as long as the level launches they replace (24.2 and
+// 35.0 us against 24.3 and 35.4 us per sweep pair: each round of a subtree
+// still waits out a memory latency), and during an eigen-solve their
+// CU-wide workgroups slow the other spectrum slice's kernels.
+// RIGA_SUBTREE_HEIGHTS=n fuses n heights; "auto" applies the rule above.
+void setup_subtrees(riga_problem* pr) {
+  constexpr int SUB_MIN_SUBTREES = 256;
+  constexpr double SUB_MAX_BYTES = 262144.0;
+  constexpr size_t SUB_LDS_MAX = 64 * 1024;
+  const Analysis& an = pr->an;
+  hipStream_t s = pr->home;
+  pr->sub = SubtreeDev{};
+  const int nl = pr->top.cut >= 0 ? pr->top.cut : an.height;
+  const int nf = an.n_fronts;
+  struct Plan {
+    int nh = 0;
+    std::vector<int> subs;        // roots, heaviest first
+    std::vector<int> first;       // per root: its first front (post-order)
+    int max_units = 0, max_np = 0, max_ncb = 0, max_k = 0, max_f = 0;
+    size_t lds_fwd = 0, lds_bwd = 0;
+    double max_bytes = 0.0;
+  };
+  // the plan for nh fused heights; false if a subtree is not a post-order
+  // range or does not fit the LDS budget
+  auto plan = [&](int nh, Plan& P) {
+    P = Plan{};
+    P.nh = nh;
+    std::vector<int> root(nf, -1), lo(nf, -1);
+    std::vector<double> bytes(nf, 0.0);
+    std::vector<int> units(nf, 0), cnt(nf, 0);
+    for (int F = 0; F < nf; ++F) {
+      if (an.f_height[F] >= nh) continue;
+      int R = F;
+      while (an.f_parent[R] >= 0 && an.f_height[an.f_parent[R]] < nh) R = an.f_parent[R];
+      root[F] = R;
+      if (lo[R] < 0) lo[R] = F;
+      ++cnt[R];
+      bytes[R] += (double)an.f_f[F] * an.f_k[F] * 8.0;
+      units[R] += std::max((an.f_f[F] + SUB_ROWS - 1) / SUB_ROWS, (an.f_k[F] + SUB_COLS - 1) / SUB_COLS);
+      P.max_k = std::max(P.max_k, an.f_k[F]);
+      P.max_f = std::max(P.max_f, an.f_f[F]);
+    }
+    for (int R = 0; R < nf; ++R) {
+      if (root[R] != R) continue;
+      if (cnt[R] != R - lo[R] + 1) return false;  // not a post-order range
+      P.subs.push_back(R);
+      const int np = an.f_start[R] + an.f_k[R] - an.f_start[lo[R]];
+      const int64_t ncb = an.f_cb_off[R + 1] - an.f_cb_off[lo[R]];
+      if (ncb > INT32_MAX) return false;
+      P.max_units = std::max(P.max_units, units[R]);
+      P.max_np = std::max(P.max_np, np);
+      P.max_ncb = std::max(P.max_ncb, (int)ncb);
+      P.max_bytes = std::max(P.max_bytes, bytes[R]);
+    }
+    std::stable_sort(P.subs.begin(), P.subs.end(), [&](int a, int b) { return bytes[a] > bytes[b]; });
+    for (int R : P.subs) P.first.push_back(lo[R]);
+    const size_t ucache = (size_t)P.max_units * sizeof(WorkUnit);
+    P.lds_fwd = ucache + sizeof(double) * ((size_t)P.max_np + P.max_ncb + (size_t)SUB_GROUPS * (P.max_k + 256));
+    P.lds_bwd = ucache + sizeof(double) * (2 * (size_t)P.max_np + (size_t)SUB_GROUPS * P.max_f);
+    return P.lds_fwd <= SUB_LDS_MAX && P.lds_bwd <= SUB_LDS_MAX;
+  };
+  Plan best, P;
+  const char* env = std::getenv("RIGA_SUBTREE_HEIGHTS");
+  if (!env || !*env) return;
+  if (std::strcmp(env, "auto") != 0) {
+    const int nh = std::max(0, std::min(std::atoi(env), nl));
+    if (nh >= 2 && plan(nh, P)) best = std::move(P);
+  } else {
+    for (int c = 2; c <= nl; ++c)
+      if (plan(c, P) && ((int)P.subs.size() >= SUB_MIN_SUBTREES || P.max_bytes <= SUB_MAX_BYTES))
+        best = std::move(P);
+  }
+  if (best.nh < 2) return;
+  const int nh = best.nh, n_sub = (int)best.subs.size();
+  auto unit = [&](int F, int lo, int hi) {
+    WorkUnit w{};
+    w.front = F;
+    w.lo = lo;
+    w.hi = hi;
+    w.f = an.f_f[F];
+    w.k = an.f_k[F];
+    w.start = an.f_start[F];
+    w.ldh = h_ld(an.f_f[F]);
+    w.h_off = an.f_h_off[F];
+    w.rows_off = an.f_rows_off[F];
+    w.cb_off = an.f_cb_off[F];
+    w.gmap_off = an.f_rows_off[F] * pr->gstride;
+    // `pad` marks the subtree's root: its update vector is also the
+    // input of the sweep above the fused heights
+    w.pad = an.f_parent[F] < 0 || an.f_height[an.f_parent[F]] >= nh;
+    return w;
+  };
+  std::vector<WorkUnit> fu, bu;
+  std::vector<int32_t> fo, bo;
+  std::vector<SubInfo> info;
+  for (int i = 0; i < n_sub; ++i) {
+    const int R = best.subs[i], F0 = best.first[i];
+    SubInfo si{};
+    si.p0 = an.f_start[F0];
+    si.np = an.f_start[R] + an.f_k[R] - si.p0;
+    si.cb0 = (int32_t)an.f_cb_off[F0];
+    si.ncb = (int32_t)(an.f_cb_off[R + 1] - an.f_cb_off[F0]);
+    info.push_back(si);
+    for (int h = 0; h <= nh; ++h) {
+      fo.push_back((int32_t)fu.size());
+      bo.push_back((int32_t)bu.size());
+      if (h == nh) break;
+      for (int F = F0; F <= R; ++F) {
+        if (an.f_height[F] != h) continue;
+        for (int a = 0; a < an.f_f[F]; a += SUB_ROWS) fu.push_back(unit(F, a, std::min(an.f_f[F], a + SUB_ROWS)));
+        for (int a = 0; a < an.f_k[F]; a += SUB_COLS) bu.push_back(unit(F, a, std::min(an.f_k[F], a + SUB_COLS)));
+      }
+    }
+  }
+  SubtreeDev& S = pr->sub;
+  S.nh = nh;
+  S.n_sub = n_sub;
+  S.max_units = best.max_units;
+  S.max_np = best.max_np;
+  S.max_ncb = best.max_ncb;
+  S.grp_fwd = best.max_k + 256;
+  S.grp_bwd = std::max(best.max_f, 1);
+  S.lds_fwd = best.lds_fwd;
+  S.lds_bwd = best.lds_bwd;
+  S.fwd_units.upload(fu, s);
+  S.bwd_units.upload(bu, s);
+  S.fwd_off.upload(fo, s);
+  S.bwd_off.upload(bo, s);
+  S.info.upload(info, s);
 }
 
 }  // namespace riga

@@ -32,7 +32,8 @@ class MeshDesc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("ne", C.c_int32 * 3), ("p", C.c_int32),
                 ("sep_spacing", C.c_int32), ("nquad", C.c_int32),
                 ("kappa", C.c_void_p), ("rho", C.c_void_p), ("coeffs_on_device", C.c_int32),
-                ("leaf_dofs", C.c_int32), ("stream", C.c_void_p)]
+                ("leaf_dofs", C.c_int32), ("stream", C.c_void_p), ("hermitian", C.c_int32),
+                ("potential", C.c_double * 3)]
 
 
 class EigsOpts(C.Structure):
@@ -60,7 +61,9 @@ class ProblemInfo(C.Structure):
                 ("max_front", C.c_int32), ("max_fs", C.c_int32), ("nnz_l", C.c_int64),
                 ("flops_fact", C.c_double), ("front_pool", C.c_int64),
                 ("nnz_l_exact", C.c_int64), ("flops_fact_exact", C.c_double),
-                ("sweep_bytes_stored", C.c_double)]
+                ("components", C.c_int32), ("sweep_bytes_stored", C.c_double),
+                ("top_cut", C.c_int32), ("fused_heights", C.c_int32),
+                ("fused_subtrees", C.c_int32)]
 
 
 class Allocator(C.Structure):
@@ -150,6 +153,8 @@ class Problem:
                      for f, _ in ProblemInfo._fields_}
         self.n_dof = int(inf.n_dof)
         self.n_elem = int(inf.n_elem)
+        # a complex Hermitian pencil: n_dof real unknowns, n_dof / 2 complex DOFs
+        self.hermitian = int(inf.components) == 2
 
     def refresh_info(self):
         """riga_problem_info again (its sweep bytes depend on the device set-up)."""
@@ -265,7 +270,8 @@ class Problem:
     def eigs(self, nev, lo=0.0, hi=math.inf, precision=RIGA_FP64, tol=1e-9, max_basis=0,
              max_restarts=0, per_shift=0, seed=0, vectors=True, stream=None, allow_partial=False):
         """nev lowest eigenpairs in [lo, hi).  Returns (lam numpy, U torch
-        [n_dof, nev] or None, resid numpy, stats dict)."""
+        [n_dof, nev] or None, resid numpy, stats dict); for a complex
+        Hermitian problem U is complex128 [n_dof / 2, nev]."""
         import torch
         o = EigsOpts(lo=lo, hi=hi, nev=nev, precision=precision, tol=tol, max_basis=max_basis,
                      max_restarts=max_restarts, per_shift=per_shift, seed=seed,
@@ -282,7 +288,10 @@ class Problem:
         _check(code, allow=(RIGA_ENOCONV,) if allow_partial else ())
         n = int(nf.value)
         if U is not None:
-            U = U[:n].T
+            U = U[:n]
+            if self.hermitian:
+                U = torch.view_as_complex(U.reshape(n, self.n_dof // 2, 2))
+            U = U.T
         d = st.as_dict()
         d["status"] = code
         return lam[:n], U, res[:n], d
@@ -395,9 +404,16 @@ def exact_eigenvalues(dim, count):
     return out
 
 
-def _desc(dim, ne, p, s, kappa, rho, nquad, leaf_dofs, stream, keep):
+def _desc(dim, ne, p, s, kappa, rho, nquad, leaf_dofs, stream, keep, potential=None):
     d = MeshDesc()
     d.dim = dim
+    if potential is not None:
+        pot = list(np.asarray(potential, dtype=np.float64).ravel())
+        if len(pot) != dim:
+            raise ValueError("potential needs one entry per direction")
+        d.hermitian = 1
+        for i in range(3):
+            d.potential[i] = pot[i] if i < dim else 0.0
     nes = [ne] * dim if np.isscalar(ne) else list(ne)
     for i in range(3):
         d.ne[i] = nes[i] if i < dim else 1
@@ -425,23 +441,26 @@ def _desc(dim, ne, p, s, kappa, rho, nquad, leaf_dofs, stream, keep):
     return d
 
 
-def analyze(dim, ne, p, s, nquad=0, leaf_dofs=0):
-    """Host-only analysis (no device needed)."""
+def analyze(dim, ne, p, s, nquad=0, leaf_dofs=0, potential=None):
+    """Host-only analysis (no device needed); `potential` (one entry per
+    direction) selects the complex Hermitian (magnetic) pencil."""
     keep = []
-    d = _desc(dim, ne, p, s, None, None, nquad, leaf_dofs, None, keep)
+    d = _desc(dim, ne, p, s, None, None, nquad, leaf_dofs, None, keep, potential)
     h = C.c_void_p()
     _check(lib().riga_analyze(C.byref(d), C.byref(h)))
     return Problem(h, dim, ne, p, s, None)
 
 
 def assemble(dim, ne, p, s, kappa=None, rho=None, nquad=0, leaf_dofs=0, device="cuda:0",
-             stream=None):
-    """Analyse and assemble K, M on the device."""
+             stream=None, potential=None):
+    """Analyse and assemble K, M on the device.  `potential` (the constant
+    vector potential A, one entry per direction) assembles the complex
+    Hermitian pencil of the magnetic Laplacian instead (kappa = rho = 1)."""
     import torch
     dev = torch.device(device)
     with torch.cuda.device(dev):
         keep = []
-        d = _desc(dim, ne, p, s, kappa, rho, nquad, leaf_dofs, _stream(stream), keep)
+        d = _desc(dim, ne, p, s, kappa, rho, nquad, leaf_dofs, _stream(stream), keep, potential)
         h = C.c_void_p()
         _check(lib().riga_assemble(C.byref(d), C.byref(h)))
         return Problem(h, dim, ne, p, s, dev)

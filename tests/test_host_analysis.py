@@ -207,3 +207,62 @@ def test_supernode_splitting_keeps_order_fill_and_flops(dim, ne, p, s, split, mo
         P = tp["parent"][F]
         if P == F + 1 and tp["k"][F] == split:
             assert starts[P] == starts[F] + split
+
+
+@pytest.mark.parametrize("dim,ne,p,s,A", [(2, 10, 2, 5, (0.9, -1.7)), (3, 4, 2, 2, (0.4, 1.1, -0.6)),
+                                          (2, 12, 3, 0, (2.5, 0.7))])
+def test_complex_pencil_analysis(dim, ne, p, s, A):
+    """The complex Hermitian pencil in real-equivalent form: the pattern is
+    the scalar one with every coupling a 2 x 2 block (real and imaginary
+    parts of a DOF adjacent); the same tree with doubled fronts is a valid
+    elimination tree of it, its fronts contain the exact fill of the
+    real-equivalent matrix (SuperLU, natural order on the permuted matrix),
+    and the library's exact-fill count equals SuperLU's."""
+    _lib_or_skip()
+    from oracle import hermitian
+    pr = riga.analyze(dim, ne, p, s, potential=A)
+    sc = riga.analyze(dim, ne, p, s)
+    assert pr.hermitian and pr.n_dof == 2 * sc.n_dof
+    rp, ci = pr.pattern()
+    rps, cis = sc.pattern()
+    n = pr.n_dof
+    P = sp.csr_matrix((np.ones(len(ci)), ci, rp), shape=(n, n))
+    S = sp.csr_matrix((np.ones(len(cis)), cis, rps), shape=(n // 2, n // 2))
+    assert (P != sp.kron(S, np.ones((2, 2)), format="csr")).nnz == 0
+    t = pr.tree()
+    perm = t["perm"]
+    assert sorted(perm) == list(range(n))
+    assert (perm[0::2] % 2 == 0).all() and (perm[1::2] == perm[0::2] + 1).all()
+    fronts = _fronts(t)
+    owner = -np.ones(n, np.int64)
+    start = 0
+    for F in range(len(fronts)):
+        k = t["k"][F]
+        assert k % 2 == 0 and t["f"][F] % 2 == 0
+        fs = fronts[F][:k]
+        assert (perm[fs] == np.arange(start, start + k)).all()
+        start += k
+        owner[fs] = F
+    # the stored pattern is the oracle's real-equivalent matrix's, plus the
+    # diagonal blocks' off-diagonal entries (Im K is antisymmetric: zero there)
+    Kc, Mc = hermitian.assemble_magnetic(dim, ne, p, s, A)
+    K2, M2 = hermitian.real_equivalent(Kc + Mc, Mc)
+    N = Kc.shape[0]
+    il = np.empty(2 * N, dtype=np.int64)
+    il[0::2] = np.arange(N)
+    il[1::2] = N + np.arange(N)
+    Ko = (abs(K2[il][:, il]) > 0).astype(float)
+    assert (Ko.multiply(P) != Ko).nnz == 0
+    # exact fill of the stored pattern: SuperLU without pivoting on a
+    # diagonally dominant matrix with that pattern (no cancellation)
+    Ai = (P + (P.sum(axis=1).max() + 1.0) * sp.identity(n)).tocsr()
+    Pm = sp.csr_matrix((np.ones(n), (perm, np.arange(n))), shape=(n, n))
+    Ap = (Pm @ Ai @ Pm.T).tocsc()
+    lu = spla.splu(Ap, permc_spec="NATURAL", diag_pivot_thresh=0.0, options=dict(SymmetricMode=True))
+    assert (lu.perm_r == np.arange(n)).all()
+    L = sp.tril(lu.L, -1).tocoo()
+    iperm = np.argsort(perm)
+    fsets = [set(perm[f]) for f in fronts]
+    for i, j in zip(L.row, L.col):
+        assert i in fsets[owner[iperm[j]]]
+    assert pr.info["nnz_l_exact"] == L.nnz + n
