@@ -119,6 +119,10 @@ typedef struct {
   double t_fact, t_fb, t_mv, t_orth, t_proj, t_ritz, t_total;
   double flops_fact;      /* algorithmic flops of one factorisation */
   double bytes_fb;        /* algorithmic bytes of one forward+backward elimination */
+  int32_t n_thick;        /* Lanczos runs continued from a thick-restart basis (Sec. 4.2,
+                             Eq. LanczosRestart: a run whose basis filled up keeps its
+                             unconverged Ritz vectors nearest the shift, up to half the
+                             basis, and its last Lanczos vector) */
 } riga_stats;
 
 /* Static facts about an assembled problem (host-side analysis). */

@@ -73,6 +73,79 @@ bool deflate_window_on() {
   return !(v && *v && *v != '0');
 }
 
+// Thick restarts (RIGA_THICK_RESTART=0 switches them off: a run whose basis
+// fills up then restarts from a fresh vector, as a run that found its pairs).
+bool thick_restart_on() {
+  const char* v = std::getenv("RIGA_THICK_RESTART");
+  return !(v && *v == '0');
+}
+
+// A restart basis for thick-restart Lanczos (Sec. 4.2, Eq. LanczosRestart):
+// with Ritz pairs (theta_i, s_i) of T_m kept and b_i = beta_{m+1} s_i[m-1],
+// the projection on [V S, v_{m+1}] is the arrowhead [[diag(theta), b],
+// [b^T, .]].  Lanczos on diag(theta) from b / |b| (full re-orthogonalisation,
+// in FP64 on the host) gives an orthonormal Q, its columns reversed so that
+// the last one is b / |b|, with Q^T diag(theta) Q tridiagonal: on
+// [V S Q, v_{m+1}] the projection is tridiagonal with coupling |b| between
+// the last kept vector and v_{m+1}, and the recurrence continues unchanged.
+// Returns Q (c x c', column-major) with c' <= c (fewer when the Krylov space
+// of diag(theta) and b is smaller), alpha[0..c'), beta[1..c'] (beta[c'] = |b|).
+struct ThickBasis {
+  int c = 0;
+  std::vector<double> Q, alpha, beta;
+};
+
+ThickBasis thick_basis(const std::vector<double>& theta, const std::vector<double>& b) {
+  ThickBasis T;
+  const int c = (int)theta.size();
+  double nb = 0.0, tmax = 0.0;
+  for (int i = 0; i < c; ++i) {
+    nb += b[i] * b[i];
+    tmax = std::max(tmax, std::fabs(theta[i]));
+  }
+  nb = std::sqrt(nb);
+  if (c == 0 || !(nb > 0.0)) return T;
+  std::vector<double> U, a, g(1, 0.0);  // U: c x t, column-major
+  std::vector<double> u(c), w(c);
+  for (int i = 0; i < c; ++i) u[i] = b[i] / nb;
+  for (int t = 0; t < c; ++t) {
+    U.insert(U.end(), u.begin(), u.end());
+    double at = 0.0;
+    for (int i = 0; i < c; ++i) {
+      w[i] = theta[i] * u[i];
+      at += u[i] * w[i];
+    }
+    a.push_back(at);
+    // w -= U (U^T w), twice
+    for (int pass = 0; pass < 2; ++pass)
+      for (int q = 0; q <= t; ++q) {
+        const double* uq = &U[(size_t)q * c];
+        double d = 0.0;
+        for (int i = 0; i < c; ++i) d += uq[i] * w[i];
+        for (int i = 0; i < c; ++i) w[i] -= d * uq[i];
+      }
+    double gn = 0.0;
+    for (int i = 0; i < c; ++i) gn += w[i] * w[i];
+    gn = std::sqrt(gn);
+    if (t + 1 == c || gn <= 1e-12 * tmax) break;  // invariant subspace
+    g.push_back(gn);
+    for (int i = 0; i < c; ++i) u[i] = w[i] / gn;
+  }
+  const int cp = (int)a.size();
+  T.c = cp;
+  T.Q.resize((size_t)c * cp);
+  T.alpha.resize(cp);
+  T.beta.assign(cp + 1, 0.0);
+  for (int q = 0; q < cp; ++q) {
+    const int t = cp - 1 - q;
+    std::memcpy(&T.Q[(size_t)q * c], &U[(size_t)t * c], c * sizeof(double));
+    T.alpha[q] = a[t];
+    if (q >= 1) T.beta[q] = g[cp - q];
+  }
+  T.beta[cp] = nb;
+  return T;
+}
+
 // RIGA_LOG=1 prints one line per Lanczos run and per shift to stderr.
 bool log_on() {
   static const bool on = [] {
@@ -353,15 +426,31 @@ struct Solver {
   // `restart_from` is not empty, the sum of those columns as a restart
   // vector; lock the pairs that pass the residual test.  Returns the number
   // locked.
+  // With a thick restart (`thick`: cz = thick->c columns of Z = S_kept Q,
+  // m x cz), also V Z and W Z (its M images) into columns nw + 1 .. nw + cz
+  // of Ub and MU, and v_{m+1}, M v_{m+1} into column nw + 1 + cz: they are
+  // formed before the locked pairs overwrite the basis, and copied into the
+  // new basis by the caller.
   int lock_pairs(const Ritz& r, double sigma, const std::vector<double>& Sv,
                  const std::vector<int>& which, const std::vector<int>& restart_from,
-                 const std::vector<double>& lam_ritz, bool* have_restart) {
+                 const std::vector<double>& lam_ritz, bool* have_restart,
+                 const std::vector<double>* Z = nullptr, int cz = 0) {
     auto a = clk::now();
     const int m = r.m;
     const int nw = (int)which.size();
     const int nc = nw + (restart_from.empty() ? 0 : 1);
     *have_restart = !restart_from.empty();
     (void)lam_ritz;
+    if (cz > 0) {
+      // (column nw is the restart vector's, present whenever cz > 0)
+      const int z0 = nw + 1;
+      HIPCHECK(hipMemcpyAsync(Sh.p + (size_t)z0 * m, Z->data(), (size_t)m * cz * sizeof(double),
+                              hipMemcpyHostToDevice, s));
+      launch_gemm_nn(Bc(nl), N, m, Sh.p + (size_t)z0 * m, m, cz, Ub.p + (int64_t)z0 * N, s);
+      launch_gemm_nn(Wc(nl), N, m, Sh.p + (size_t)z0 * m, m, cz, MU.p + (int64_t)z0 * N, s);
+      launch_copy(Ub.p + (int64_t)(z0 + cz) * N, Bc(nl + m), N, s);
+      launch_copy(MU.p + (int64_t)(z0 + cz) * N, Wc(nl + m), N, s);
+    }
     if (nc == 0) return 0;
     std::vector<double> Sh_h((size_t)m * nc, 0.0);
     for (int i = 0; i < nw; ++i)
@@ -499,11 +588,21 @@ struct Solver {
   // on_check (optional) sees the Ritz data of every convergence check.
   Ritz run(double sigma, int need_below, int need_above, const double* init, int* n_new,
            const std::function<void(const Ritz&)>& on_check = nullptr) {
-    start_vector(init);
-    const int maxm = (int)std::min<int64_t>(mb, N - nl - 1);
+    // a run at the shift of a run whose basis filled up continues from its
+    // thick-restart basis (columns 0 .. thick_c of V, T's entries uploaded)
     int j = 0;
+    if (thick_c > 0 && init == nullptr && sigma == thick_sigma) {
+      HIPCHECK(hipMemsetAsync(flag.p, 0, 4 * sizeof(int32_t), s));
+      j = thick_c;
+      st.n_thick++;
+    } else {
+      start_vector(init);
+    }
+    thick_c = 0;
+    const int maxm = (int)std::min<int64_t>(mb, N - nl - 1);
     Ritz r;
     int next_check = std::min(maxm, std::max(16, std::min(need_below + need_above, maxm)));
+    bool met = false, breakdown = false;
     while (true) {
       step(j);
       ++j;
@@ -518,8 +617,9 @@ struct Solver {
         const double l = sigma + 1.0 / r.theta[i];
         if (l < sigma) cb += per; else ca += per;
       }
-      const bool breakdown = r.beta_m == 0.0;
-      if ((cb >= need_below && ca >= need_above) || j >= maxm || breakdown) break;
+      breakdown = r.beta_m == 0.0;
+      met = cb >= need_below && ca >= need_above;
+      if (met || j >= maxm || breakdown) break;
       next_check = std::min(maxm, j + 8);
     }
     st.n_it++;
@@ -529,21 +629,72 @@ struct Solver {
     std::sort(unc.begin(), unc.end(), [&](int a, int b) {
       return std::fabs(r.theta[a]) > std::fabs(r.theta[b]);
     });
+    // Thick restart (Sec. 4.2, Eq. LanczosRestart) when the basis filled up
+    // before the pairs this run is after converged: keep the unconverged
+    // Ritz vectors nearest the shift, up to half the basis, and the last
+    // Lanczos vector.  (A run that found its pairs but left some missing --
+    // further copies of a multiple eigenvalue, which its Krylov space cannot
+    // reach -- restarts from a fresh vector instead.)
+    std::vector<int> keep;
+    if (thick_restart_on() && !met && !breakdown && j >= maxm && unc.size() >= 2) {
+      const int c = std::min<int>((int)unc.size() - 1, maxm / 2);
+      keep.assign(unc.begin(), unc.begin() + c);
+    }
     if (unc.size() > 8) unc.resize(8);
     std::vector<int> idx = conv;
+    for (int q : keep)
+      if (std::find(unc.begin(), unc.end(), q) == unc.end()) idx.push_back(q);
     idx.insert(idx.end(), unc.begin(), unc.end());
     std::sort(idx.begin(), idx.end());
     auto a = clk::now();
     std::vector<double> Sv = vectors(r, idx);
     st.t_proj += secs(a, clk::now());
-    std::vector<int> which, rest;
+    std::vector<int> which, rest, kpos;
     for (size_t q = 0; q < idx.size(); ++q) {
       if (converged(r, idx[q])) which.push_back((int)q);
-      else rest.push_back((int)q);
+      else if (std::find(unc.begin(), unc.end(), idx[q]) != unc.end()) rest.push_back((int)q);
+    }
+    for (int q : keep) kpos.push_back((int)(std::lower_bound(idx.begin(), idx.end(), q) - idx.begin()));
+    // the restart basis: Z = S_kept Q (m x c')
+    ThickBasis TB;
+    std::vector<double> Z;
+    if (!keep.empty()) {
+      const int m = r.m;
+      std::vector<double> th(keep.size()), bb(keep.size());
+      for (size_t i = 0; i < keep.size(); ++i) {
+        th[i] = r.theta[keep[i]];
+        bb[i] = r.beta_m * Sv[(size_t)kpos[i] * m + (m - 1)];
+      }
+      TB = thick_basis(th, bb);
+      Z.assign((size_t)m * TB.c, 0.0);
+      for (int q = 0; q < TB.c; ++q)
+        for (size_t i = 0; i < keep.size(); ++i) {
+          const double w = TB.Q[(size_t)q * keep.size() + i];
+          const double* sv = &Sv[(size_t)kpos[i] * m];
+          double* z = &Z[(size_t)q * m];
+          for (int t = 0; t < m; ++t) z[t] += w * sv[t];
+        }
+      if (rest.empty()) TB.c = 0;  // (unreachable: keep is a superset of rest)
     }
     bool have_restart = false;
-    *n_new = lock_pairs(r, sigma, Sv, which, rest, r.theta, &have_restart);
+    *n_new = lock_pairs(r, sigma, Sv, which, rest, r.theta, &have_restart, TB.c > 0 ? &Z : nullptr, TB.c);
     restart_valid = have_restart && r.beta_m != 0.0;
+    if (TB.c > 0) {
+      // V := [V Z, v_{m+1}] after the locked columns, T's leading block
+      // := the re-tridiagonalised arrowhead
+      const int cz = TB.c, z0 = (int)which.size() + 1;
+      std::vector<int> dst, src;
+      for (int q = 0; q <= cz; ++q) {
+        dst.push_back(nl + q);
+        src.push_back(z0 + q);
+      }
+      launch_copy_cols(dst, src, N, B.p, Ub.p, W.p, MU.p, s);
+      HIPCHECK(hipMemcpyAsync(alpha.p, TB.alpha.data(), cz * sizeof(double), hipMemcpyHostToDevice, s));
+      HIPCHECK(hipMemcpyAsync(beta.p, TB.beta.data(), (cz + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+      HIPCHECK(hipStreamSynchronize(s));  // the host arrays must outlive their uploads
+      thick_c = cz;
+      thick_sigma = sigma;
+    }
     if (log_on())
       std::fprintf(stderr, "[riga] run sigma=%.6g steps=%d need=(%d,%d) converged=%zu locked=%d total_locked=%d "
                    "window=[%.6g, from column %d]\n",
@@ -551,6 +702,10 @@ struct Solver {
     return r;
   }
   bool restart_valid = false;
+  // thick-restart basis for the next run at thick_sigma: columns 0 .. thick_c
+  // of V (0 when there is none)
+  int thick_c = 0;
+  double thick_sigma = 0.0;
 };
 
 
@@ -963,8 +1118,10 @@ void run_slice(Slice& S) {
       // their FP64 residuals stay above the tolerance (an FP32 factor, or an
       // FP64 one of an ill-conditioned K - sigma M).  Refine the solves more
       // from here on.
-      const bool stalled = 8 * n_new < need_below + need_above ||
-                           (runs >= 1 && need_below > 0 && sv.count_locked(lo, sigma) == below);
+      // (a run continued by a thick restart ran out of basis, not accuracy)
+      const bool stalled = sv.thick_c == 0 &&
+                           (8 * n_new < need_below + need_above ||
+                            (runs >= 1 && need_below > 0 && sv.count_locked(lo, sigma) == below));
       if (stalled) {
         if (sv.precision == RIGA_MIXED && sv.max_ir < MAX_IR_ESCALATED) {
           sv.max_ir = std::min(MAX_IR_ESCALATED, std::max(1, 2 * sv.max_ir));
@@ -1052,6 +1209,7 @@ void add_stats(riga_stats& a, const riga_stats& b) {
   a.n_ir += b.n_ir;
   a.n_perturbed_pivots += b.n_perturbed_pivots;
   a.n_2x2_pivots += b.n_2x2_pivots;
+  a.n_thick += b.n_thick;
   a.t_fact += b.t_fact;
   a.t_fb += b.t_fb;
   a.t_mv += b.t_mv;

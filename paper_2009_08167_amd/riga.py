@@ -49,7 +49,8 @@ class Stats(C.Structure):
                 ("n_perturbed_pivots", C.c_int32), ("n_2x2_pivots", C.c_int32),
                 ("t_fact", C.c_double), ("t_fb", C.c_double), ("t_mv", C.c_double),
                 ("t_orth", C.c_double), ("t_proj", C.c_double), ("t_ritz", C.c_double),
-                ("t_total", C.c_double), ("flops_fact", C.c_double), ("bytes_fb", C.c_double)]
+                ("t_total", C.c_double), ("flops_fact", C.c_double), ("bytes_fb", C.c_double),
+                ("n_thick", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

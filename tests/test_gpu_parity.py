@@ -570,3 +570,29 @@ def test_project_rejects_bad_sizes():
         code = L.riga_project(n, m, C.c_void_p(W.data_ptr()), C.c_void_p(W.data_ptr()),
                               C.c_void_p(x.data_ptr()), C.c_void_p(c.data_ptr()), None)
         assert code == riga.RIGA_EINVAL
+
+
+@pytest.mark.parametrize("w", [workloads.small(2, 40, 3, 8, 60, 0.3), workloads.small(3, 10, 2, 5, 40, 0.3)],
+                         ids=lambda w: w.name)
+def test_thick_restart_matches_oracle(w, monkeypatch):
+    """Runs whose basis fills up before their pairs converge (a basis of 40
+    for 24 pairs per shift) continue from a thick-restart basis (Sec. 4.2,
+    Eq. LanczosRestart): the pairs match the dense oracle to the usual bars,
+    thick restarts happened (stats n_thick), and explicit restarts from a
+    fresh vector (RIGA_THICK_RESTART=0) reach the same pairs with more
+    forward/backward eliminations."""
+    riga = _riga()
+    kappa, rho = w.coefficients()
+    Ko, Mo = assembly.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
+    lr, Ur = eigen.dense_eigh(Ko, Mo)
+    pr = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
+    lam, U, res, st = pr.eigs(w.nev, per_shift=24, max_basis=40, max_restarts=40)
+    _say("thick", w.name, st)
+    assert st["n_thick"] > 0
+    _check_pairs(Ko, Mo, lr, Ur, lam, U.cpu().numpy(), res, w.nev)
+    monkeypatch.setenv("RIGA_THICK_RESTART", "0")
+    lam0, U0, res0, st0 = pr.eigs(w.nev, per_shift=24, max_basis=40, max_restarts=40)
+    _say("explicit", w.name, st0)
+    assert st0["n_thick"] == 0
+    _check_pairs(Ko, Mo, lr, Ur, lam0, U0.cpu().numpy(), res0, w.nev)
+    assert st["n_fb"] < st0["n_fb"], (st["n_fb"], st0["n_fb"])
