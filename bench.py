@@ -689,57 +689,68 @@ def factor_profile(riga, torch):
 def mfma_summary(counter_csv, fprof_log):
     """Markdown summary of `rocprofv3 --pmc SQ_INSTS_VALU_MFMA_MOPS_F64
     SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE` over
-    `bench.py --factor-profile`: the dispatches of each case (split at its
-    assembly) summed per counter, matrix-core flops (512 per MOPS unit),
-    MFMA busy share of the SIMDs over the GPU-active cycles, and the
-    achieved rate over the case's event-timed factorisation (printed by the
-    profiled run itself, `fprof_log`)."""
+    `bench.py --factor-profile` (per case and precision: one factorisation,
+    one warm-up, three timed: five).  The dispatches of each case (split at
+    its assembly) are summed per counter: matrix-core flops = MOPS x 512
+    (rocprofv3's own MFMA_FLOPS metrics), per factorisation; MFMA busy share
+    as rocprofv3's MfmaUtil metric, busy cycles over (GRBM_GUI_ACTIVE summed
+    over the dispatches and divided by the 8 XCDs it is summed over) x 1024
+    SIMDs, i.e. over the kernels' active time; and the matrix-core rate over
+    the event-timed factorisation of an unprofiled run (`fprof_log`, lines
+    of `bench.py --factor-profile`: the profiler serialises the kernels)."""
     import csv
+    reps = 5
+    xcd, simd = 8, 256 * 4
     rows = list(csv.DictReader(open(counter_csv)))
     rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+
+    def short(name):
+        n = name.replace("(anonymous namespace)::", "").replace("void ", "").replace("riga::", "")
+        return n.split("(")[0]
+
     cases, cur = [], None
     for r in rows:
-        name = r["Kernel_Name"]
-        if "assemble_kernel" in name and "front_assemble" not in name:
+        name = short(r["Kernel_Name"])
+        if name == "assemble_kernel":
             if cur is None or cur["seen_other"]:
                 cur = {"seen_other": False, "c": {}, "kern": {}}
                 cases.append(cur)
+            continue
         if cur is None:
             continue
-        if "assemble_kernel" not in name:
-            cur["seen_other"] = True
+        cur["seen_other"] = True
         cn, v = r["Counter_Name"], float(r["Counter_Value"])
         cur["c"][cn] = cur["c"].get(cn, 0.0) + v
-        short = name.split("(")[0].replace("void ", "").replace("riga::", "").replace("(anonymous namespace)::", "")
-        kd = cur["kern"].setdefault(short, {})
+        kd = cur["kern"].setdefault(name, {})
         kd[cn] = kd.get(cn, 0.0) + v
     lines = [json.loads(l) for l in open(fprof_log) if l.startswith("{")]
-    simd = 256 * 4
-    print("| case | precision | factorisation (events) | exact flops | MFMA flops (counted, all 6 factorisations) |"
-          " MFMA busy / SIMD-cycles | achieved on exact flops |")
+    print("| case | FP64 factorisation (unprofiled) | exact flops | FP64 MFMA flops | FP64 MFMA rate "
+          "| FP32 MFMA flops (mixed) | MFMA busy over kernel-active time (both precisions) |")
     print("|---|---|---|---|---|---|---|")
     for i, c in enumerate(cases):
-        if i >= len(lines) // 2:
+        if 2 * i + 1 >= len(lines):
             break
-        f64 = c["c"].get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) * 512
-        f32 = c["c"].get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) * 512
-        busy = c["c"].get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)
-        act = c["c"].get("GRBM_GUI_ACTIVE", 0.0)
         a, b = lines[2 * i], lines[2 * i + 1]
+        f64 = c["c"].get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) * 512 / reps
+        f32 = c["c"].get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) * 512 / reps
+        busy = c["c"].get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)
+        act = c["c"].get("GRBM_GUI_ACTIVE", 0.0) / xcd
         util = 100.0 * busy / (act * simd) if act else 0.0
-        print("| %s | fp64 + mixed | %.2f / %.2f ms | %.3g | FP64 %.3g, FP32 %.3g | %.2f%% | %.2f / %.2f TFLOP/s |"
-              % (a["case"], a["fact_ms"], b["fact_ms"], a["flops_exact"], f64, f32, util,
-                 a["tflops_exact"], b["tflops_exact"]))
-    print("\n## MFMA work by kernel (all cases)\n")
-    print("| case | kernel | FP64 MFMA flops | FP32 MFMA flops | MFMA busy cycles |\n|---|---|---|---|---|")
+        print("| %s | %.2f ms | %.3g | %.3g | %.2f TFLOP/s (%.1f%% of 78.6) | %.3g | %.2f%% |"
+              % (a["case"], a["fact_ms"], a["flops_exact"], f64, f64 / (a["fact_ms"] * 1e-3) / 1e12,
+                 100 * f64 / (a["fact_ms"] * 1e-3) / 78.6e12, f32, util))
+    print("\n## MFMA work by kernel (per factorisation, FP64 and mixed runs together)\n")
+    print("| case | kernel | FP64 MFMA flops | FP32 MFMA flops | MFMA busy, share of the case's |\n|---|---|---|---|---|")
     for i, c in enumerate(cases):
         tag = lines[2 * i]["case"] if 2 * i < len(lines) else str(i)
+        tot = c["c"].get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) or 1.0
         for kname, kd in sorted(c["kern"].items(), key=lambda t: -t[1].get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)):
             if kd.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) <= 0:
                 continue
-            print("| %s | `%s` | %.3g | %.3g | %.3g |" % (tag, kname, kd.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) * 512,
-                                                         kd.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) * 512,
-                                                         kd.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)))
+            print("| %s | `%s` | %.3g | %.3g | %.1f%% |" % (
+                tag, kname, kd.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) * 512 / reps,
+                kd.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) * 512 / reps,
+                100 * kd.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / tot))
 
 
 def main():
