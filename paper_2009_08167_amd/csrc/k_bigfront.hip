@@ -13,10 +13,13 @@
 //  2. big_cbrows_kernel (many workgroups): the update-block rows [k, f) of
 //     the panel columns receive the same interchanges and eliminations:
 //     lanes hold the panel columns, pivots are broadcast with readlane.
-//  3. big_trailing_kernel (many workgroups): the trailing block
-//     [j0 + nb, f)^2 (lower triangle) receives A -= L_p W_p^T, W_p = L_p D_p,
-//     in 64 x 64 tiles on the FP64 MFMA units (operands staged in LDS, the
-//     tile read-modified-written coalesced).
+//  3. big_trailing_kernel (many workgroups): the trailing columns
+//     [j0 + nb, k) of the fully-summed block, all rows below the diagonal,
+//     receive A -= L_p W_p^T, W_p = L_p D_p, in 64 x 64 tiles on the MFMA
+//     units (operands staged in LDS, the tile read-modified-written
+//     coalesced).
+//  After the last panel, big_cbupdate_kernel applies the whole rank-k update
+//  to the update block [k, f)^2 at once.
 //
 // The panel start of each front lives in device memory, so the host issues
 // a fixed number of steps computed for panels that never end early, then
@@ -393,9 +396,9 @@ __global__ void __launch_bounds__(256) big_trailing_kernel(BigArgs a, T* pool) {
   const BigState st = a.st[b];
   if (st.kb == 0) return;
   const int F = a.fronts[b];
-  const int f = a.ff[F], start = a.fstart[F];
+  const int f = a.ff[F], k = a.fk[F], start = a.fstart[F];
   const int j0 = st.cur, kb = st.kb, c0 = st.cur + st.nb;
-  if (c0 >= f) return;
+  if (c0 >= f || c0 >= k) return;
   const int nt = (f - c0 + BF_TILE - 1) / BF_TILE;
   const int ntiles = nt * (nt + 1) / 2;
   T* A = pool + a.pool_off[F];
@@ -417,6 +420,8 @@ __global__ void __launch_bounds__(256) big_trailing_kernel(BigArgs a, T* pool) {
     while (bi * (bi + 1) / 2 > tile) --bi;
     const int bj = tile - bi * (bi + 1) / 2;
     const int r0 = c0 + bi * BF_TILE, cb0 = c0 + bj * BF_TILE;
+    // the update block's own columns wait for big_cbupdate_kernel
+    if (cb0 >= k) continue;
     // stage L rows of the tile and W of its columns (zero beyond kb / f)
     for (int e = tid; e < BF_NB * BF_TILE; e += 256) {
       const int ii = e & 63, t = e >> 6;
@@ -471,12 +476,108 @@ __global__ void __launch_bounds__(256) big_trailing_kernel(BigArgs a, T* pool) {
     for (int e = tid; e < BF_TILE * BF_TILE; e += 256) {
       const int ii = e & 63, cc = e >> 6;
       const int i = r0 + ii, c = cb0 + cc;
-      if (i < f && c < f && i >= c) {
+      if (i < f && c < k && i >= c) {
         T* ap = A + (int64_t)c * f + i;
         *ap = (T)((double)*ap - Ct[ii * (BF_TILE + 1) + cc]);
       }
     }
     __syncthreads();
+  }
+}
+
+// The update block C = A[k:f, k:f] (lower triangle) receives C -= L21 W21^T,
+// W21 = L21 D, over all k fully-summed columns at once after the level's
+// last panel step (the panels' trailing updates stop at column k): C is read
+// and written once per front instead of once per panel, and each 64 x 64
+// tile accumulates the whole inner dimension on the matrix cores, in chunks
+// of 64 columns staged through LDS (a 2x2 block of D may straddle two
+// chunks: W reads L's neighbouring column from global memory).
+template <class T>
+__global__ void __launch_bounds__(256) big_cbupdate_kernel(BigArgs a, T* pool) {
+  __shared__ double La[BF_NB * (BF_TILE + 1)];  // La[t][ii] = L(r0 + ii, j0 + t)
+  __shared__ double Wb[BF_NB * (BF_TILE + 1)];  // Wb[t][cc] = W(c0 + cc, j0 + t); tile result later
+  __shared__ double dA[BF_NB], dB[BF_NB];
+  __shared__ int ty[BF_NB];
+  const int b = blockIdx.y;
+  const int F = a.fronts[b];
+  const int f = a.ff[F], k = a.fk[F], start = a.fstart[F];
+  if (k >= f) return;
+  const int nt = (f - k + BF_TILE - 1) / BF_TILE;
+  const int ntiles = nt * (nt + 1) / 2;
+  T* A = pool + a.pool_off[F];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int bi = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+    while ((bi + 1) * (bi + 2) / 2 <= tile) ++bi;
+    while (bi * (bi + 1) / 2 > tile) --bi;
+    const int bj = tile - bi * (bi + 1) / 2;
+    const int r0 = k + bi * BF_TILE, cb0 = k + bj * BF_TILE;
+    Tile16<T> acc[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) acc[rt].zero();
+    for (int j0 = 0; j0 < k; j0 += BF_NB) {
+      const int kb = min(BF_NB, k - j0);
+      __syncthreads();  // the previous chunk's LDS reads are done
+      if (tid < kb) {
+        const int t = tid, g = j0 + t;
+        const int tt = a.piv_type[start + g];
+        ty[t] = tt;
+        dA[t] = (double)A[(int64_t)g * f + g];
+        if (tt == 2) dB[t] = (double)A[(int64_t)g * f + g + 1];
+        else if (tt == 3) dB[t] = (double)A[(int64_t)(g - 1) * f + g];
+        else dB[t] = 0.0;
+      }
+      __syncthreads();
+      for (int e = tid; e < BF_NB * BF_TILE; e += 256) {
+        const int ii = e & 63, t = e >> 6;
+        double lv = 0.0, wv = 0.0;
+        if (t < kb) {
+          const int i = r0 + ii, c = cb0 + ii, g = j0 + t;
+          if (i < f) lv = (double)A[(int64_t)g * f + i];
+          if (c < f) {
+            const int tt = ty[t];
+            if (tt == 1) {
+              wv = (double)A[(int64_t)g * f + c] * dA[t];
+            } else if (tt == 2) {
+              wv = (double)A[(int64_t)g * f + c] * dA[t] + (double)A[(int64_t)(g + 1) * f + c] * dB[t];
+            } else {
+              wv = (double)A[(int64_t)(g - 1) * f + c] * dB[t] + (double)A[(int64_t)g * f + c] * dA[t];
+            }
+          }
+        }
+        La[t * (BF_TILE + 1) + ii] = lv;
+        Wb[t * (BF_TILE + 1) + ii] = wv;
+      }
+      __syncthreads();
+      const int kpad = (kb + 3) & ~3;
+      for (int t0 = 0; t0 < kpad; t0 += 4) {
+        const int kr = t0 + (lane >> 4);
+        const double bv = Wb[kr * (BF_TILE + 1) + wave * 16 + (lane & 15)];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+          const double av = La[kr * (BF_TILE + 1) + rt * 16 + (lane & 15)];
+          acc[rt].step(av, bv);
+        }
+      }
+    }
+    __syncthreads();
+    double* Ct = Wb;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ii = rt * 16 + Tile16<T>::row(lane, r);
+        Ct[ii * (BF_TILE + 1) + wave * 16 + (lane & 15)] = acc[rt].get(r);
+      }
+    __syncthreads();
+    for (int e = tid; e < BF_TILE * BF_TILE; e += 256) {
+      const int ii = e & 63, cc = e >> 6;
+      const int i = r0 + ii, c = cb0 + cc;
+      if (i < f && c < f && i >= c) {
+        T* ap = A + (int64_t)c * f + i;
+        *ap = (T)((double)*ap - Ct[ii * (BF_TILE + 1) + cc]);
+      }
+    }
   }
 }
 
@@ -531,7 +632,7 @@ void factor_big_fronts(riga_problem* pr, Factor& F, T* pool, const int32_t* fron
                        double pivtol, int level, bool checked, hipStream_t s) {
   const int nbig = (int)big_f.size();
   if (nbig == 0) return;
-  int maxk = 0, maxcb = 0, max_tiles = 0;
+  int maxk = 0, maxcb = 0, max_tiles = 0, max_cb_tiles = 0;
   int steps = 0;
   for (int i = 0; i < nbig; ++i) {
     const int f = big_f[i], k = big_k[i];
@@ -546,6 +647,8 @@ void factor_big_fronts(riga_problem* pr, Factor& F, T* pool, const int32_t* fron
     const int nb0 = panel_width(k);
     const int nt = (f - nb0 + BF_TILE - 1) / BF_TILE;
     max_tiles = std::max(max_tiles, nt * (nt + 1) / 2);
+    const int ntc = (f - k + BF_TILE - 1) / BF_TILE;
+    max_cb_tiles = std::max(max_cb_tiles, ntc * (ntc + 1) / 2);
   }
   if (maxk > bigfront_max_k())
     throw Error(RIGA_EUNSUPPORTED, "fully-summed block too large for the panel kernel");
@@ -583,11 +686,20 @@ void factor_big_fronts(riga_problem* pr, Factor& F, T* pool, const int32_t* fron
     }
     HIPCHECK(hipGetLastError());
   };
+  // the update blocks, once every panel of the level is done
+  const unsigned cpf = (unsigned)std::max(1, std::min(max_cb_tiles, std::max(1, 4096 / nbig)));
+  auto cb_update = [&]() {
+    if (maxcb > 0) big_cbupdate_kernel<T><<<dim3(cpf, nbig), 256, 0, s>>>(a, pool);
+    HIPCHECK(hipGetLastError());
+  };
   if (!checked) {
     // one step more than predicted covers a panel that ended early (a 2x2
-    // pivot at its edge); the steps of finished fronts return at once
+    // pivot at its edge); the steps of finished fronts return at once.  A
+    // front left unfinished gets an incomplete update block and is counted:
+    // the factorisation is then repeated in checked mode.
     if (F.big_pend.n < pr->levels.size()) throw Error(RIGA_EINVAL, "pending counts not reserved");
     run(steps + 1);
+    cb_update();
     big_pending_kernel<<<1, 256, 0, s>>>(a, nbig, F.big_pend.p + level);
     big_finish_kernel<<<nbig, 256, 0, s>>>(a, nbig);
     HIPCHECK(hipGetLastError());
@@ -605,6 +717,7 @@ void factor_big_fronts(riga_problem* pr, Factor& F, T* pool, const int32_t* fron
     if (guard > maxk) throw Error(RIGA_EDEVICE, "blocked factorisation made no progress");
     run(4);
   }
+  cb_update();
   big_finish_kernel<<<nbig, 256, 0, s>>>(a, nbig);
   HIPCHECK(hipGetLastError());
 }
