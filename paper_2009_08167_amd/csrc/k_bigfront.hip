@@ -485,99 +485,172 @@ __global__ void __launch_bounds__(256) big_trailing_kernel(BigArgs a, T* pool) {
   }
 }
 
-// The update block C = A[k:f, k:f] (lower triangle) receives C -= L21 W21^T,
-// W21 = L21 D, over all k fully-summed columns at once after the level's
-// last panel step (the panels' trailing updates stop at column k): C is read
-// and written once per front instead of once per panel, and each 64 x 64
-// tile accumulates the whole inner dimension on the matrix cores, in chunks
-// of 64 columns staged through LDS (a 2x2 block of D may straddle two
-// chunks: W reads L's neighbouring column from global memory).
+// W21 = L21 D of every big front of the level (1x1 and 2x2 blocks of D),
+// stored transposed in the front's unused upper-right block: W(c, t) at
+// A[c f + t] for t < k <= c (column-major, so row t of column c lies above
+// the diagonal).  64 x 64 tiles through LDS: L read down its columns, W
+// written down the block's columns.
 template <class T>
-__global__ void __launch_bounds__(256) big_cbupdate_kernel(BigArgs a, T* pool) {
-  __shared__ double La[BF_NB * (BF_TILE + 1)];  // La[t][ii] = L(r0 + ii, j0 + t)
-  __shared__ double Wb[BF_NB * (BF_TILE + 1)];  // Wb[t][cc] = W(c0 + cc, j0 + t); tile result later
-  __shared__ double dA[BF_NB], dB[BF_NB];
-  __shared__ int ty[BF_NB];
+__global__ void __launch_bounds__(256) big_w21_kernel(BigArgs a, T* pool) {
+  __shared__ double Wt[64][65];
+  __shared__ double dA[64], dB[64];
+  __shared__ int ty[64];
   const int b = blockIdx.y;
   const int F = a.fronts[b];
   const int f = a.ff[F], k = a.fk[F], start = a.fstart[F];
   if (k >= f) return;
-  const int nt = (f - k + BF_TILE - 1) / BF_TILE;
-  const int ntiles = nt * (nt + 1) / 2;
+  const int nr = (f - k + 63) / 64, nc = (k + 63) / 64;
   T* A = pool + a.pool_off[F];
+  const int tid = threadIdx.x;
+  for (int tile = blockIdx.x; tile < nr * nc; tile += gridDim.x) {
+    const int c0 = k + (tile / nc) * 64, t0 = (tile % nc) * 64;
+    __syncthreads();  // the previous tile's LDS reads are done
+    if (tid < 64) {
+      const int g = t0 + tid;
+      int tt = 1;
+      double d = 0.0, e = 0.0;
+      if (g < k) {
+        tt = a.piv_type[start + g];
+        d = (double)A[(int64_t)g * f + g];
+        if (tt == 2) e = (double)A[(int64_t)g * f + g + 1];
+        else if (tt == 3) e = (double)A[(int64_t)(g - 1) * f + g];
+      }
+      ty[tid] = tt;
+      dA[tid] = d;
+      dB[tid] = e;
+    }
+    __syncthreads();
+    // lanes over c: L(c, g) and its 2x2 partner column, coalesced
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int cc = e & 63, t = e >> 6;
+      const int c = c0 + cc, g = t0 + t;
+      double w = 0.0;
+      if (c < f && g < k) {
+        const double l = (double)A[(int64_t)g * f + c];
+        if (ty[t] == 1) w = l * dA[t];
+        else if (ty[t] == 2) w = l * dA[t] + (double)A[(int64_t)(g + 1) * f + c] * dB[t];
+        else w = (double)A[(int64_t)(g - 1) * f + c] * dB[t] + l * dA[t];
+      }
+      Wt[cc][t] = w;
+    }
+    __syncthreads();
+    // lanes over t: W(c, g) at A[c f + g]
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int t = e & 63, cc = e >> 6;
+      const int c = c0 + cc, g = t0 + t;
+      if (c < f && g < k) A[(int64_t)c * f + g] = (T)Wt[cc][t];
+    }
+  }
+}
+
+// The update block C = A[k:f, k:f] (lower triangle) receives C -= L21 W21^T,
+// W21 = L21 D, over all k fully-summed columns at once after the level's
+// last panel step (the panels' trailing updates stop at column k): C is read
+// and written once per front instead of once per panel.  A GEMM on the
+// matrix cores: 128 x 128 tiles of C (lower-triangle tiles only), four waves
+// of 64 x 64 each (4 x 4 MFMA tiles), the inner dimension in chunks of 16
+// columns staged through LDS in two buffers, the next chunk's global loads
+// in flight while the current one is multiplied.  The transposed product
+// C^T = W L^T is formed, so that a lane's MFMA output column is a row of C:
+// sixteen lanes write sixteen consecutive doubles of a column of the
+// column-major front.  W21 is read from the front's upper-right block,
+// where big_w21_kernel has stored it transposed.
+constexpr int CB_T = 128;
+constexpr int CB_K = 16;
+constexpr int CB_LD = CB_T + 4;
+constexpr size_t CB_LDS = 2 * 2 * CB_K * CB_LD * sizeof(double);
+
+template <class T>
+__global__ void __launch_bounds__(256, 2) big_cbupdate_kernel(BigArgs a, T* pool) {
+  extern __shared__ double cbs[];
+  // As[buf][t][row] = L(r0 + row, j0 + t), Bs[buf][t][col] = W(c0 + col, j0 + t)
+  auto As = [&](int buf, int t, int r) -> double& { return cbs[((buf * 2 + 0) * CB_K + t) * CB_LD + r]; };
+  auto Bs = [&](int buf, int t, int r) -> double& { return cbs[((buf * 2 + 1) * CB_K + t) * CB_LD + r]; };
+  const int b = blockIdx.y;
+  const int F = a.fronts[b];
+  const int f = a.ff[F], k = a.fk[F], start = a.fstart[F];
+  if (k >= f) return;
+  const int nt = (f - k + CB_T - 1) / CB_T;
+  const int ntiles = nt * (nt + 1) / 2;
+  const T* A = pool + a.pool_off[F];
+  T* Aw = pool + a.pool_off[F];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int srow = tid & (CB_T - 1), st0 = tid >> 7;  // staging of L: row, first t (0 or 1)
+  const int wcol = tid >> 1, wt0 = (tid & 1) * (CB_K / 2);  // staging of W: column, first t
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     int bi = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
     while ((bi + 1) * (bi + 2) / 2 <= tile) ++bi;
     while (bi * (bi + 1) / 2 > tile) --bi;
     const int bj = tile - bi * (bi + 1) / 2;
-    const int r0 = k + bi * BF_TILE, cb0 = k + bj * BF_TILE;
-    Tile16<T> acc[4];
+    const int r0 = k + bi * CB_T, c0 = k + bj * CB_T;
+    const int i = r0 + srow, c = c0 + wcol;
+    T la[CB_K / 2], wb[CB_K / 2];
+    // chunk j0: L(i, j0 + st0 + 2 q) down a column of L21, W(c, j0 + wt0 + q)
+    // down a column of the stored W21^T (plain loads: nothing waits on them
+    // before the chunk's multiplications)
+    auto load = [&](int j0) {
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) acc[rt].zero();
-    for (int j0 = 0; j0 < k; j0 += BF_NB) {
-      const int kb = min(BF_NB, k - j0);
-      __syncthreads();  // the previous chunk's LDS reads are done
-      if (tid < kb) {
-        const int t = tid, g = j0 + t;
-        const int tt = a.piv_type[start + g];
-        ty[t] = tt;
-        dA[t] = (double)A[(int64_t)g * f + g];
-        if (tt == 2) dB[t] = (double)A[(int64_t)g * f + g + 1];
-        else if (tt == 3) dB[t] = (double)A[(int64_t)(g - 1) * f + g];
-        else dB[t] = 0.0;
+      for (int q = 0; q < CB_K / 2; ++q) {
+        const int g = j0 + st0 + 2 * q;
+        la[q] = (g < k && i < f) ? A[(int64_t)g * f + i] : (T)0;
+        const int h = j0 + wt0 + q;
+        wb[q] = (h < k && c < f) ? A[(int64_t)c * f + h] : (T)0;
       }
-      __syncthreads();
-      for (int e = tid; e < BF_NB * BF_TILE; e += 256) {
-        const int ii = e & 63, t = e >> 6;
-        double lv = 0.0, wv = 0.0;
-        if (t < kb) {
-          const int i = r0 + ii, c = cb0 + ii, g = j0 + t;
-          if (i < f) lv = (double)A[(int64_t)g * f + i];
-          if (c < f) {
-            const int tt = ty[t];
-            if (tt == 1) {
-              wv = (double)A[(int64_t)g * f + c] * dA[t];
-            } else if (tt == 2) {
-              wv = (double)A[(int64_t)g * f + c] * dA[t] + (double)A[(int64_t)(g + 1) * f + c] * dB[t];
-            } else {
-              wv = (double)A[(int64_t)(g - 1) * f + c] * dB[t] + (double)A[(int64_t)g * f + c] * dA[t];
-            }
-          }
-        }
-        La[t * (BF_TILE + 1) + ii] = lv;
-        Wb[t * (BF_TILE + 1) + ii] = wv;
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+      for (int q = 0; q < CB_K / 2; ++q) {
+        As(buf, st0 + 2 * q, srow) = (double)la[q];
+        Bs(buf, wt0 + q, wcol) = (double)wb[q];
       }
-      __syncthreads();
-      const int kpad = (kb + 3) & ~3;
-      for (int t0 = 0; t0 < kpad; t0 += 4) {
+    };
+    Tile16<T> acc[4][4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) acc[ct][rt].zero();
+    __syncthreads();  // the previous tile's LDS reads are done
+    load(0);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int j0 = 0; j0 < k; j0 += CB_K) {
+      const bool more = j0 + CB_K < k;
+      if (more) load(j0 + CB_K);
+#pragma unroll
+      for (int t0 = 0; t0 < CB_K; t0 += 4) {
         const int kr = t0 + (lane >> 4);
-        const double bv = Wb[kr * (BF_TILE + 1) + wave * 16 + (lane & 15)];
+        double av[4], bv[4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) av[rt] = As(buf, kr, wr * 64 + rt * 16 + (lane & 15));
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) bv[ct] = Bs(buf, kr, wc * 64 + ct * 16 + (lane & 15));
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) acc[ct][rt].step(bv[ct], av[rt]);
+      }
+      if (more) store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+    // acc[ct][rt] holds (W L^T)(c, i): c = c0 + wc 64 + ct 16 + row(lane, q),
+    // i = r0 + wr 64 + rt 16 + (lane & 15)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int cc = c0 + wc * 64 + ct * 16 + Tile16<T>::row(lane, q);
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
-          const double av = La[kr * (BF_TILE + 1) + rt * 16 + (lane & 15)];
-          acc[rt].step(av, bv);
+          const int ii = r0 + wr * 64 + rt * 16 + (lane & 15);
+          if (ii < f && cc < f && ii >= cc) {
+            T* ap = Aw + (int64_t)cc * f + ii;
+            *ap = (T)((double)*ap - acc[ct][rt].get(q));
+          }
         }
       }
-    }
-    __syncthreads();
-    double* Ct = Wb;
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int ii = rt * 16 + Tile16<T>::row(lane, r);
-        Ct[ii * (BF_TILE + 1) + wave * 16 + (lane & 15)] = acc[rt].get(r);
-      }
-    __syncthreads();
-    for (int e = tid; e < BF_TILE * BF_TILE; e += 256) {
-      const int ii = e & 63, cc = e >> 6;
-      const int i = r0 + ii, c = cb0 + cc;
-      if (i < f && c < f && i >= c) {
-        T* ap = A + (int64_t)c * f + i;
-        *ap = (T)((double)*ap - Ct[ii * (BF_TILE + 1) + cc]);
-      }
-    }
   }
 }
 
@@ -622,6 +695,10 @@ void set_bigfront_attributes() {
                                hipFuncAttributeMaxDynamicSharedMemorySize, BF_LDS * (int)sizeof(double)));
   HIPCHECK(hipFuncSetAttribute((const void*)big_panel_kernel<float>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, BF_LDS * (int)sizeof(double)));
+  HIPCHECK(hipFuncSetAttribute((const void*)big_cbupdate_kernel<double>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)CB_LDS));
+  HIPCHECK(hipFuncSetAttribute((const void*)big_cbupdate_kernel<float>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)CB_LDS));
 }
 
 int bigfront_max_k() { return BF_LDS; }
@@ -647,7 +724,7 @@ void factor_big_fronts(riga_problem* pr, Factor& F, T* pool, const int32_t* fron
     const int nb0 = panel_width(k);
     const int nt = (f - nb0 + BF_TILE - 1) / BF_TILE;
     max_tiles = std::max(max_tiles, nt * (nt + 1) / 2);
-    const int ntc = (f - k + BF_TILE - 1) / BF_TILE;
+    const int ntc = (f - k + CB_T - 1) / CB_T;
     max_cb_tiles = std::max(max_cb_tiles, ntc * (ntc + 1) / 2);
   }
   if (maxk > bigfront_max_k())
@@ -689,7 +766,12 @@ void factor_big_fronts(riga_problem* pr, Factor& F, T* pool, const int32_t* fron
   // the update blocks, once every panel of the level is done
   const unsigned cpf = (unsigned)std::max(1, std::min(max_cb_tiles, std::max(1, 4096 / nbig)));
   auto cb_update = [&]() {
-    if (maxcb > 0) big_cbupdate_kernel<T><<<dim3(cpf, nbig), 256, 0, s>>>(a, pool);
+    if (maxcb > 0) {
+      const unsigned wpf = (unsigned)std::max(1, std::min(((maxcb + 63) / 64) * ((maxk + 63) / 64),
+                                                          std::max(1, 2048 / nbig)));
+      big_w21_kernel<T><<<dim3(wpf, nbig), 256, 0, s>>>(a, pool);
+      big_cbupdate_kernel<T><<<dim3(cpf, nbig), 256, CB_LDS, s>>>(a, pool);
+    }
     HIPCHECK(hipGetLastError());
   };
   if (!checked) {
