@@ -80,6 +80,16 @@ bool thick_restart_on() {
   return !(v && *v == '0');
 }
 
+// Lanczos steps replayed from a HIP graph captured once per run
+// (RIGA_GRAPH=1).  Off by default: bitwise the eager results, but measured
+// slower on one MI355X (2D 256^2 p=3 rIGA 2,239 against 2,305 eigenpairs/s,
+// its IGA 1,398 against 1,576): the launches of a step are not host-bound
+// here, and each run pays its capture and instantiation.
+bool graph_on() {
+  const char* v = std::getenv("RIGA_GRAPH");
+  return v && *v == '1';
+}
+
 // A restart basis for thick-restart Lanczos (Sec. 4.2, Eq. LanczosRestart):
 // with Ritz pairs (theta_i, s_i) of T_m kept and b_i = beta_{m+1} s_i[m-1],
 // the projection on [V S, v_{m+1}] is the arrowhead [[diag(theta), b],
@@ -202,6 +212,11 @@ struct Solver {
   int64_t nu_lo = 0;     // eigenvalues below lo
   DBuf<double> B, W, x, y, c1, c2, partial, dotp, alpha, beta, scal;
   DBuf<int32_t> flag;
+  DBuf<int32_t> dstep;   // the step index j read by a replayed step
+  DBuf<double> rhs;      // the replayed step's right-hand side (M v_j)
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap = nullptr;  // capture only (the solve's own stream may be the null stream)
+  int32_t hstep = 0;     // host copy of the step index uploaded before replays
   DBuf<double> chk, S, Sh, Ub, KU, MU, res3, rqn, lam, rpart, bpart;
   double* theta = nullptr;  // in chk: theta[mb + 1], est[mb + 1], beta_m, flag
   double* tdest = nullptr;
@@ -254,6 +269,18 @@ struct Solver {
     rpart.alloc(residual_partials(N, umax), s);
     ir_r.alloc(N, s);
     ir_d.alloc(N, s);
+    dstep.alloc(1, s);
+    rhs.alloc(N, s);
+  }
+
+  ~Solver() {
+    drop_graph();
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
   }
 
   SolveCtx* ctx = nullptr;  // the solve's factorisations and sweep scratch
@@ -279,23 +306,85 @@ struct Solver {
 
   // x = A^{-1} b (FP64), or FP32 solve + FP64 refinement (mixed); FP64
   // solves are refined too once a stall has raised max_ir_fp64
-  void apply_inverse(const double* b, double* out) {
+  int ir_steps() { return cur().precision == RIGA_MIXED ? max_ir : max_ir_fp64; }
+
+  // the launches of one application of (K - sigma M)^{-1} (with its
+  // refinement steps); counts them when `count`
+  void apply_inverse(const double* b, double* out, bool count = true) {
     const Factor& F = cur();
     solve_fb(pr, F, b, out, s);
-    st.n_fb++;
-    const int nir = F.precision == RIGA_MIXED ? max_ir : max_ir_fp64;
-    {
-      for (int it = 0; it < nir; ++it) {
-        // r = b - A x
-        launch_spmv(pr, F.av.p, out, ir_r.p, nullptr, s);
-        st.n_mv++;
-        axpy_launch(-1.0, ir_r.p, b, ir_r.p);
-        solve_fb(pr, F, ir_r.p, ir_d.p, s);
-        st.n_fb++;
-        st.n_ir++;
-        axpy_launch(1.0, ir_d.p, out, out);
-      }
+    const int nir = ir_steps();
+    for (int it = 0; it < nir; ++it) {
+      // r = b - A x
+      launch_spmv(pr, F.av.p, out, ir_r.p, nullptr, s);
+      axpy_launch(-1.0, ir_r.p, b, ir_r.p);
+      solve_fb(pr, F, ir_r.p, ir_d.p, s);
+      axpy_launch(1.0, ir_d.p, out, out);
     }
+    if (count) {
+      st.n_fb += 1 + nir;
+      st.n_mv += nir;
+      st.n_ir += nir;
+    }
+  }
+
+  // One Lanczos step with every quantity that depends on the step index j
+  // read from dstep (and dstep advanced at its end): the same launches as
+  // step(j), captured once per run into a HIP graph and replayed for each
+  // step of it (the basis columns, the locked window, the factorisation and
+  // the refinement count are fixed within a run).
+  void enqueue_step_dyn(int maxm) {
+    launch_copy_col_dyn(rhs.p, Wc(nl), N, dstep.p, s);
+    apply_inverse(rhs.p, x.p, false);
+    const int m1 = nl + 1 - c_win;
+    launch_project(Wc(c_win), Bc(c_win), N, m1, x.p, partial.p, c1.p + c_win, nullptr, nullptr, s, dstep.p,
+                   m1 + maxm - 1);
+    launch_project(Wc(nl), Bc(nl), N, 1, x.p, partial.p, c2.p + nl, alpha.p, c1.p + nl, s, dstep.p, maxm);
+    if (cplx) {
+      launch_jrot(x.p, N, 1.0, s);
+      launch_project(Wc(nl), Bc(nl), N, 1, x.p, partial.p, c2.p + nl, nullptr, nullptr, s, dstep.p, maxm);
+      launch_jrot(x.p, N, -1.0, s);
+    }
+    launch_spmv(pr, pr->mv.p, x.p, y.p, dotp.p, s);
+    launch_scale2(x.p, y.p, dotp.p, spmv_dot_blocks(pr), Bc(nl + 1), Wc(nl + 1), N, beta.p + 1, flag.p, s,
+                  dstep.p);
+    launch_step_advance(dstep.p, s);
+  }
+
+  // The step's launches recorded on a stream of the solver's own (nothing
+  // runs during a capture; the graph is launched on the solve's stream).
+  void capture_step_graph(int maxm) {
+    drop_graph();
+    if (!cap) HIPCHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    const hipStream_t run_s = s;
+    HIPCHECK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    s = cap;
+    try {
+      enqueue_step_dyn(maxm);
+    } catch (...) {
+      s = run_s;
+      (void)hipStreamEndCapture(cap, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    s = run_s;
+    HIPCHECK(hipStreamEndCapture(cap, &g));
+    const hipError_t e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      gexec = nullptr;
+      throw Error(RIGA_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+  }
+
+  // the launches of step j, replayed from the run's graph
+  void replay_step() {
+    HIPCHECK(hipGraphLaunch(gexec, s));
+    const int nir = ir_steps();
+    st.n_fb += 1 + nir;
+    st.n_mv += nir + 1;
+    st.n_ir += nir;
   }
 
   // out = a * u + v
@@ -600,11 +689,18 @@ struct Solver {
     }
     thick_c = 0;
     const int maxm = (int)std::min<int64_t>(mb, N - nl - 1);
+    const bool graph = graph_on() && maxm > j;
+    if (graph) {
+      hstep = j;
+      HIPCHECK(hipMemcpyAsync(dstep.p, &hstep, sizeof(int32_t), hipMemcpyHostToDevice, s));
+      capture_step_graph(maxm);
+    }
     Ritz r;
     int next_check = std::min(maxm, std::max(16, std::min(need_below + need_above, maxm)));
     bool met = false, breakdown = false;
     while (true) {
-      step(j);
+      if (graph) replay_step();
+      else step(j);
       ++j;
       if (j < next_check && j < maxm) continue;
       r = check(j);

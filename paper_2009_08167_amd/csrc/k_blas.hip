@@ -128,13 +128,17 @@ constexpr int PROJ_RB = 4096;  // rows per partial sum (1024 per wave)
 
 __global__ void __launch_bounds__(256) proj_t_kernel(const double* __restrict__ W, int64_t n, int m,
                                                    const double* __restrict__ x,
-                                                   double* __restrict__ partial) {
+                                                   double* __restrict__ partial,
+                                                   const int32_t* __restrict__ dj) {
   // workgroup: 2 columns x PROJ_RB rows; wave w takes rows
   // [rb * PROJ_RB + w * PROJ_RB / 4, ...), 16 per lane, all loads issued first
+  // (with dj, a replayed launch: m + *dj columns, the grid sized for the most)
   __shared__ double red[2][4];
+  if (dj) m += *dj;
   const int rb = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j0 = blockIdx.y * 2;
+  if (j0 >= m) return;
   const bool two = j0 + 1 < m;
   const int64_t r0 = (int64_t)rb * PROJ_RB + (int64_t)wave * (PROJ_RB / 4);
   const int64_t r1 = min((int64_t)rb * PROJ_RB + PROJ_RB, n);
@@ -177,8 +181,16 @@ __global__ void __launch_bounds__(256) proj_t_kernel(const double* __restrict__ 
 __global__ void __launch_bounds__(256) proj_n_kernel(const double* __restrict__ B, int64_t n, int m,
                                                    const double* __restrict__ partial, int nrb,
                                                    double* c_out, double* alpha_out,
-                                                   const double* addend, double* __restrict__ x) {
+                                                   const double* addend, double* __restrict__ x,
+                                                   const int32_t* __restrict__ dj) {
   extern __shared__ double cs[];
+  if (dj) {
+    // a replayed launch: m + *dj columns, alpha_out and addend advanced by *dj
+    const int d = *dj;
+    m += d;
+    if (alpha_out) alpha_out += d;
+    if (addend) addend += d;
+  }
   for (int j = threadIdx.x; j < m; j += blockDim.x) {
     double sj = 0.0;
     for (int rb = 0; rb < nrb; rb += 8) {
@@ -243,8 +255,15 @@ __global__ void fill_random_kernel(double* x, int64_t n, uint64_t seed, uint64_t
 __global__ void __launch_bounds__(256) scale2_kernel(const double* x, const double* y,
                                                    const double* partial, int np, double* v,
                                                    double* w, int64_t n, double* beta_out,
-                                                   int32_t* flag) {
+                                                   int32_t* flag, const int32_t* __restrict__ dj) {
   __shared__ double sm[4];
+  if (dj) {
+    // a replayed launch: columns and beta advanced by *dj
+    const int d = *dj;
+    v += (int64_t)d * n;
+    w += (int64_t)d * n;
+    if (beta_out) beta_out += d;
+  }
   // every workgroup sums all partials: eight loads in flight per thread,
   // then the wave and workgroup reductions (fixed order)
   double t = 0.0;
@@ -566,13 +585,35 @@ int gemv_row_blocks(int64_t n) { return (int)((n + GEMV_RB - 1) / GEMV_RB); }
 int proj_row_blocks(int64_t n) { return (int)((n + PROJ_RB - 1) / PROJ_RB); }
 
 void launch_project(const double* W, const double* B, int64_t n, int m, double* x, double* partial,
-                    double* c, double* alpha_out, const double* addend, hipStream_t s) {
-  if (m <= 0) return;
+                    double* c, double* alpha_out, const double* addend, hipStream_t s,
+                    const int32_t* dj, int m_max) {
+  if (m <= 0 && !dj) return;
+  const int mg = dj ? m_max : m;
   const int nrb = proj_row_blocks(n);
-  dim3 grid(nrb, (m + 1) / 2);
-  proj_t_kernel<<<grid, 256, 0, s>>>(W, n, m, x, partial);
-  proj_n_kernel<<<(unsigned)((n + 255) / 256), 256, (size_t)m * sizeof(double), s>>>(
-      B, n, m, partial, nrb, c, alpha_out, addend, x);
+  dim3 grid(nrb, (mg + 1) / 2);
+  proj_t_kernel<<<grid, 256, 0, s>>>(W, n, m, x, partial, dj);
+  proj_n_kernel<<<(unsigned)((n + 255) / 256), 256, (size_t)mg * sizeof(double), s>>>(
+      B, n, m, partial, nrb, c, alpha_out, addend, x, dj);
+  HIPCHECK(hipGetLastError());
+}
+
+// dst = src + *dj n (a column chosen by the step index; n entries)
+__global__ void copy_col_dyn_kernel(double* dst, const double* src, int64_t n, const int32_t* dj) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[(int64_t)(*dj) * n + i];
+}
+
+__global__ void step_advance_kernel(int32_t* dj) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dj += 1;
+}
+
+void launch_copy_col_dyn(double* dst, const double* src, int64_t n, const int32_t* dj, hipStream_t s) {
+  copy_col_dyn_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(dst, src, n, dj);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_step_advance(int32_t* dj, hipStream_t s) {
+  step_advance_kernel<<<1, 64, 0, s>>>(dj);
   HIPCHECK(hipGetLastError());
 }
 
@@ -587,8 +628,9 @@ void launch_fill_random(double* x, int64_t n, uint64_t seed, uint64_t sid, hipSt
 }
 
 void launch_scale2(const double* x, const double* y, const double* partial, int np, double* v,
-                   double* w, int64_t n, double* beta_out, int32_t* flag, hipStream_t s) {
-  scale2_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, y, partial, np, v, w, n, beta_out, flag);
+                   double* w, int64_t n, double* beta_out, int32_t* flag, hipStream_t s,
+                   const int32_t* dj) {
+  scale2_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, y, partial, np, v, w, n, beta_out, flag, dj);
   HIPCHECK(hipGetLastError());
 }
 

@@ -389,15 +389,25 @@ double* noalloc_scratch();
 int gemv_row_blocks(int64_t n);
 // One Gram-Schmidt pass: c = W^T x, then x -= B c (W, B: n x m column-major,
 // ld = n); partial holds proj_row_blocks(n) * m doubles.  With alpha_out,
-// also *alpha_out = *addend + c[m - 1].
+// also *alpha_out = *addend + c[m - 1].  With dj (a launch captured once
+// and replayed for every Lanczos step of a run), the pass covers m + *dj
+// columns (at most m_max: partial holds proj_row_blocks(n) * m_max) and
+// alpha_out, addend are advanced by *dj.
 int proj_row_blocks(int64_t n);
 void launch_project(const double* W, const double* B, int64_t n, int m, double* x, double* partial,
-                    double* c, double* alpha_out, const double* addend, hipStream_t s);
+                    double* c, double* alpha_out, const double* addend, hipStream_t s,
+                    const int32_t* dj = nullptr, int m_max = 0);
+// dst = column *dj of the n-row block src
+void launch_copy_col_dyn(double* dst, const double* src, int64_t n, const int32_t* dj, hipStream_t s);
+// *dj += 1
+void launch_step_advance(int32_t* dj, hipStream_t s);
 void launch_reduce_partials(const double* partial, int nblk, double* out, hipStream_t s);
 void launch_fill_random(double* x, int64_t n, uint64_t seed, uint64_t stream_id, hipStream_t s);
-// v = x / beta, w = y / beta with beta^2 the sum of partial[0..np).
+// v = x / beta, w = y / beta with beta^2 the sum of partial[0..np).  With
+// dj, v, w and beta_out are advanced by *dj columns / entries.
 void launch_scale2(const double* x, const double* y, const double* partial, int np, double* v,
-                   double* w, int64_t n, double* beta_out, int32_t* flag, hipStream_t s);
+                   double* w, int64_t n, double* beta_out, int32_t* flag, hipStream_t s,
+                   const int32_t* dj = nullptr);
 void launch_gemm_nn(const double* V, int64_t n, int k, const double* S, int lds, int m,
                     double* U, hipStream_t s);
 // U -= B (W^T U) for the n x c blocks W, B and the n x m block U (all

@@ -596,3 +596,32 @@ def test_thick_restart_matches_oracle(w, monkeypatch):
     assert st0["n_thick"] == 0
     _check_pairs(Ko, Mo, lr, Ur, lam0, U0.cpu().numpy(), res0, w.nev)
     assert st["n_fb"] < st0["n_fb"], (st["n_fb"], st0["n_fb"])
+
+
+def test_graph_replayed_steps_equal_eager_steps(monkeypatch):
+    """Lanczos steps replayed from a HIP graph captured once per run
+    (RIGA_GRAPH=1) give bitwise the results of the same steps launched one
+    by one (RIGA_GRAPH=0, the default), over every replay of a solve: FP64 with two spectrum
+    slices, mixed precision (refinement launches in the graph), a thick
+    restart (a run resumed at a later step index), and a complex pencil."""
+    riga = _riga()
+    w = workloads.small(2, 40, 3, 8, 70, 0.3)
+    kappa, rho = w.coefficients()
+    pr = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho)
+    runs = [dict(per_shift=16), dict(precision=riga.RIGA_MIXED, per_shift=16),
+            dict(per_shift=24, max_basis=40, max_restarts=40)]
+    for kw in runs:
+        monkeypatch.setenv("RIGA_GRAPH", "1")
+        lam_g, U_g, res_g, st_g = pr.eigs(w.nev, **kw)
+        monkeypatch.setenv("RIGA_GRAPH", "0")
+        lam_e, U_e, res_e, st_e = pr.eigs(w.nev, **kw)
+        _say("graph vs eager", kw, st_g["n_fb"], st_e["n_fb"], st_g["n_thick"])
+        assert np.array_equal(lam_g, lam_e) and np.array_equal(res_g, res_e)
+        assert torch.equal(U_g, U_e)
+        assert st_g["n_fb"] == st_e["n_fb"] and st_g["n_mv"] == st_e["n_mv"]
+    monkeypatch.setenv("RIGA_GRAPH", "1")
+    pc = riga.assemble(2, 12, 3, 0, potential=(2.5, 0.7))
+    lam_g, U_g, _, _ = pc.eigs(24, per_shift=12)
+    monkeypatch.setenv("RIGA_GRAPH", "0")
+    lam_e, U_e, _, _ = pc.eigs(24, per_shift=12)
+    assert np.array_equal(lam_g, lam_e) and torch.equal(U_g, U_e)
