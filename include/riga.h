@@ -236,6 +236,26 @@ riga_status riga_spmv(riga_problem* pr, int32_t which, const double* x_dev, doub
 riga_status riga_factor(riga_problem* pr, double sigma, int32_t precision,
                         int64_t* neg_pivots, riga_stats* stats);
 
+/* riga_factor_batched: riga_factor of `count` independent problems at once,
+ * problem i at sigmas[i] (host array), all in `precision` (Sec. 5's one
+ * numeric factorisation per shift, for many instances): the fronts of one
+ * tree height of every problem go in one launch per kernel (assembly,
+ * LDS-resident fronts, the blocked fronts' panel, update and finishing
+ * kernels), heights in order from the leaves.  Each front gets the same
+ * arithmetic as in riga_factor, so every factorisation, inertia and later
+ * riga_solve result is identical bit for bit to riga_factor's at the same
+ * shift.  probs: `count` distinct problems assembled on the current device.
+ * neg_pivots [count] (host, may be NULL): the inertias; stats [count] (may
+ * be NULL): as riga_factor's.  The call waits for earlier work on each
+ * problem's stream, runs on a stream of its own and returns when all are
+ * done.  A problem with perturbed pivots is handled as in riga_factor: the
+ * call returns RIGA_ESINGULAR (riga_last_error() names the first such
+ * instance) with every output filled and every factorisation kept.
+ * count = 0 is a no-op; a repeated problem, another device or a
+ * non-finite shift is RIGA_EINVAL. */
+riga_status riga_factor_batched(riga_problem* const* probs, int32_t count, const double* sigmas,
+                                int32_t precision, int64_t* neg_pivots, riga_stats* stats);
+
 /* riga_solve: x = (K - sigma M)^{-1} b with the last factorisation (one
  * forward/backward elimination; in RIGA_MIXED the FP32 solve is refined in
  * FP64 until ||b - A x|| <= 1e-13 ||b|| or `max_ir` corrections).  b_dev,

@@ -216,6 +216,57 @@ riga_status riga_factor(riga_problem* pr, double sigma, int32_t precision, int64
   });
 }
 
+riga_status riga_factor_batched(riga_problem* const* probs, int32_t count, const double* sigmas,
+                                int32_t precision, int64_t* neg_pivots, riga_stats* stats) {
+  return guarded([&]() -> riga_status {
+    if (!probs || count < 0 || (count > 0 && !sigmas)) return fail(RIGA_EINVAL, "bad arguments");
+    if (precision != RIGA_FP64 && precision != RIGA_MIXED) return fail(RIGA_EINVAL, "bad precision");
+    if (count == 0) return RIGA_OK;
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    std::vector<riga_problem*> prs(probs, probs + count);
+    std::vector<riga::Factor*> Fs(count);
+    std::vector<double> sg(sigmas, sigmas + count);
+    for (int i = 0; i < count; ++i) {
+      if (!need_device(prs[i])) return fail(RIGA_EINVAL, "instance without device data");
+      if (prs[i]->device != dev) return fail(RIGA_EINVAL, "instances must be on the current device");
+      if (!std::isfinite(sg[i])) return fail(RIGA_EINVAL, "sigma must be finite");
+      for (int j = 0; j < i; ++j)
+        if (prs[j] == prs[i]) return fail(RIGA_EINVAL, "an instance appears twice");
+    }
+    for (int i = 0; i < count; ++i) {
+      Fs[i] = &prs[i]->ctx[0].current();
+      riga::factor_reserve(prs[i], *Fs[i], precision, prs[i]->home);
+    }
+    // the buffers (and earlier work on the problems) are ready before the
+    // batched launches, which run on a stream of this call
+    for (int i = 0; i < count; ++i) HIPCHECK(hipStreamSynchronize(prs[i]->home));
+    hipStream_t s = nullptr;
+    HIPCHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    struct Destroy {
+      hipStream_t s;
+      ~Destroy() { (void)hipStreamDestroy(s); }
+    } destroy{s};
+    riga::factor_numeric_batched(prs, Fs, sg, precision, s);
+    int singular = 0;
+    for (int i = 0; i < count; ++i) {
+      const riga::Factor& F = *Fs[i];
+      if (neg_pivots) neg_pivots[i] = F.inertia;
+      if (stats) {
+        std::memset(&stats[i], 0, sizeof(stats[i]));
+        stats[i].n_fact = 1;
+        stats[i].n_perturbed_pivots = F.perturbed;
+        stats[i].n_2x2_pivots = F.two;
+        stats[i].flops_fact = prs[i]->an.flops_fact;
+      }
+      if (F.perturbed > 0 && singular++ == 0)
+        g_err = "instance " + std::to_string(i) + ": " + std::to_string(F.perturbed) +
+                " pivot(s) perturbed: K - sigma M is singular to working precision";
+    }
+    return singular ? RIGA_ESINGULAR : RIGA_OK;
+  });
+}
+
 namespace {
 
 // x = A^{-1} b with the current factorisation; in mixed precision refined in

@@ -297,6 +297,17 @@ struct Solver {
   // shift moved down if sigma is singular; cur().sigma holds the one used)
   void factor(double sigma, int prec = -1) {
     if (prec < 0) prec = precision;
+    // the solve's first factorisation may have been made ahead together
+    // with other problems' (riga_eigs_batched): the same arithmetic, used
+    // as it is when shift and precision match
+    Factor& P = cur();
+    if (P.pre && P.factored && P.sigma == sigma && P.precision == prec && P.perturbed == 0) {
+      P.pre = false;
+      P.refactored = 0;
+      count_factor(P);
+      return;
+    }
+    P.pre = false;
     auto a = clk::now();
     factor_reserve(pr, cur(), prec, pr->home);
     factor_shift(pr, cur(), sigma, prec, s);
@@ -1552,9 +1563,60 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
   return status;
 }
 
-// Many independent problems at once: a pool of host threads, each with its
-// own HIP stream, takes instances in order and runs the full solve on its
-// stream, so the kernels of different instances overlap on the device.
+namespace {
+
+// RIGA_BATCH_FACTOR=0: every batched instance makes its first
+// factorisation itself
+bool batch_factor_on() {
+  const char* v = std::getenv("RIGA_BATCH_FACTOR");
+  return !(v && *v == '0');
+}
+
+// The shift and precision of the first factorisation of run_eigs (the
+// first slice's finite upper end, counted first, else its lower end; an
+// end other than 0 in FP64).
+void first_factorisation(const riga_eigs_opts* o, double* sigma, int* prec) {
+  double lo = o->lo - END_SHIFT * std::fabs(o->lo);
+  double hi = std::isfinite(o->hi) ? o->hi - END_SHIFT * std::fabs(o->hi) : o->hi;
+  if (!(hi > lo)) {
+    lo = o->lo;
+    hi = o->hi;
+  }
+  *sigma = std::isfinite(hi) ? hi : lo;
+  *prec = *sigma == 0.0 ? o->precision : (int)RIGA_FP64;
+}
+
+// The instances' first factorisations, all at once (one launch per kernel
+// and tree height over every instance), marked for their solves to use.
+void prefactor(riga_problem* const* probs, int count, const riga_eigs_opts* o) {
+  double sigma = 0.0;
+  int prec = 0;
+  first_factorisation(o, &sigma, &prec);
+  std::vector<riga_problem*> prs(probs, probs + count);
+  std::vector<Factor*> Fs(count);
+  std::vector<double> sg(count, sigma);
+  for (int i = 0; i < count; ++i) {
+    Fs[i] = &prs[i]->ctx[0].current();
+    factor_reserve(prs[i], *Fs[i], prec, prs[i]->home);
+  }
+  for (int i = 0; i < count; ++i) HIPCHECK(hipStreamSynchronize(prs[i]->home));
+  hipStream_t s = nullptr;
+  HIPCHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  struct Destroy {
+    hipStream_t s;
+    ~Destroy() { (void)hipStreamDestroy(s); }
+  } destroy{s};
+  factor_numeric_batched(prs, Fs, sg, prec, s);
+  for (Factor* F : Fs) F->pre = true;
+}
+
+}  // namespace
+
+// Many independent problems at once: the instances' first factorisations
+// in one batched factorisation, then a pool of host threads, each with its
+// own HIP stream, takes instances in order and runs the rest of the solve
+// on its stream, so the kernels of different instances overlap on the
+// device.
 riga_status run_eigs_batched(riga_problem* const* probs, int count, const riga_eigs_opts* o,
                              int32_t* n_found, double* const* evals, double* const* evecs,
                              double* const* resid, riga_stats* stats, int workers,
@@ -1571,6 +1633,17 @@ riga_status run_eigs_batched(riga_problem* const* probs, int count, const riga_e
   // kernel attributes are per device and process: set them once here, not
   // from the workers while others launch
   set_kernel_attributes();
+  // a factorisation made ahead and not used (a solve that failed before
+  // its first factorisation) is not left for later calls
+  struct ClearPre {
+    riga_problem* const* p;
+    int n;
+    ~ClearPre() {
+      for (int i = 0; i < n; ++i)
+        for (Factor& F : p[i]->ctx[0].fac) F.pre = false;
+    }
+  } clear_pre{probs, count};
+  if (batch_factor_on()) prefactor(probs, count, o);
   std::vector<std::thread> pool;
   for (int w = 0; w < workers; ++w) {
     pool.emplace_back([&, w] {

@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "mfma_tile.h"
@@ -64,7 +65,44 @@ struct BigArgs {
   int32_t* lperm;         // [slot * BF_NB]: this step's panel column order
   BigState* st;
   double pivtol;
+  void* pool;             // the factor pool (T*), for launches over several problems
+  int32_t* pend;          // fronts left unfinished at the end (big_pending_kernel)
+  int32_t nbig;
 };
+
+// Launches over the big fronts of one height of several problems: front y
+// of the grid belongs to job j with ystart[j] <= y < ystart[j + 1] (jobs
+// null: a single problem, the arguments passed by value).
+struct BigJobs {
+  const BigArgs* jobs;
+  const int32_t* ystart;
+  int njobs;
+};
+
+__device__ __forceinline__ int big_job_of(const BigJobs& J, int y) {
+  int lo = 0, hi = J.njobs;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (J.ystart[mid] <= y) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// this workgroup's problem and front (y: its front index in the grid)
+template <class T>
+__device__ __forceinline__ void big_pick(const BigArgs& a0, T* pool0, const BigJobs& J, int y, BigArgs& a,
+                                         T*& pool, int& b) {
+  if (J.jobs) {
+    const int j = big_job_of(J, y);
+    a = J.jobs[j];
+    pool = reinterpret_cast<T*>(a.pool);
+    b = y - J.ystart[j];
+  } else {
+    a = a0;
+    pool = pool0;
+    b = y;
+  }
+}
 
 struct Decision {
   int kind;   // 1 or 2
@@ -92,12 +130,15 @@ __device__ __forceinline__ double bcast(double v, int l) {
 // (which reads only later columns); the rank-1/2 update uses the unscaled
 // columns.
 template <class T>
-__global__ void __launch_bounds__(1024) big_panel_kernel(BigArgs a, T* pool) {
+__global__ void __launch_bounds__(1024) big_panel_kernel(BigArgs a0, T* pool0, BigJobs J) {
+  BigArgs a;
+  T* pool;
+  int b;
+  big_pick(a0, pool0, J, blockIdx.x, a, pool, b);
   extern __shared__ double Pn[];
   __shared__ Decision dec;
   __shared__ int lp[BF_NB];
   constexpr int NT = 1024, NW = NT / 64;
-  const int b = blockIdx.x;
   BigState* st = a.st + b;
   const int F = a.fronts[b];
   const int f = a.ff[F], k = a.fk[F], start = a.fstart[F];
@@ -297,11 +338,14 @@ __global__ void __launch_bounds__(1024) big_panel_kernel(BigArgs a, T* pool) {
 // stores coalesced across the rows), W(c, t) = (L_pp D)(c, t) read from LDS
 // as a broadcast.
 template <class T>
-__global__ void __launch_bounds__(256) big_cbrows_kernel(BigArgs a, T* pool) {
+__global__ void __launch_bounds__(256) big_cbrows_kernel(BigArgs a0, T* pool0, BigJobs J) {
+  BigArgs a;
+  T* pool;
+  int b;
+  big_pick(a0, pool0, J, blockIdx.y, a, pool, b);
   __shared__ double W[BF_NB * BF_NB];   // W[t * BF_NB + c] = (L_pp D)(j0 + c, j0 + t)
   __shared__ double dA[BF_NB], dB[BF_NB], dinv[BF_NB];
   __shared__ int ty[BF_NB], lp[BF_NB];
-  const int b = blockIdx.y;
   const BigState st = a.st[b];
   if (st.kb == 0) return;
   const int F = a.fronts[b];
@@ -387,12 +431,15 @@ __global__ void __launch_bounds__(256) big_cbrows_kernel(BigArgs a, T* pool) {
 // Trailing update of one 64 x 64 lower-triangle tile of [j0 + nb, f)^2:
 // A(i, c) -= sum_t L(i, t) W(c, t) over the kb factorised panel columns.
 template <class T>
-__global__ void __launch_bounds__(256) big_trailing_kernel(BigArgs a, T* pool) {
+__global__ void __launch_bounds__(256) big_trailing_kernel(BigArgs a0, T* pool0, BigJobs J) {
+  BigArgs a;
+  T* pool;
+  int b;
+  big_pick(a0, pool0, J, blockIdx.y, a, pool, b);
   __shared__ double La[BF_NB * (BF_TILE + 1)];  // La[t][ii] = L(r0 + ii, j0 + t)
   __shared__ double Wb[BF_NB * (BF_TILE + 1)];  // Wb[t][cc] = W(c0 + cc, j0 + t); tile result later
   __shared__ double dA[BF_NB], dB[BF_NB];
   __shared__ int ty[BF_NB];
-  const int b = blockIdx.y;
   const BigState st = a.st[b];
   if (st.kb == 0) return;
   const int F = a.fronts[b];
@@ -491,11 +538,14 @@ __global__ void __launch_bounds__(256) big_trailing_kernel(BigArgs a, T* pool) {
 // the diagonal).  64 x 64 tiles through LDS: L read down its columns, W
 // written down the block's columns.
 template <class T>
-__global__ void __launch_bounds__(256) big_w21_kernel(BigArgs a, T* pool) {
+__global__ void __launch_bounds__(256) big_w21_kernel(BigArgs a0, T* pool0, BigJobs J) {
+  BigArgs a;
+  T* pool;
+  int b;
+  big_pick(a0, pool0, J, blockIdx.y, a, pool, b);
   __shared__ double Wt[64][65];
   __shared__ double dA[64], dB[64];
   __shared__ int ty[64];
-  const int b = blockIdx.y;
   const int F = a.fronts[b];
   const int f = a.ff[F], k = a.fk[F], start = a.fstart[F];
   if (k >= f) return;
@@ -561,12 +611,15 @@ constexpr int CB_LD = CB_T + 4;
 constexpr size_t CB_LDS = 2 * 2 * CB_K * CB_LD * sizeof(double);
 
 template <class T>
-__global__ void __launch_bounds__(256, 2) big_cbupdate_kernel(BigArgs a, T* pool) {
+__global__ void __launch_bounds__(256, 2) big_cbupdate_kernel(BigArgs a0, T* pool0, BigJobs J) {
+  BigArgs a;
+  T* pool;
+  int b;
+  big_pick(a0, pool0, J, blockIdx.y, a, pool, b);
   extern __shared__ double cbs[];
   // As[buf][t][row] = L(r0 + row, j0 + t), Bs[buf][t][col] = W(c0 + col, j0 + t)
   auto As = [&](int buf, int t, int r) -> double& { return cbs[((buf * 2 + 0) * CB_K + t) * CB_LD + r]; };
   auto Bs = [&](int buf, int t, int r) -> double& { return cbs[((buf * 2 + 1) * CB_K + t) * CB_LD + r]; };
-  const int b = blockIdx.y;
   const int F = a.fronts[b];
   const int f = a.ff[F], k = a.fk[F], start = a.fstart[F];
   if (k >= f) return;
@@ -654,16 +707,26 @@ __global__ void __launch_bounds__(256, 2) big_cbupdate_kernel(BigArgs a, T* pool
   }
 }
 
-__global__ void big_init_kernel(BigArgs a, int nbig) {
-  const int b = blockIdx.x;
-  if (b >= nbig) return;
+__global__ void big_init_kernel(BigArgs a0, int nbig, BigJobs J) {
+  BigArgs a;
+  double* pool;
+  int b;
+  big_pick<double>(a0, nullptr, J, blockIdx.x, a, pool, b);
+  if (b >= (J.jobs ? a.nbig : nbig)) return;
   const int k = a.fk[a.fronts[b]];
   int* perm = a.perm + (int64_t)b * a.perm_stride;
   for (int t = threadIdx.x; t < k; t += blockDim.x) perm[t] = t;
   if (threadIdx.x == 0) a.st[b] = BigState{0, 0, 0, 0, 0, 0, 0, 0};
 }
 
-__global__ void big_pending_kernel(BigArgs a, int nbig, int* pending) {
+// (with jobs: one workgroup per job, each writing its job's count)
+__global__ void big_pending_kernel(BigArgs a0, int nbig, int* pending, BigJobs J) {
+  BigArgs a = a0;
+  if (J.jobs) {
+    a = J.jobs[blockIdx.x];
+    nbig = a.nbig;
+    pending = a.pend;
+  }
   int c = 0;
   for (int b = threadIdx.x; b < nbig; b += blockDim.x)
     if (a.st[b].next < a.fk[a.fronts[b]]) ++c;
@@ -674,9 +737,12 @@ __global__ void big_pending_kernel(BigArgs a, int nbig, int* pending) {
   if (threadIdx.x == 0) *pending = part[0] + part[1] + part[2] + part[3];
 }
 
-__global__ void big_finish_kernel(BigArgs a, int nbig) {
-  const int b = blockIdx.x;
-  if (b >= nbig) return;
+__global__ void big_finish_kernel(BigArgs a0, int nbig, BigJobs J) {
+  BigArgs a;
+  double* pool;
+  int b;
+  big_pick<double>(a0, nullptr, J, blockIdx.x, a, pool, b);
+  if (b >= (J.jobs ? a.nbig : nbig)) return;
   const int F = a.fronts[b];
   const int k = a.fk[F], start = a.fstart[F];
   const int* perm = a.perm + (int64_t)b * a.perm_stride;
@@ -703,40 +769,21 @@ void set_bigfront_attributes() {
 
 int bigfront_max_k() { return BF_LDS; }
 
-template <class T>
-void factor_big_fronts(riga_problem* pr, Factor& F, T* pool, const int32_t* fronts,
-                       const std::vector<int>& big_f, const std::vector<int>& big_k,
-                       double pivtol, int level, bool checked, hipStream_t s) {
-  const int nbig = (int)big_f.size();
-  if (nbig == 0) return;
-  int maxk = 0, maxcb = 0, max_tiles = 0, max_cb_tiles = 0;
-  int steps = 0;
-  for (int i = 0; i < nbig; ++i) {
-    const int f = big_f[i], k = big_k[i];
-    maxk = std::max(maxk, k);
-    maxcb = std::max(maxcb, f - k);
-    int j0 = 0, n = 0;
-    while (j0 < k) {
-      j0 += panel_width(k - j0);
-      ++n;
-    }
-    steps = std::max(steps, n);
-    const int nb0 = panel_width(k);
-    const int nt = (f - nb0 + BF_TILE - 1) / BF_TILE;
-    max_tiles = std::max(max_tiles, nt * (nt + 1) / 2);
-    const int ntc = (f - k + CB_T - 1) / CB_T;
-    max_cb_tiles = std::max(max_cb_tiles, ntc * (ntc + 1) / 2);
-  }
-  if (maxk > bigfront_max_k())
+namespace {
+
+// The arguments of one problem's blocked fronts at one height.
+BigArgs big_args(riga_problem* pr, Factor& F, void* pool, const int32_t* fronts, const BigPlan& P,
+                 double pivtol, int level) {
+  if (P.maxk > bigfront_max_k())
     throw Error(RIGA_EUNSUPPORTED, "fully-summed block too large for the panel kernel");
   // scratch reserved before the factorisation for the largest level: it is
   // never reallocated while kernels of an earlier level may still use it
-  const int64_t stride = maxk + 1;
-  const size_t need_perm = (size_t)nbig * stride, need_lp = (size_t)nbig * BF_NB;
-  const size_t need_st = (size_t)nbig * sizeof(BigState) / sizeof(int32_t) + 1;
+  const int64_t stride = P.maxk + 1;
+  const size_t need_perm = (size_t)P.nbig * stride, need_lp = (size_t)P.nbig * BF_NB;
+  const size_t need_st = (size_t)P.nbig * sizeof(BigState) / sizeof(int32_t) + 1;
   if (F.big_perm.n < need_perm || F.big_lperm.n < need_lp || F.big_state.n < need_st)
     throw Error(RIGA_EINVAL, "blocked-factorisation scratch not reserved");
-  int32_t* pending = F.big_state.p + (F.big_state.n - 1);
+  if (F.big_pend.n < pr->levels.size()) throw Error(RIGA_EINVAL, "pending counts not reserved");
   BigArgs a{};
   a.fronts = fronts;
   a.ff = pr->d_ff.p;
@@ -751,56 +798,128 @@ void factor_big_fronts(riga_problem* pr, Factor& F, T* pool, const int32_t* fron
   a.lperm = F.big_lperm.p;
   a.st = reinterpret_cast<BigState*>(F.big_state.p);
   a.pivtol = pivtol;
-  big_init_kernel<<<nbig, 256, 0, s>>>(a, nbig);
+  a.pool = pool;
+  a.pend = F.big_pend.p + level;
+  a.nbig = P.nbig;
+  return a;
+}
+
+// `n` rounds of panel, update-block rows and trailing update over the
+// P.nbig fronts of the grid.
+template <class T>
+void big_rounds(const BigArgs& a, T* pool, const BigJobs& J, const BigPlan& P, int n, hipStream_t s) {
+  const int nb = P.nbig;
+  const unsigned cb_blocks = (unsigned)std::max(1, (P.maxcb + 255) / 256);
+  const unsigned tpf = (unsigned)std::max(1, std::min(P.max_tiles, std::max(1, 2048 / nb)));
+  for (int it = 0; it < n; ++it) {
+    big_panel_kernel<T><<<nb, 1024, BF_LDS * sizeof(double), s>>>(a, pool, J);
+    if (P.maxcb > 0) big_cbrows_kernel<T><<<dim3(cb_blocks, nb), 256, 0, s>>>(a, pool, J);
+    big_trailing_kernel<T><<<dim3(tpf, nb), 256, 0, s>>>(a, pool, J);
+  }
   HIPCHECK(hipGetLastError());
-  const unsigned cb_blocks = (unsigned)std::max(1, (maxcb + 255) / 256);
-  const unsigned tpf = (unsigned)std::max(1, std::min(max_tiles, std::max(1, 2048 / nbig)));
-  auto run = [&](int n) {
-    for (int it = 0; it < n; ++it) {
-      big_panel_kernel<T><<<nbig, 1024, BF_LDS * sizeof(double), s>>>(a, pool);
-      if (maxcb > 0) big_cbrows_kernel<T><<<dim3(cb_blocks, nbig), 256, 0, s>>>(a, pool);
-      big_trailing_kernel<T><<<dim3(tpf, nbig), 256, 0, s>>>(a, pool);
+}
+
+// the update blocks, once every panel of the level is done
+template <class T>
+void big_cb_update(const BigArgs& a, T* pool, const BigJobs& J, const BigPlan& P, hipStream_t s) {
+  if (P.maxcb == 0) return;
+  const int nb = P.nbig;
+  const unsigned cpf = (unsigned)std::max(1, std::min(P.max_cb_tiles, std::max(1, 4096 / nb)));
+  const unsigned wpf = (unsigned)std::max(1, std::min(((P.maxcb + 63) / 64) * ((P.maxk + 63) / 64),
+                                                      std::max(1, 2048 / nb)));
+  big_w21_kernel<T><<<dim3(wpf, nb), 256, 0, s>>>(a, pool, J);
+  big_cbupdate_kernel<T><<<dim3(cpf, nb), 256, CB_LDS, s>>>(a, pool, J);
+  HIPCHECK(hipGetLastError());
+}
+
+// The predicted panel steps plus one (covering a panel that ended early at
+// a 2x2 pivot on its edge; the steps of finished fronts return at once),
+// the update blocks, the count of unfinished fronts into each problem's
+// pending counter and the pivot orders.  A front left unfinished gets an
+// incomplete update block and is counted: the caller then repeats the
+// factorisation in checked mode.
+template <class T>
+void big_unchecked(const BigArgs& a, T* pool, const BigJobs& J, const BigPlan& P, hipStream_t s) {
+  const int nb = P.nbig;
+  big_init_kernel<<<nb, 256, 0, s>>>(a, nb, J);
+  HIPCHECK(hipGetLastError());
+  big_rounds<T>(a, pool, J, P, P.steps + 1, s);
+  big_cb_update<T>(a, pool, J, P, s);
+  if (J.jobs) big_pending_kernel<<<J.njobs, 256, 0, s>>>(a, nb, nullptr, J);
+  else big_pending_kernel<<<1, 256, 0, s>>>(a, nb, a.pend, J);
+  big_finish_kernel<<<nb, 256, 0, s>>>(a, nb, J);
+  HIPCHECK(hipGetLastError());
+}
+
+}  // namespace
+
+BigPlan big_plan(const std::vector<int>& big_f, const std::vector<int>& big_k) {
+  BigPlan P;
+  P.nbig = (int)big_f.size();
+  for (int i = 0; i < P.nbig; ++i) {
+    const int f = big_f[i], k = big_k[i];
+    P.maxk = std::max(P.maxk, k);
+    P.maxcb = std::max(P.maxcb, f - k);
+    int j0 = 0, n = 0;
+    while (j0 < k) {
+      j0 += panel_width(k - j0);
+      ++n;
     }
-    HIPCHECK(hipGetLastError());
-  };
-  // the update blocks, once every panel of the level is done
-  const unsigned cpf = (unsigned)std::max(1, std::min(max_cb_tiles, std::max(1, 4096 / nbig)));
-  auto cb_update = [&]() {
-    if (maxcb > 0) {
-      const unsigned wpf = (unsigned)std::max(1, std::min(((maxcb + 63) / 64) * ((maxk + 63) / 64),
-                                                          std::max(1, 2048 / nbig)));
-      big_w21_kernel<T><<<dim3(wpf, nbig), 256, 0, s>>>(a, pool);
-      big_cbupdate_kernel<T><<<dim3(cpf, nbig), 256, CB_LDS, s>>>(a, pool);
-    }
-    HIPCHECK(hipGetLastError());
-  };
+    P.steps = std::max(P.steps, n);
+    const int nb0 = panel_width(k);
+    const int nt = (f - nb0 + BF_TILE - 1) / BF_TILE;
+    P.max_tiles = std::max(P.max_tiles, nt * (nt + 1) / 2);
+    const int ntc = (f - k + CB_T - 1) / CB_T;
+    P.max_cb_tiles = std::max(P.max_cb_tiles, ntc * (ntc + 1) / 2);
+  }
+  return P;
+}
+
+size_t big_args_bytes() { return sizeof(BigArgs); }
+
+void big_args_fill(riga_problem* pr, Factor& F, void* pool, const int32_t* fronts, const BigPlan& P,
+                   double pivtol, int level, void* out) {
+  const BigArgs a = big_args(pr, F, pool, fronts, P, pivtol, level);
+  std::memcpy(out, &a, sizeof(a));
+}
+
+template <class T>
+void factor_big_fronts_batched(const void* jobs, const int32_t* ystart, int njobs, const BigPlan& P,
+                               hipStream_t s) {
+  if (njobs == 0 || P.nbig == 0) return;
+  const BigJobs J{static_cast<const BigArgs*>(jobs), ystart, njobs};
+  big_unchecked<T>(BigArgs{}, nullptr, J, P, s);
+}
+
+template <class T>
+void factor_big_fronts(riga_problem* pr, Factor& F, T* pool, const int32_t* fronts,
+                       const std::vector<int>& big_f, const std::vector<int>& big_k,
+                       double pivtol, int level, bool checked, hipStream_t s) {
+  const BigPlan P = big_plan(big_f, big_k);
+  if (P.nbig == 0) return;
+  const BigArgs a = big_args(pr, F, pool, fronts, P, pivtol, level);
   if (!checked) {
-    // one step more than predicted covers a panel that ended early (a 2x2
-    // pivot at its edge); the steps of finished fronts return at once.  A
-    // front left unfinished gets an incomplete update block and is counted:
-    // the factorisation is then repeated in checked mode.
-    if (F.big_pend.n < pr->levels.size()) throw Error(RIGA_EINVAL, "pending counts not reserved");
-    run(steps + 1);
-    cb_update();
-    big_pending_kernel<<<1, 256, 0, s>>>(a, nbig, F.big_pend.p + level);
-    big_finish_kernel<<<nbig, 256, 0, s>>>(a, nbig);
-    HIPCHECK(hipGetLastError());
+    big_unchecked<T>(a, pool, BigJobs{}, P, s);
     return;
   }
-  run(steps);
+  const int nbig = P.nbig;
+  int32_t* pending = F.big_state.p + (F.big_state.n - 1);
+  big_init_kernel<<<nbig, 256, 0, s>>>(a, nbig, BigJobs{});
+  HIPCHECK(hipGetLastError());
+  big_rounds<T>(a, pool, BigJobs{}, P, P.steps, s);
   // panels that ended early leave columns for further steps
   for (int guard = 0;; ++guard) {
-    big_pending_kernel<<<1, 256, 0, s>>>(a, nbig, pending);
+    big_pending_kernel<<<1, 256, 0, s>>>(a, nbig, pending, BigJobs{});
     HIPCHECK(hipGetLastError());
     int left = 0;
     HIPCHECK(hipMemcpyAsync(&left, pending, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     if (left == 0) break;
-    if (guard > maxk) throw Error(RIGA_EDEVICE, "blocked factorisation made no progress");
-    run(4);
+    if (guard > P.maxk) throw Error(RIGA_EDEVICE, "blocked factorisation made no progress");
+    big_rounds<T>(a, pool, BigJobs{}, P, 4, s);
   }
-  cb_update();
-  big_finish_kernel<<<nbig, 256, 0, s>>>(a, nbig);
+  big_cb_update<T>(a, pool, BigJobs{}, P, s);
+  big_finish_kernel<<<nbig, 256, 0, s>>>(a, nbig, BigJobs{});
   HIPCHECK(hipGetLastError());
 }
 
@@ -830,5 +949,7 @@ template void factor_big_fronts<double>(riga_problem*, Factor&, double*, const i
 template void factor_big_fronts<float>(riga_problem*, Factor&, float*, const int32_t*,
                                        const std::vector<int>&, const std::vector<int>&, double,
                                        int, bool, hipStream_t);
+template void factor_big_fronts_batched<double>(const void*, const int32_t*, int, const BigPlan&, hipStream_t);
+template void factor_big_fronts_batched<float>(const void*, const int32_t*, int, const BigPlan&, hipStream_t);
 
 }  // namespace riga

@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <mutex>
 
 #include "problem.h"
@@ -50,15 +51,13 @@ struct FrontArgs {
   int32_t* stat;   // per front: negative pivots, perturbed pivots, 2x2 pivots
 };
 
+// workgroup gid of an assembly launch: cpw consecutive columns of one front,
+// one wave each, lanes over rows; the column is built in LDS and written once
 template <class T>
-__global__ void __launch_bounds__(64 * ASM_COLS) front_assemble_kernel(FrontArgs fa, T* pool,
-                                                                     const int32_t* fronts,
-                                                                     const int64_t* col_prefix,
-                                                                     int nf, int cpw, double sigma) {
-  // workgroup: cpw consecutive columns of one front, one wave each,
-  // lanes over rows; the column is built in LDS and written once
+__device__ __forceinline__ void front_assemble_body(const FrontArgs& fa, T* pool, const int32_t* fronts,
+                                                    const int64_t* col_prefix, int nf, int cpw,
+                                                    double sigma, int64_t gid) {
   extern __shared__ double cols[];
-  const int64_t gid = blockIdx.x;
   int lo = 0, hi = nf;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
@@ -124,6 +123,38 @@ __global__ void __launch_bounds__(64 * ASM_COLS) front_assemble_kernel(FrontArgs
   __syncthreads();
   if (j < f)
     for (int r = j + lane; r < f; r += 64) front[(int64_t)j * f + r] = (T)col[r];
+}
+
+template <class T>
+__global__ void __launch_bounds__(64 * ASM_COLS) front_assemble_kernel(FrontArgs fa, T* pool,
+                                                                     const int32_t* fronts,
+                                                                     const int64_t* col_prefix,
+                                                                     int nf, int cpw, double sigma) {
+  front_assemble_body<T>(fa, pool, fronts, col_prefix, nf, cpw, sigma, blockIdx.x);
+}
+
+// One height of several problems: job j owns workgroups [g0, next job's g0).
+struct AsmJob {
+  FrontArgs fa;
+  void* pool;
+  const int32_t* fronts;
+  const int64_t* col_prefix;
+  int64_t g0;
+  double sigma;
+  int32_t nf, cpw;
+};
+
+template <class T>
+__global__ void __launch_bounds__(64 * ASM_COLS) front_assemble_batched_kernel(const AsmJob* jobs, int njobs) {
+  const int64_t gid = blockIdx.x;
+  int lo = 0, hi = njobs;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (jobs[mid].g0 <= gid) lo = mid; else hi = mid;
+  }
+  const AsmJob& J = jobs[lo];
+  front_assemble_body<T>(J.fa, static_cast<T*>(J.pool), J.fronts, J.col_prefix, J.nf, J.cpw, J.sigma,
+                         gid - J.g0);
 }
 
 constexpr double BK_ALPHA = 0.6403882032022076;  // (1 + sqrt(17)) / 8
@@ -342,15 +373,14 @@ __device__ __forceinline__ void ldlt_partial(Acc A, int f, int k, double* lbuf, 
 // The front in LDS as a packed lower triangle (column j holds rows j..f-1),
 // f (f + 1) / 2 entries, so that two workgroups fit on a CU.
 template <class T, int MAXF>
-__global__ void __launch_bounds__(256) front_factor_lds_kernel(FrontArgs fa, T* pool,
-                                                             const int32_t* fronts,
-                                                             double pivtol) {
+__device__ __forceinline__ void front_factor_lds_body(const FrontArgs& fa, T* pool, const int32_t* fronts,
+                                                      double pivtol, int blk) {
   __shared__ T sa[MAXF * (MAXF + 1) / 2];
   __shared__ double lbuf[2 * MAXF];
   __shared__ int perm[MAXF];
   __shared__ int32_t type[MAXF];
   __shared__ PivotStep dec;
-  const int F = fronts[blockIdx.x];
+  const int F = fronts[blk];
   const int f = fa.ff[F], k = fa.fk[F];
   T* g = pool + fa.pool_off[F];
   auto pk = [f](int i, int j) { return j * f - ((j * (j - 1)) >> 1) + (i - j); };
@@ -391,6 +421,34 @@ __global__ void __launch_bounds__(256) front_factor_lds_kernel(FrontArgs fa, T* 
   }
 }
 
+template <class T, int MAXF>
+__global__ void __launch_bounds__(256) front_factor_lds_kernel(FrontArgs fa, T* pool,
+                                                             const int32_t* fronts,
+                                                             double pivtol) {
+  front_factor_lds_body<T, MAXF>(fa, pool, fronts, pivtol, blockIdx.x);
+}
+
+// One height of several problems: job j owns workgroups [y0, next job's y0).
+struct LdsJob {
+  FrontArgs fa;
+  void* pool;
+  const int32_t* fronts;
+  double pivtol;
+  int64_t y0;
+};
+
+template <class T, int MAXF>
+__global__ void __launch_bounds__(256) front_factor_lds_batched_kernel(const LdsJob* jobs, int njobs) {
+  const int64_t y = blockIdx.x;
+  int lo = 0, hi = njobs;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (jobs[mid].y0 <= y) lo = mid; else hi = mid;
+  }
+  const LdsJob& J = jobs[lo];
+  front_factor_lds_body<T, MAXF>(J.fa, static_cast<T*>(J.pool), J.fronts, J.pivtol, (int)(y - J.y0));
+}
+
 FrontArgs front_args(riga_problem* pr, Factor& F) {
   FrontArgs fa{};
   fa.fk = pr->d_fk.p;
@@ -412,15 +470,18 @@ FrontArgs front_args(riga_problem* pr, Factor& F) {
   return fa;
 }
 
-template <class T, int MAXF>
-void factor_levels(riga_problem* pr, Factor& F, T* pool, T* hpool, double sigma, bool checked,
-                   hipStream_t s) {
-  FrontArgs fa = front_args(pr, F);
-  // a pivot below pivtol is replaced by +-pivtol and counted (static
-  // pivoting); RIGA_PIVTOL_REL overrides the relative threshold 1e-20
+// a pivot below the tolerance is replaced by +-tolerance and counted (static
+// pivoting); RIGA_PIVTOL_REL overrides the relative threshold 1e-20
+double pivot_tolerance(const riga_problem* pr, double sigma) {
   double rel = 1e-20;
   if (const char* v = std::getenv("RIGA_PIVTOL_REL")) rel = std::atof(v);
-  const double pivtol = rel * (pr->normK1 + fabs(sigma) * pr->normM1);
+  return rel * (pr->normK1 + fabs(sigma) * pr->normM1);
+}
+
+template <class T, int MAXF>
+void factor_levels(riga_problem* pr, Factor& F, T* pool, double sigma, bool checked, hipStream_t s) {
+  FrontArgs fa = front_args(pr, F);
+  const double pivtol = pivot_tolerance(pr, sigma);
   set_kernel_attributes();
   for (size_t h = 0; h < pr->levels.size(); ++h) {
     LevelDev& L = pr->levels[h];
@@ -440,8 +501,6 @@ void factor_levels(riga_problem* pr, Factor& F, T* pool, T* hpool, double sigma,
       factor_big_fronts<T>(pr, F, pool, L.fronts.p + ns, bf, bk, pivtol, (int)h, checked, s);
     }
   }
-  launch_front_inverse<T>(pr, F, pool, hpool, s);
-  launch_pivot_maps(pr, F, s);
 }
 
 }  // namespace
@@ -450,6 +509,10 @@ void set_front_attributes() {
   HIPCHECK(hipFuncSetAttribute((const void*)front_assemble_kernel<double>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, ASM_LDS));
   HIPCHECK(hipFuncSetAttribute((const void*)front_assemble_kernel<float>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, ASM_LDS));
+  HIPCHECK(hipFuncSetAttribute((const void*)front_assemble_batched_kernel<double>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, ASM_LDS));
+  HIPCHECK(hipFuncSetAttribute((const void*)front_assemble_batched_kernel<float>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, ASM_LDS));
 }
 
@@ -484,9 +547,10 @@ void factor_reserve(riga_problem* pr, Factor& F, int precision, hipStream_t s) {
   top_reserve(pr, F, precision, s);
 }
 
-void factor_numeric(riga_problem* pr, Factor& F, double sigma, int precision, hipStream_t s) {
+namespace {
+
+void check_reserved(const riga_problem* pr, const Factor& F, int precision) {
   const Analysis& an = pr->an;
-  F.factored = false;
   if (F.av.n < pr->kv.n) throw Error(RIGA_EINVAL, "factorisation buffers not reserved");
   if (precision == RIGA_MIXED) {
     if (F.pool32.n < (size_t)an.pool_size || F.h32.n < (size_t)an.h_size)
@@ -494,37 +558,36 @@ void factor_numeric(riga_problem* pr, Factor& F, double sigma, int precision, hi
   } else if (F.pool64.n < (size_t)an.pool_size || F.h64.n < (size_t)an.h_size) {
     throw Error(RIGA_EINVAL, "factorisation buffers not reserved");
   }
+}
+
+// after the levels: partitioned inverses, sweep maps, the top block and
+// K - sigma M for the refinement residuals (mixed precision, and FP64
+// solves refined after a stall); queues the copies of the per-front counts
+// and the pending counters into st and pend
+void factor_tail(riga_problem* pr, Factor& F, double sigma, int precision, std::vector<int32_t>& st,
+                 std::vector<int32_t>& pend, hipStream_t s) {
   const size_t nlev = pr->levels.size();
-  std::vector<int32_t> st((size_t)an.n_fronts * 4), pend(nlev, 0);
-  // the blocked fronts run their predicted panel steps without waiting for
-  // the host; in the rare case that a front needed more, the whole
-  // factorisation is repeated with the host checking every level
-  // (RIGA_FACTOR_CHECKED=1 checks every level from the start)
-  const char* ev = std::getenv("RIGA_FACTOR_CHECKED");
-  const int first = (ev && *ev == '1') ? 1 : 0;
-  for (int pass = first; pass < 2; ++pass) {
-    const bool checked = pass == 1;
-    if (nlev) HIPCHECK(hipMemsetAsync(F.big_pend.p, 0, nlev * sizeof(int32_t), s));
-    if (precision == RIGA_MIXED) {
-      factor_levels<float, LDS_FRONT_MAX_F32>(pr, F, F.pool32.p, F.h32.p, sigma, checked, s);
-      build_top<float>(pr, F, F.h32.p, F.trow32.p, F.tcol32.p, s);
-    } else {
-      factor_levels<double, LDS_FRONT_MAX_F64>(pr, F, F.pool64.p, F.h64.p, sigma, checked, s);
-      build_top<double>(pr, F, F.h64.p, F.trow64.p, F.tcol64.p, s);
-    }
-    // K - sigma M for the refinement residuals (mixed precision, and FP64
-    // solves refined after a stall)
-    launch_axpby_vals(pr->kv.p, pr->mv.p, sigma, F.av.p, (int64_t)pr->kv.n, s);
-    HIPCHECK(hipMemcpyAsync(st.data(), F.front_stat.p, st.size() * sizeof(int32_t),
-                            hipMemcpyDeviceToHost, s));
-    if (nlev)
-      HIPCHECK(hipMemcpyAsync(pend.data(), F.big_pend.p, nlev * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
-    if (std::all_of(pend.begin(), pend.end(), [](int32_t v) { return v == 0; })) break;
+  if (precision == RIGA_MIXED) {
+    launch_front_inverse<float>(pr, F, F.pool32.p, F.h32.p, s);
+    launch_pivot_maps(pr, F, s);
+    build_top<float>(pr, F, F.h32.p, F.trow32.p, F.tcol32.p, s);
+  } else {
+    launch_front_inverse<double>(pr, F, F.pool64.p, F.h64.p, s);
+    launch_pivot_maps(pr, F, s);
+    build_top<double>(pr, F, F.h64.p, F.trow64.p, F.tcol64.p, s);
   }
+  launch_axpby_vals(pr->kv.p, pr->mv.p, sigma, F.av.p, (int64_t)pr->kv.n, s);
+  st.assign((size_t)pr->an.n_fronts * 4, 0);
+  pend.assign(nlev, 0);
+  HIPCHECK(hipMemcpyAsync(st.data(), F.front_stat.p, st.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  if (nlev) HIPCHECK(hipMemcpyAsync(pend.data(), F.big_pend.p, nlev * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+}
+
+// inertia and pivot counts from the per-front counts (after synchronising)
+void factor_done(riga_problem* pr, Factor& F, double sigma, int precision, const std::vector<int32_t>& st) {
   int64_t neg = 0;
   int pert = 0, two = 0;
-  for (int f = 0; f < an.n_fronts; ++f) {
+  for (int f = 0; f < pr->an.n_fronts; ++f) {
     neg += st[4 * f];
     pert += st[4 * f + 1];
     two += st[4 * f + 2];
@@ -535,6 +598,228 @@ void factor_numeric(riga_problem* pr, Factor& F, double sigma, int precision, hi
   F.sigma = sigma;
   F.precision = precision;
   F.factored = true;
+}
+
+bool all_zero(const std::vector<int32_t>& v) {
+  return std::all_of(v.begin(), v.end(), [](int32_t x) { return x == 0; });
+}
+
+}  // namespace
+
+void factor_numeric(riga_problem* pr, Factor& F, double sigma, int precision, hipStream_t s) {
+  F.factored = false;
+  F.pre = false;
+  check_reserved(pr, F, precision);
+  const size_t nlev = pr->levels.size();
+  std::vector<int32_t> st, pend;
+  // the blocked fronts run their predicted panel steps without waiting for
+  // the host; in the rare case that a front needed more, the whole
+  // factorisation is repeated with the host checking every level
+  // (RIGA_FACTOR_CHECKED=1 checks every level from the start)
+  const char* ev = std::getenv("RIGA_FACTOR_CHECKED");
+  const int first = (ev && *ev == '1') ? 1 : 0;
+  for (int pass = first; pass < 2; ++pass) {
+    const bool checked = pass == 1;
+    if (nlev) HIPCHECK(hipMemsetAsync(F.big_pend.p, 0, nlev * sizeof(int32_t), s));
+    if (precision == RIGA_MIXED) factor_levels<float, LDS_FRONT_MAX_F32>(pr, F, F.pool32.p, sigma, checked, s);
+    else factor_levels<double, LDS_FRONT_MAX_F64>(pr, F, F.pool64.p, sigma, checked, s);
+    factor_tail(pr, F, sigma, precision, st, pend, s);
+    HIPCHECK(hipStreamSynchronize(s));
+    if (all_zero(pend)) break;
+  }
+  factor_done(pr, F, sigma, precision, st);
+}
+
+namespace {
+
+// The argument blocks of one batched factorisation, every height's in one
+// device table: per height, the assembly jobs grouped by columns per
+// workgroup, the LDS jobs and the blocked-front jobs.
+struct BatchHeight {
+  struct AsmGroup {
+    size_t off;  // byte offset of the AsmJob array
+    int njobs, cpw;
+    int64_t blocks;
+    size_t lds;
+  };
+  std::vector<AsmGroup> asm_groups;
+  size_t lds_off = 0;
+  int lds_jobs = 0;
+  int64_t lds_blocks = 0;
+  size_t big_off = 0, big_ystart_off = 0;
+  int big_jobs = 0;
+  BigPlan big;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <class T, int MAXF>
+void factor_levels_batched(const std::vector<riga_problem*>& prs, const std::vector<Factor*>& Fs,
+                           const std::vector<double>& sigmas, const std::vector<T*>& pools,
+                           std::vector<uint8_t>& tab, DBuf<uint8_t>& dtab, hipStream_t s) {
+  const int count = (int)prs.size();
+  size_t H = 0;
+  for (riga_problem* pr : prs) H = std::max(H, pr->levels.size());
+  std::vector<double> pivtol(count);
+  std::vector<FrontArgs> fas(count);
+  for (int i = 0; i < count; ++i) {
+    pivtol[i] = pivot_tolerance(prs[i], sigmas[i]);
+    fas[i] = front_args(prs[i], *Fs[i]);
+  }
+  // host image of the table
+  tab.clear();
+  auto put = [&](const void* src, size_t bytes) {
+    const size_t off = align_up(tab.size());
+    tab.resize(off + bytes);
+    std::memcpy(tab.data() + off, src, bytes);
+    return off;
+  };
+  const size_t big_bytes = big_args_bytes();
+  std::vector<BatchHeight> hts(H);
+  for (size_t h = 0; h < H; ++h) {
+    BatchHeight& B = hts[h];
+    // assembly: one group per columns-per-workgroup value
+    std::vector<std::pair<int, std::vector<AsmJob>>> groups;
+    std::vector<LdsJob> lds;
+    std::vector<uint8_t> bigs;
+    std::vector<int32_t> ystart(1, 0);
+    std::vector<int> all_f, all_k;
+    for (int i = 0; i < count; ++i) {
+      riga_problem* pr = prs[i];
+      if (h >= pr->levels.size()) continue;
+      LevelDev& L = pr->levels[h];
+      if (L.n == 0) continue;
+      auto g = std::find_if(groups.begin(), groups.end(), [&](const auto& x) { return x.first == L.asm_cols; });
+      if (g == groups.end()) {
+        groups.emplace_back(L.asm_cols, std::vector<AsmJob>());
+        g = groups.end() - 1;
+      }
+      AsmJob aj{};
+      aj.fa = fas[i];
+      aj.pool = pools[i];
+      aj.fronts = L.fronts.p;
+      aj.col_prefix = L.col_prefix.p;
+      aj.g0 = 0;  // set below, once the group is complete
+      aj.sigma = sigmas[i];
+      aj.nf = L.n;
+      aj.cpw = L.asm_cols;
+      g->second.push_back(aj);
+      const int ns = L.n_upto(MAXF);
+      if (ns > 0) {
+        LdsJob lj{};
+        lj.fa = fas[i];
+        lj.pool = pools[i];
+        lj.fronts = L.fronts.p;
+        lj.pivtol = pivtol[i];
+        lj.y0 = B.lds_blocks;
+        lds.push_back(lj);
+        B.lds_blocks += ns;
+      }
+      if (L.n > ns) {
+        std::vector<int> bf(L.host_f.begin() + ns, L.host_f.end());
+        std::vector<int> bk(L.host_k.begin() + ns, L.host_k.end());
+        const BigPlan P = big_plan(bf, bk);
+        const size_t o = bigs.size();
+        bigs.resize(o + big_bytes);
+        big_args_fill(pr, *Fs[i], pools[i], L.fronts.p + ns, P, pivtol[i], (int)h, bigs.data() + o);
+        ystart.push_back(ystart.back() + P.nbig);
+        B.big.nbig += P.nbig;
+        B.big.steps = std::max(B.big.steps, P.steps);
+        B.big.maxk = std::max(B.big.maxk, P.maxk);
+        B.big.maxcb = std::max(B.big.maxcb, P.maxcb);
+        B.big.max_tiles = std::max(B.big.max_tiles, P.max_tiles);
+        B.big.max_cb_tiles = std::max(B.big.max_cb_tiles, P.max_cb_tiles);
+      }
+    }
+    for (auto& g : groups) {
+      // workgroup offsets of the group's jobs
+      int64_t blocks = 0;
+      size_t max_f = 0;
+      int q = 0;
+      for (int i = 0; i < count; ++i) {
+        riga_problem* pr = prs[i];
+        if (h >= pr->levels.size()) continue;
+        LevelDev& L = pr->levels[h];
+        if (L.n == 0 || L.asm_cols != g.first) continue;
+        g.second[q].g0 = blocks;
+        blocks += L.cols;
+        max_f = std::max(max_f, (size_t)L.max_f);
+        ++q;
+      }
+      BatchHeight::AsmGroup ag;
+      ag.off = put(g.second.data(), g.second.size() * sizeof(AsmJob));
+      ag.njobs = (int)g.second.size();
+      ag.cpw = g.first;
+      ag.blocks = blocks;
+      ag.lds = (size_t)g.first * max_f * sizeof(double);
+      B.asm_groups.push_back(ag);
+    }
+    if (!lds.empty()) {
+      B.lds_off = put(lds.data(), lds.size() * sizeof(LdsJob));
+      B.lds_jobs = (int)lds.size();
+    }
+    if (B.big.nbig > 0) {
+      B.big_off = put(bigs.data(), bigs.size());
+      B.big_ystart_off = put(ystart.data(), ystart.size() * sizeof(int32_t));
+      B.big_jobs = (int)ystart.size() - 1;
+    }
+  }
+  if (tab.empty()) return;
+  dtab.alloc(tab.size(), s);
+  HIPCHECK(hipMemcpyAsync(dtab.p, tab.data(), tab.size(), hipMemcpyHostToDevice, s));
+  set_kernel_attributes();
+  for (size_t h = 0; h < H; ++h) {
+    const BatchHeight& B = hts[h];
+    for (const auto& ag : B.asm_groups) {
+      front_assemble_batched_kernel<T><<<(unsigned)ag.blocks, 64 * ag.cpw, ag.lds, s>>>(
+          reinterpret_cast<const AsmJob*>(dtab.p + ag.off), ag.njobs);
+      HIPCHECK(hipGetLastError());
+    }
+    if (B.lds_jobs > 0) {
+      front_factor_lds_batched_kernel<T, MAXF><<<(unsigned)B.lds_blocks, 256, 0, s>>>(
+          reinterpret_cast<const LdsJob*>(dtab.p + B.lds_off), B.lds_jobs);
+      HIPCHECK(hipGetLastError());
+    }
+    if (B.big_jobs > 0)
+      factor_big_fronts_batched<T>(dtab.p + B.big_off, reinterpret_cast<const int32_t*>(dtab.p + B.big_ystart_off),
+                                   B.big_jobs, B.big, s);
+  }
+}
+
+}  // namespace
+
+void factor_numeric_batched(const std::vector<riga_problem*>& prs, const std::vector<Factor*>& Fs,
+                            const std::vector<double>& sigmas, int precision, hipStream_t s) {
+  const int count = (int)prs.size();
+  for (int i = 0; i < count; ++i) {
+    Fs[i]->factored = false;
+    Fs[i]->pre = false;
+    check_reserved(prs[i], *Fs[i], precision);
+    const size_t nlev = prs[i]->levels.size();
+    if (nlev) HIPCHECK(hipMemsetAsync(Fs[i]->big_pend.p, 0, nlev * sizeof(int32_t), s));
+  }
+  // the job table (host image and device copy) lives until the
+  // synchronisation below
+  std::vector<uint8_t> tab;
+  DBuf<uint8_t> dtab;
+  if (precision == RIGA_MIXED) {
+    std::vector<float*> pools(count);
+    for (int i = 0; i < count; ++i) pools[i] = Fs[i]->pool32.p;
+    factor_levels_batched<float, LDS_FRONT_MAX_F32>(prs, Fs, sigmas, pools, tab, dtab, s);
+  } else {
+    std::vector<double*> pools(count);
+    for (int i = 0; i < count; ++i) pools[i] = Fs[i]->pool64.p;
+    factor_levels_batched<double, LDS_FRONT_MAX_F64>(prs, Fs, sigmas, pools, tab, dtab, s);
+  }
+  std::vector<std::vector<int32_t>> st(count), pend(count);
+  for (int i = 0; i < count; ++i) factor_tail(prs[i], *Fs[i], sigmas[i], precision, st[i], pend[i], s);
+  HIPCHECK(hipStreamSynchronize(s));
+  for (int i = 0; i < count; ++i) {
+    // a blocked front that needed more panel steps than predicted: that
+    // problem alone again, checked where needed
+    if (all_zero(pend[i])) factor_done(prs[i], *Fs[i], sigmas[i], precision, st[i]);
+    else factor_numeric(prs[i], *Fs[i], sigmas[i], precision, s);
+  }
 }
 
 }  // namespace riga

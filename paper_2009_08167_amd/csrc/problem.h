@@ -240,6 +240,7 @@ struct Factor {
   int64_t inertia = 0;
   int perturbed = 0, two = 0;
   int refactored = 0;  // repeats at a shift moved off a singular one (riga_eigs)
+  bool pre = false;    // made ahead by a batched call for the solve's first factorisation
 };
 
 // The mutable state of one solve: two factorisations (the current one and
@@ -328,6 +329,13 @@ void launch_spmm_km(const riga_problem* pr, const double* U, int nw, double* KU,
 // data and matrices, so it may run on another thread and stream while the
 // sweeps use the other Factor.
 void factor_numeric(riga_problem* pr, Factor& F, double sigma, int precision, hipStream_t s);
+// factor_numeric of several problems (each Fs[i] reserved for `precision`)
+// with every tree height of all of them in one launch per kernel: the same
+// per-front arithmetic as one problem alone, so the factorisations are
+// identical bit for bit.  Problems of different heights share the launches
+// of the heights they have.  Synchronises s.
+void factor_numeric_batched(const std::vector<riga_problem*>& prs, const std::vector<Factor*>& Fs,
+                            const std::vector<double>& sigmas, int precision, hipStream_t s);
 // Allocates every buffer factor_numeric(F, precision) writes (a no-op once
 // done): call it on the thread and stream that own the problem before a
 // factorisation runs on another stream.
@@ -348,6 +356,26 @@ void factor_big_fronts(riga_problem* pr, Factor& F, T* pool, const int32_t* fron
                        const std::vector<int>& big_f, const std::vector<int>& big_k,
                        double pivtol, int level, bool checked, hipStream_t s);
 int bigfront_max_k();
+// Launch shape of the blocked fronts of one height: fronts in the grid,
+// panel steps predicted for the widest, largest fully-summed and update
+// orders, trailing and update-block tiles of the largest front.
+struct BigPlan {
+  int nbig = 0, steps = 0, maxk = 0, maxcb = 0, max_tiles = 0, max_cb_tiles = 0;
+};
+BigPlan big_plan(const std::vector<int>& big_f, const std::vector<int>& big_k);
+// The device argument block of one problem's blocked fronts at one height
+// (big_args_bytes() bytes, written to host memory at `out`).
+size_t big_args_bytes();
+void big_args_fill(riga_problem* pr, Factor& F, void* pool, const int32_t* fronts, const BigPlan& P,
+                   double pivtol, int level, void* out);
+// The blocked fronts of one height of several problems in one launch per
+// kernel: `jobs` (device) holds njobs argument blocks, ystart[j] (device,
+// njobs + 1 entries) the first grid front of job j; P merges the jobs'
+// plans (nbig: their sum, the rest: maxima).  Unchecked: each job's count of
+// unfinished fronts goes to its own pending counter.
+template <class T>
+void factor_big_fronts_batched(const void* jobs, const int32_t* ystart, int njobs, const BigPlan& P,
+                               hipStream_t s);
 // Allocates the blocked-factorisation scratch of F for every level (fronts
 // above lds_max_f), so that no level reallocates it mid-factorisation.
 void bigfront_reserve(riga_problem* pr, Factor& F, int lds_max_f, hipStream_t s);

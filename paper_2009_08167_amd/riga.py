@@ -21,7 +21,7 @@ RIGA_MAT_K, RIGA_MAT_M, RIGA_MAT_A = 0, 1, 2
 
 EXPORTED = ["riga_set_allocator", "riga_analyze", "riga_assemble", "riga_update_coefficients",
             "riga_problem_info",
-            "riga_tree_export", "riga_get_matrices", "riga_spmv", "riga_factor", "riga_solve",
+            "riga_tree_export", "riga_get_matrices", "riga_spmv", "riga_factor", "riga_factor_batched", "riga_solve",
             "riga_solve_multi", "riga_project", "riga_project_noalloc", "riga_eigs", "riga_eigs_batched", "riga_eig_grad",
             "riga_mode_errors", "riga_exact_eigenvalues", "riga_destroy", "riga_status_string",
             "riga_last_error"]
@@ -99,6 +99,7 @@ def lib():
         L.riga_get_matrices.argtypes = [P, P, P, P, P]
         L.riga_spmv.argtypes = [P, C.c_int32, P, P, P]
         L.riga_factor.argtypes = [P, C.c_double, C.c_int32, C.POINTER(C.c_int64), C.POINTER(Stats)]
+        L.riga_factor_batched.argtypes = [P, C.c_int32, P, C.c_int32, P, P]
         L.riga_solve.argtypes = [P, P, P, C.c_int32, P]
         L.riga_solve_multi.argtypes = [P, P, P, C.c_int32, C.c_int64, C.c_int32, P]
         L.riga_eigs.argtypes = [P, C.POINTER(EigsOpts), C.POINTER(C.c_int32), P, P, P,
@@ -471,6 +472,28 @@ def eigs(dim, ne, p, s, nev, kappa=None, rho=None, lo=0.0, hi=math.inf, precisio
          **kw):
     pr = assemble(dim, ne, p, s, kappa, rho)
     return pr.eigs(nev, lo=lo, hi=hi, precision=precision, **kw)
+
+
+def factor_batched(problems, sigmas, precision=RIGA_FP64, allow_singular=False):
+    """Factorise K_i - sigma_i M_i of every problem (same device, each once)
+    with every tree height of all of them in one launch per kernel; each
+    problem keeps its factorisation for solve().  Returns [(inertia, stats)]
+    as factor() does for each."""
+    n = len(problems)
+    if len(sigmas) != n:
+        raise ValueError("one shift per problem")
+    handles = (C.c_void_p * max(n, 1))(*[p._h for p in problems])
+    sg = (C.c_double * max(n, 1))(*[float(x) for x in sigmas])
+    neg = (C.c_int64 * max(n, 1))()
+    sts = (Stats * max(n, 1))()
+    code = lib().riga_factor_batched(handles, n, sg, precision, neg, sts)
+    _check(code, allow=(RIGA_ESINGULAR,) if allow_singular else ())
+    out = []
+    for i in range(n):
+        d = sts[i].as_dict()
+        d["status"] = RIGA_ESINGULAR if d["n_perturbed_pivots"] > 0 else RIGA_OK
+        out.append((int(neg[i]), d))
+    return out
 
 
 def eigs_batched(problems, nev, lo=0.0, hi=math.inf, precision=RIGA_FP64, tol=1e-9, workers=0,
