@@ -199,6 +199,26 @@ def secondary_lines(riga, workloads, torch, np):
         bat[name] = {"value": npairs / dt, "seconds": dt, "pairs": npairs,
                      "max_residual": float(max(r[2].max() for r in res))}
         log("batch %s: %.1f eigenpairs/s" % (name, npairs / dt))
+    # the 64 first factorisations (sigma = 0) in one batched call against a
+    # loop of single factorisations
+    fac = {}
+    for name, prec in (("fp64", riga.RIGA_FP64), ("mixed", riga.RIGA_MIXED)):
+        sig = [0.0] * len(probs)
+        riga.factor_batched(probs, sig, precision=prec)
+        t0 = time.perf_counter()
+        riga.factor_batched(probs, sig, precision=prec)
+        tb = time.perf_counter() - t0
+        for pr in probs:
+            pr.factor(0.0, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for pr in probs:
+            pr.factor(0.0, precision=prec)
+        torch.cuda.synchronize()
+        tl = time.perf_counter() - t0
+        fac[name] = {"batched_ms": tb * 1e3, "single_loop_ms": tl * 1e3}
+        log("batch factorisation %s: %.1f ms batched, %.1f ms one by one" % (name, tb * 1e3, tl * 1e3))
+    bat["first_factorisations"] = fac
     out["batched_64_riga"] = bat
     del probs
     # adjoint gradient of sum w_i lambda_i, 20 pairs, with central FD on 50

@@ -153,6 +153,8 @@ typedef struct {
   int32_t fused_heights;  /* bottom heights swept in one launch per direction (one
                              workgroup per subtree); 0: none */
   int32_t fused_subtrees; /* workgroups of those launches */
+  int32_t tuned;          /* 1: top_cut and fused_heights are a measured choice
+                             (riga_tune, or its cache at assembly) */
 } riga_problem_info_t;
 
 /* Allocation hooks (e.g. torch's caching allocator).  Optional. */
@@ -255,6 +257,41 @@ riga_status riga_factor(riga_problem* pr, double sigma, int32_t precision,
  * non-finite shift is RIGA_EINVAL. */
 riga_status riga_factor_batched(riga_problem* const* probs, int32_t count, const double* sigmas,
                                 int32_t precision, int64_t* neg_pivots, riga_stats* stats);
+
+/* riga_tune: measured choice of how the forward/backward elimination of
+ * `pr` is decomposed (Sec. 4.2's sweeps, applied once per Lanczos step):
+ * the height from which the top tree levels are swept through their
+ * explicit inverse (-1: none); the bottom heights swept in one launch per
+ * subtree are left off (0).  Every cut within the size limits, and none, is
+ * timed on the problem itself -- the best
+ * of two factorisations at sigma = 0 in `precision` and the median of
+ * `reps` sweep pairs (reps <= 0: 20), each after a 320 MB write that takes
+ * the factor out of the caches as the eigensolver's Gram-Schmidt passes
+ * do -- and the fastest by sweep pair + factorisation / 70, if it beats the
+ * configuration in place by more than 3%, is applied to the problem and
+ * stored in
+ * the tuning cache under a key of the device (architecture, compute units)
+ * and of the elimination tree.  Problems assembled later with the same key
+ * take the stored choice, unless RIGA_TOP_CUT or RIGA_SUBTREE_HEIGHTS is
+ * set.  The cache is the text file named by RIGA_TUNE_CACHE, else
+ * $XDG_CACHE_HOME/riga/tune.txt, else $HOME/.cache/riga/tune.txt
+ * (RIGA_TUNE_CACHE="" keeps choices in the problem only).  Choices differ
+ * in the order of the same operations: results differ between them by
+ * rounding only.  The problem's factorisations are discarded: factorise
+ * again before riga_solve.  out (host, may be NULL) receives the choice,
+ * its times and those of the configuration in place before the call. */
+typedef struct riga_tune_result {
+  int32_t top_cut;              /* chosen cut height (-1: no top block) */
+  int32_t fused_heights;        /* chosen fused bottom heights (0: none) */
+  int32_t candidates;           /* configurations timed */
+  int32_t before_top_cut;       /* the configuration before the call */
+  int32_t before_fused_heights;
+  double sweep_us;              /* chosen: one forward + backward elimination, us */
+  double fact_us;               /* chosen: one factorisation (host clock), us */
+  double before_sweep_us;
+  double before_fact_us;
+} riga_tune_result;
+riga_status riga_tune(riga_problem* pr, int32_t precision, int32_t reps, riga_tune_result* out);
 
 /* riga_solve: x = (K - sigma M)^{-1} b with the last factorisation (one
  * forward/backward elimination; in RIGA_MIXED the FP32 solve is refined in

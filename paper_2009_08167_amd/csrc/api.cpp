@@ -132,6 +132,7 @@ riga_status riga_problem_info(const riga_problem* pr, riga_problem_info_t* info)
   info->top_cut = pr->has_device ? pr->top.cut : -1;
   info->fused_heights = pr->has_device ? pr->sub.nh : 0;
   info->fused_subtrees = pr->has_device ? pr->sub.n_sub : 0;
+  info->tuned = pr->has_device && pr->tuned ? 1 : 0;
   if (pr->has_device) {
     const int cut = pr->top.cut >= 0 ? pr->top.cut : a.height;
     double e = (double)pr->top.e_row + (double)pr->top.e_col;
@@ -212,6 +213,17 @@ riga_status riga_factor(riga_problem* pr, double sigma, int32_t precision, int64
     if (F.perturbed > 0)
       return fail(RIGA_ESINGULAR, std::to_string(F.perturbed) +
                                       " pivot(s) perturbed: K - sigma M is singular to working precision");
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_tune(riga_problem* pr, int32_t precision, int32_t reps, riga_tune_result* out) {
+  return guarded([&]() -> riga_status {
+    if (!need_device(pr)) return fail(RIGA_EINVAL, "problem has no device data");
+    if (precision != RIGA_FP64 && precision != RIGA_MIXED) return fail(RIGA_EINVAL, "bad precision");
+    riga::StreamBind bind(pr, pr->home);
+    riga::tune_problem(pr, precision, reps > 0 ? reps : 20, out);
+    pr->tuned = true;
     return RIGA_OK;
   });
 }

@@ -95,9 +95,20 @@ Sizes top_sizes(const Analysis& an, int cut) {
   return z;
 }
 
-int choose_cut(const Analysis& an) {
+// a top block from height c up stays within the size limits
+bool cut_fits(const Analysis& an, int c) {
+  if (c < 1 || c >= an.height) return false;
+  const Sizes z = top_sizes(an, c);
+  return z.e_row + z.e_col + z.e_cb <= TOP_MAX_ENTRIES && z.max_h <= TOP_MAX_STACK &&
+         z.max_depth <= TOP_MAX_ANC;
+}
+
+// The cut: `forced` (a measured choice: -1 none, c >= 1 that height), else
+// RIGA_TOP_CUT, else the cost model below.
+int choose_cut(const Analysis& an, int forced) {
   const int H = an.height;
   if (H < 2) return -1;
+  if (forced != TOP_CUT_MODEL) return cut_fits(an, forced) ? forced : -1;
   if (const char* env = std::getenv("RIGA_TOP_CUT")) {
     if (*env) {
       const int c = std::atoi(env);
@@ -115,10 +126,8 @@ int choose_cut(const Analysis& an) {
   double best = 0.95 * all;  // take the top block only for a clear gain
   int cut = -1;
   for (int c = 1; c < H; ++c) {
+    if (!cut_fits(an, c)) continue;
     const Sizes z = top_sizes(an, c);
-    if (z.e_row + z.e_col + z.e_cb > TOP_MAX_ENTRIES || z.max_h > TOP_MAX_STACK ||
-        z.max_depth > TOP_MAX_ANC)
-      continue;
     double t = 3.0 * TOP_LATENCY + (double)(z.e_row + z.e_col) * 8.0 / TOP_BW;
     for (int h = 0; h < c; ++h) t += level(h);
     if (t < best) {
@@ -459,12 +468,19 @@ __global__ void __launch_bounds__(256) top_fold_kernel(const int32_t* __restrict
 
 }  // namespace
 
-void setup_top(riga_problem* pr) {
+std::vector<int> top_cut_candidates(const riga_problem* pr) {
+  std::vector<int> c(1, -1);
+  for (int h = 1; h < pr->an.height; ++h)
+    if (cut_fits(pr->an, h)) c.push_back(h);
+  return c;
+}
+
+void setup_top(riga_problem* pr, int forced) {
   const Analysis& an = pr->an;
   hipStream_t s = pr->home;
   pr->top = TopDev{};
   TopDev& T = pr->top;
-  const int cut = choose_cut(an);
+  const int cut = choose_cut(an, forced);
   if (cut < 0) return;
   const int nf = an.n_fronts;
   std::vector<int> tstart(nf, -1), sub_lo(nf, -1), tf_of(nf, -1), Tf;

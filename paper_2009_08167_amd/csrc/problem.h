@@ -300,6 +300,7 @@ struct riga_problem {
   int gstride = 1;
   riga::TopDev top;                         // explicit inverse of the top levels
   riga::SubtreeDev sub;                     // fused sweeps of the bottom heights
+  bool tuned = false;                       // top and sub from a measured choice
   riga::DBuf<double> ir_r, ir_x, ir_d;      // iterative refinement vectors
 
   riga_stats stats{};
@@ -384,8 +385,23 @@ void launch_pivot_maps(riga_problem* pr, Factor& F, hipStream_t s);
 // Top block: chooses the cut and builds its static maps (at set-up); builds
 // L_TT^{-1} of factorisation F from its partitioned inverses h; runs the
 // top part of a forward/backward sweep.
-void setup_top(riga_problem* pr);
-void setup_subtrees(riga_problem* pr);
+// forced = TOP_CUT_MODEL: RIGA_TOP_CUT, else the cost model; -1: no top
+// block; c >= 1: the cut at height c (none if it exceeds the size limits).
+constexpr int TOP_CUT_MODEL = -1000;
+void setup_top(riga_problem* pr, int forced = TOP_CUT_MODEL);
+// the cuts within the size limits, and -1 (no top block)
+std::vector<int> top_cut_candidates(const riga_problem* pr);
+// Fused bottom heights of the sweeps: forced = SUB_FROM_ENV reads
+// RIGA_SUBTREE_HEIGHTS (unset: none); 0: none; SUB_AUTO: the automatic
+// choice; n >= 2: n heights where they fit.
+constexpr int SUB_FROM_ENV = -1000, SUB_AUTO = -1;
+void setup_subtrees(riga_problem* pr, int forced = SUB_FROM_ENV);
+// The measured choice for this problem's device and tree in the tuning
+// cache, if any (tune.cpp).
+bool tune_lookup(const riga_problem* pr, int* cut, int* fused);
+// Times the candidate decompositions, applies and caches the fastest;
+// the problem's factorisations are invalidated.
+void tune_problem(riga_problem* pr, int precision, int reps, riga_tune_result* out);
 void top_reserve(riga_problem* pr, Factor& F, int precision, hipStream_t s);
 template <class T>
 void build_top(riga_problem* pr, Factor& F, const T* h, T* trow, T* tcol, hipStream_t s);

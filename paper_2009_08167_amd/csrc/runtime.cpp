@@ -287,8 +287,15 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
     throw Error(RIGA_EUNSUPPORTED, "fully-summed block too large for the panel kernel");
   if (front_inverse_lds(an.max_fs) > 159 * 1024)
     throw Error(RIGA_EUNSUPPORTED, "fully-summed block too large for the inverse kernel's LDS");
-  setup_top(pr);
-  setup_subtrees(pr);
+  // a measured choice of the sweep decomposition for this device and tree
+  // (riga_tune's cache), unless the environment fixes either part
+  int cut = TOP_CUT_MODEL, fused = SUB_FROM_ENV;
+  const char* env_cut = std::getenv("RIGA_TOP_CUT");
+  const char* env_sub = std::getenv("RIGA_SUBTREE_HEIGHTS");
+  pr->tuned = false;
+  if (!(env_cut && *env_cut) && !(env_sub && *env_sub) && tune_lookup(pr, &cut, &fused)) pr->tuned = true;
+  setup_top(pr, cut);
+  setup_subtrees(pr, fused);
   HIPCHECK(hipStreamSynchronize(s));
   pr->has_device = true;
 }
@@ -309,7 +316,7 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
 // still waits out a memory latency), and during an eigen-solve their
 // CU-wide workgroups slow the other spectrum slice's kernels.
 // RIGA_SUBTREE_HEIGHTS=n fuses n heights; "auto" applies the rule above.
-void setup_subtrees(riga_problem* pr) {
+void setup_subtrees(riga_problem* pr, int forced) {
   constexpr int SUB_MIN_SUBTREES = 256;
   constexpr double SUB_MAX_BYTES = 262144.0;
   constexpr size_t SUB_LDS_MAX = 64 * 1024;
@@ -366,10 +373,15 @@ void setup_subtrees(riga_problem* pr) {
     return P.lds_fwd <= SUB_LDS_MAX && P.lds_bwd <= SUB_LDS_MAX;
   };
   Plan best, P;
-  const char* env = std::getenv("RIGA_SUBTREE_HEIGHTS");
-  if (!env || !*env) return;
-  if (std::strcmp(env, "auto") != 0) {
-    const int nh = std::max(0, std::min(std::atoi(env), nl));
+  int want = forced;
+  if (want == SUB_FROM_ENV) {
+    const char* env = std::getenv("RIGA_SUBTREE_HEIGHTS");
+    if (!env || !*env) return;
+    want = std::strcmp(env, "auto") == 0 ? SUB_AUTO : std::atoi(env);
+  }
+  if (want == 0) return;
+  if (want != SUB_AUTO) {
+    const int nh = std::max(0, std::min(want, nl));
     if (nh >= 2 && plan(nh, P)) best = std::move(P);
   } else {
     for (int c = 2; c <= nl; ++c)

@@ -21,7 +21,7 @@ RIGA_MAT_K, RIGA_MAT_M, RIGA_MAT_A = 0, 1, 2
 
 EXPORTED = ["riga_set_allocator", "riga_analyze", "riga_assemble", "riga_update_coefficients",
             "riga_problem_info",
-            "riga_tree_export", "riga_get_matrices", "riga_spmv", "riga_factor", "riga_factor_batched", "riga_solve",
+            "riga_tree_export", "riga_get_matrices", "riga_spmv", "riga_tune", "riga_factor", "riga_factor_batched", "riga_solve",
             "riga_solve_multi", "riga_project", "riga_project_noalloc", "riga_eigs", "riga_eigs_batched", "riga_eig_grad",
             "riga_mode_errors", "riga_exact_eigenvalues", "riga_destroy", "riga_status_string",
             "riga_last_error"]
@@ -64,7 +64,14 @@ class ProblemInfo(C.Structure):
                 ("nnz_l_exact", C.c_int64), ("flops_fact_exact", C.c_double),
                 ("components", C.c_int32), ("sweep_bytes_stored", C.c_double),
                 ("top_cut", C.c_int32), ("fused_heights", C.c_int32),
-                ("fused_subtrees", C.c_int32)]
+                ("fused_subtrees", C.c_int32), ("tuned", C.c_int32)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("top_cut", C.c_int32), ("fused_heights", C.c_int32), ("candidates", C.c_int32),
+                ("before_top_cut", C.c_int32), ("before_fused_heights", C.c_int32),
+                ("sweep_us", C.c_double), ("fact_us", C.c_double),
+                ("before_sweep_us", C.c_double), ("before_fact_us", C.c_double)]
 
 
 class Allocator(C.Structure):
@@ -100,6 +107,7 @@ def lib():
         L.riga_spmv.argtypes = [P, C.c_int32, P, P, P]
         L.riga_factor.argtypes = [P, C.c_double, C.c_int32, C.POINTER(C.c_int64), C.POINTER(Stats)]
         L.riga_factor_batched.argtypes = [P, C.c_int32, P, C.c_int32, P, P]
+        L.riga_tune.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(TuneResult)]
         L.riga_solve.argtypes = [P, P, P, C.c_int32, P]
         L.riga_solve_multi.argtypes = [P, P, P, C.c_int32, C.c_int64, C.c_int32, P]
         L.riga_eigs.argtypes = [P, C.POINTER(EigsOpts), C.POINTER(C.c_int32), P, P, P,
@@ -251,6 +259,15 @@ class Problem:
         d = st.as_dict()
         d["status"] = code
         return int(neg.value), d
+
+    def tune(self, precision=RIGA_FP64, reps=0):
+        """riga_tune: time the sweep decompositions of this problem, apply
+        and cache the fastest; returns the result fields as a dict.  The
+        factorisation is discarded (factor again before solve)."""
+        r = TuneResult()
+        _check(lib().riga_tune(self._h, precision, reps, C.byref(r)))
+        self.refresh_info()
+        return {f: getattr(r, f) for f, _ in TuneResult._fields_}
 
     def solve(self, b, max_ir=0, stream=None):
         import torch
