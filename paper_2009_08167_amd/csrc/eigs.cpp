@@ -47,8 +47,9 @@ constexpr double DEFLATE_SPACINGS = 4.0;
 
 // Candidate Ritz vectors are projected once against the locked pairs when
 // N * (locked pairs) * ceil(candidates / 8) is at most this (the block
-// projection reads the locked block once per 8 candidates)
-constexpr double LOCK_PROJECT_MAX = 268435456.0;
+// projection reads the locked block once per 8 candidates): every 4096-pair
+// request up to 2D 1024^2 (about 1.7e10) is covered
+constexpr double LOCK_PROJECT_MAX = 17179869184.0;
 
 // A shift whose factorisation had to perturb a pivot (K - sigma M singular
 // to working precision: the shift sits on an eigenvalue) is moved down by

@@ -34,6 +34,7 @@
 
 #include "mfma_tile.h"
 #include "problem.h"
+#include "wave_reduce.h"
 
 namespace riga {
 namespace {
@@ -191,12 +192,8 @@ __global__ void __launch_bounds__(1024) big_panel_kernel(BigArgs a0, T* pool0, B
         cmax = fmax(cmax, v);
         if (i < pend && v > rin) { rin = v; r = i; }
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        cmax = fmax(cmax, __shfl_xor(cmax, off));
-        const double ov = __shfl_xor(rin, off);
-        const int orr = __shfl_xor(r, off);
-        if (ov > rin || (ov == rin && orr >= 0 && (r < 0 || orr < r))) { rin = ov; r = orr; }
-      }
+      cmax = wave_max(cmax);
+      wave_argmax(rin, r);
       const double ajj = fabs(P(j, j));
       int kind = 1, sa = -1, sb = -1, end = 0;
       if (cmax == 0.0 || ajj >= BF_ALPHA * cmax) {
@@ -209,7 +206,7 @@ __global__ void __launch_bounds__(1024) big_panel_kernel(BigArgs a0, T* pool0, B
           if (i == r) continue;
           rmax = fmax(rmax, i < r ? fabs(P(r, i)) : fabs(P(i, r)));
         }
-        for (int off = 32; off > 0; off >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, off));
+        rmax = wave_max(rmax);
         const double arr = fabs(P(r, r));
         if (ajj * rmax >= BF_ALPHA * cmax * cmax) {
           kind = 1;

@@ -28,6 +28,7 @@
 #include <mutex>
 
 #include "problem.h"
+#include "wave_reduce.h"
 
 namespace riga {
 namespace {
@@ -191,11 +192,7 @@ __device__ __forceinline__ void ldlt_partial(Acc A, int f, int k, double* lbuf, 
         const double v = fabs((double)A(i, j));
         if (v > cmax) { cmax = v; r = i; }
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(cmax, off);
-        const int orr = __shfl_xor(r, off);
-        if (ov > cmax || (ov == cmax && orr >= 0 && (r < 0 || orr < r))) { cmax = ov; r = orr; }
-      }
+      wave_argmax(cmax, r);
       const double akk = fabs((double)A(j, j));
       int kind = 1, sa = -1, sb = -1, pz = 0;
       if (cmax == 0.0 || akk >= BK_ALPHA * cmax) {
@@ -209,7 +206,7 @@ __device__ __forceinline__ void ldlt_partial(Acc A, int f, int k, double* lbuf, 
           const double v = i < r ? fabs((double)A(r, i)) : fabs((double)A(i, r));
           rmax = fmax(rmax, v);
         }
-        for (int off = 32; off > 0; off >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, off));
+        rmax = wave_max(rmax);
         const double arr = fabs((double)A(r, r));
         if (akk * rmax >= BK_ALPHA * cmax * cmax) {
           kind = 1;

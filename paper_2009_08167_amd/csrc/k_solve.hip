@@ -24,6 +24,7 @@
 #include <mutex>
 
 #include "problem.h"
+#include "wave_reduce.h"
 
 namespace riga {
 namespace {
@@ -204,8 +205,7 @@ __device__ __forceinline__ void bwd_unit(const SolveArgs& sa, const T* __restric
   }
 #pragma unroll
   for (int c = 0; c < CPW; ++c) {
-    double s = acc[c];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    const double s = wave_sum(acc[c]);
     const int j = jc[c];
     if (lane == 0 && j < hi) x[sa.piv_dof[start + j]] = v[j - lo] + s;
   }
@@ -590,8 +590,7 @@ __global__ void __launch_bounds__(256 * SUB_GROUPS) bwd_subtree_kernel(
     bwd_prefetch<T, CPW>(sa, H, nx, tid, P);
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
-      double sm = acc[c];
-      for (int w = 32; w > 0; w >>= 1) sm += __shfl_xor(sm, w);
+      const double sm = wave_sum(acc[c]);
       const int j = jc[c];
       if (lane == 0 && j < hi) {
         const double val = v[j - lo] + sm;

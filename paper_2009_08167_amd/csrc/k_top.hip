@@ -39,6 +39,7 @@
 
 #include "mfma_tile.h"
 #include "problem.h"
+#include "wave_reduce.h"
 
 namespace riga {
 namespace {
@@ -393,7 +394,7 @@ __global__ void __launch_bounds__(256) top_bwd_kernel(const TopColUnit* __restri
 #pragma unroll
     for (int q = 0; q < 8; ++q) s += i + 64 * q < F.h ? cw[q] * v[i + 64 * q] : 0.0;
   }
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  s = wave_sum(s);
   if (lane == 0) x[dof] = s;
 }
 
