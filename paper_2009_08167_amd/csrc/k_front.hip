@@ -169,11 +169,10 @@ struct PivotStep {
 };
 
 // Partial LDL^T of the front `a` (f x f, ld = f, lower), fully-summed block
-// of order k.  NT threads.  `lbuf` holds 2 f doubles of scratch, `perm` k
-// ints, `dec` the broadcast decision.  Works for `a` in LDS or in global
-// memory.
+// of order k.  NT threads.  `perm` holds k ints, `dec` the broadcast
+// decision.  Works for `a` in LDS or in global memory.
 template <class T, int NT, class Acc>
-__device__ __forceinline__ void ldlt_partial(Acc A, int f, int k, double* lbuf, int* perm,
+__device__ __forceinline__ void ldlt_partial(Acc A, int f, int k, int* perm,
                                              PivotStep* dec, double pivtol, int* n_neg,
                                              int* n_pert, int* n_2x2, int32_t* type_out) {
   const int tid = threadIdx.x;
@@ -183,8 +182,27 @@ __device__ __forceinline__ void ldlt_partial(Acc A, int f, int k, double* lbuf, 
   int neg = 0, pert = 0, two = 0;
   __syncthreads();
   int j = 0;
+  // The column(s) of a pivot are scaled into L lazily, by waves 1.. while
+  // wave 0 takes the next decision (which reads later columns only); the
+  // rank-1/2 update uses the unscaled columns.  Two barriers per pivot (one
+  // more with an interchange).
+  int pj = -1, pkind = 0;
+  double p11 = 0.0, p21 = 0.0, p22 = 0.0;
+  auto scale_pending = [&](int t0, int nt) {
+    if (pkind == 1) {
+      const double dinv = 1.0 / p11;
+      for (int i = pj + 1 + t0; i < f; i += nt) A(i, pj) = (T)((double)A(i, pj) * dinv);
+    } else if (pkind == 2) {
+      const double idet = 1.0 / (p11 * p22 - p21 * p21);
+      for (int i = pj + 2 + t0; i < f; i += nt) {
+        const double u1 = (double)A(i, pj), u2 = (double)A(i, pj + 1);
+        A(i, pj) = (T)((u1 * p22 - u2 * p21) * idet);
+        A(i, pj + 1) = (T)((u2 * p11 - u1 * p21) * idet);
+      }
+    }
+  };
   while (j < k) {
-    // ---- pivot decision (wave 0)
+    // ---- pivot decision (wave 0); the previous pivot's scaling (others)
     if (wave == 0) {
       double cmax = 0.0;
       int r = -1;
@@ -225,8 +243,11 @@ __device__ __forceinline__ void ldlt_partial(Acc A, int f, int k, double* lbuf, 
         dec->swap_b = sb;
         dec->perturbed = pz;
       }
+    } else {
+      scale_pending(tid - 64, NT - 64);
     }
     __syncthreads();
+    pkind = 0;
     const int kind = dec->kind;
     const int p = dec->swap_a, q = dec->swap_b;  // p < q
     // ---- symmetric interchange of indices p and q (lower storage)
@@ -243,34 +264,30 @@ __device__ __forceinline__ void ldlt_partial(Acc A, int f, int k, double* lbuf, 
         }
       }
       if (tid == 0) { int tp = perm[p]; perm[p] = perm[q]; perm[q] = tp; }
+      __syncthreads();
     }
-    __syncthreads();
     if (kind == 1) {
       double d = (double)A(j, j);
-      if (fabs(d) < pivtol) {
-        d = d < 0.0 ? -pivtol : pivtol;
-        if (tid == 0) { A(j, j) = (T)d; ++pert; }
-      }
+      const bool small = fabs(d) < pivtol;
+      if (small) d = d < 0.0 ? -pivtol : pivtol;
       if (tid == 0) {
+        if (small) ++pert;
         if (d < 0.0) ++neg;
         type_out[j] = 1;
       }
-      const double dinv = 1.0 / d;
-      for (int i = j + 1 + tid; i < f; i += NT) {
-        const double u = (double)A(i, j);
-        lbuf[i] = u * dinv;     // L(i, j)
-        lbuf[f + i] = u;        // unscaled column
-      }
-      __syncthreads();
-      // trailing update a(i,m) -= L(i,j) * a(m,j), j < m <= i, on the
+      // trailing update a(i,m) -= a(i,j) a(m,j) / d, j < m <= i, on the
       // fully-summed columns only (the contribution block is updated once,
       // after the last pivot)
+      const double dinv = 1.0 / d;
       for (int m = j + 1 + wave; m < k; m += NW) {
-        const double um = lbuf[f + m];
-        for (int i = m + lane; i < f; i += 64) A(i, m) = (T)((double)A(i, m) - lbuf[i] * um);
+        const double um = (double)A(m, j) * dinv;
+        for (int i = m + lane; i < f; i += 64) A(i, m) = (T)((double)A(i, m) - (double)A(i, j) * um);
       }
       __syncthreads();
-      for (int i = j + 1 + tid; i < f; i += NT) A(i, j) = (T)lbuf[i];
+      if (tid == 0 && small) A(j, j) = (T)d;
+      pj = j;
+      pkind = 1;
+      p11 = d;
       j += 1;
     } else {
       const double d11 = (double)A(j, j), d21 = (double)A(j + 1, j), d22 = (double)A(j + 1, j + 1);
@@ -283,28 +300,25 @@ __device__ __forceinline__ void ldlt_partial(Acc A, int f, int k, double* lbuf, 
         type_out[j + 1] = 3;
       }
       const double idet = 1.0 / det;
-      // lbuf[i] = L(i, j), lbuf[f + i] = L(i, j+1); keep the unscaled
-      // columns in place until the update is done
-      for (int i = j + 2 + tid; i < f; i += NT) {
-        const double u1 = (double)A(i, j), u2 = (double)A(i, j + 1);
-        lbuf[i] = (u1 * d22 - u2 * d21) * idet;
-        lbuf[f + i] = (u2 * d11 - u1 * d21) * idet;
-      }
-      __syncthreads();
+      // a(i,m) -= [a_ij a_ij+1] D^{-1} [a_mj; a_mj+1] with the unscaled columns
       for (int m = j + 2 + wave; m < k; m += NW) {
         const double u1 = (double)A(m, j), u2 = (double)A(m, j + 1);
+        const double w1 = (u1 * d22 - u2 * d21) * idet, w2 = (u2 * d11 - u1 * d21) * idet;
         for (int i = m + lane; i < f; i += 64)
-          A(i, m) = (T)((double)A(i, m) - lbuf[i] * u1 - lbuf[f + i] * u2);
+          A(i, m) = (T)((double)A(i, m) - ((double)A(i, j) * w1 + (double)A(i, j + 1) * w2));
       }
       __syncthreads();
-      for (int i = j + 2 + tid; i < f; i += NT) {
-        A(i, j) = (T)lbuf[i];
-        A(i, j + 1) = (T)lbuf[f + i];
-      }
+      pj = j;
+      pkind = 2;
+      p11 = d11;
+      p21 = d21;
+      p22 = d22;
       j += 2;
     }
-    __syncthreads();
   }
+  // the last pivot's column(s)
+  scale_pending(tid, NT);
+  __syncthreads();
   // contribution block: C(i, m) -= sum_t L(i, t) W(m, t), k <= m <= i < f,
   // with W = L21 D (D block diagonal: 1x1 and 2x2 pivots).  Each thread
   // owns 4 x 4 tiles of the lower triangle of C, entries in registers.
@@ -373,7 +387,6 @@ template <class T, int MAXF>
 __device__ __forceinline__ void front_factor_lds_body(const FrontArgs& fa, T* pool, const int32_t* fronts,
                                                       double pivtol, int blk) {
   __shared__ T sa[MAXF * (MAXF + 1) / 2];
-  __shared__ double lbuf[2 * MAXF];
   __shared__ int perm[MAXF];
   __shared__ int32_t type[MAXF];
   __shared__ PivotStep dec;
@@ -400,7 +413,7 @@ __device__ __forceinline__ void front_factor_lds_body(const FrontArgs& fa, T* po
   __syncthreads();
   int neg = 0, pert = 0, two = 0;
   auto A = [&](int i, int j) -> T& { return sa[pk(i, j)]; };
-  ldlt_partial<T, 256>(A, f, k, lbuf, perm, &dec, pivtol, &neg, &pert, &two, type);
+  ldlt_partial<T, 256>(A, f, k, perm, &dec, pivtol, &neg, &pert, &two, type);
   __syncthreads();
   for (int e = threadIdx.x; e < n2; e += blockDim.x) {
     const int c = e / f, r = e % f;
