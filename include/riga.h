@@ -372,7 +372,7 @@ riga_status riga_eigs(riga_problem* pr, const riga_eigs_opts* opts, int32_t* n_f
 
 /* riga_eigs_batched: riga_eigs on `count` independent assembled problems at
  * once (instances of uneven size run concurrently on the device: a pool of
- * `workers` host threads, 0 -> 8, each with its own HIP stream; opts->stream
+ * `workers` host threads, 0 -> 16, each with its own HIP stream; opts->stream
  * is ignored and the call returns when all instances are done).  Per
  * instance i: n_found[i], evals_host[i] ([nev] host), evecs_dev[i] ([n_dof_i
  * * nev] device, or NULL; evecs_dev itself may be NULL), resid_host[i] (or

@@ -178,7 +178,9 @@ def element_unit_matrices(spaces, e_multi):
             vals = np.einsum('ap,bq->bapq', vals, Bd).reshape(-1, vals.shape[1] * Bd.shape[1])
             gl = [np.einsum('ap,bq->bapq', gl[dd], dBd if dd == d else Bd).reshape(vals.shape)
                   for dd in range(dim)]
-            wq = np.einsum('p,q->qp', wq, wd).ravel()
+            # quadrature points of the directions so far (p) slowest, this
+            # direction's (q) fastest: the same order as vals and gl
+            wq = np.einsum('p,q->pq', wq, wd).ravel()
     k0 = sum(np.einsum('ap,bp,p->ab', g, g, wq) for g in gl)
     m0 = np.einsum('ap,bp,p->ab', vals, vals, wq)
     gidx = np.zeros(1, dtype=np.int64)

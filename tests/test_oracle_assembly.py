@@ -27,6 +27,37 @@ def test_kronecker_eq_2dmatrix(dim, ne, p, s):
     assert abs(M - Mk).max() < 1e-13 * abs(M).max()
 
 
+@pytest.mark.parametrize("dim,nes,qs", [(2, (6, 9), (3, 5)), (2, (7, 4), (6, 3)),
+                                         (3, (4, 5, 3), (3, 5, 4))])
+def test_kronecker_anisotropic_mesh_and_rules(dim, nes, qs):
+    """Eq. 2Dmatrix on meshes with a different element count and a
+    different Gauss rule in each direction: the element loop's tensor
+    quadrature must pair each point's weight with that point's basis
+    products (an ordering that only works when every direction uses the
+    same rule fails here).  p = 2, s = 1; every rule is exact for the
+    degree-4 integrands, so the 1D factors do not depend on q."""
+    p, s = 2, 1
+    spaces = [assembly.Space1D(nes[d], p, s, qs[d]) for d in range(dim)]
+    Kf, Mf = assembly.assemble_full(spaces)
+    K, M = assembly.dirichlet(Kf, Mf, spaces)
+    f = []
+    for d in range(dim):
+        k1, m1 = assembly.matrices_1d(nes[d], p, s, qs[d])
+        f.append((sp.csr_matrix(k1[1:-1, 1:-1]), sp.csr_matrix(m1[1:-1, 1:-1])))
+    # x fastest: the last direction's factor is leftmost
+    Kk, Mk = None, None
+    for d in range(dim):
+        kd = None
+        for e in range(dim - 1, -1, -1):
+            a = f[e][0] if e == d else f[e][1]
+            kd = a if kd is None else sp.kron(kd, a)
+        Kk = kd if Kk is None else Kk + kd
+    for e in range(dim - 1, -1, -1):
+        Mk = f[e][1] if Mk is None else sp.kron(Mk, f[e][1])
+    assert abs(K - Kk).max() < 1e-13 * abs(K).max()
+    assert abs(M - Mk).max() < 1e-13 * abs(M).max()
+
+
 def test_p2_uniform_stencils():
     """Interior rows of the 1D quadratic C^1 matrices on a uniform mesh:
     M = (h/120)[1, 26, 66, 26, 1], K = (1/(6h))[-1, -2, 6, -2, -1]
