@@ -1446,11 +1446,14 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
       const double umax = (double)sv.mb + 1.0;
       const Analysis& an = pr->an;
       const TopDev& td = pr->top;
-      const double fact = (double)an.pool_size + (double)an.h_size + (double)td.e_row + (double)td.e_col +
-                          (double)td.e_cb + 4.0 * (double)n + (double)pr->kv.n;
+      const double fact = (double)an.h_size + (double)td.e_row + (double)td.e_col + (double)td.e_cb +
+                          4.0 * (double)n + (double)pr->kv.n;
       // (a further factorisation's worth of margin per slice: the first
-      // slice's look-ahead factorisation may not be allocated yet)
-      const double need = 8.0 * (nsl - 1) * (2.0 * n * cols + 3.0 * n * umax + 3.0 * fact);
+      // slice's look-ahead factorisation may not be allocated yet.  The
+      // front pool is per slice, shared by its factorisations, plus a
+      // second one while its first two factorisations overlap.)
+      const double need = 8.0 * (nsl - 1) * (2.0 * n * cols + 3.0 * n * umax + 3.0 * fact +
+                                             2.0 * (double)an.pool_size);
       size_t free_b = 0, total_b = 0;
       HIPCHECK(hipMemGetInfo(&free_b, &total_b));
       if (need * 1.15 > (double)free_b) {

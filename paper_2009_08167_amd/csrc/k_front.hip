@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 
 #include "problem.h"
@@ -546,11 +547,9 @@ void factor_reserve(riga_problem* pr, Factor& F, int precision, hipStream_t s) {
   }
   if (F.av.n < pr->kv.n) F.av.alloc(pr->kv.n, s);
   if (precision == RIGA_MIXED) {
-    if (F.pool32.n < (size_t)an.pool_size) F.pool32.alloc(an.pool_size, s);
     if (F.h32.n < (size_t)an.h_size) F.h32.alloc(an.h_size, s);
     bigfront_reserve(pr, F, LDS_FRONT_MAX_F32, s);
   } else {
-    if (F.pool64.n < (size_t)an.pool_size) F.pool64.alloc(an.pool_size, s);
     if (F.h64.n < (size_t)an.h_size) F.h64.alloc(an.h_size, s);
     bigfront_reserve(pr, F, LDS_FRONT_MAX_F64, s);
   }
@@ -563,26 +562,91 @@ void check_reserved(const riga_problem* pr, const Factor& F, int precision) {
   const Analysis& an = pr->an;
   if (F.av.n < pr->kv.n) throw Error(RIGA_EINVAL, "factorisation buffers not reserved");
   if (precision == RIGA_MIXED) {
-    if (F.pool32.n < (size_t)an.pool_size || F.h32.n < (size_t)an.h_size)
-      throw Error(RIGA_EINVAL, "factorisation buffers not reserved");
-  } else if (F.pool64.n < (size_t)an.pool_size || F.h64.n < (size_t)an.h_size) {
+    if (F.h32.n < (size_t)an.h_size) throw Error(RIGA_EINVAL, "factorisation buffers not reserved");
+  } else if (F.h64.n < (size_t)an.h_size) {
     throw Error(RIGA_EINVAL, "factorisation buffers not reserved");
   }
 }
+
+// A second pool slot up to this size stays allocated for the next overlap
+constexpr size_t POOL_KEEP_BYTES = (size_t)1 << 30;
+
+SolveCtx& ctx_of(riga_problem* pr, const Factor& F) {
+  for (SolveCtx& c : pr->ctx)
+    if (&F == &c.fac[0] || &F == &c.fac[1]) return c;
+  throw Error(RIGA_EINVAL, "factorisation outside the problem's solve contexts");
+}
+
+// The front pool of one factorisation of F: a free slot of F's context,
+// sized on first use; held until destruction, which waits for the
+// factorisation's stream first.
+struct PoolLease {
+  SolveCtx* c = nullptr;
+  int slot = -1;
+  hipStream_t s = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  bool mixed = false;
+  PoolLease(riga_problem* pr, Factor& F, int precision, hipStream_t st) : s(st) {
+    c = &ctx_of(pr, F);
+    {
+      std::lock_guard<std::mutex> lk(c->pool_mu);
+      for (int i = 0; i < 2 && slot < 0; ++i)
+        if (!c->pool_busy[i]) {
+          c->pool_busy[i] = true;
+          slot = i;
+        }
+    }
+    if (slot < 0) throw Error(RIGA_EDEVICE, "more than two factorisations at once in one solve context");
+    const size_t n = (size_t)pr->an.pool_size;
+    mixed = precision == RIGA_MIXED;
+    // (allocated on the problem's own stream, as its other persistent
+    // buffers: a factorisation's stream may not outlive the pool)
+    try {
+      if (mixed) {
+        if (c->pool32[slot].n < n) c->pool32[slot].alloc(n, pr->home);
+        p = c->pool32[slot].p;
+        bytes = n * sizeof(float);
+      } else {
+        if (c->pool64[slot].n < n) c->pool64[slot].alloc(n, pr->home);
+        p = c->pool64[slot].p;
+        bytes = n * sizeof(double);
+      }
+    } catch (...) {
+      std::lock_guard<std::mutex> lk(c->pool_mu);
+      c->pool_busy[slot] = false;
+      throw;
+    }
+  }
+  PoolLease(const PoolLease&) = delete;
+  PoolLease& operator=(const PoolLease&) = delete;
+  template <class T>
+  T* get() const { return static_cast<T*>(p); }
+  ~PoolLease() {
+    if (slot < 0) return;
+    (void)hipStreamSynchronize(s);
+    if (slot == 1 && bytes > POOL_KEEP_BYTES) {
+      if (mixed) c->pool32[1].reset();
+      else c->pool64[1].reset();
+    }
+    std::lock_guard<std::mutex> lk(c->pool_mu);
+    c->pool_busy[slot] = false;
+  }
+};
 
 // after the levels: partitioned inverses, sweep maps, the top block and
 // K - sigma M for the refinement residuals (mixed precision, and FP64
 // solves refined after a stall); queues the copies of the per-front counts
 // and the pending counters into st and pend
-void factor_tail(riga_problem* pr, Factor& F, double sigma, int precision, std::vector<int32_t>& st,
-                 std::vector<int32_t>& pend, hipStream_t s) {
+void factor_tail(riga_problem* pr, Factor& F, const PoolLease& pool, double sigma, int precision,
+                 std::vector<int32_t>& st, std::vector<int32_t>& pend, hipStream_t s) {
   const size_t nlev = pr->levels.size();
   if (precision == RIGA_MIXED) {
-    launch_front_inverse<float>(pr, F, F.pool32.p, F.h32.p, s);
+    launch_front_inverse<float>(pr, F, pool.get<float>(), F.h32.p, s);
     launch_pivot_maps(pr, F, s);
     build_top<float>(pr, F, F.h32.p, F.trow32.p, F.tcol32.p, s);
   } else {
-    launch_front_inverse<double>(pr, F, F.pool64.p, F.h64.p, s);
+    launch_front_inverse<double>(pr, F, pool.get<double>(), F.h64.p, s);
     launch_pivot_maps(pr, F, s);
     build_top<double>(pr, F, F.h64.p, F.trow64.p, F.tcol64.p, s);
   }
@@ -622,6 +686,7 @@ void factor_numeric(riga_problem* pr, Factor& F, double sigma, int precision, hi
   check_reserved(pr, F, precision);
   const size_t nlev = pr->levels.size();
   std::vector<int32_t> st, pend;
+  const PoolLease pool(pr, F, precision, s);
   // the blocked fronts run their predicted panel steps without waiting for
   // the host; in the rare case that a front needed more, the whole
   // factorisation is repeated with the host checking every level
@@ -631,9 +696,11 @@ void factor_numeric(riga_problem* pr, Factor& F, double sigma, int precision, hi
   for (int pass = first; pass < 2; ++pass) {
     const bool checked = pass == 1;
     if (nlev) HIPCHECK(hipMemsetAsync(F.big_pend.p, 0, nlev * sizeof(int32_t), s));
-    if (precision == RIGA_MIXED) factor_levels<float, LDS_FRONT_MAX_F32>(pr, F, F.pool32.p, sigma, checked, s);
-    else factor_levels<double, LDS_FRONT_MAX_F64>(pr, F, F.pool64.p, sigma, checked, s);
-    factor_tail(pr, F, sigma, precision, st, pend, s);
+    if (precision == RIGA_MIXED)
+      factor_levels<float, LDS_FRONT_MAX_F32>(pr, F, pool.get<float>(), sigma, checked, s);
+    else
+      factor_levels<double, LDS_FRONT_MAX_F64>(pr, F, pool.get<double>(), sigma, checked, s);
+    factor_tail(pr, F, pool, sigma, precision, st, pend, s);
     HIPCHECK(hipStreamSynchronize(s));
     if (all_zero(pend)) break;
   }
@@ -812,18 +879,22 @@ void factor_numeric_batched(const std::vector<riga_problem*>& prs, const std::ve
   // synchronisation below
   std::vector<uint8_t> tab;
   DBuf<uint8_t> dtab;
+  std::vector<std::unique_ptr<PoolLease>> lease(count);
+  for (int i = 0; i < count; ++i) lease[i].reset(new PoolLease(prs[i], *Fs[i], precision, s));
   if (precision == RIGA_MIXED) {
     std::vector<float*> pools(count);
-    for (int i = 0; i < count; ++i) pools[i] = Fs[i]->pool32.p;
+    for (int i = 0; i < count; ++i) pools[i] = lease[i]->get<float>();
     factor_levels_batched<float, LDS_FRONT_MAX_F32>(prs, Fs, sigmas, pools, tab, dtab, s);
   } else {
     std::vector<double*> pools(count);
-    for (int i = 0; i < count; ++i) pools[i] = Fs[i]->pool64.p;
+    for (int i = 0; i < count; ++i) pools[i] = lease[i]->get<double>();
     factor_levels_batched<double, LDS_FRONT_MAX_F64>(prs, Fs, sigmas, pools, tab, dtab, s);
   }
   std::vector<std::vector<int32_t>> st(count), pend(count);
-  for (int i = 0; i < count; ++i) factor_tail(prs[i], *Fs[i], sigmas[i], precision, st[i], pend[i], s);
+  for (int i = 0; i < count; ++i)
+    factor_tail(prs[i], *Fs[i], *lease[i], sigmas[i], precision, st[i], pend[i], s);
   HIPCHECK(hipStreamSynchronize(s));
+  lease.clear();  // (a repeat below takes its own)
   for (int i = 0; i < count; ++i) {
     // a blocked front that needed more panel steps than predicted: that
     // problem alone again, checked where needed

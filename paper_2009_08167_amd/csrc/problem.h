@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -214,8 +215,8 @@ struct TopDev {
 // from it.  A problem holds two, so that the factorisation at the next shift
 // can proceed on another stream while the sweeps use the current one.
 struct Factor {
-  DBuf<double> pool64, h64;            // fronts (f x f) and partitioned inverses
-  DBuf<float> pool32, h32;             // the same in FP32 (mixed precision)
+  DBuf<double> h64;                    // partitioned inverses (the fronts: SolveCtx pools)
+  DBuf<float> h32;                     // the same in FP32 (mixed precision)
   DBuf<int32_t> piv_perm, piv_type;    // by new index
   DBuf<int32_t> front_stat;            // [n_fronts * 4]: neg, perturbed, 2x2, spare
   DBuf<int32_t> piv_dof, piv_gmap;     // pivot-order gather maps of the sweeps
@@ -244,11 +245,22 @@ struct Factor {
 };
 
 // The mutable state of one solve: two factorisations (the current one and
-// the one made ahead), each with its own sweep scratch.  A problem has two,
-// so that two slices of the spectrum can be solved at once.
+// the one made ahead), each with its own sweep scratch, and the dense front
+// pools (one f x f block per front) their factorisations work in.  A pool
+// is needed only while a factorisation runs -- the sweeps read the
+// partitioned inverses H, D and the top block -- so the two factorisations
+// share pool slot 0; slot 1 serves a factorisation that overlaps another
+// one of the same context (the first shift made ahead beside the one at the
+// slice's lower end) and is given back to the allocator afterwards when it
+// is large.  A problem has several, so that slices of the spectrum can be
+// solved at once.
 struct SolveCtx {
   Factor fac[2];
   int cur = 0;
+  DBuf<double> pool64[2];
+  DBuf<float> pool32[2];
+  std::mutex pool_mu;
+  bool pool_busy[2] = {false, false};
   Factor& current() { return fac[cur]; }
   Factor& spare() { return fac[1 - cur]; }
 };

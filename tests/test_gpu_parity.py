@@ -473,6 +473,44 @@ def test_allocator_hook_routes_every_buffer():
         riga.set_allocator()
 
 
+def test_front_pools_shared_by_a_slices_factorisations():
+    """The dense front pool is needed only while a factorisation runs: the
+    two factorisations of a spectrum slice (current and made ahead) share
+    one, and a second is taken only while two of them overlap (the second
+    slice's first shift beside its lower end).  A solve that splits into two
+    slices therefore allocates at most three pools (counted through the
+    allocator hook), not one per factorisation buffer; its eigenpairs are
+    bitwise those of a solve without the hook."""
+    riga = _riga()
+    w = workloads.small(2, 40, 3, 8, 140, 0.3)
+    kappa, rho = w.coefficients()
+    ref = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho, leaf_dofs=32)
+    pool_bytes = ref.info["front_pool"] * 8
+    l0, _, _, _ = ref.eigs(w.nev)
+    ref.close()
+    sizes = []
+
+    def alloc(nbytes, stream):
+        sizes.append(nbytes)
+        return torch.cuda.caching_allocator_alloc(nbytes, stream=stream)
+
+    def free(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    riga.set_allocator(alloc, free)
+    try:
+        pr = riga.assemble(w.dim, w.ne, w.p, w.s, kappa, rho, leaf_dofs=32)
+        lam, _, _, st = pr.eigs(w.nev)
+        pools = sum(1 for b in sizes if b == pool_bytes)
+        _say("pool allocations", pools, "of", pool_bytes, "bytes; factorisations", st["n_fact"])
+        assert np.array_equal(lam, l0)
+        assert st["n_fact"] >= 4 and 1 <= pools <= 3
+        pr.close()
+        torch.cuda.synchronize()
+    finally:
+        riga.set_allocator()
+
+
 def test_allocator_hook_failure_gives_enomem():
     """A hook that returns NULL once it has handed out n blocks: riga_assemble
     or riga_eigs fails with RIGA_ENOMEM, and every block the hook did hand out
