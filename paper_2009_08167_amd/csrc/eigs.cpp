@@ -1055,6 +1055,7 @@ struct Slice {
   riga_status status = RIGA_OK;
   double verified = 0.0;
   bool requested_ends = true;  // lo and a finite hi are the request's (not a split point)
+  bool serial_first = false;   // factorise the first shift after lo, not beside it (memory)
   bool count_hi_first = true;  // a finite hi is counted before the runs (else reached by the shifts)
   std::function<void(Slice&)> after_lo;
 };
@@ -1097,7 +1098,8 @@ void run_slice(Slice& S) {
   la.ctx = sv.ctx;
   // an open-ended slice with a first shift inside it factorises there on
   // the look-ahead stream while the factorisation at lo proceeds
-  const bool first_ahead = lookahead_on() && (!std::isfinite(hi) || !S.count_hi_first) && !S.after_lo &&
+  const bool first_ahead = lookahead_on() && !S.serial_first && (!std::isfinite(hi) || !S.count_hi_first) &&
+                           !S.after_lo &&
                            std::isfinite(S.first_shift) && S.first_shift > lo;
   if (first_ahead) la.start(S.first_shift, sv.precision, sv.s);
   // the counts at the ends decide which eigenvalues the slice returns: in
@@ -1454,13 +1456,20 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
       // second one while its first two factorisations overlap.)
       const double need = 8.0 * (nsl - 1) * (2.0 * n * cols + 3.0 * n * umax + 3.0 * fact +
                                              2.0 * (double)an.pool_size);
+      // without the overlap of a slice's first two factorisations, one
+      // pool per slice
+      const double need_serial = need - 8.0 * (nsl - 1) * (double)an.pool_size;
       size_t free_b = 0, total_b = 0;
       HIPCHECK(hipMemGetInfo(&free_b, &total_b));
+      bool serial_first = false;
       if (need * 1.15 > (double)free_b) {
-        if (log_on())
-          std::fprintf(stderr, "[riga] no split: %d more slices need %.1f GB, %.1f GB free\n", nsl - 1,
-                       need * 1e-9, (double)free_b * 1e-9);
-        return;
+        if (need_serial * 1.15 > (double)free_b) {
+          if (log_on())
+            std::fprintf(stderr, "[riga] no split: %d more slices need %.1f GB, %.1f GB free\n", nsl - 1,
+                         need_serial * 1e-9, (double)free_b * 1e-9);
+          return;
+        }
+        serial_first = true;
       }
       a.hi = b[1];
       const int dev = pr->device;
@@ -1474,6 +1483,7 @@ riga_status run_eigs(riga_problem* pr, const riga_eigs_opts* o, int32_t* n_found
         S.hi = i + 1 < nsl ? b[i + 1] : o->hi;
         S.requested_ends = false;
         S.count_hi_first = false;
+        S.serial_first = serial_first;
         S.nev = o->nev;
         S.nu_base = i + 1 < nsl ? -1 : sv.nu_lo;
         S.first_shift = s1[i];
