@@ -51,6 +51,7 @@ struct FrontArgs {
   int32_t* piv_perm;
   int32_t* piv_type;
   int32_t* stat;   // per front: negative pivots, perturbed pivots, 2x2 pivots
+  const int32_t* ident;  // per front: 1 if its one child's update block is the front, row for row
 };
 
 // workgroup gid of an assembly launch: cpw consecutive columns of one front,
@@ -72,7 +73,26 @@ __device__ __forceinline__ void front_assemble_body(const FrontArgs& fa, T* pool
   double* col = cols + (size_t)wave * f;
   T* front = pool + fa.pool_off[F];
   const int c0 = fa.child_ptr[F], nc = fa.child_ptr[F + 1] - c0;
-  if (j < f) {
+  if (j < f && nc == 1 && fa.ident[F]) {
+    // (a front of a split separator's chain: its child's update block,
+    // column j, rows j.. are contiguous in the child's pool slot)
+    const int C = fa.child_list[c0];
+    const int kc = fa.fk[C], fc = fa.ff[C];
+    const T* src = pool + fa.pool_off[C] + (int64_t)(kc + j) * fc + kc;
+    for (int r0 = j; r0 < f; r0 += 64 * 4) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = r0 + lane + 64 * u;
+        v[u] = r < f ? (double)src[r] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = r0 + lane + 64 * u;
+        if (r < f) col[r] = v[u];
+      }
+    }
+  } else if (j < f) {
     // children's contributions: positions of column j in each child first
     int cc[4], kc[4], fc[4];
     int64_t po[4];
@@ -478,6 +498,7 @@ FrontArgs front_args(riga_problem* pr, Factor& F) {
   fa.piv_perm = F.piv_perm.p;
   fa.piv_type = F.piv_type.p;
   fa.stat = F.front_stat.p;
+  fa.ident = pr->d_asm_ident.p;
   return fa;
 }
 

@@ -296,6 +296,7 @@ struct riga_problem {
   riga::DBuf<int32_t> d_rows, d_fk, d_ff, d_fstart, d_child_ptr, d_child_list, d_inv;
   riga::DBuf<int64_t> d_rows_off, d_pool_off, d_cb_off, d_inv_off, d_amap_ptr;
   riga::DBuf<int32_t> d_amap_row, d_amap_val;
+  riga::DBuf<int32_t> d_asm_ident;  // per front: one child whose update block maps row for row
   std::vector<riga::LevelDev> levels;
 
   // numeric factorisations: ctx[0].current() is the one riga_factor /

@@ -149,6 +149,20 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
   pr->d_amap_ptr.upload(an.amap_ptr, s);
   pr->d_amap_row.upload(an.amap_row, s);
   pr->d_amap_val.upload(an.amap_val, s);
+  {
+    // fronts whose one child's update block is the front row for row (the
+    // chains of split separators): assembled by contiguous copies
+    std::vector<int32_t> ident(std::max(an.n_fronts, 1), 0);
+    for (int F = 0; F < an.n_fronts; ++F) {
+      if (an.child_ptr[F + 1] - an.child_ptr[F] != 1) continue;
+      const int ci = an.child_ptr[F], C = an.child_list[ci];
+      if (an.f_f[C] - an.f_k[C] != an.f_f[F]) continue;
+      bool same = true;
+      for (int i = 0; i < an.f_f[F] && same; ++i) same = an.inv[an.inv_off[ci] + i] == i;
+      ident[F] = same ? 1 : 0;
+    }
+    pr->d_asm_ident.upload(ident, s);
+  }
   // solve descriptors and the flattened gather map: for each front position,
   // the absolute index in the update vectors of each child's contribution
   {
