@@ -79,15 +79,15 @@ __device__ __forceinline__ void front_assemble_body(const FrontArgs& fa, T* pool
     const int C = fa.child_list[c0];
     const int kc = fa.fk[C], fc = fa.ff[C];
     const T* src = pool + fa.pool_off[C] + (int64_t)(kc + j) * fc + kc;
-    for (int r0 = j; r0 < f; r0 += 64 * 4) {
-      double v[4];
+    for (int r0 = j; r0 < f; r0 += 64 * 8) {
+      double v[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 8; ++u) {
         const int r = r0 + lane + 64 * u;
         v[u] = r < f ? (double)src[r] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 8; ++u) {
         const int r = r0 + lane + 64 * u;
         if (r < f) col[r] = v[u];
       }
@@ -109,27 +109,35 @@ __device__ __forceinline__ void front_assemble_body(const FrontArgs& fa, T* pool
         cc[q] = inv[q][j];
       }
     }
-    for (int r0 = j; r0 < f; r0 += 64 * 4) {
-      double v[4];
+    // per child holding column j (a wave-uniform test): the map entries of
+    // AU rows, then their values, each batch of loads in flight together;
+    // the children are added in their fixed order
+    constexpr int AU = 8;
+    for (int r0 = j; r0 < f; r0 += 64 * AU) {
+      double t[AU];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int r = r0 + lane + 64 * u;
-        double t = 0.0;
-        if (r < f) {
+      for (int u = 0; u < AU; ++u) t[u] = 0.0;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            if (cc[q] >= 0) {
-              const int cr = inv[q][r];
-              if (cr >= 0) t += (double)pool[po[q] + (int64_t)(kc[q] + cc[q]) * fc[q] + (kc[q] + cr)];
-            }
-          }
+      for (int q = 0; q < 4; ++q) {
+        if (cc[q] < 0) continue;
+        const T* src = pool + po[q] + (int64_t)(kc[q] + cc[q]) * fc[q] + kc[q];
+        int cr[AU];
+#pragma unroll
+        for (int u = 0; u < AU; ++u) {
+          const int r = r0 + lane + 64 * u;
+          cr[u] = r < f ? inv[q][r] : -1;
         }
-        v[u] = t;
+        double v[AU];
+#pragma unroll
+        for (int u = 0; u < AU; ++u) v[u] = cr[u] >= 0 ? (double)src[cr[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < AU; ++u)
+          if (cr[u] >= 0) t[u] += v[u];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < AU; ++u) {
         const int r = r0 + lane + 64 * u;
-        if (r < f) col[r] = v[u];
+        if (r < f) col[r] = t[u];
       }
     }
   }
