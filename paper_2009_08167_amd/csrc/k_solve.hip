@@ -178,19 +178,37 @@ __device__ __forceinline__ void bwd_unit(const SolveArgs& sa, const T* __restric
   // above a column's diagonal are masked
   const int ibeg = (lo + 1) & ~15;
   if (ibeg < f) load(ibeg);
-  for (int i = lo + tid; i < f; i += 256) {
-    double val;
-    if (i < k) {
-      // neighbours inside the front's own pivots (a 2x2 block never
-      // crosses a front); their coefficient is zero otherwise
-      const int n = start + i;
-      const double* c3 = sa.dc + 3 * (int64_t)n;
-      val = c3[0] * sa.fwd[n] + c3[1] * sa.fwd[start + min(i + 1, k - 1)] +
-            c3[2] * sa.fwd[start + max(i - 1, 0)];
-    } else {
-      val = -x[rows[i]];
+  // v in batches of GB rows per thread: the update rows' indices of a batch,
+  // then their values, each set of loads in flight together (the rows of a
+  // tall front's update block are many more than the threads)
+  constexpr int GB = 4;
+  for (int i0 = lo + tid; i0 < f; i0 += 256 * GB) {
+    int ri[GB];
+#pragma unroll
+    for (int g = 0; g < GB; ++g) {
+      const int i = i0 + 256 * g;
+      ri[g] = (i >= k && i < f) ? rows[i] : -1;
     }
-    v[i - lo] = val;
+    double xv[GB];
+#pragma unroll
+    for (int g = 0; g < GB; ++g) xv[g] = ri[g] >= 0 ? x[ri[g]] : 0.0;
+#pragma unroll
+    for (int g = 0; g < GB; ++g) {
+      const int i = i0 + 256 * g;
+      if (i >= f) continue;
+      double val;
+      if (i < k) {
+        // neighbours inside the front's own pivots (a 2x2 block never
+        // crosses a front); their coefficient is zero otherwise
+        const int n = start + i;
+        const double* c3 = sa.dc + 3 * (int64_t)n;
+        val = c3[0] * sa.fwd[n] + c3[1] * sa.fwd[start + min(i + 1, k - 1)] +
+              c3[2] * sa.fwd[start + max(i - 1, 0)];
+      } else {
+        val = -xv[g];
+      }
+      v[i - lo] = val;
+    }
   }
   __syncthreads();
   for (int i0 = ibeg; i0 < f; i0 += 64 * RCH) {

@@ -97,6 +97,7 @@ constexpr int SWEEP_COLS = 16;
 constexpr int SWEEP_ROWS_THIN = 16;
 constexpr int SWEEP_COLS_THIN = 4;
 constexpr int SWEEP_THIN_BELOW = 512;  // units of the default shape
+constexpr int XCD_PIECE = 16;          // sweep units of one front kept on one XCD
 constexpr int XCDS = 8;                // accelerator complex dies of an MI355X
 // Fused sweeps of the bottom heights (one workgroup per subtree): four
 // 256-thread groups, forward units of SUB_ROWS rows, backward units of

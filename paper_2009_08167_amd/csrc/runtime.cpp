@@ -253,15 +253,21 @@ void setup_device(riga_problem* pr, const riga_mesh_desc* desc) {
     // 8 XCDs round-robin by index), so the gathers that every unit of a
     // front repeats hit that XCD's L2; fronts are spread over the XCDs
     // largest first, and empty slots (front -1) pad the interleave.
+    // A front of more than XCD_PIECE units (the tall fronts of split
+    // separators, alone on their level) is dealt out in pieces of that many
+    // consecutive units, so that one front does not leave seven XCDs idle.
     auto xcd_order = [&](bool rows_split, int width) {
       std::vector<std::vector<WorkUnit>> q(XCDS);
       std::vector<int64_t> load(XCDS, 0);
       for (auto it = fr.rbegin(); it != fr.rend(); ++it) {
         const int F = *it, f = an.f_f[F], k = an.f_k[F];
-        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         const int n = rows_split ? f : k;
-        for (int a = 0; a < n; a += width) q[x].push_back(unit(F, a, std::min(n, a + width)));
-        load[x] += (n + width - 1) / width;
+        for (int a0 = 0; a0 < n; a0 += XCD_PIECE * width) {
+          const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+          const int a1 = std::min(n, a0 + XCD_PIECE * width);
+          for (int a = a0; a < a1; a += width) q[x].push_back(unit(F, a, std::min(n, a + width)));
+          load[x] += (a1 - a0 + width - 1) / width;
+        }
       }
       size_t len = 0;
       for (auto& v : q) len = std::max(len, v.size());
