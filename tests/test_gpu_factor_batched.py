@@ -86,6 +86,25 @@ def test_factor_batched_equals_individual(precision):
             assert berr <= 1e-12, (w.name, berr)
 
 
+def test_factor_batched_with_complex_hermitian_pencils():
+    """Real and complex Hermitian pencils (the magnetic Laplacian in its
+    real-equivalent form, 2 x 2 blocks) in one batched call: each equals its
+    single factorisation bit for bit (inertia and solve)."""
+    riga = _riga()
+    probs = [riga.assemble(2, 16, 2, 4, potential=(1.0, 0.5)), _problems(riga, CASES[:1])[0],
+             riga.assemble(3, 6, 2, 3, potential=(0.3, -0.7, 1.1))]
+    assert probs[0].hermitian and probs[2].hermitian
+    sigmas = [40.0, 0.0, 60.0]
+    out = riga.factor_batched(probs, sigmas)
+    rng = np.random.default_rng(8)
+    bs = [torch.tensor(rng.standard_normal(pr.n_dof), dtype=torch.float64, device="cuda") for pr in probs]
+    xb = [pr.solve(b).cpu().numpy() for pr, b in zip(probs, bs)]
+    for pr, sg, b, x, (neg, st) in zip(probs, sigmas, bs, xb, out):
+        neg1, _ = pr.factor(sg)
+        assert neg == neg1
+        assert np.array_equal(x, pr.solve(b).cpu().numpy())
+
+
 def test_factor_batched_repeated_and_reordered():
     """Two batched calls in a row over the same problems in another order
     and at other shifts: each factorisation depends only on its problem and
