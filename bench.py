@@ -706,6 +706,55 @@ def factor_profile(riga, torch):
         del pr
 
 
+def stall_summary(counter_csv):
+    """Markdown summary of `rocprofv3 --pmc SQ_WAVE_CYCLES SQ_BUSY_CYCLES
+    SQ_WAIT_ANY SQ_WAIT_INST_LDS SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT
+    SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_VALU_MFMA_MOPS_F64` over `bench.py
+    --factor-profile`, per case (split at its assembly) and FP64 kernel:
+    the kernel's share of the case's wave cycles, the share of its wave
+    cycles spent waiting on anything (memory, LDS, barriers), LDS bank
+    conflict cycles per LDS instruction, and its FP64 matrix-core flops per
+    factorisation (MOPS x 512 over the five factorisations)."""
+    import csv
+    reps = 5
+    rows = list(csv.DictReader(open(counter_csv)))
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+
+    def short(name):
+        n = name.replace("(anonymous namespace)::", "").replace("void ", "").replace("riga::", "")
+        return n.split("(")[0]
+
+    cases, cur = [], None
+    for r in rows:
+        name = short(r["Kernel_Name"])
+        if name == "assemble_kernel":
+            if cur is None or cur["seen_other"]:
+                cur = {"seen_other": False, "kern": {}}
+                cases.append(cur)
+            continue
+        if cur is None:
+            continue
+        cur["seen_other"] = True
+        kd = cur["kern"].setdefault(name, {})
+        kd[r["Counter_Name"]] = kd.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    names = ["3d_32_p2_s8", "3d_32_p2_s0", "3d_64_p2_s8"]
+    print("| case | kernel (FP64) | share of wave cycles | waiting | LDS bank conflict cycles per LDS instruction "
+          "| FP64 matrix-core flops per factorisation |")
+    print("|---|---|---|---|---|---|")
+    for i, c in enumerate(cases):
+        kern = {k: v for k, v in c["kern"].items() if "<float" not in k}
+        tot = sum(v.get("SQ_WAVE_CYCLES", 0.0) for v in kern.values()) or 1.0
+        top = sorted(kern.items(), key=lambda kv: -kv[1].get("SQ_WAVE_CYCLES", 0.0))[:6]
+        for k, v in top:
+            wc = v.get("SQ_WAVE_CYCLES", 0.0) or 1.0
+            lds = v.get("SQ_INSTS_LDS", 0.0)
+            print("| %s | `%s` | %.1f%% | %.0f%% | %s | %.3g |"
+                  % (names[i] if i < len(names) else str(i), k, 100.0 * wc / tot,
+                     100.0 * v.get("SQ_WAIT_ANY", 0.0) / wc,
+                     "%.2f" % (v.get("SQ_LDS_BANK_CONFLICT", 0.0) / lds) if lds else "-",
+                     v.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) * 512 / reps))
+
+
 def mfma_summary(counter_csv, fprof_log):
     """Markdown summary of `rocprofv3 --pmc SQ_INSTS_VALU_MFMA_MOPS_F64
     SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE` over
@@ -804,6 +853,8 @@ def main():
                     help="with --large-n0: only the meshes with this many elements per direction")
     ap.add_argument("--mfma-summary", nargs=2, metavar=("COUNTER_CSV", "FPROF_LOG"),
                     help="summarise an MFMA counter run over --factor-profile and exit")
+    ap.add_argument("--stall-summary", metavar="COUNTER_CSV",
+                    help="markdown summary of wait and LDS counters over --factor-profile")
     ap.add_argument("--factor-profile", action="store_true",
                     help="factorisations only (3D 32^3 rIGA / IGA, 64^3 rIGA; FP64 and mixed) and exit")
     ap.add_argument("--large-n0-summary", metavar="JSONL",
@@ -826,6 +877,9 @@ def main():
         return
     if args.mfma_summary:
         mfma_summary(*args.mfma_summary)
+        return
+    if args.stall_summary:
+        stall_summary(args.stall_summary)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
