@@ -594,8 +594,8 @@ __global__ void __launch_bounds__(256) big_w21_kernel(BigArgs a0, T* pool0, BigJ
 // W21 = L21 D, over all k fully-summed columns at once after the level's
 // last panel step (the panels' trailing updates stop at column k): C is read
 // and written once per front instead of once per panel.  A GEMM on the
-// matrix cores: 128 x 128 tiles of C (lower-triangle tiles only), eight waves
-// of 32 x 64 each (2 x 4 MFMA tiles), the inner dimension in chunks of 16
+// matrix cores: 128 x 128 tiles of C (lower-triangle tiles only), a grid of
+// waves over each tile (below), the inner dimension in chunks of 16
 // columns staged through LDS in two buffers, the next chunk's global loads
 // in flight while the current one is multiplied.  The transposed product
 // C^T = W L^T is formed, so that a lane's MFMA output column is a row of C:
@@ -606,11 +606,21 @@ constexpr int CB_T = 128;
 constexpr int CB_K = 16;
 constexpr int CB_LD = CB_T + 4;
 constexpr size_t CB_LDS = 2 * 2 * CB_K * CB_LD * sizeof(double);
-constexpr int CB_NT = 512;               // threads of the update-block GEMM
-constexpr int CB_QS = CB_K * CB_T / CB_NT;  // staged entries of each operand per thread
+// the wave grid of a tile: WR waves down by WC across, each with RT x CT MFMA
+// tiles of 16 x 16; FP64 takes sixteen waves of 32 x 32 (few accumulators per
+// lane, four waves per SIMD in one workgroup), FP32 eight of 32 x 64 (two
+// workgroups per compute unit)
+template <class T>
+struct CbShape {
+  static constexpr int WR = 4, WC = sizeof(T) == 8 ? 4 : 2;
+  static constexpr int NT = 64 * WR * WC;          // threads
+  static constexpr int RT = CB_T / WR / 16, CT = CB_T / WC / 16;
+  static constexpr int SP = NT / CB_T;             // threads per staged row or column
+  static constexpr int QS = CB_K * CB_T / NT;      // staged entries of each operand per thread
+};
 
 template <class T>
-__global__ void __launch_bounds__(CB_NT, 2) big_cbupdate_kernel(BigArgs a0, T* pool0, BigJobs J) {
+__global__ void __launch_bounds__(CbShape<T>::NT) big_cbupdate_kernel(BigArgs a0, T* pool0, BigJobs J) {
   BigArgs a;
   T* pool;
   int b;
@@ -627,11 +637,11 @@ __global__ void __launch_bounds__(CB_NT, 2) big_cbupdate_kernel(BigArgs a0, T* p
   const T* A = pool + a.pool_off[F];
   T* Aw = pool + a.pool_off[F];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // eight waves: four row groups of 32 (two 16-row MFMA tiles) by two
-  // column groups of 64 (four tiles)
-  const int wr = wave >> 1, wc = wave & 1;
-  const int srow = tid & (CB_T - 1), st0 = tid >> 7;  // staging of L: row, first t (0..3)
-  const int wcol = tid >> 2, wt0 = (tid & 3) * CB_QS;  // staging of W: column, first t
+  using S = CbShape<T>;
+  constexpr int QS = S::QS, SP = S::SP, RT = S::RT, CT = S::CT;
+  const int wr = wave / S::WC, wc = wave % S::WC;
+  const int srow = tid % CB_T, st0 = tid / CB_T;         // staging of L: row, first t
+  const int wcol = tid / SP, wt0 = (tid % SP) * QS;      // staging of W: column, first t
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     int bi = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
     while ((bi + 1) * (bi + 2) / 2 <= tile) ++bi;
@@ -639,14 +649,14 @@ __global__ void __launch_bounds__(CB_NT, 2) big_cbupdate_kernel(BigArgs a0, T* p
     const int bj = tile - bi * (bi + 1) / 2;
     const int r0 = k + bi * CB_T, c0 = k + bj * CB_T;
     const int i = r0 + srow, c = c0 + wcol;
-    T la[CB_QS], wb[CB_QS];
-    // chunk j0: L(i, j0 + st0 + 4 q) down a column of L21, W(c, j0 + wt0 + q)
+    T la[QS], wb[QS];
+    // chunk j0: L(i, j0 + st0 + SP q) down a column of L21, W(c, j0 + wt0 + q)
     // down a column of the stored W21^T (plain loads: nothing waits on them
     // before the chunk's multiplications)
     auto load = [&](int j0) {
 #pragma unroll
-      for (int q = 0; q < CB_QS; ++q) {
-        const int g = j0 + st0 + 4 * q;
+      for (int q = 0; q < QS; ++q) {
+        const int g = j0 + st0 + SP * q;
         la[q] = (g < k && i < f) ? A[(int64_t)g * f + i] : (T)0;
         const int h = j0 + wt0 + q;
         wb[q] = (h < k && c < f) ? A[(int64_t)c * f + h] : (T)0;
@@ -654,16 +664,16 @@ __global__ void __launch_bounds__(CB_NT, 2) big_cbupdate_kernel(BigArgs a0, T* p
     };
     auto store = [&](int buf) {
 #pragma unroll
-      for (int q = 0; q < CB_QS; ++q) {
-        As(buf, st0 + 4 * q, srow) = (double)la[q];
+      for (int q = 0; q < QS; ++q) {
+        As(buf, st0 + SP * q, srow) = (double)la[q];
         Bs(buf, wt0 + q, wcol) = (double)wb[q];
       }
     };
-    Tile16<T> acc[4][2];
+    Tile16<T> acc[CT][RT];
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct)
+    for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-      for (int rt = 0; rt < 2; ++rt) acc[ct][rt].zero();
+      for (int rt = 0; rt < RT; ++rt) acc[ct][rt].zero();
     __syncthreads();  // the previous tile's LDS reads are done
     load(0);
     store(0);
@@ -675,30 +685,30 @@ __global__ void __launch_bounds__(CB_NT, 2) big_cbupdate_kernel(BigArgs a0, T* p
 #pragma unroll
       for (int t0 = 0; t0 < CB_K; t0 += 4) {
         const int kr = t0 + (lane >> 4);
-        double av[2], bv[4];
+        double av[RT], bv[CT];
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt) av[rt] = As(buf, kr, wr * 32 + rt * 16 + (lane & 15));
+        for (int rt = 0; rt < RT; ++rt) av[rt] = As(buf, kr, (wr * RT + rt) * 16 + (lane & 15));
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) bv[ct] = Bs(buf, kr, wc * 64 + ct * 16 + (lane & 15));
+        for (int ct = 0; ct < CT; ++ct) bv[ct] = Bs(buf, kr, (wc * CT + ct) * 16 + (lane & 15));
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct)
+        for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-          for (int rt = 0; rt < 2; ++rt) acc[ct][rt].step(bv[ct], av[rt]);
+          for (int rt = 0; rt < RT; ++rt) acc[ct][rt].step(bv[ct], av[rt]);
       }
       if (more) store(buf ^ 1);
       __syncthreads();
       buf ^= 1;
     }
-    // acc[ct][rt] holds (W L^T)(c, i): c = c0 + wc 64 + ct 16 + row(lane, q),
-    // i = r0 + wr 32 + rt 16 + (lane & 15)
+    // acc[ct][rt] holds (W L^T)(c, i): c = c0 + (wc CT + ct) 16 + row(lane, q),
+    // i = r0 + (wr RT + rt) 16 + (lane & 15)
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct)
+    for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int cc = c0 + wc * 64 + ct * 16 + Tile16<T>::row(lane, q);
+        const int cc = c0 + (wc * CT + ct) * 16 + Tile16<T>::row(lane, q);
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt) {
-          const int ii = r0 + wr * 32 + rt * 16 + (lane & 15);
+        for (int rt = 0; rt < RT; ++rt) {
+          const int ii = r0 + (wr * RT + rt) * 16 + (lane & 15);
           if (ii < f && cc < f && ii >= cc) {
             T* ap = Aw + (int64_t)cc * f + ii;
             *ap = (T)((double)*ap - acc[ct][rt].get(q));
@@ -829,7 +839,7 @@ void big_cb_update(const BigArgs& a, T* pool, const BigJobs& J, const BigPlan& P
   const unsigned wpf = (unsigned)std::max(1, std::min(((P.maxcb + 63) / 64) * ((P.maxk + 63) / 64),
                                                       std::max(1, 2048 / nb)));
   big_w21_kernel<T><<<dim3(wpf, nb), 256, 0, s>>>(a, pool, J);
-  big_cbupdate_kernel<T><<<dim3(cpf, nb), CB_NT, CB_LDS, s>>>(a, pool, J);
+  big_cbupdate_kernel<T><<<dim3(cpf, nb), CbShape<T>::NT, CB_LDS, s>>>(a, pool, J);
   HIPCHECK(hipGetLastError());
 }
 
