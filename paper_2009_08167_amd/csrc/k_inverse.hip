@@ -22,7 +22,8 @@
 // columns from the right in 64-wide panels:
 //     Hp = R(:, panel) - H(:, right of panel) * L11(right of panel, panel)
 //     (a GEMM on the matrix cores in the factor's precision, operands
-//     staged in LDS), then the
+//     staged in LDS; the panel Hp then takes the LDS of the GEMM's first
+//     operand, so that two workgroups fit in a compute unit), then the
 //     unit-triangular solve with the panel's diagonal block of L11.
 // The columns to the right were written by the same workgroup earlier; the
 // workgroup barrier orders those global writes before the reads.
@@ -53,7 +54,7 @@ __device__ __forceinline__ double l_entry(const T* L, int f, int m, int c, const
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) front_inverse_kernel(const FrontDesc* __restrict__ desc,
+__global__ void __launch_bounds__(256, 2) front_inverse_kernel(const FrontDesc* __restrict__ desc,
                                                             const WorkUnit* __restrict__ units,
                                                             const T* __restrict__ pool, T* H,
                                                             const int32_t* __restrict__ piv_type,
@@ -61,8 +62,8 @@ __global__ void __launch_bounds__(256) front_inverse_kernel(const FrontDesc* __r
   extern __shared__ double smem[];
   double* Ac = smem;              // Ac[mm * LDP + ii] = H(r0 + ii, m0 + mm)
   double* Bc = Ac + IB * LDP;     // Bc[mm * LDP + c]  = L(m0 + mm, j0 + c)
-  double* Hp = Bc + IB * LDP;     // Hp[ii * LDP + c]  = H(r0 + ii, j0 + c)
-  int32_t* type = (int32_t*)(Hp + IB * LDP);
+  double* Hp = Ac;                // Hp[ii * LDP + c]  = H(r0 + ii, j0 + c), after the GEMM
+  int32_t* type = (int32_t*)(Bc + IB * LDP);
   const WorkUnit u = units[blockIdx.x];
   const FrontDesc d = desc[u.front];
   const int f = d.f, k = d.k, ldh = d.ldh;
@@ -78,32 +79,11 @@ __global__ void __launch_bounds__(256) front_inverse_kernel(const FrontDesc* __r
   const int nrt = (nr + 15) / 16;
   for (int q = qlast; q >= 0; --q) {
     const int j0 = q * IB, pw = min(IB, k - j0), j1 = j0 + pw;
-    // right-hand side rows: e_i in the top block, L21 rows below (every
-    // load of the thread's share issued before the LDS stores)
-    {
-      double rv[IB * IB / 256];
-#pragma unroll
-      for (int q = 0; q < IB * IB / 256; ++q) {
-        const int e = tid + 256 * q;
-        const int ii = e & 63, c = e >> 6;
-        double v = 0.0;
-        if (ii < nr && c < pw) {
-          const int i = r0 + ii, j = j0 + c;
-          v = i < k ? (i == j ? 1.0 : 0.0) : (double)L[(int64_t)j * f + i];
-        }
-        rv[q] = v;
-      }
-#pragma unroll
-      for (int q = 0; q < IB * IB / 256; ++q) {
-        const int e = tid + 256 * q;
-        Hp[(e & 63) * LDP + (e >> 6)] = rv[q];
-      }
-    }
     // Hp -= H(:, j1:k) * L11(j1:k, panel), 64-deep chunks on the MFMA units
-    if (j1 < k) {
-      Tile16<T> acc[4];
+    Tile16<T> acc[4];
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt) acc[rt].zero();
+    for (int rt = 0; rt < 4; ++rt) acc[rt].zero();
+    if (j1 < k) {
       for (int m0 = j1; m0 < k; m0 += IB) {
         const int mw = min(IB, k - m0);
         double ar[IB * IB / 256], br[IB * IB / 256];
@@ -143,6 +123,31 @@ __global__ void __launch_bounds__(256) front_inverse_kernel(const FrontDesc* __r
         }
         __syncthreads();
       }
+    }
+    // right-hand side rows: e_i in the top block, L21 rows below (every
+    // load of the thread's share issued before the LDS stores), into the
+    // LDS of the GEMM's first operand: the GEMM's last barrier is behind
+    {
+      double rv[IB * IB / 256];
+#pragma unroll
+      for (int q = 0; q < IB * IB / 256; ++q) {
+        const int e = tid + 256 * q;
+        const int ii = e & 63, c = e >> 6;
+        double v = 0.0;
+        if (ii < nr && c < pw) {
+          const int i = r0 + ii, j = j0 + c;
+          v = i < k ? (i == j ? 1.0 : 0.0) : (double)L[(int64_t)j * f + i];
+        }
+        rv[q] = v;
+      }
+#pragma unroll
+      for (int q = 0; q < IB * IB / 256; ++q) {
+        const int e = tid + 256 * q;
+        Hp[(e & 63) * LDP + (e >> 6)] = rv[q];
+      }
+    }
+    __syncthreads();
+    if (j1 < k) {
       // lane holds the product at row Tile16::row(lane, r) of the row
       // tile, column lane & 15 of this wave's column tile
 #pragma unroll
@@ -219,7 +224,7 @@ __global__ void __launch_bounds__(256) front_inverse_kernel(const FrontDesc* __r
   }
 }
 
-constexpr size_t INV_LDS_FIXED = (size_t)3 * IB * LDP * sizeof(double);
+constexpr size_t INV_LDS_FIXED = (size_t)2 * IB * LDP * sizeof(double);
 
 }  // namespace
 
