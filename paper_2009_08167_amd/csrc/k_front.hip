@@ -410,12 +410,19 @@ __device__ __forceinline__ void ldlt_partial(Acc A, int f, int k, int* perm,
   if (tid == 0) { *n_neg = neg; *n_pert = pert; *n_2x2 = two; }
 }
 
+// bytes of the packed lower triangle of a front of order f
+template <class T>
+constexpr size_t lds_front_bytes(int f) { return (size_t)f * (f + 1) / 2 * sizeof(T); }
+
 // The front in LDS as a packed lower triangle (column j holds rows j..f-1),
-// f (f + 1) / 2 entries, so that two workgroups fit on a CU.
+// f (f + 1) / 2 entries in dynamic LDS sized by the launch's largest front,
+// so that two workgroups fit on a CU at the largest orders and more on the
+// levels of small fronts.
 template <class T, int MAXF>
 __device__ __forceinline__ void front_factor_lds_body(const FrontArgs& fa, T* pool, const int32_t* fronts,
                                                       double pivtol, int blk) {
-  __shared__ T sa[MAXF * (MAXF + 1) / 2];
+  extern __shared__ double lds_front[];
+  T* sa = reinterpret_cast<T*>(lds_front);
   __shared__ int perm[MAXF];
   __shared__ int32_t type[MAXF];
   __shared__ PivotStep dec;
@@ -532,7 +539,8 @@ void factor_levels(riga_problem* pr, Factor& F, T* pool, double sigma, bool chec
     HIPCHECK(hipGetLastError());
     const int ns = L.n_upto(MAXF);
     if (ns > 0) {
-      front_factor_lds_kernel<T, MAXF><<<ns, 256, 0, s>>>(fa, pool, L.fronts.p, pivtol);
+      front_factor_lds_kernel<T, MAXF><<<ns, 256, lds_front_bytes<T>(L.host_f[ns - 1]), s>>>(
+          fa, pool, L.fronts.p, pivtol);
       HIPCHECK(hipGetLastError());
     }
     if (L.n > ns) {
@@ -546,6 +554,14 @@ void factor_levels(riga_problem* pr, Factor& F, T* pool, double sigma, bool chec
 }  // namespace
 
 void set_front_attributes() {
+  HIPCHECK(hipFuncSetAttribute((const void*)front_factor_lds_kernel<double, 128>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_front_bytes<double>(128)));
+  HIPCHECK(hipFuncSetAttribute((const void*)front_factor_lds_kernel<float, 176>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_front_bytes<float>(176)));
+  HIPCHECK(hipFuncSetAttribute((const void*)front_factor_lds_batched_kernel<double, 128>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_front_bytes<double>(128)));
+  HIPCHECK(hipFuncSetAttribute((const void*)front_factor_lds_batched_kernel<float, 176>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_front_bytes<float>(176)));
   HIPCHECK(hipFuncSetAttribute((const void*)front_assemble_kernel<double>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, ASM_LDS));
   HIPCHECK(hipFuncSetAttribute((const void*)front_assemble_kernel<float>,
@@ -752,6 +768,7 @@ struct BatchHeight {
   size_t lds_off = 0;
   int lds_jobs = 0;
   int64_t lds_blocks = 0;
+  int lds_max_f = 0;  // largest front of the LDS jobs
   size_t big_off = 0, big_ystart_off = 0;
   int big_jobs = 0;
   BigPlan big;
@@ -820,6 +837,7 @@ void factor_levels_batched(const std::vector<riga_problem*>& prs, const std::vec
         lj.y0 = B.lds_blocks;
         lds.push_back(lj);
         B.lds_blocks += ns;
+        B.lds_max_f = std::max(B.lds_max_f, L.host_f[ns - 1]);
       }
       if (L.n > ns) {
         std::vector<int> bf(L.host_f.begin() + ns, L.host_f.end());
@@ -882,7 +900,8 @@ void factor_levels_batched(const std::vector<riga_problem*>& prs, const std::vec
       HIPCHECK(hipGetLastError());
     }
     if (B.lds_jobs > 0) {
-      front_factor_lds_batched_kernel<T, MAXF><<<(unsigned)B.lds_blocks, 256, 0, s>>>(
+      front_factor_lds_batched_kernel<T, MAXF><<<(unsigned)B.lds_blocks, 256,
+                                                 lds_front_bytes<T>(B.lds_max_f), s>>>(
           reinterpret_cast<const LdsJob*>(dtab.p + B.lds_off), B.lds_jobs);
       HIPCHECK(hipGetLastError());
     }
